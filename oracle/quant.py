@@ -1,0 +1,100 @@
+"""Rounding emulation for the reduced-precision forms (oracle).
+
+* BF16: IEEE binary32 with the low 16 mantissa bits removed, rounded to
+  nearest with ties to even (RNE), computed on the float32 bit pattern.
+* FP8 E4M3 "fn" (OCP 8-bit floating point specification): 1 sign bit,
+  4 exponent bits (bias 7), 3 mantissa bits, no infinities; largest finite
+  value 448, smallest normal 2^-6, subnormal quantum 2^-9.  Conversion rounds
+  to nearest even and saturates to +-448.
+* Per-grain FP8 scale: ``s_g = amax_{i in g, j} |z_ij| / 448`` and the stored
+  code is ``fp8(z / s_g)``; the decoded value is ``code * s_g``.
+
+These are written from the format definitions, not from any library.
+Pins: exhaustive round-trip of every representable value, midpoint ties,
+saturation, and the float32 -> bf16 -> float32 identity on bf16 values.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FP8_MAX = 448.0
+
+
+def bf16_round(x) -> np.ndarray:
+    """float32 -> nearest bf16 (RNE), returned as float32 values."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def bf16_bits(x) -> np.ndarray:
+    return (bf16_round(x).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def fp8_e4m3_round(x) -> np.ndarray:
+    """Nearest E4M3fn value (RNE, saturating), as float64."""
+    v = np.asarray(x, dtype=np.float64)
+    s = np.sign(v)
+    a = np.abs(v)
+    out = np.zeros_like(a)
+    nz = a > 0
+    e = np.floor(np.log2(np.where(nz, a, 1.0)))
+    e = np.maximum(e, -6.0)
+    quantum = np.exp2(e - 3.0)
+    q = np.rint(a / quantum) * quantum
+    out = np.where(nz, q, 0.0)
+    out = np.minimum(out, FP8_MAX)
+    return s * out
+
+
+def fp8_e4m3_values() -> np.ndarray:
+    """All finite non-negative E4M3fn values, from the bit-field definition."""
+    vals = []
+    for e in range(16):
+        for m in range(8):
+            if e == 15 and m == 7:
+                continue  # NaN encoding
+            if e == 0:
+                vals.append(m * 2.0 ** -9)
+            else:
+                vals.append((1 + m / 8.0) * 2.0 ** (e - 7))
+    return np.array(vals)
+
+
+def fp8_encode_byte(x) -> np.ndarray:
+    """E4M3fn bit pattern (uint8) of already-rounded values."""
+    v = np.asarray(x, dtype=np.float64)
+    sign = (v < 0).astype(np.uint8) << 7
+    a = np.abs(v)
+    out = np.zeros(a.shape, dtype=np.uint8)
+    sub = a < 2.0 ** -6
+    m_sub = np.rint(a / 2.0 ** -9).astype(np.int64)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0))).astype(np.int64)
+    m_norm = np.rint((a / np.exp2(e) - 1.0) * 8).astype(np.int64)
+    norm_bits = ((e + 7) << 3) | m_norm
+    out = np.where(sub, m_sub, norm_bits).astype(np.uint8)
+    return out | sign
+
+
+def fp8_decode_byte(b) -> np.ndarray:
+    b = np.asarray(b, dtype=np.uint8).astype(np.int64)
+    s = np.where(b & 0x80, -1.0, 1.0)
+    e = (b >> 3) & 0xF
+    m = b & 7
+    v = np.where(e == 0, m * 2.0 ** -9, (1 + m / 8.0) * np.exp2(e - 7))
+    return s * v
+
+
+def grain_fp8_scales(codes: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    """Per-grain FP32 scale amax/448 (1.0 for an empty or all-zero grain)."""
+    G = len(offsets) - 1
+    sc = np.ones(G, dtype=np.float32)
+    for g in range(G):
+        a, b = int(offsets[g]), int(offsets[g + 1])
+        if b > a:
+            amax = float(np.abs(codes[a:b]).max())
+            if amax > 0:
+                sc[g] = np.float32(amax / FP8_MAX)
+    return sc

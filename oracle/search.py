@@ -1,0 +1,158 @@
+"""HNTL search, step by step (oracle, FP64 on the stored index values).
+
+Query lifecycle of Section 2.1 in Mode B (tiered filter), with the
+hierarchical routing of Section 2.3:
+
+1. ``route``   - squared Euclidean distance from q to every centroid mu_g;
+   the P smallest, ordered by (distance, g).
+2. ``project`` - for each probed grain: eq. (1) ``q' = q - mu_g``, eq. (2)
+   ``z_q = W_g^T q'``, eq. (3) ``e_q = q' - W_g z_q``, eq. (4)
+   ``eps_q = ||e_q||^2``.
+3. ``scan_pool`` - eq. (6) score ``D_i = ||z_q - z_i||^2 + eps_q + eps_i`` for
+   every member i of every probed grain; the candidate pool is the C smallest
+   (D, id) over the union of the probed grains (ids are original row ids);
+   fewer than C candidates are padded with (id -1, D +inf).
+4. ``rerank``  - exact squared L2 ``||q - x_i||^2`` against the raw vectors of
+   the pool; the k smallest (distance, id).
+
+Each stage accepts the previous stage's output as an argument, so any stage
+can be checked on its own.  The quantisation envelope filter of Section 2.3
+prunes grains whose int16 query coordinates saturate; float32 query
+coordinates never saturate, so it is the identity here.
+
+Parity: pinned by brute force on tiny inputs (P = G and C = N give the exact
+k-NN), by the r = d identity (scan score equals the exact distance), and by
+the isotropic rows of the paper's recall table.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+INF = np.inf
+
+
+def _lexsmallest(dist: np.ndarray, ids: np.ndarray, m: int):
+    """The m smallest (dist, id) pairs, ascending; pads with (+inf, -1)."""
+    order = np.lexsort((ids, dist))[:m]
+    out_d = np.full(m, INF)
+    out_i = np.full(m, -1, dtype=np.int64)
+    out_d[: len(order)] = dist[order]
+    out_i[: len(order)] = ids[order]
+    return out_i, out_d
+
+
+def route(Q: np.ndarray, centroids: np.ndarray, P: int):
+    """Probes (nq, P) grain ids and their squared distances, by direct differences."""
+    Q = np.asarray(Q, dtype=np.float64)
+    M = np.asarray(centroids, dtype=np.float64)
+    G = M.shape[0]
+    if not 1 <= P <= G:
+        raise ValueError("need 1 <= P <= G")
+    probes = np.empty((Q.shape[0], P), dtype=np.int64)
+    pdist = np.empty((Q.shape[0], P))
+    gid = np.arange(G)
+    for i, q in enumerate(Q):
+        dc = ((q[None, :] - M) ** 2).sum(axis=1)
+        probes[i], pdist[i] = _lexsmallest(dc, gid, P)
+    return probes, pdist
+
+
+def project(Q: np.ndarray, probes: np.ndarray, stored: dict):
+    """Tangent coordinates z_q (nq, P, r) and residual energies eps_q (nq, P)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    M = stored["centroids"].astype(np.float64)
+    B = stored["basis"]
+    nq, P = probes.shape
+    r = B.shape[1]
+    zq = np.zeros((nq, P, r))
+    epsq = np.zeros((nq, P))
+    for i in range(nq):
+        for s in range(P):
+            g = int(probes[i, s])
+            if g < 0:
+                continue
+            W = B[g].astype(np.float64).T          # (d, r)
+            qp = Q[i] - M[g]                       # eq. (1)
+            z = W.T @ qp                           # eq. (2)
+            e = qp - W @ z                         # eq. (3)
+            zq[i, s] = z
+            epsq[i, s] = e @ e                     # eq. (4)
+    return zq, epsq
+
+
+def grain_scores(zq: np.ndarray, epsq: float, g: int, stored: dict):
+    """eq. (6) for every member of grain g: returns (original ids, D)."""
+    a, b = int(stored["offsets"][g]), int(stored["offsets"][g + 1])
+    Z = stored["codes"][a:b].astype(np.float64)
+    ei = stored["eps"][a:b].astype(np.float64)
+    D = ((zq[None, :] - Z) ** 2).sum(axis=1) + epsq + ei
+    return stored["perm"][a:b].astype(np.int64), D
+
+
+def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict, C: int):
+    """Candidate pool (nq, C) ids and scores over the union of the probed grains."""
+    nq, P = probes.shape
+    pool_ids = np.full((nq, C), -1, dtype=np.int64)
+    pool_D = np.full((nq, C), INF)
+    for i in range(nq):
+        ids, Ds = [], []
+        for s in range(P):
+            g = int(probes[i, s])
+            if g < 0:
+                continue
+            gi, gd = grain_scores(zq[i, s], epsq[i, s], g, stored)
+            ids.append(gi)
+            Ds.append(gd)
+        if ids:
+            pool_ids[i], pool_D[i] = _lexsmallest(np.concatenate(Ds), np.concatenate(ids), C)
+    return pool_ids, pool_D
+
+
+def rerank(Q: np.ndarray, pool_ids: np.ndarray, X: np.ndarray, k: int):
+    """Exact squared L2 over the pool by direct differences; k smallest (dist, id)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    nq = Q.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    dist = np.full((nq, k), INF)
+    for i in range(nq):
+        cand = pool_ids[i][pool_ids[i] >= 0]
+        if len(cand) == 0:
+            continue
+        xv = np.asarray(X[cand], dtype=np.float64)
+        dd = ((xv - Q[i][None, :]) ** 2).sum(axis=1)
+        ids[i], dist[i] = _lexsmallest(dd, cand.astype(np.int64), k)
+    return ids, dist
+
+
+def search(Q, stored: dict, X, P: int, C: int, k: int, probes=None, zq=None, epsq=None,
+           pool_ids=None):
+    """The whole lifecycle; any stage's input may be supplied to check later stages."""
+    G = stored["centroids"].shape[0]
+    if not (1 <= P <= G) or k < 1 or C < k:
+        raise ValueError("invalid P, C or k")
+    out = {}
+    if probes is None:
+        probes, pdist = route(Q, stored["centroids"], P)
+        out["pdist"] = pdist
+    out["probes"] = probes
+    if zq is None or epsq is None:
+        zq, epsq = project(Q, probes, stored)
+    out["zq"], out["epsq"] = zq, epsq
+    if pool_ids is None:
+        pool_ids, pool_D = scan_pool(zq, epsq, probes, stored, C)
+        out["pool_D"] = pool_D
+    out["pool_ids"] = pool_ids
+    out["ids"], out["dist"] = rerank(Q, pool_ids, X, k)
+    return out
+
+
+def candidate_recall(pool_ids: np.ndarray, gt: np.ndarray, k: int = 10) -> float:
+    """Recall of the approximate top-k (the first k of the pool) against the
+    true top-k; the paper's 'Cand. Recall@10' column."""
+    hits = [len(set(p[:k].tolist()) & set(t[:k].tolist())) for p, t in zip(pool_ids, gt)]
+    return float(np.mean(hits)) / k
+
+
+def recall(ids: np.ndarray, gt: np.ndarray, k: int = 10) -> float:
+    hits = [len(set(a[:k].tolist()) & set(t[:k].tolist())) for a, t in zip(ids, gt)]
+    return float(np.mean(hits)) / k
