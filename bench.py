@@ -1,0 +1,193 @@
+"""Benchmark of the HNTL search path on one MI355X.
+
+Workload (default): 1,000,000 patch-mixture vectors, d = 768, 1,024 patches;
+index G = 1,024 k-means grains, r = 32; one batch of 10,000 queries; P = 8,
+C = 64, k = 10; FP32.  A step is one full search of the batch (route, bucket,
+project, scan + select, merge + rerank), inputs resident in HBM.
+
+Prints one JSON line: queries/s (whole job), ns per vector scanned,
+Recall@10 against exact brute force on a query sample, per-stage device times
+from HIP events recorded by the library on its stream during the timed steps,
+the roofline of the dominant kernel, and the CPU oracle timed on a bounded
+query sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "queries/sec and ns/vector scanned at Recall@10≥0.95; scan HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="patch1M_d768_G1024_r32")
+    ap.add_argument("--codes", default="fp32")
+    ap.add_argument("--recall-sample", type=int, default=200)
+    ap.add_argument("--cpu-sample", type=int, default=400, help="queries timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-stage HIP event records")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(each GPU box has a single MI355X; multi-GPU sharding is design-only).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from workloads import WORKLOADS
+    from paper_2606_08813_amd import hntl
+
+    W = WORKLOADS[args.workload]
+    t0 = time.time()
+    corpus = W.corpus()
+    queries = W.queries()
+    log(f"[bench] generated {W.N}x{W.d} corpus + {W.nq} queries in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(corpus.X).to(dev)
+    Q = torch.from_numpy(queries.X).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.time()
+    codes_list = ("fp32",) if args.codes == "fp32" else ("fp32", args.codes)
+    ix = hntl.hntl_build(X, W.G, W.r, seed=W.kmeans_seed, codes=codes_list)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    info = hntl.hntl_index_info_get(ix)
+    log(f"[bench] build {build_s:.1f}s, captured variance {info['captured_variance']:.4f}, "
+        f"k-means iters {info['kmeans_iters_run']}, max grain {info['max_grain']}")
+    del X
+    torch.cuda.empty_cache()
+
+    stream = torch.cuda.current_stream()
+    ids = torch.empty((W.nq, W.k), dtype=torch.int32, device=dev)
+    dist = torch.empty((W.nq, W.k), dtype=torch.float32, device=dev)
+    flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
+    for _ in range(args.warmup):
+        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, out=(ids, dist))
+    torch.cuda.synchronize()
+    hntl.hntl_profile_read()  # drop warm-up records
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, flags=flags, out=(ids, dist))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    stage_ms, calls = hntl.hntl_profile_read()
+    stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
+    qps = W.nq / (ms_per_step / 1e3)
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
+        f"{qps:,.0f} queries/s; stages {stage_avg}")
+
+    # work accounting from one staged run (probes -> vectors scanned per step)
+    o = hntl.hntl_search_stages(ix, Q, W.P, W.C, W.k, codes=args.codes)
+    probes = o["probes"].cpu().numpy()
+    ex = hntl.hntl_index_export(ix)
+    sizes = np.diff(ex["offsets"])
+    scanned = int(sizes[probes[probes >= 0]].sum())
+    ids_h = ids.cpu().numpy()
+
+    # Recall@10 against exact brute force on a query sample
+    from oracle import brute, search as osr
+    rs = np.random.default_rng(7).choice(W.nq, size=min(args.recall_sample, W.nq), replace=False)
+    t0 = time.time()
+    gt, _ = brute.knn(corpus.X, queries.X[rs], W.k)
+    recall = osr.recall(ids_h[rs], gt, W.k)
+    log(f"[bench] Recall@10 on {len(rs)} sampled queries: {recall:.4f} (brute force {time.time() - t0:.1f}s)")
+
+    # rooflines per stage (algorithmic work per launch / average stage time)
+    npairs = W.nq * W.P
+    rp = (W.r + 7) // 8 * 8
+    code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1}[args.codes]
+    per_stage = {
+        "route": dict(bound="mfma", work=2.0 * W.nq * W.G * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
+        "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
+        "scan": dict(bound="alu", work=3.0 * W.r * scanned, unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
+        "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * W.P * W.C * 8, unit="GB/s",
+                       peak=HBM_PEAK_GBS),
+    }
+    roof = {}
+    for name, s in per_stage.items():
+        t = stage_avg.get(name, 0.0) / 1e3
+        if t <= 0:
+            continue
+        achieved = s["work"] / t / (1e12 if s["unit"] == "TFLOP/s" else 1e9)
+        roof[name] = {"bound": s["bound"], "achieved": round(achieved, 3), "peak": s["peak"], "unit": s["unit"],
+                      "frac": round(achieved / s["peak"], 4), "ms": round(stage_avg[name], 4)}
+    dominant = max(roof, key=lambda n: roof[n]["ms"]) if roof else None
+    scan_bytes = scanned * (rp * code_bytes + 4)
+    scan_ms = stage_avg.get("scan", 0.0)
+    scan_stream_gbs = scan_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None
+
+    # CPU oracle on a bounded query sample against the same index (timing only)
+    cpu = None
+    if args.cpu_sample > 0:
+        from threadpoolctl import threadpool_limits
+        cs = np.random.default_rng(11).choice(W.nq, size=min(args.cpu_sample, W.nq), replace=False)
+        with threadpool_limits(1):
+            t0 = time.time()
+            osr.search(queries.X[cs], ex, corpus.X, W.P, W.C, W.k)
+            el = time.time() - t0
+        cpu = {"value": round(len(cs) / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(cs)} of the {W.nq} queries, full lifecycle in float64 (numpy, 1 thread), "
+                         f"same index, {el:.1f}s",
+               "ns_per_vector_scanned": round(el / len(cs) / (scanned / W.nq) * 1e9, 2)}
+        log(f"[bench] CPU oracle: {cpu['value']} queries/s on 1 core")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.codes],
+        "data": "synthetic",
+        "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
+                   "P": W.P, "C": W.C, "k": W.k, "codes": args.codes},
+        "recall_at_10": round(recall, 4),
+        "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
+        "scan_ns_per_vector": round(scan_ms * 1e6 / scanned, 5) if scan_ms else None,
+        "vectors_scanned_per_step": scanned,
+        "scan_code_GBps": round(scan_stream_gbs, 1) if scan_stream_gbs else None,
+        "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "build_s": round(build_s, 2),
+        "captured_variance": round(info["captured_variance"], 5),
+        "roofline": dict(roof.get(dominant, {}), kernel=dominant, traffic=None) if dominant else None,
+        "stage_rooflines": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

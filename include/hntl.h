@@ -1,0 +1,213 @@
+/*
+ * hntl.h - C ABI of the HNTL search library for AMD Instinct MI355X (gfx950).
+ *
+ * HNTL ("Hierarchical No-pointer Tangent-Local" search) answers approximate
+ * k-nearest-neighbour queries in four steps (paper, Section 2.1 "Query
+ * Execution Lifecycle", Mode B):
+ *
+ *   1. centroid routing   - the P grains whose centroids are closest to the
+ *                           query (Section 2.1 step 1, Section 2.3)
+ *   2. projection         - q' = q - mu_g, z_q = W_g^T q', eps_q = ||q' - W_g z_q||^2
+ *                           for each probed grain (Section 2.2, eq. 1-4)
+ *   3. Block-SoA scan     - D_i = ||z_q - z_i||^2 + eps_q + eps_i over every member
+ *                           of every probed grain (eq. 6, Section 2.4), keeping the
+ *                           C smallest (D, id) per query: the candidate pool
+ *   4. exact rerank       - squared L2 against the raw float32 vectors of the pool,
+ *                           top-k (Section 2.1 step 4, Mode B)
+ *
+ * The index is built by k-means grain partitioning plus a per-grain local PCA
+ * basis of rank r (Section 2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an hntl_status and never throws; on failure a
+ *   thread-local message is available from hntl_last_error().
+ * - Array arguments are plain pointers.  Pointers marked "device" must point to
+ *   memory on the index's GPU; pointers marked "host or device" may be either
+ *   (they are read with a unified-address copy).  The caller owns every array
+ *   it passes; the library owns the index and everything inside it, including
+ *   its own copy of the raw vectors used for rerank.
+ * - Matrices are row-major, float32 unless stated.  Ids are int32 original row
+ *   indices (N < 2^31); -1 pads a list that has fewer valid entries.
+ * - Distances are squared Euclidean, float32.
+ * - Ties are broken by the lower id (grain id for routing).
+ * - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *   Search calls are asynchronous on that stream unless HNTL_FLAG_SYNC is set;
+ *   outputs are valid after the stream synchronises.  Concurrent searches on
+ *   one index are allowed (per-call scratch is stream-ordered).
+ */
+#ifndef HNTL_H_
+#define HNTL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hntl_status {
+  HNTL_OK = 0,
+  HNTL_EINVAL = -1,      /* invalid argument (sizes, null pointers, non-finite input) */
+  HNTL_ENOMEM = -2,      /* device or host allocation failed */
+  HNTL_EDEVICE = -3,     /* no usable GPU, or a HIP runtime error */
+  HNTL_ESTATE = -4,      /* the index lacks what the call needs (e.g. codes form not built) */
+  HNTL_EUNSUPPORTED = -6 /* a size outside the compiled limits (see HNTL_MAX_*) */
+} hntl_status;
+
+/* Compiled limits. */
+#define HNTL_MAX_R 64       /* tangent rank r */
+#define HNTL_MAX_C 256      /* candidate pool C */
+#define HNTL_MAX_P 64       /* probes P */
+#define HNTL_BLOCK 64       /* Block-SoA block size B (vectors per block) */
+
+/* Code storage of the tangent coordinates scanned in step 3. */
+typedef enum hntl_codes {
+  HNTL_CODES_FP32 = 0,
+  HNTL_CODES_BF16 = 1,      /* bf16, round-to-nearest-even of the fp32 codes */
+  HNTL_CODES_FP8_E4M3 = 2   /* OCP e4m3fn of z / s_g, per-grain fp32 scale s_g = amax / 448 */
+} hntl_codes;
+
+/* Search flags. */
+#define HNTL_FLAG_SYNC 1u       /* synchronise the stream before returning and report device errors */
+#define HNTL_FLAG_CHECK_Q 2u    /* reject non-finite query values with HNTL_EINVAL (implies a sync) */
+#define HNTL_FLAG_PROFILE 4u    /* record HIP events around each stage on the call's stream (see hntl_profile_read) */
+
+/* Stages timed by HNTL_FLAG_PROFILE, in order. */
+#define HNTL_STAGE_ROUTE 0      /* centroid distances (MFMA) + top-P select */
+#define HNTL_STAGE_BUCKET 1     /* grouping of (query, probe) pairs by grain */
+#define HNTL_STAGE_PROJECT 2    /* projection GEMM + eps_q */
+#define HNTL_STAGE_SCAN 3       /* Block-SoA scan + per-grain top-C */
+#define HNTL_STAGE_RERANK 4     /* pool merge + exact rerank + top-k */
+#define HNTL_NUM_STAGES 5
+
+typedef struct hntl_index hntl_index; /* opaque */
+
+/* Parameters of hntl_build. */
+typedef struct hntl_build_params {
+  uint32_t G;                 /* number of grains (k-means clusters), 1 <= G <= N */
+  uint32_t r;                 /* tangent rank, 1 <= r <= min(d, HNTL_MAX_R) */
+  uint32_t kmeans_iters;      /* maximum Lloyd iterations (0 = default 25) */
+  uint32_t train_per_grain;   /* k-means trains on at most this many rows per grain (0 = default 256) */
+  uint32_t eig_iters;         /* subspace iterations of the eigensolver (0 = default 40) */
+  uint32_t codes_mask;        /* bit (1 << hntl_codes) for every code form to build; FP32 is always built */
+  uint64_t seed;              /* seed of the build's counter-based random numbers */
+  const float* init_centroids;/* optional G x d starting centroids (host or device); NULL = k-means++ */
+} hntl_build_params;
+
+/*
+ * hntl_build - build an index from N raw vectors (Section 2.2: grains, local PCA
+ * basis per grain, codes eq. 1-4, Block-SoA layout of Section 2.4).
+ *   X       device, N x d float32, row-major.  Copied; the caller may free it after return.
+ *   out     receives the new index; free it with hntl_index_free.
+ * Synchronous.  Errors: EINVAL (null pointers, N == 0, d == 0, G > N, r > d),
+ * EUNSUPPORTED (r > HNTL_MAX_R), ENOMEM, EDEVICE.
+ */
+hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const hntl_build_params* params,
+                       void* stream, hntl_index** out);
+
+/*
+ * hntl_index_create - make an index from arrays in the stored format (import of an
+ * index built elsewhere, e.g. exported earlier).  All pointers host or device.
+ *   centroids  G x d          grain centroids mu_g
+ *   basis      G x r x d      row j of grain g = column j of W_g (orthonormal columns)
+ *   offsets    G + 1 int64    grain g owns grain-order positions [offsets[g], offsets[g+1])
+ *   perm       N int32        grain-order position -> original row id (ascending inside a grain)
+ *   codes      N x r          tangent coordinates z_i in grain order
+ *   eps        N              residual energies eps_i in grain order (>= 0)
+ *   X          N x d          raw vectors in original row order (copied for rerank)
+ *   codes_mask as in hntl_build_params (derived reduced-precision codes to build)
+ * Synchronous.  Errors: EINVAL (null pointer, inconsistent offsets/perm), EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, const float* centroids,
+                              const float* basis, const int64_t* offsets, const int32_t* perm,
+                              const float* codes, const float* eps, const float* X, uint32_t codes_mask,
+                              hntl_index** out);
+
+/*
+ * hntl_index_export - copy the stored-format arrays out of an index.  Any pointer may
+ * be NULL to skip that array; all are host or device, sized as in hntl_index_create.
+ * scales receives the G per-grain FP8 scales (ESTATE if FP8 codes were not built).
+ * Synchronous.
+ */
+hntl_status hntl_index_export(const hntl_index* index, float* centroids, float* basis, int64_t* offsets,
+                              int32_t* perm, float* codes, float* eps, float* scales);
+
+typedef struct hntl_index_info {
+  uint64_t N;
+  uint32_t d, G, r;
+  uint32_t block;             /* Block-SoA block size B */
+  uint32_t codes_mask;        /* code forms present */
+  uint64_t n_blocks;          /* total Block-SoA blocks over all grains */
+  uint64_t device_bytes;      /* device memory held by the index */
+  double captured_variance;   /* mean over non-empty grains of the captured fraction (build only, else -1) */
+  uint32_t kmeans_iters_run;  /* Lloyd iterations executed (build only) */
+  uint32_t max_grain;         /* largest grain size */
+} hntl_index_info;
+
+hntl_status hntl_index_info_get(const hntl_index* index, hntl_index_info* out);
+
+/* hntl_index_captured - per-grain captured-variance fraction (G floats, host). Build only. */
+hntl_status hntl_index_captured(const hntl_index* index, double* out);
+
+void hntl_index_free(hntl_index* index);
+
+/* Parameters of a search. */
+typedef struct hntl_search_params {
+  uint32_t P;       /* probes per query, 1 <= P <= min(G, HNTL_MAX_P) */
+  uint32_t C;       /* candidate pool per query, k <= C <= HNTL_MAX_C */
+  uint32_t k;       /* results per query, >= 1 */
+  uint32_t codes;   /* hntl_codes form to scan */
+  uint32_t flags;   /* HNTL_FLAG_* */
+} hntl_search_params;
+
+/*
+ * hntl_search - the whole query lifecycle for nq queries.
+ *   Q     device, nq x d float32
+ *   ids   device, nq x k int32  (original row ids, ascending distance, -1 padded)
+ *   dist  device, nq x k float32 (squared L2; +inf where ids is -1)
+ * nq == 0 is a no-op.  Errors: EINVAL, ESTATE (codes form not built), EUNSUPPORTED, EDEVICE.
+ */
+hntl_status hntl_search(const hntl_index* index, const float* Q, uint32_t nq, const hntl_search_params* sp,
+                        int32_t* ids, float* dist, void* stream);
+
+/*
+ * hntl_search_stages - the same lifecycle with every stage's output observable and
+ * every stage's input injectable, for stage-by-stage checking.  All pointers device;
+ * any may be NULL.
+ *   probes_in   nq x P int32   replaces step 1 (probe lists; each row distinct grain ids)
+ *   probes_out  nq x P int32,  pdist_out nq x P float32 (squared distance to the centroid)
+ *   tangent_in  nq x P x r float32 and epsq_in nq x P: replace step 2 (both or neither)
+ *   tangent_out nq x P x r,    epsq_out nq x P
+ *   pool_in     nq x C int32   replaces steps 1-3 (candidate pool ids, -1 padded)
+ *   pool_out    nq x C int32,  pool_D_out nq x C float32 (eq. 6 score, +inf padded)
+ *   ids, dist   as in hntl_search
+ * When pool_in is given, Q, ids and dist are still required and steps 1-3 are skipped.
+ */
+hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t nq,
+                               const hntl_search_params* sp, const int32_t* probes_in,
+                               int32_t* probes_out, float* pdist_out, const float* tangent_in,
+                               const float* epsq_in, float* tangent_out, float* epsq_out,
+                               const int32_t* pool_in, int32_t* pool_out, float* pool_D_out,
+                               int32_t* ids, float* dist, void* stream);
+
+/*
+ * hntl_profile_read - per-stage device time of the searches issued by the calling
+ * thread with HNTL_FLAG_PROFILE since the last read.  Waits for those events to
+ * complete, then writes the summed milliseconds per stage into ms[0..n) and the
+ * number of timed calls into *calls (either may be NULL), and clears the record.
+ * Stages skipped by stage injection count 0 ms.
+ */
+hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls);
+
+/* Last error message of the calling thread ("" if none). */
+const char* hntl_last_error(void);
+
+/* Library version string. */
+const char* hntl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNTL_H_ */

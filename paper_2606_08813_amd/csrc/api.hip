@@ -1,0 +1,450 @@
+// C ABI of the HNTL library: argument checking, index import/export and the
+// search pipeline (route -> bucket -> project -> scan -> merge/rerank).
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+hntl_status fail(hntl_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+Index::~Index() {
+  void* ptrs[] = {centroids, cnorm, basis, goff, boff, perm, codes, eps, codes_bf16, codes_fp8, scales, basis_bf16, X};
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(device);
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  (void)hipSetDevice(prev);
+}
+
+namespace {
+
+std::mutex g_pool_mu;
+bool g_pool_done[64] = {};
+
+void ensure_pool(int dev) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (dev < 0 || dev >= 64 || g_pool_done[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = std::numeric_limits<uint64_t>::max();
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  g_pool_done[dev] = true;
+}
+
+// Run f and turn exceptions into status codes.
+template <class F>
+hntl_status guarded(F&& f) {
+  try {
+    f();
+    return HNTL_OK;
+  } catch (const ArgError& e) {
+    return fail(e.code, e.msg);
+  } catch (const HipError& e) {
+    return fail(e.code == hipErrorOutOfMemory || e.code == hipErrorMemoryAllocation ? HNTL_ENOMEM : HNTL_EDEVICE,
+                e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HNTL_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HNTL_EDEVICE, e.what());
+  }
+}
+
+void require(bool ok, const std::string& msg, hntl_status code = HNTL_EINVAL) {
+  if (!ok) throw ArgError{code, msg};
+}
+
+template <class T>
+std::vector<T> to_host(const T* p, size_t n) {
+  std::vector<T> v(n);
+  if (n) HIP_TRY(hipMemcpy(v.data(), p, n * sizeof(T), hipMemcpyDefault));
+  return v;
+}
+
+template <class T>
+T* upload(Index* ix, const T* src, size_t n) {
+  T* d = dev_alloc<T>(ix, n);
+  if (n) HIP_TRY(hipMemcpy(d, src, n * sizeof(T), hipMemcpyDefault));
+  return d;
+}
+
+// Per-thread record of HIP events for HNTL_FLAG_PROFILE.
+struct ProfRec {
+  hipEvent_t ev[HNTL_NUM_STAGES + 1];
+  bool used[HNTL_NUM_STAGES];
+};
+struct Profiler {
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfRec> recs;
+  ~Profiler() {
+    for (auto& r : recs)
+      for (auto e : r.ev) pool.push_back(e);
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    return e;
+  }
+};
+thread_local Profiler g_prof;
+
+// Marks stage boundaries of one profiled call.
+struct StageClock {
+  bool on;
+  hipStream_t s;
+  ProfRec rec{};
+  int cur = -1;
+  StageClock(bool enable, hipStream_t st) : on(enable), s(st) {
+    if (!on) return;
+    for (int i = 0; i <= HNTL_NUM_STAGES; ++i) rec.ev[i] = g_prof.get();
+    for (int i = 0; i < HNTL_NUM_STAGES; ++i) rec.used[i] = false;
+  }
+  // enter stage i (stages are entered in increasing order)
+  void at(int i) {
+    if (!on) return;
+    HIP_TRY(hipEventRecord(rec.ev[i], s));
+    for (int j = cur + 1; j < i; ++j) HIP_TRY(hipEventRecord(rec.ev[j], s));
+    rec.used[i] = true;
+    cur = i;
+  }
+  void done() {
+    if (!on) return;
+    for (int j = cur + 1; j <= HNTL_NUM_STAGES; ++j) HIP_TRY(hipEventRecord(rec.ev[j], s));
+    g_prof.recs.push_back(rec);
+    on = false;
+  }
+  ~StageClock() {
+    if (on)
+      for (auto e : rec.ev) g_prof.pool.push_back(e);
+  }
+};
+
+__global__ void nonfinite_kernel(const float* __restrict__ A, int64_t n, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(A[i])) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+// Finish an index whose host-side grain offsets, codes and eps (grain order) are
+// known: block offsets, Block-SoA packing, centroid norms.
+void finish_index(Index* ix, const std::vector<int64_t>& off, const float* codes_go_host, const float* eps_go_host) {
+  const uint32_t G = ix->G, r = ix->r, rp = ix->rp;
+  ix->offsets_h = off;
+  ix->boff_h.assign(G + 1, 0);
+  uint32_t maxg = 0;
+  for (uint32_t g = 0; g < G; ++g) {
+    const int64_t n = off[g + 1] - off[g];
+    maxg = std::max<uint32_t>(maxg, (uint32_t)n);
+    ix->boff_h[g + 1] = ix->boff_h[g] + (int32_t)((n + B - 1) / B);
+  }
+  ix->max_grain = maxg;
+  ix->nblocks = (uint64_t)ix->boff_h[G];
+  std::vector<float> blk((size_t)ix->nblocks * rp * B, 0.f);
+  std::vector<float> eb((size_t)ix->nblocks * B, std::numeric_limits<float>::infinity());
+  for (uint32_t g = 0; g < G; ++g) {
+    const int64_t a = off[g], n = off[g + 1] - off[g];
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t blkid = ix->boff_h[g] + i / B, lane = i % B;
+      const float* z = codes_go_host + (size_t)(a + i) * r;
+      float* dst = blk.data() + (size_t)blkid * rp * B + lane;
+      for (uint32_t j = 0; j < r; ++j) dst[(size_t)j * B] = z[j];
+      eb[(size_t)blkid * B + lane] = eps_go_host[a + i];
+    }
+  }
+  std::vector<int32_t> goff32(G + 1);
+  for (uint32_t g = 0; g <= G; ++g) goff32[g] = (int32_t)off[g];
+  ix->goff = upload(ix, goff32.data(), G + 1);
+  ix->boff = upload(ix, ix->boff_h.data(), G + 1);
+  ix->codes = upload(ix, blk.data(), blk.size());
+  ix->eps = upload(ix, eb.data(), eb.size());
+  ix->cnorm = dev_alloc<float>(ix, G);
+  launch_row_norms(ix->centroids, G, (int)ix->d, ix->cnorm, nullptr);
+  HIP_TRY(hipDeviceSynchronize());
+}
+
+}  // namespace hntl
+
+using namespace hntl;
+
+extern "C" {
+
+const char* hntl_last_error(void) { return g_last_error.c_str(); }
+
+const char* hntl_version(void) { return "hntl-mi355x 0.1 (gfx950)"; }
+
+void hntl_index_free(hntl_index* index) { delete index; }
+
+hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, const float* centroids,
+                              const float* basis, const int64_t* offsets, const int32_t* perm, const float* codes,
+                              const float* eps, const float* X, uint32_t codes_mask, hntl_index** out) {
+  g_last_error.clear();
+  if (!out) return fail(HNTL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!centroids || !basis || !offsets || !perm || !codes || !eps || !X)
+    return fail(HNTL_EINVAL, "null array pointer");
+  if (N == 0 || d == 0 || G == 0 || r == 0) return fail(HNTL_EINVAL, "N, d, G and r must be positive");
+  if (G > N) return fail(HNTL_EINVAL, "G > N");
+  if (r > d) return fail(HNTL_EINVAL, "r > d");
+  if (r > HNTL_MAX_R) return fail(HNTL_EUNSUPPORTED, "r exceeds HNTL_MAX_R");
+  if (N >= (1ull << 31)) return fail(HNTL_EUNSUPPORTED, "N must be below 2^31");
+  hntl_index* h = nullptr;
+  hntl_status st = guarded([&] {
+    int dev = 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw ArgError{HNTL_EDEVICE, "no GPU device"};
+    HIP_TRY(hipGetDevice(&dev));
+    auto off = to_host(offsets, (size_t)G + 1);
+    require(off[0] == 0 && off[G] == (int64_t)N, "offsets must start at 0 and end at N");
+    for (uint32_t g = 0; g < G; ++g) require(off[g + 1] >= off[g], "offsets must be non-decreasing");
+    auto pm = to_host(perm, (size_t)N);
+    std::vector<uint8_t> seen(N, 0);
+    for (uint64_t i = 0; i < N; ++i) {
+      require(pm[i] >= 0 && (uint64_t)pm[i] < N && !seen[pm[i]], "perm must be a permutation of 0..N-1");
+      seen[pm[i]] = 1;
+    }
+    for (uint32_t g = 0; g < G; ++g)
+      for (int64_t i = off[g] + 1; i < off[g + 1]; ++i)
+        require(pm[i] > pm[i - 1], "ids inside a grain must ascend");
+    auto cz = to_host(codes, (size_t)N * r);
+    auto ce = to_host(eps, (size_t)N);
+    for (uint64_t i = 0; i < N; ++i) require(ce[i] >= 0.f && std::isfinite(ce[i]), "eps must be finite and >= 0");
+    h = new hntl_index();
+    Index* ix = &h->ix;
+    ix->device = dev;
+    ix->N = N;
+    ix->d = d;
+    ix->G = G;
+    ix->r = r;
+    ix->rp = (r + 7) / 8 * 8;
+    ix->centroids = upload(ix, centroids, (size_t)G * d);
+    ix->basis = upload(ix, basis, (size_t)G * r * d);
+    ix->perm = upload(ix, pm.data(), N);
+    ix->X = upload(ix, X, (size_t)N * d);
+    finish_index(ix, off, cz.data(), ce.data());
+    ix->captured.assign(G, -1.0);
+    ix->codes_mask = 1u;
+    if (codes_mask & ~1u) {
+      ix->codes_mask |= codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3));
+      launch_derive_lowp(*ix, nullptr);
+      HIP_TRY(hipDeviceSynchronize());
+    }
+  });
+  if (st != HNTL_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return HNTL_OK;
+}
+
+hntl_status hntl_index_export(const hntl_index* index, float* centroids, float* basis, int64_t* offsets,
+                              int32_t* perm, float* codes, float* eps, float* scales) {
+  g_last_error.clear();
+  if (!index) return fail(HNTL_EINVAL, "index is NULL");
+  const Index& ix = index->ix;
+  if (scales && !ix.scales) return fail(HNTL_ESTATE, "FP8 codes were not built");
+  return guarded([&] {
+    const uint32_t G = ix.G, r = ix.r, rp = ix.rp, d = ix.d;
+    if (centroids) HIP_TRY(hipMemcpy(centroids, ix.centroids, sizeof(float) * G * d, hipMemcpyDefault));
+    if (basis) HIP_TRY(hipMemcpy(basis, ix.basis, sizeof(float) * (size_t)G * r * d, hipMemcpyDefault));
+    if (offsets) HIP_TRY(hipMemcpy(offsets, ix.offsets_h.data(), sizeof(int64_t) * (G + 1), hipMemcpyDefault));
+    if (perm) HIP_TRY(hipMemcpy(perm, ix.perm, sizeof(int32_t) * ix.N, hipMemcpyDefault));
+    if (scales) HIP_TRY(hipMemcpy(scales, ix.scales, sizeof(float) * G, hipMemcpyDefault));
+    if (codes || eps) {
+      auto blk = to_host(ix.codes, (size_t)ix.nblocks * rp * B);
+      auto eb = to_host(ix.eps, (size_t)ix.nblocks * B);
+      std::vector<float> cz(codes ? (size_t)ix.N * r : 0), ce(eps ? ix.N : 0);
+      for (uint32_t g = 0; g < G; ++g) {
+        const int64_t a = ix.offsets_h[g], n = ix.offsets_h[g + 1] - a;
+        for (int64_t i = 0; i < n; ++i) {
+          const int64_t blkid = ix.boff_h[g] + i / B, lane = i % B;
+          if (codes)
+            for (uint32_t j = 0; j < r; ++j) cz[(size_t)(a + i) * r + j] = blk[((size_t)blkid * rp + j) * B + lane];
+          if (eps) ce[a + i] = eb[(size_t)blkid * B + lane];
+        }
+      }
+      if (codes) HIP_TRY(hipMemcpy(codes, cz.data(), sizeof(float) * cz.size(), hipMemcpyDefault));
+      if (eps) HIP_TRY(hipMemcpy(eps, ce.data(), sizeof(float) * ce.size(), hipMemcpyDefault));
+    }
+  });
+}
+
+hntl_status hntl_index_info_get(const hntl_index* index, hntl_index_info* out) {
+  g_last_error.clear();
+  if (!index || !out) return fail(HNTL_EINVAL, "null pointer");
+  const Index& ix = index->ix;
+  std::memset(out, 0, sizeof(*out));
+  out->N = ix.N;
+  out->d = ix.d;
+  out->G = ix.G;
+  out->r = ix.r;
+  out->block = B;
+  out->codes_mask = ix.codes_mask;
+  out->n_blocks = ix.nblocks;
+  out->device_bytes = ix.device_bytes;
+  double s = 0;
+  int n = 0;
+  for (uint32_t g = 0; g < ix.G; ++g)
+    if (ix.captured.size() == ix.G && ix.captured[g] >= 0 && ix.offsets_h[g + 1] > ix.offsets_h[g]) {
+      s += ix.captured[g];
+      ++n;
+    }
+  out->captured_variance = n ? s / n : -1.0;
+  out->kmeans_iters_run = ix.kmeans_iters_run;
+  out->max_grain = ix.max_grain;
+  return HNTL_OK;
+}
+
+hntl_status hntl_index_captured(const hntl_index* index, double* out) {
+  g_last_error.clear();
+  if (!index || !out) return fail(HNTL_EINVAL, "null pointer");
+  const Index& ix = index->ix;
+  if (ix.captured.size() != ix.G) return fail(HNTL_ESTATE, "no captured-variance record");
+  std::memcpy(out, ix.captured.data(), sizeof(double) * ix.G);
+  return HNTL_OK;
+}
+
+hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t nq, const hntl_search_params* sp,
+                               const int32_t* probes_in, int32_t* probes_out, float* pdist_out,
+                               const float* tangent_in, const float* epsq_in, float* tangent_out, float* epsq_out,
+                               const int32_t* pool_in, int32_t* pool_out, float* pool_D_out, int32_t* ids,
+                               float* dist, void* stream) {
+  g_last_error.clear();
+  if (!index || !sp) return fail(HNTL_EINVAL, "null index or params");
+  const Index& ix = index->ix;
+  const uint32_t P = sp->P, C = sp->C, k = sp->k;
+  if (P < 1 || P > ix.G) return fail(HNTL_EINVAL, "need 1 <= P <= G");
+  if (P > HNTL_MAX_P) return fail(HNTL_EUNSUPPORTED, "P exceeds HNTL_MAX_P");
+  if (k < 1 || C < k) return fail(HNTL_EINVAL, "need 1 <= k <= C");
+  if (C > HNTL_MAX_C) return fail(HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C");
+  if (sp->codes > HNTL_CODES_FP8_E4M3) return fail(HNTL_EINVAL, "unknown codes form");
+  if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
+  if ((tangent_in == nullptr) != (epsq_in == nullptr)) return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
+  if (nq == 0) return HNTL_OK;
+  if (!Q || !ids || !dist) return fail(HNTL_EINVAL, "Q, ids and dist are required");
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    ensure_pool(ix.device);
+    Scratch sc(s);
+    if (sp->flags & HNTL_FLAG_CHECK_Q) {
+      int* flag = sc.get<int>(1);
+      HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+      const int64_t n = (int64_t)nq * ix.d;
+      hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, n, flag);
+      HIP_TRY(hipGetLastError());
+      int hflag = 0;
+      HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      require(hflag == 0, "queries contain NaN or Inf");
+    }
+    const int64_t npairs = (int64_t)nq * P;
+    StageClock clk((sp->flags & HNTL_FLAG_PROFILE) != 0, s);
+    const uint64_t* part = nullptr;
+    const int32_t* probes = probes_in;
+    if (!pool_in) {
+      // 1. routing
+      if (!probes) {
+        clk.at(HNTL_STAGE_ROUTE);
+        int32_t* pr = probes_out ? probes_out : sc.get<int32_t>(npairs);
+        float* qn = sc.get<float>(nq);
+        launch_row_norms(Q, nq, (int)ix.d, qn, s);
+        const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
+        float* Dm = sc.get<float>((size_t)std::min<int64_t>(chunk, nq) * ix.G);
+        for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+          const int64_t rows = std::min<int64_t>(chunk, nq - q0);
+          launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
+          launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,
+                           Q + q0 * ix.d, ix.centroids, (int)ix.d);
+        }
+        probes = pr;
+      }
+      // 2. bucketing by grain
+      clk.at(HNTL_STAGE_BUCKET);
+      Buckets b;
+      b.tile = 16;
+      b.max_items = (int)(npairs / b.tile + std::min<int64_t>(ix.G, npairs) + 1);
+      b.gcount = sc.get<int32_t>(ix.G);
+      b.gstart = sc.get<int32_t>(ix.G);
+      b.cursor = sc.get<int32_t>(ix.G);
+      b.order = sc.get<int32_t>(npairs);
+      b.items = sc.get<int32_t>(2 * (size_t)b.max_items);
+      b.nitems = sc.get<int32_t>(1);
+      launch_bucket(probes, npairs, (int)ix.G, b, s);
+      // 3. projection
+      const float* T = tangent_in;
+      const float* eq = epsq_in;
+      if (!T) {
+        clk.at(HNTL_STAGE_PROJECT);
+        float* To = tangent_out ? tangent_out : sc.get<float>((size_t)npairs * ix.r);
+        float* eo = epsq_out ? epsq_out : sc.get<float>(npairs);
+        launch_project(ix, Q, (int)P, b, To, eo, s);
+        T = To;
+        eq = eo;
+      }
+      // 4. scan + per-pair top-C
+      uint64_t* pt = sc.get<uint64_t>((size_t)npairs * C);
+      clk.at(HNTL_STAGE_SCAN);
+      launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, pt, s);
+      part = pt;
+    }
+    // 5. pool merge + exact rerank
+    clk.at(HNTL_STAGE_RERANK);
+    launch_merge_rerank(ix, Q, nq, (int)P, (int)C, (int)k, probes, part, pool_in, pool_out, pool_D_out, ids, dist, s);
+    clk.done();
+    if (sp->flags & HNTL_FLAG_SYNC) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipGetLastError());
+    }
+  });
+}
+
+hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls) {
+  g_last_error.clear();
+  return guarded([&] {
+    std::vector<double> acc(HNTL_NUM_STAGES, 0.0);
+    for (auto& r : g_prof.recs) {
+      HIP_TRY(hipEventSynchronize(r.ev[HNTL_NUM_STAGES]));
+      for (int i = 0; i < HNTL_NUM_STAGES; ++i) {
+        if (!r.used[i]) continue;
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, r.ev[i], r.ev[i + 1]));
+        acc[i] += t;
+      }
+    }
+    if (calls) *calls = (uint32_t)g_prof.recs.size();
+    for (auto& r : g_prof.recs)
+      for (auto e : r.ev) g_prof.pool.push_back(e);
+    g_prof.recs.clear();
+    if (ms)
+      for (uint32_t i = 0; i < n; ++i) ms[i] = i < (uint32_t)HNTL_NUM_STAGES ? acc[i] : 0.0;
+  });
+}
+
+hntl_status hntl_search(const hntl_index* index, const float* Q, uint32_t nq, const hntl_search_params* sp,
+                        int32_t* ids, float* dist, void* stream) {
+  return hntl_search_stages(index, Q, nq, sp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, ids, dist, stream);
+}
+
+}  // extern "C"

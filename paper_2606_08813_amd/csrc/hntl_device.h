@@ -1,0 +1,161 @@
+// Device helpers shared by the HNTL kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HNTL_WAVE 64
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace hntl {
+
+// ---------------------------------------------------------------- sort keys
+// A candidate is one 64-bit key: the float's order-preserving bit image in the
+// high half, the id in the low half.  Unsigned comparison of keys is then the
+// lexicographic (distance, id) order, which is the tie rule everywhere.
+__device__ __forceinline__ uint32_t f2ord(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
+  return ((uint64_t)f2ord(d) << 32) | (uint64_t)id;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) { return ord2f((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)k; }
+constexpr uint64_t KEY_NONE = ~0ull;
+
+// ---------------------------------------------------------------- wave utils
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders LDS accesses of the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int mbcnt64(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------- wave top-C selection
+// One wave keeps the C smallest keys of a stream in LDS.  Layout: best[CAP]
+// (sorted ascending) followed by stage[CAP] (unsorted arrivals).  A key is
+// staged only if it beats the current threshold (the C-th best key); when the
+// stage would overflow it is bitonic-sorted and merged into best.  CAP is a
+// power of two >= max(C, 64).  This is the threshold + buffer + merging
+// network scheme of GPU k-selection (Johnson, Douze, Jegou, "Billion-scale
+// similarity search with GPUs"), laid out for 64-wide waves and LDS.
+template <int CAP>
+struct WaveTopC {
+  uint64_t* best;
+  uint64_t* stage;
+  uint64_t thr;
+  int nstage;
+  int C;
+
+  __device__ __forceinline__ void init(uint64_t* lds, int C_) {
+    best = lds;
+    stage = lds + CAP;
+    C = C_;
+    nstage = 0;
+    thr = KEY_NONE;
+    for (int i = lane_id(); i < CAP; i += HNTL_WAVE) best[i] = KEY_NONE;
+    wave_sync();
+  }
+
+  __device__ __forceinline__ static void cas(uint64_t* s, int i, int p, bool up) {
+    uint64_t a = s[i], b = s[p];
+    if ((a > b) == up) {
+      s[i] = b;
+      s[p] = a;
+    }
+  }
+
+  __device__ void sort_stage() {
+    const int lane = lane_id();
+#pragma unroll 1
+    for (int k = 2; k <= CAP; k <<= 1) {
+#pragma unroll 1
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = lane; t < CAP / 2; t += HNTL_WAVE) {
+          int i = 2 * t - (t & (j - 1));
+          cas(stage, i, i + j, (i & k) == 0);
+        }
+        wave_sync();
+      }
+    }
+  }
+
+  __device__ void flush() {
+    if (nstage == 0) return;
+    const int lane = lane_id();
+    for (int i = nstage + lane; i < CAP; i += HNTL_WAVE) stage[i] = KEY_NONE;
+    wave_sync();
+    sort_stage();
+    // half-cleaner: min of ascending best and descending stage is bitonic and
+    // holds the CAP smallest of the union
+    for (int i = lane; i < CAP; i += HNTL_WAVE) {
+      uint64_t a = best[i], b = stage[CAP - 1 - i];
+      best[i] = a < b ? a : b;
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int j = CAP >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < CAP / 2; t += HNTL_WAVE) {
+        int i = 2 * t - (t & (j - 1));
+        cas(best, i, i + j, true);
+      }
+      wave_sync();
+    }
+    thr = best[C - 1];
+    nstage = 0;
+  }
+
+  // Every lane offers one key (valid == false: no candidate from this lane).
+  __device__ __forceinline__ void offer(uint64_t key, bool valid) {
+    bool pass = valid && key < thr;
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    if (nstage + cnt > CAP) {
+      flush();
+      pass = valid && key < thr;
+      m = __ballot(pass);
+      if (m == 0) return;
+      cnt = __popcll(m);
+    }
+    if (pass) stage[nstage + mbcnt64(m)] = key;
+    nstage += cnt;
+  }
+
+  __device__ __forceinline__ void finish() {
+    flush();
+    wave_sync();
+  }
+};
+
+// ------------------------------------------------------------------- MFMA
+// v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16] and B[l/16][l%16] of a
+// 16x4 by 4x16 product and holds D[4*(l/16)+i][l%16] for i = 0..3.
+__device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+}  // namespace hntl

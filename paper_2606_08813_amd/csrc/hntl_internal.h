@@ -1,0 +1,151 @@
+// Host-side internals of the HNTL library: the index object, error plumbing and
+// the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hntl.h"
+
+namespace hntl {
+
+// Block-SoA layout (Section 2.4 of the paper, re-laid for wave64): the members
+// of each grain occupy ceil(n_g / B) consecutive blocks of B = 64 vectors.  A
+// block stores its tangent coordinates dimension-major, code[j][b] for
+// j < rp and lane b < 64, followed nowhere by ids: a member's position
+// (block-local lane + the grain's first position) maps to its original id
+// through perm, read only for the candidates that survive the scan.  The rank
+// is padded to rp = 8 * ceil(r / 8) with zero coordinates, and padding lanes
+// of a grain's last block hold eps = +inf.
+constexpr int B = HNTL_BLOCK;
+
+struct Index {
+  int device = 0;
+  uint64_t N = 0;
+  uint32_t d = 0, G = 0, r = 0, rp = 0;
+  uint64_t nblocks = 0;
+  uint32_t codes_mask = 1u;
+  uint32_t max_grain = 0;
+  uint32_t kmeans_iters_run = 0;
+
+  float* centroids = nullptr;  // G x d
+  float* cnorm = nullptr;      // G, ||mu_g||^2
+  float* basis = nullptr;      // G x r x d
+  int32_t* goff = nullptr;     // G + 1 grain-order offsets
+  int32_t* boff = nullptr;     // G + 1 block offsets
+  int32_t* perm = nullptr;     // N
+  float* codes = nullptr;      // nblocks x rp x B
+  float* eps = nullptr;        // nblocks x B
+  uint16_t* codes_bf16 = nullptr;  // nblocks x rp x B (bf16 bits)
+  uint8_t* codes_fp8 = nullptr;    // nblocks x rp x B (e4m3fn bits)
+  float* scales = nullptr;         // G fp8 scales
+  uint16_t* basis_bf16 = nullptr;  // G x r x d (bf16 bits)
+  float* X = nullptr;          // N x d, original row order
+
+  std::vector<int64_t> offsets_h;
+  std::vector<int32_t> boff_h;
+  std::vector<double> captured;  // per grain (build only)
+  uint64_t device_bytes = 0;
+
+  ~Index();
+};
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+hntl_status fail(hntl_status s, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t _e = (expr);                                                                    \
+    if (_e != hipSuccess)                                                                      \
+      throw ::hntl::HipError(_e, std::string(#expr) + ": " + hipGetErrorString(_e));           \
+  } while (0)
+
+struct HipError {
+  hipError_t code;
+  std::string msg;
+  HipError(hipError_t c, std::string m) : code(c), msg(std::move(m)) {}
+};
+struct ArgError {
+  hntl_status code;
+  std::string msg;
+};
+
+template <class T>
+T* dev_alloc(Index* ix, size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipError(e, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  if (ix) ix->device_bytes += n * sizeof(T);
+  return (T*)p;
+}
+
+// Stream-ordered scratch of one call: allocations are released on the stream
+// when the object goes out of scope.
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  template <class T>
+  T* get(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMallocAsync(&p, n * sizeof(T), s);
+    if (e != hipSuccess) throw HipError(e, "hipMallocAsync of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+};
+
+// ----------------------------------------------------------- launchers
+// routing / k-means distances: D[i][j] = ||a_i||^2 + ||b_j||^2 - 2 a_i . b_j
+void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream_t s);
+void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
+                        int cols, int d, float* D, hipStream_t s);
+void launch_argmin_rows(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
+                        int cols, int d, int32_t* label, float* dmin, hipStream_t s);
+// top-P per row of D; with A and Bm given, the winners are re-scored by exact
+// direct differences (routing)
+void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
+                      const float* A = nullptr, const float* Bm = nullptr, int d = 0);
+
+// grain bucketing of (query, probe) pairs
+struct Buckets {
+  int32_t* gcount;   // G
+  int32_t* gstart;   // G
+  int32_t* cursor;   // G
+  int32_t* order;    // npairs: pair ids grouped by grain
+  int32_t* items;    // 2 * max_items: (grain, start) tiles
+  int32_t* nitems;   // 1
+  int max_items;
+  int tile;
+};
+void launch_bucket(const int32_t* probes, int64_t npairs, int G, Buckets& b, hipStream_t s);
+
+void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                    hipStream_t s);
+void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, int P, int C,
+                 const Buckets& b, uint64_t* part, hipStream_t s);
+void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k,
+                         const int32_t* probes, const uint64_t* part, const int32_t* pool_in, int32_t* pool_out,
+                         float* pool_D_out, int32_t* ids, float* dist, hipStream_t s);
+
+// build helpers
+void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);
+void launch_derive_lowp(Index& ix, hipStream_t s);
+
+int pow2_at_least(int x);
+
+}  // namespace hntl
+
+// The opaque handle of the C ABI.
+struct hntl_index {
+  hntl::Index ix;
+};

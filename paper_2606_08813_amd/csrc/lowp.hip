@@ -1,0 +1,118 @@
+// Reduced-precision tangent codes (the precision form): BF16 codes, and FP8
+// E4M3 codes with one FP32 scale per grain, derived from the FP32 Block-SoA
+// codes; plus a BF16 copy of the bases for the BF16 projection.
+//
+// BF16: round-to-nearest-even of the FP32 bit pattern (drop 16 mantissa bits).
+// FP8 E4M3 "fn" (OCP 8-bit float specification): bias 7, 3 mantissa bits,
+// largest finite 448, no infinities.  Code = e4m3(z / s_g) rounded to nearest
+// even with saturation to +-448, s_g = amax_{i in g, j < r} |z_ij| / 448
+// (1 for an all-zero grain).  The paper's own reduced form is int16 with a
+// per-grain step (eq. 5); these are its MI355X counterparts.
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline uint8_t f32_to_e4m3_rne_sat(float x) {
+  const uint8_t sign = x < 0.f ? 0x80 : 0x00;
+  float a = fabsf(x);
+  if (!(a < 448.f)) return sign | 0x7E;  // saturate (also NaN -> max, inputs are finite)
+  if (a < 0.015625f) {                   // below 2^-6: subnormal, quantum 2^-9
+    const int m = (int)rintf(a * 512.f); // 0..8; 8 encodes 2^-6 (the first normal)
+    return sign | (uint8_t)m;
+  }
+  int e;
+  const float mant = frexpf(a, &e);  // a = mant * 2^e, mant in [0.5, 1)
+  const int E = e - 1;               // a = (2 mant) * 2^E, 2 mant in [1, 2)
+  int m = (int)rintf((2.f * mant - 1.f) * 8.f);
+  int Eb = E + 7;
+  if (m == 8) {
+    m = 0;
+    ++Eb;
+  }
+  int code = (Eb << 3) | m;
+  if (code > 0x7E) code = 0x7E;
+  return sign | (uint8_t)code;
+}
+
+namespace {
+
+__global__ void bf16_kernel(const float* __restrict__ in, int64_t n, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f32_to_bf16_rne(in[i]);
+}
+
+// one workgroup per grain: amax over valid members and j < r
+__global__ __launch_bounds__(256) void grain_scale_kernel(const float* __restrict__ codes, int rp, int r,
+                                                          const int32_t* __restrict__ goff,
+                                                          const int32_t* __restrict__ boff,
+                                                          float* __restrict__ scales) {
+  __shared__ float red[256];
+  const int g = blockIdx.x;
+  const int b0 = boff[g], nb = boff[g + 1] - b0, ng = goff[g + 1] - goff[g];
+  float m = 0.f;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * rp * B; e += 256) {
+    const int blk = (int)(e / (rp * B)), rem = (int)(e % (rp * B)), j = rem / B, lane = rem % B;
+    if (j < r && blk * B + lane < ng) m = fmaxf(m, fabsf(codes[(size_t)(b0 + blk) * rp * B + rem]));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scales[g] = red[0] > 0.f ? red[0] / 448.f : 1.f;
+}
+
+__global__ void fp8_kernel(const float* __restrict__ codes, int rp, const int32_t* __restrict__ block_grain,
+                           const float* __restrict__ scales, int64_t nblocks, uint8_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblocks * rp * B) return;
+  const int64_t blk = i / (rp * B);
+  const float s = scales[block_grain[blk]];
+  out[i] = f32_to_e4m3_rne_sat(codes[i] / s);
+}
+
+}  // namespace
+
+void launch_derive_lowp(Index& ix, hipStream_t s) {
+  const int64_t n = (int64_t)ix.nblocks * ix.rp * B;
+  if (ix.codes_mask & (1u << HNTL_CODES_BF16)) {
+    if (!ix.codes_bf16) ix.codes_bf16 = dev_alloc<uint16_t>(&ix, n);
+    hipLaunchKernelGGL(bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ix.codes, n, ix.codes_bf16);
+    HIP_TRY(hipGetLastError());
+  }
+  if (ix.codes_mask & (1u << HNTL_CODES_FP8_E4M3)) {
+    if (!ix.scales) ix.scales = dev_alloc<float>(&ix, ix.G);
+    if (!ix.codes_fp8) ix.codes_fp8 = dev_alloc<uint8_t>(&ix, n);
+    hipLaunchKernelGGL(grain_scale_kernel, dim3(ix.G), dim3(256), 0, s, ix.codes, (int)ix.rp, (int)ix.r, ix.goff,
+                       ix.boff, ix.scales);
+    std::vector<int32_t> bg(ix.nblocks);
+    for (uint32_t g = 0; g < ix.G; ++g)
+      for (int q = ix.boff_h[g]; q < ix.boff_h[g + 1]; ++q) bg[q] = (int32_t)g;
+    int32_t* d_bg = nullptr;
+    HIP_TRY(hipMalloc((void**)&d_bg, sizeof(int32_t) * std::max<size_t>(1, bg.size())));
+    HIP_TRY(hipMemcpy(d_bg, bg.data(), sizeof(int32_t) * bg.size(), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(fp8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp, d_bg,
+                       ix.scales, (int64_t)ix.nblocks, ix.codes_fp8);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(d_bg));
+  }
+  if (!ix.basis_bf16) {
+    const int64_t nb = (int64_t)ix.G * ix.r * ix.d;
+    ix.basis_bf16 = dev_alloc<uint16_t>(&ix, nb);
+    hipLaunchKernelGGL(bf16_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, ix.basis, nb, ix.basis_bf16);
+    HIP_TRY(hipGetLastError());
+  }
+}
+
+}  // namespace hntl

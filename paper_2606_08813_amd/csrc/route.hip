@@ -1,0 +1,318 @@
+// Centroid routing (paper Section 2.1 step 1 and Section 2.3): squared
+// Euclidean distance from every query to every grain centroid, then the P
+// nearest grains per query.  The same distance tile also serves the k-means
+// assignment of the build (nearest centroid per row).
+//
+// Distances use the expansion ||a||^2 + ||b||^2 - 2 a.b with the a.b term on
+// FP32 MFMA (v_mfma_f32_16x16x4_f32).  Its rounding error (about 1e-4
+// relative when ||q|| and ||mu|| are large against ||q - mu||) is harmless for
+// the k-means assignment; routing re-scores a short list of the nearest
+// centroids by direct differences before it picks the P probes.
+#include <algorithm>
+
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 32, LDT = TK + 1;
+
+__global__ __launch_bounds__(256) void row_norms_kernel(const float* __restrict__ A, int64_t rows, int d,
+                                                        float* __restrict__ out) {
+  const int lane = lane_id();
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* a = A + row * d;
+  float acc = 0.f;
+  for (int j = lane; j < d; j += HNTL_WAVE) acc = fmaf(a[j], a[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) out[row] = acc;
+}
+
+// Loads a TM x TK tile of row-major M (rows x d) starting at (r0, k0) into LDS.
+__device__ __forceinline__ void load_tile(float (*S)[LDT], const float* __restrict__ M, int64_t nrows, int d,
+                                          int64_t r0, int k0, bool vec4) {
+  const int tid = threadIdx.x;
+  const int rr = tid >> 2, cc = (tid & 3) * 8;
+  const int64_t gr = r0 + rr;
+  if (vec4) {
+#pragma unroll
+    for (int u = 0; u < 8; u += 4) {
+      const int gk = k0 + cc + u;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < nrows && gk < d) v = *reinterpret_cast<const float4*>(M + gr * d + gk);
+      S[rr][cc + u] = v.x;
+      S[rr][cc + u + 1] = v.y;
+      S[rr][cc + u + 2] = v.z;
+      S[rr][cc + u + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int gk = k0 + cc + u;
+      S[rr][cc + u] = (gr < nrows && gk < d) ? M[gr * d + gk] : 0.f;
+    }
+  }
+}
+
+// One 64 x 64 tile of A.B^T accumulated over the full depth d; each of the 4
+// waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 tiles.
+__device__ __forceinline__ void tile_dot(floatx4 (&acc)[2][2], float (*As)[LDT], float (*Bs)[LDT],
+                                         const float* __restrict__ A, int64_t rows, const float* __restrict__ Bm,
+                                         int cols, int d, int64_t row0, int col0, bool vec4) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < d; k0 += TK) {
+    load_tile(As, A, rows, d, row0, k0, vec4);
+    load_tile(Bs, Bm, cols, d, col0, k0, vec4);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const float a0 = As[wr + (lane & 15)][kr];
+      const float a1 = As[wr + 16 + (lane & 15)][kr];
+      const float b0 = Bs[wc + (lane & 15)][kr];
+      const float b1 = Bs[wc + 16 + (lane & 15)][kr];
+      acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void dist_matrix_kernel(const float* __restrict__ A, const float* __restrict__ an,
+                                                          int64_t rows, const float* __restrict__ Bm,
+                                                          const float* __restrict__ bn, int cols, int d,
+                                                          float* __restrict__ D, bool vec4) {
+  __shared__ float As[TM][LDT];
+  __shared__ float Bs[TN][LDT];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * TM;
+  const int col0 = blockIdx.y * TN;
+  floatx4 acc[2][2];
+  tile_dot(acc, As, Bs, A, rows, Bm, cols, d, row0, col0, vec4);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + wr + rt * 16 + 4 * (lane >> 4) + i;
+        const int col = col0 + wc + ct * 16 + (lane & 15);
+        if (row < rows && col < cols) {
+          const float v = an[row] + bn[col] - 2.f * acc[rt][ct][i];
+          D[row * cols + col] = fmaxf(v, 0.f);
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void argmin_rows_kernel(const float* __restrict__ A, const float* __restrict__ an,
+                                                          int64_t rows, const float* __restrict__ Bm,
+                                                          const float* __restrict__ bn, int cols, int d,
+                                                          int32_t* __restrict__ label, float* __restrict__ dmin,
+                                                          bool vec4) {
+  __shared__ float As[TM][LDT];
+  __shared__ float Bs[TN][LDT];
+  __shared__ float red_d[4][32];
+  __shared__ int red_i[4][32];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * TM;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  float bd[2][4];
+  int bi[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bd[rt][i] = __builtin_inff();
+      bi[rt][i] = 0x7fffffff;
+    }
+  for (int col0 = 0; col0 < cols; col0 += TN) {
+    floatx4 acc[2][2];
+    tile_dot(acc, As, Bs, A, rows, Bm, cols, d, row0, col0, vec4);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t row = row0 + wr + rt * 16 + 4 * (lane >> 4) + i;
+          const int col = col0 + wc + ct * 16 + (lane & 15);
+          if (row < rows && col < cols) {
+            const float v = fmaxf(an[row] + bn[col] - 2.f * acc[rt][ct][i], 0.f);
+            if (v < bd[rt][i] || (v == bd[rt][i] && col < bi[rt][i])) {
+              bd[rt][i] = v;
+              bi[rt][i] = col;
+            }
+          }
+        }
+  }
+  // reduce over the 16 lanes that share a row, then over the two waves that
+  // share the same rows
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = bd[rt][i];
+      int c = bi[rt][i];
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const float ov = __shfl_xor(v, o, 64);
+        const int oc = __shfl_xor(c, o, 64);
+        if (ov < v || (ov == v && oc < c)) {
+          v = ov;
+          c = oc;
+        }
+      }
+      if ((lane & 15) == 0) {
+        red_d[wave][rt * 16 + 4 * (lane >> 4) + i] = v;
+        red_i[wave][rt * 16 + 4 * (lane >> 4) + i] = c;
+      }
+    }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    const int w0 = 2 * (r >> 5);
+    float v = red_d[w0][r & 31];
+    int c = red_i[w0][r & 31];
+    const float v1 = red_d[w0 + 1][r & 31];
+    const int c1 = red_i[w0 + 1][r & 31];
+    if (v1 < v || (v1 == v && c1 < c)) {
+      v = v1;
+      c = c1;
+    }
+    const int64_t row = row0 + r;
+    if (row < rows) {
+      label[row] = c;
+      if (dmin) dmin[row] = v;
+    }
+  }
+}
+
+// Top-P per row.  Without A/Bm: the P smallest entries of D.  With them
+// (routing): a shortlist of the M = min(cols, P + 16) smallest expansion
+// distances is re-scored by direct differences ||a - b||^2 in FP32 and the P
+// smallest exact distances are kept, so the probe order and the reported
+// distances carry direct-difference accuracy; the FP32 expansion error (about
+// 1e-4 relative at these magnitudes) is far below the gap that 16 extra ranks
+// open between the P-th and M-th centroid.
+template <int CAP>
+__global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
+                                                        int M, const float* __restrict__ A,
+                                                        const float* __restrict__ Bm, int d,
+                                                        int32_t* __restrict__ idx, float* __restrict__ val) {
+  __shared__ uint64_t lists[4][2 * CAP];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= rows) return;
+  WaveTopC<CAP> L;
+  const bool exact = A != nullptr;
+  L.init(lists[wave], exact ? M : P);
+  const float* drow = D + row * cols;
+  for (int c0 = 0; c0 < cols; c0 += HNTL_WAVE) {
+    const int c = c0 + lane;
+    const bool ok = c < cols;
+    const float v = ok ? drow[c] : 0.f;
+    L.offer(make_key(v, (uint32_t)c), ok);
+  }
+  L.finish();
+  if (exact) {
+    // re-score the shortlist exactly, then sort it by (exact distance, column)
+    const float* a = A + row * d;
+    constexpr int RB = 8;  // shortlist entries re-scored together
+    for (int j0 = 0; j0 < M; j0 += RB) {
+      int cs[RB];
+      const float* bp[RB];
+      float acc[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        cs[u] = j0 + u < M ? (int)key_id(L.best[j0 + u]) : (int)key_id(L.best[j0]);
+        bp[u] = Bm + (size_t)cs[u] * d;
+        acc[u] = 0.f;
+      }
+      for (int t = lane; t < d; t += HNTL_WAVE) {
+        const float av = a[t];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const float df = av - bp[u][t];
+          acc[u] = fmaf(df, df, acc[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const float tot = wave_sum(acc[u]);
+        if (lane == 0 && j0 + u < M) L.stage[j0 + u] = make_key(tot, (uint32_t)cs[u]);
+      }
+    }
+    wave_sync();
+    for (int j = M + lane; j < CAP; j += HNTL_WAVE) L.stage[j] = KEY_NONE;
+    wave_sync();
+    L.sort_stage();
+    for (int j = lane; j < P; j += HNTL_WAVE) {
+      const uint64_t kk = L.stage[j];
+      idx[row * P + j] = (int32_t)key_id(kk);
+      if (val) val[row * P + j] = key_dist(kk);
+    }
+    return;
+  }
+  for (int j = lane; j < P; j += HNTL_WAVE) {
+    const uint64_t kk = L.best[j];
+    idx[row * P + j] = kk == KEY_NONE ? -1 : (int32_t)key_id(kk);
+    if (val) val[row * P + j] = kk == KEY_NONE ? __builtin_inff() : key_dist(kk);
+  }
+}
+
+}  // namespace
+
+void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, A, rows, d, out);
+  HIP_TRY(hipGetLastError());
+}
+
+void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn, int cols,
+                        int d, float* D, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const bool vec4 = (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
+  dim3 grid((unsigned)((rows + TM - 1) / TM), (unsigned)((cols + TN - 1) / TN));
+  hipLaunchKernelGGL(dist_matrix_kernel, grid, dim3(256), 0, s, A, an, rows, Bm, bn, cols, d, D, vec4);
+  HIP_TRY(hipGetLastError());
+}
+
+void launch_argmin_rows(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn, int cols,
+                        int d, int32_t* label, float* dmin, hipStream_t s) {
+  if (rows <= 0) return;
+  const bool vec4 = (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
+  hipLaunchKernelGGL(argmin_rows_kernel, dim3((unsigned)((rows + TM - 1) / TM)), dim3(256), 0, s, A, an, rows, Bm,
+                     bn, cols, d, label, dmin, vec4);
+  HIP_TRY(hipGetLastError());
+}
+
+void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
+                      const float* A, const float* Bm, int d) {
+  if (rows <= 0) return;
+  dim3 grid((unsigned)((rows + 3) / 4));
+  const int M = A ? std::min(cols, P + 16) : P;
+  if (M <= 64)
+    hipLaunchKernelGGL(topk_rows_kernel<64>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, Bm, d, idx, val);
+  else
+    hipLaunchKernelGGL(topk_rows_kernel<128>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, Bm, d, idx, val);
+  HIP_TRY(hipGetLastError());
+}
+
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace hntl

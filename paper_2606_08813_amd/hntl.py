@@ -1,0 +1,267 @@
+"""Python binding of the HNTL C ABI (``include/hntl.h``).
+
+Argument marshalling only: every step of the search runs in the HIP library.
+PyTorch supplies device memory (tensors) and streams.  The functions keep the
+C names; array arguments are torch CUDA tensors (or, where the C ABI accepts
+host memory, contiguous numpy arrays).
+
+Loading fails loudly when the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
+
+HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
+HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE = 1, 2, 4
+STAGES = ("route", "bucket", "project", "scan", "rerank")
+HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 64, 64
+CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3}
+
+
+class hntl_build_params(C.Structure):
+    _fields_ = [("G", C.c_uint32), ("r", C.c_uint32), ("kmeans_iters", C.c_uint32),
+                ("train_per_grain", C.c_uint32), ("eig_iters", C.c_uint32), ("codes_mask", C.c_uint32),
+                ("seed", C.c_uint64), ("init_centroids", C.c_void_p)]
+
+
+class hntl_search_params(C.Structure):
+    _fields_ = [("P", C.c_uint32), ("C", C.c_uint32), ("k", C.c_uint32), ("codes", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+class hntl_index_info(C.Structure):
+    _fields_ = [("N", C.c_uint64), ("d", C.c_uint32), ("G", C.c_uint32), ("r", C.c_uint32),
+                ("block", C.c_uint32), ("codes_mask", C.c_uint32), ("n_blocks", C.c_uint64),
+                ("device_bytes", C.c_uint64), ("captured_variance", C.c_double),
+                ("kmeans_iters_run", C.c_uint32), ("max_grain", C.c_uint32)]
+
+
+class HNTLError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hntl status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = {
+    "hntl_build": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.POINTER(hntl_build_params), C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    "hntl_index_create": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32] + [C.c_void_p] * 7
+                          + [C.c_uint32, C.POINTER(C.c_void_p)]),
+    "hntl_index_export": (C.c_int, [C.c_void_p] * 8),
+    "hntl_index_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_index_info)]),
+    "hntl_index_captured": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hntl_index_free": (None, [C.c_void_p]),
+    "hntl_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params), C.c_void_p,
+                              C.c_void_p, C.c_void_p]),
+    "hntl_search_stages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params)]
+                           + [C.c_void_p] * 13),
+    "hntl_profile_read": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "hntl_last_error": (C.c_char_p, []),
+    "hntl_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"HNTL HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or paper_2606_08813_amd/build_lib.py)")
+        L = C.CDLL(str(LIB_PATH))
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != HNTL_OK:
+        raise HNTLError(status, lib().hntl_last_error().decode())
+
+
+def hntl_last_error() -> str:
+    return lib().hntl_last_error().decode()
+
+
+def hntl_version() -> str:
+    return lib().hntl_version().decode()
+
+
+def _ptr(x):
+    """Device or host address of a tensor / ndarray (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    assert x.is_contiguous(), "tensors passed to the library must be contiguous"
+    return x.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _cuda_f32(x, name):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return x
+
+
+@dataclass
+class Index:
+    """An index handle (freed when garbage collected or by ``hntl_index_free``)."""
+
+    handle: C.c_void_p
+    N: int
+    d: int
+    G: int
+    r: int
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hntl_index_free(self.handle)
+            self.handle = None
+
+
+def hntl_build(X, G: int, r: int, *, kmeans_iters=0, train_per_grain=0, eig_iters=0, codes=("fp32",), seed=0,
+               init_centroids=None, stream=None) -> Index:
+    """Build an index from X (N x d float32 CUDA tensor)."""
+    _cuda_f32(X, "X")
+    N, d = X.shape
+    mask = 0
+    for c in codes:
+        mask |= 1 << CODES[c]
+    p = hntl_build_params(G, r, kmeans_iters, train_per_grain, eig_iters, mask, seed,
+                          _ptr(init_centroids))
+    out = C.c_void_p()
+    _check(lib().hntl_build(X.data_ptr(), N, d, C.byref(p), _stream(stream), C.byref(out)))
+    return Index(out, N, d, G, r)
+
+
+def hntl_index_create(stored: dict, X, codes=("fp32",)) -> Index:
+    """Index from stored-format arrays (numpy host arrays or CUDA tensors)."""
+    def prep(a, dt):
+        if isinstance(a, np.ndarray):
+            return np.ascontiguousarray(a, dtype=dt)
+        return a.contiguous()
+    cen = prep(stored["centroids"], np.float32)
+    bas = prep(stored["basis"], np.float32)
+    off = prep(stored["offsets"], np.int64)
+    per = prep(stored["perm"], np.int32)
+    cod = prep(stored["codes"], np.float32)
+    eps = prep(stored["eps"], np.float32)
+    Xc = prep(X, np.float32)
+    G, d = cen.shape
+    r = bas.shape[1]
+    N = per.shape[0]
+    mask = 0
+    for c in codes:
+        mask |= 1 << CODES[c]
+    out = C.c_void_p()
+    _check(lib().hntl_index_create(N, d, G, r, _ptr(cen), _ptr(bas), _ptr(off), _ptr(per), _ptr(cod), _ptr(eps),
+                                   _ptr(Xc), mask, C.byref(out)))
+    return Index(out, N, d, G, r)
+
+
+def hntl_index_export(index: Index, with_scales=False) -> dict:
+    G, d, r, N = index.G, index.d, index.r, index.N
+    o = dict(centroids=np.empty((G, d), np.float32), basis=np.empty((G, r, d), np.float32),
+             offsets=np.empty(G + 1, np.int64), perm=np.empty(N, np.int32), codes=np.empty((N, r), np.float32),
+             eps=np.empty(N, np.float32))
+    sc = np.empty(G, np.float32) if with_scales else None
+    _check(lib().hntl_index_export(index.handle, _ptr(o["centroids"]), _ptr(o["basis"]), _ptr(o["offsets"]),
+                                   _ptr(o["perm"]), _ptr(o["codes"]), _ptr(o["eps"]), _ptr(sc)))
+    if with_scales:
+        o["scales"] = sc
+    return o
+
+
+def hntl_index_info_get(index: Index) -> dict:
+    info = hntl_index_info()
+    _check(lib().hntl_index_info_get(index.handle, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def hntl_index_captured(index: Index) -> np.ndarray:
+    out = np.empty(index.G, np.float64)
+    _check(lib().hntl_index_captured(index.handle, out.ctypes.data))
+    return out
+
+
+def hntl_index_free(index: Index):
+    if index.handle:
+        lib().hntl_index_free(index.handle)
+        index.handle = None
+
+
+def _params(P, C_, k, codes, flags):
+    return hntl_search_params(P, C_, k, CODES[codes] if isinstance(codes, str) else codes, flags)
+
+
+def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None):
+    """Top-k ids (int32) and squared distances (float32) per query, as CUDA tensors."""
+    import torch
+    _cuda_f32(Q, "Q")
+    nq = Q.shape[0]
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    else:
+        ids, dist = out
+    sp = _params(P, C_, k, codes, flags)
+    _check(lib().hntl_search(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
+                             _stream(stream)))
+    return ids, dist
+
+
+def hntl_profile_read():
+    """Summed per-stage milliseconds of profiled searches since the last read, and their count."""
+    ms = np.zeros(len(STAGES), np.float64)
+    calls = C.c_uint32(0)
+    _check(lib().hntl_profile_read(ms.ctypes.data, len(STAGES), C.byref(calls)))
+    return dict(zip(STAGES, ms.tolist())), calls.value
+
+
+def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=HNTL_FLAG_SYNC,
+                       probes_in=None, tangent_in=None, epsq_in=None, pool_in=None, stream=None):
+    """Run the lifecycle with stage outputs returned and optional stage inputs (CUDA tensors)."""
+    import torch
+    _cuda_f32(Q, "Q")
+    nq = Q.shape[0]
+    dev = Q.device
+    r = index.r
+    o = {}
+    if pool_in is None:
+        if probes_in is None:
+            o["probes"] = torch.full((nq, P), -7, dtype=torch.int32, device=dev)
+            o["pdist"] = torch.full((nq, P), float("nan"), dtype=torch.float32, device=dev)
+        if tangent_in is None:
+            o["zq"] = torch.full((nq, P, r), float("nan"), dtype=torch.float32, device=dev)
+            o["epsq"] = torch.full((nq, P), float("nan"), dtype=torch.float32, device=dev)
+        o["pool_ids"] = torch.full((nq, C_), -7, dtype=torch.int32, device=dev)
+        o["pool_D"] = torch.full((nq, C_), float("nan"), dtype=torch.float32, device=dev)
+    o["ids"] = torch.full((nq, k), -7, dtype=torch.int32, device=dev)
+    o["dist"] = torch.full((nq, k), float("nan"), dtype=torch.float32, device=dev)
+    sp = _params(P, C_, k, codes, flags)
+    _check(lib().hntl_search_stages(
+        index.handle, Q.data_ptr(), nq, C.byref(sp), _ptr(probes_in), _ptr(o.get("probes")), _ptr(o.get("pdist")),
+        _ptr(tangent_in), _ptr(epsq_in), _ptr(o.get("zq")), _ptr(o.get("epsq")), _ptr(pool_in),
+        _ptr(o.get("pool_ids")), _ptr(o.get("pool_D")), _ptr(o["ids"]), _ptr(o["dist"]), _stream(stream)))
+    return o
