@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--recall-sample", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=400, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-stage HIP event records")
+    ap.add_argument("--no-prune", action="store_true", help="scan every member of every probed grain")
     return ap.parse_args()
 
 
@@ -83,8 +84,11 @@ def main():
     ids = torch.empty((W.nq, W.k), dtype=torch.int32, device=dev)
     dist = torch.empty((W.nq, W.k), dtype=torch.float32, device=dev)
     flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
+    if args.no_prune:
+        flags |= hntl.HNTL_FLAG_NO_PRUNE
     for _ in range(args.warmup):
-        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, out=(ids, dist))
+        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, flags=flags & ~hntl.HNTL_FLAG_PROFILE,
+                         out=(ids, dist))
     torch.cuda.synchronize()
     hntl.hntl_profile_read()  # drop warm-up records
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -98,8 +102,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    stage_ms, calls = hntl.hntl_profile_read()
+    stage_ms, calls, scored_total = hntl.hntl_profile_read()
     stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
+    scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
     qps = W.nq / (ms_per_step / 1e3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
         f"{qps:,.0f} queries/s; stages {stage_avg}")
@@ -127,7 +132,7 @@ def main():
     per_stage = {
         "route": dict(bound="mfma", work=2.0 * W.nq * W.G * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
         "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
-        "scan": dict(bound="alu", work=3.0 * W.r * scanned, unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
+        "scan": dict(bound="alu", work=3.0 * W.r * (scored or scanned), unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
         "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * W.P * W.C * 8, unit="GB/s",
                        peak=HBM_PEAK_GBS),
     }
@@ -140,7 +145,7 @@ def main():
         roof[name] = {"bound": s["bound"], "achieved": round(achieved, 3), "peak": s["peak"], "unit": s["unit"],
                       "frac": round(achieved / s["peak"], 4), "ms": round(stage_avg[name], 4)}
     dominant = max(roof, key=lambda n: roof[n]["ms"]) if roof else None
-    scan_bytes = scanned * (rp * code_bytes + 4)
+    scan_bytes = (scored or scanned) * (rp * code_bytes + 4)
     scan_ms = stage_avg.get("scan", 0.0)
     scan_stream_gbs = scan_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None
 
@@ -176,8 +181,10 @@ def main():
                    "P": W.P, "C": W.C, "k": W.k, "codes": args.codes},
         "recall_at_10": round(recall, 4),
         "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
-        "scan_ns_per_vector": round(scan_ms * 1e6 / scanned, 5) if scan_ms else None,
-        "vectors_scanned_per_step": scanned,
+        "scan_ns_per_vector_scored": round(scan_ms * 1e6 / scored, 5) if (scan_ms and scored) else None,
+        "vectors_in_probed_grains_per_step": scanned,
+        "vectors_scored_per_step": scored,
+        "prune": not args.no_prune,
         "scan_code_GBps": round(scan_stream_gbs, 1) if scan_stream_gbs else None,
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "build_s": round(build_s, 2),

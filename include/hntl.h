@@ -58,7 +58,7 @@ typedef enum hntl_status {
 /* Compiled limits. */
 #define HNTL_MAX_R 64       /* tangent rank r */
 #define HNTL_MAX_C 256      /* candidate pool C */
-#define HNTL_MAX_P 64       /* probes P */
+#define HNTL_MAX_P 48       /* probes P */
 #define HNTL_BLOCK 64       /* Block-SoA block size B (vectors per block) */
 
 /* Code storage of the tangent coordinates scanned in step 3. */
@@ -72,6 +72,16 @@ typedef enum hntl_codes {
 #define HNTL_FLAG_SYNC 1u       /* synchronise the stream before returning and report device errors */
 #define HNTL_FLAG_CHECK_Q 2u    /* reject non-finite query values with HNTL_EINVAL (implies a sync) */
 #define HNTL_FLAG_PROFILE 4u    /* record HIP events around each stage on the call's stream (see hntl_profile_read) */
+#define HNTL_FLAG_NO_PRUNE 8u   /* scan every member of every probed grain (see below) */
+/*
+ * Exact pruning.  By default the nearest probed grain of each query is scanned
+ * first; its C-th best (D, id) key then bounds the other probed grains: their
+ * candidates must beat it to enter the pool, and a grain is skipped outright
+ * when a lower bound of eq. 6 over the grain (squared distance from z_q to the
+ * bounding box of the grain's codes, plus eps_q, plus the grain's smallest
+ * eps_i) exceeds it by a relative margin of 1e-4.  Pool and results are the
+ * same as without pruning; HNTL_FLAG_NO_PRUNE scans everything.
+ */
 
 /* Stages timed by HNTL_FLAG_PROFILE, in order. */
 #define HNTL_STAGE_ROUTE 0      /* centroid distances (MFMA) + top-P select */
@@ -194,11 +204,13 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
 /*
  * hntl_profile_read - per-stage device time of the searches issued by the calling
  * thread with HNTL_FLAG_PROFILE since the last read.  Waits for those events to
- * complete, then writes the summed milliseconds per stage into ms[0..n) and the
- * number of timed calls into *calls (either may be NULL), and clears the record.
- * Stages skipped by stage injection count 0 ms.
+ * complete, then writes the summed milliseconds per stage into ms[0..n), the
+ * number of timed calls into *calls and the number of eq. 6 scores computed
+ * (query-grain pairs scanned times their grain sizes) into *scored (any of the
+ * three may be NULL), and clears the record.  Stages skipped by stage injection
+ * count 0 ms.
  */
-hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls);
+hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls, uint64_t* scored);
 
 /* Last error message of the calling thread ("" if none). */
 const char* hntl_last_error(void);

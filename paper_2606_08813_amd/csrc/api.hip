@@ -20,7 +20,8 @@ hntl_status fail(hntl_status s, const std::string& msg) {
 }
 
 Index::~Index() {
-  void* ptrs[] = {centroids, cnorm, basis, goff, boff, perm, codes, eps, codes_bf16, codes_fp8, scales, basis_bf16, X};
+  void* ptrs[] = {centroids, cnorm, basis, goff, boff, perm, codes, eps, codes_bf16, codes_fp8, scales, basis_bf16, X,
+                  blo, bhi, emin};
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
@@ -89,6 +90,16 @@ struct ProfRec {
 struct Profiler {
   std::vector<hipEvent_t> pool;
   std::vector<ProfRec> recs;
+  unsigned long long* scored = nullptr;  // device counter of (pair, member) scores
+  int scored_dev = -1;
+  unsigned long long* counter(int dev) {
+    if (!scored || scored_dev != dev) {
+      HIP_TRY(hipMalloc((void**)&scored, sizeof(unsigned long long)));
+      HIP_TRY(hipMemset(scored, 0, sizeof(unsigned long long)));
+      scored_dev = dev;
+    }
+    return scored;
+  }
   ~Profiler() {
     for (auto& r : recs)
       for (auto e : r.ev) pool.push_back(e);
@@ -179,6 +190,7 @@ void finish_index(Index* ix, const std::vector<int64_t>& off, const float* codes
   ix->eps = upload(ix, eb.data(), eb.size());
   ix->cnorm = dev_alloc<float>(ix, G);
   launch_row_norms(ix->centroids, G, (int)ix->d, ix->cnorm, nullptr);
+  launch_grain_bounds(*ix, nullptr);
   HIP_TRY(hipDeviceSynchronize());
 }
 
@@ -375,22 +387,31 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
           const int64_t rows = std::min<int64_t>(chunk, nq - q0);
           launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
           launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,
-                           Q + q0 * ix.d, ix.centroids, (int)ix.d);
+                           Q + q0 * ix.d, qn + q0, ix.centroids, ix.cnorm, (int)ix.d);
         }
         probes = pr;
       }
-      // 2. bucketing by grain
+      // 2. bucketing by grain (each grain's probe-slot-0 pairs first, so that
+      //    slot 0 is scanned first and its C-th key bounds the other slots)
       clk.at(HNTL_STAGE_BUCKET);
       Buckets b;
-      b.tile = 16;
-      b.max_items = (int)(npairs / b.tile + std::min<int64_t>(ix.G, npairs) + 1);
+      b.G = (int)ix.G;
       b.gcount = sc.get<int32_t>(ix.G);
+      b.gcount0 = sc.get<int32_t>(ix.G);
       b.gstart = sc.get<int32_t>(ix.G);
-      b.cursor = sc.get<int32_t>(ix.G);
+      b.cur0 = sc.get<int32_t>(ix.G);
+      b.cur1 = sc.get<int32_t>(ix.G);
       b.order = sc.get<int32_t>(npairs);
-      b.items = sc.get<int32_t>(2 * (size_t)b.max_items);
-      b.nitems = sc.get<int32_t>(1);
-      launch_bucket(probes, npairs, (int)ix.G, b, s);
+      const int tiles[3] = {16, 16, 128};
+      const int64_t np[3] = {(int64_t)nq, (int64_t)nq * (P - 1), npairs};
+      for (int L = 0; L < 3; ++L) {
+        b.lists.tile[L] = tiles[L];
+        b.lists.ioff[L] = sc.get<int32_t>(ix.G + 1);
+        b.lists.lstart[L] = sc.get<int32_t>(ix.G);
+        b.lists.lcount[L] = sc.get<int32_t>(ix.G);
+        b.max_items[L] = (int)(np[L] / tiles[L] + std::min<int64_t>(ix.G, np[L]) + 1);
+      }
+      launch_bucket(probes, nq, (int)P, (int)ix.G, b, s);
       // 3. projection
       const float* T = tangent_in;
       const float* eq = epsq_in;
@@ -402,10 +423,17 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
         T = To;
         eq = eo;
       }
-      // 4. scan + per-pair top-C
+      // 4. scan + per-pair top-C: slot 0 unbounded, then the other slots
+      //    bounded by it (and pruned by the exact lower bound unless disabled)
       uint64_t* pt = sc.get<uint64_t>((size_t)npairs * C);
       clk.at(HNTL_STAGE_SCAN);
-      launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, pt, s);
+      unsigned long long* scored = (sp->flags & HNTL_FLAG_PROFILE) ? g_prof.counter(ix.device) : nullptr;
+      launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, LIST_SLOT0, pt, nullptr, false, scored, s);
+      if (P > 1) {
+        const bool bounded = !(sp->flags & HNTL_FLAG_NO_PRUNE);
+        launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, LIST_REST, pt, bounded ? pt : nullptr, bounded,
+                    scored, s);
+      }
       part = pt;
     }
     // 5. pool merge + exact rerank
@@ -419,9 +447,17 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
   });
 }
 
-hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls) {
+hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls, uint64_t* scored) {
   g_last_error.clear();
   return guarded([&] {
+    if (scored) *scored = 0;
+    if (g_prof.scored) {
+      unsigned long long v = 0;
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipMemcpy(&v, g_prof.scored, sizeof(v), hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemset(g_prof.scored, 0, sizeof(v)));
+      if (scored) *scored = v;
+    }
     std::vector<double> acc(HNTL_NUM_STAGES, 0.0);
     for (auto& r : g_prof.recs) {
       HIP_TRY(hipEventSynchronize(r.ev[HNTL_NUM_STAGES]));

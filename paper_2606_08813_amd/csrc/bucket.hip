@@ -1,8 +1,14 @@
 // Grain bucketing of (query, probe) pairs.  Routing gives every query P grains;
 // projection and scan run grain-major so that a grain's basis and Block-SoA
-// codes are read once per tile of queries instead of once per query.  This
-// groups the pair ids by grain (counting sort) and cuts each grain's pairs
-// into tiles (work items) of at most `tile` pairs.
+// codes are read once per tile of queries instead of once per query.
+//
+// A counting sort groups the pair ids q * P + slot by grain.  Inside a grain's
+// range the pairs of probe slot 0 (each query's nearest grain) come first, so
+// the scan can take slot 0 in a pass of its own whose results bound the other
+// slots.  Three work-item lists are cut from the ranges without materialising
+// them: per list L and grain g, lstart[L][g] / lcount[L][g] give the pairs, and
+// the exclusive prefix ioff[L][g] of ceil(lcount / tile_L) numbers its items;
+// a kernel finds the grain of item i by binary search in ioff.
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -10,15 +16,54 @@ namespace hntl {
 
 namespace {
 
-__global__ void bucket_hist_kernel(const int32_t* __restrict__ probes, int64_t npairs, int G,
-                                   int32_t* __restrict__ gcount) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
+constexpr int CHUNK = 4096;      // pairs per workgroup
+constexpr int LDS_MAX_G = 8192;  // grain counters kept in LDS up to this G
+
+__device__ __forceinline__ int probe_of(const int32_t* __restrict__ probes, int64_t p, int G) {
   const int g = probes[p];
-  if (g >= 0 && g < G) atomicAdd(&gcount[g], 1);
+  return (g >= 0 && g < G) ? g : -1;
 }
 
-// Exclusive scan of 1024 values held one per thread; returns the total.
+// Per-grain pair counts, all slots and slot 0; counters live in LDS per
+// workgroup and are added to the global ones once per (workgroup, grain).
+__global__ __launch_bounds__(256) void bucket_hist_kernel(const int32_t* __restrict__ probes, int64_t npairs, int P,
+                                                          int G, int32_t* __restrict__ gcount,
+                                                          int32_t* __restrict__ gcount0) {
+  extern __shared__ int lds_mem[];
+  int* lc = lds_mem;
+  int* lc0 = lds_mem + G;
+  const bool lds = G <= LDS_MAX_G;
+  if (lds) {
+    for (int g = threadIdx.x; g < G; g += 256) {
+      lc[g] = 0;
+      lc0[g] = 0;
+    }
+    __syncthreads();
+  }
+  const int64_t p0 = (int64_t)blockIdx.x * CHUNK;
+  for (int u = threadIdx.x; u < CHUNK; u += 256) {
+    const int64_t p = p0 + u;
+    if (p >= npairs) break;
+    const int g = probe_of(probes, p, G);
+    if (g < 0) continue;
+    const bool s0 = (p % P) == 0;
+    if (lds) {
+      atomicAdd(&lc[g], 1);
+      if (s0) atomicAdd(&lc0[g], 1);
+    } else {
+      atomicAdd(&gcount[g], 1);
+      if (s0) atomicAdd(&gcount0[g], 1);
+    }
+  }
+  if (!lds) return;
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += 256) {
+    if (lc[g]) atomicAdd(&gcount[g], lc[g]);
+    if (lc0[g]) atomicAdd(&gcount0[g], lc0[g]);
+  }
+}
+
+// Exclusive scan of one value per thread of a 1024-thread workgroup.
 __device__ int block_exclusive_scan(int v, int* tmp /* >= 16 ints */, int& total) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   int x = v;
@@ -41,64 +86,121 @@ __device__ int block_exclusive_scan(int v, int* tmp /* >= 16 ints */, int& total
   return wsum + x - v;
 }
 
-// Single workgroup: grain start offsets, per-grain tiles, work-item list.
-__global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __restrict__ gcount, int G, int tile,
-                                                           int max_items, int32_t* __restrict__ gstart,
-                                                           int32_t* __restrict__ cursor, int32_t* __restrict__ items,
-                                                           int32_t* __restrict__ nitems) {
+// Single workgroup: grain ranges, the three lists' ranges and item offsets.
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __restrict__ gcount,
+                                                           const int32_t* __restrict__ gcount0, int G,
+                                                           int32_t* __restrict__ gstart, int32_t* __restrict__ cur0,
+                                                           int32_t* __restrict__ cur1, ItemLists lists) {
   __shared__ int tmp[32];
-  int carry_p = 0, carry_t = 0;
+  int carry_p = 0, carry[3] = {0, 0, 0};
   for (int base = 0; base < G; base += 1024) {
     const int g = base + (int)threadIdx.x;
     const int c = g < G ? gcount[g] : 0;
-    const int nt = (c + tile - 1) / tile;
-    int tot_p, tot_t;
-    const int sp = block_exclusive_scan(c, tmp, tot_p);
-    const int st = block_exclusive_scan(nt, tmp, tot_t);
-    if (g < G) {
-      gstart[g] = carry_p + sp;
-      cursor[g] = 0;
-      for (int t = 0; t < nt; ++t) {
-        const int it = carry_t + st + t;
-        if (it < max_items) {
-          items[2 * it] = g;
-          items[2 * it + 1] = t * tile;
-        }
+    const int c0 = g < G ? gcount0[g] : 0;
+    int tot;
+    const int sp = block_exclusive_scan(c, tmp, tot);
+    const int st = carry_p + sp;
+    carry_p += tot;
+    const int lc[3] = {c0, c - c0, c};
+    const int ls[3] = {st, st + c0, st};
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+      const int tile = lists.tile[L];
+      const int nt = (lc[L] + tile - 1) / tile;
+      int tt;
+      const int so = block_exclusive_scan(nt, tmp, tt);
+      if (g < G) {
+        lists.ioff[L][g] = carry[L] + so;
+        lists.lstart[L][g] = ls[L];
+        lists.lcount[L][g] = lc[L];
       }
+      carry[L] += tt;
     }
-    carry_p += tot_p;
-    carry_t += tot_t;
+    if (g < G) {
+      gstart[g] = st;
+      cur0[g] = 0;
+      cur1[g] = 0;
+    }
   }
-  if (threadIdx.x == 0) *nitems = carry_t < max_items ? carry_t : max_items;
+  if (threadIdx.x == 0)
+    for (int L = 0; L < 3; ++L) lists.ioff[L][G] = carry[L];
 }
 
-__global__ void bucket_scatter_kernel(const int32_t* __restrict__ probes, int64_t npairs, int G,
-                                      const int32_t* __restrict__ gstart, int32_t* __restrict__ cursor,
-                                      int32_t* __restrict__ order) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
-  const int g = probes[p];
-  if (g < 0 || g >= G) return;
-  const int pos = gstart[g] + atomicAdd(&cursor[g], 1);
-  order[pos] = (int32_t)p;
+// Scatter pair ids into their grain's range (slot 0 first): each workgroup
+// reserves one run per grain and kind with a single global atomic, then ranks
+// its pairs with LDS atomics.  The order inside a grain's run is not fixed;
+// every consumer writes its results by pair id, so outputs do not depend on it.
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(const int32_t* __restrict__ probes, int64_t npairs,
+                                                             int P, int G, const int32_t* __restrict__ gstart,
+                                                             const int32_t* __restrict__ gcount0,
+                                                             int32_t* __restrict__ cur0, int32_t* __restrict__ cur1,
+                                                             int32_t* __restrict__ order) {
+  extern __shared__ int lds_mem[];
+  const bool lds = G <= LDS_MAX_G / 2;
+  const int64_t p0 = (int64_t)blockIdx.x * CHUNK;
+  if (!lds) {
+    for (int u = threadIdx.x; u < CHUNK; u += 256) {
+      const int64_t p = p0 + u;
+      if (p >= npairs) break;
+      const int g = probe_of(probes, p, G);
+      if (g < 0) continue;
+      const int pos = (p % P) == 0 ? gstart[g] + atomicAdd(&cur0[g], 1)
+                                   : gstart[g] + gcount0[g] + atomicAdd(&cur1[g], 1);
+      order[pos] = (int32_t)p;
+    }
+    return;
+  }
+  int* n0 = lds_mem;
+  int* n1 = lds_mem + G;
+  int* b0 = lds_mem + 2 * G;
+  int* b1 = lds_mem + 3 * G;
+  for (int g = threadIdx.x; g < G; g += 256) {
+    n0[g] = 0;
+    n1[g] = 0;
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < CHUNK; u += 256) {
+    const int64_t p = p0 + u;
+    if (p >= npairs) break;
+    const int g = probe_of(probes, p, G);
+    if (g >= 0) atomicAdd((p % P) == 0 ? &n0[g] : &n1[g], 1);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += 256) {
+    b0[g] = n0[g] ? gstart[g] + atomicAdd(&cur0[g], n0[g]) : 0;
+    b1[g] = n1[g] ? gstart[g] + gcount0[g] + atomicAdd(&cur1[g], n1[g]) : 0;
+    n0[g] = 0;
+    n1[g] = 0;
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < CHUNK; u += 256) {
+    const int64_t p = p0 + u;
+    if (p >= npairs) break;
+    const int g = probe_of(probes, p, G);
+    if (g < 0) continue;
+    const int pos = (p % P) == 0 ? b0[g] + atomicAdd(&n0[g], 1) : b1[g] + atomicAdd(&n1[g], 1);
+    order[pos] = (int32_t)p;
+  }
 }
 
 }  // namespace
 
-void launch_bucket(const int32_t* probes, int64_t npairs, int G, Buckets& b, hipStream_t s) {
+void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s) {
+  const int64_t npairs = nq * P;
   HIP_TRY(hipMemsetAsync(b.gcount, 0, sizeof(int32_t) * G, s));
+  HIP_TRY(hipMemsetAsync(b.gcount0, 0, sizeof(int32_t) * G, s));
+  const unsigned nb = (unsigned)((npairs + CHUNK - 1) / CHUNK);
   if (npairs > 0) {
-    const unsigned nb = (unsigned)((npairs + 255) / 256);
-    hipLaunchKernelGGL(bucket_hist_kernel, dim3(nb), dim3(256), 0, s, probes, npairs, G, b.gcount);
+    hipLaunchKernelGGL(bucket_hist_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G ? 2 * G * sizeof(int) : 0, s,
+                       probes, npairs, P, G, b.gcount, b.gcount0);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, b.gcount, G, b.tile, b.max_items, b.gstart,
-                     b.cursor, b.items, b.nitems);
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, b.gcount, b.gcount0, G, b.gstart, b.cur0, b.cur1,
+                     b.lists);
   HIP_TRY(hipGetLastError());
   if (npairs > 0) {
-    const unsigned nb = (unsigned)((npairs + 255) / 256);
-    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), 0, s, probes, npairs, G, b.gstart, b.cursor,
-                       b.order);
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G / 2 ? 4 * G * sizeof(int) : 0, s,
+                       probes, npairs, P, G, b.gstart, b.gcount0, b.cur0, b.cur1, b.order);
     HIP_TRY(hipGetLastError());
   }
 }

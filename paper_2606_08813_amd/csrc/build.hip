@@ -132,17 +132,25 @@ __global__ __launch_bounds__(64) void kpp_choose_kernel(const float* __restrict_
                                                         int32_t* __restrict__ tstar, float* __restrict__ cent,
                                                         int step) {
   __shared__ int best_t;
+  // potential of each candidate: the 64 lanes sum strided block partials, then
+  // a butterfly reduction (fixed order, so the choice is reproducible)
+  double acc[KPP_MAXL];
+#pragma unroll
+  for (int t = 0; t < KPP_MAXL; ++t) acc[t] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64)
+#pragma unroll
+    for (int t = 0; t < KPP_MAXL; ++t)
+      if (t < L) acc[t] += potpart[(size_t)b * L + t];
+#pragma unroll
+  for (int t = 0; t < KPP_MAXL; ++t) acc[t] = wave_sum_d(acc[t]);
   if (threadIdx.x == 0) {
     double best = 0.0;
     int bt = 0;
-    for (int t = 0; t < L; ++t) {
-      double p = 0.0;
-      for (int b = 0; b < nblk; ++b) p += potpart[(size_t)b * L + t];
-      if (t == 0 || p < best) {
-        best = p;
+    for (int t = 0; t < L; ++t)
+      if (t == 0 || acc[t] < best) {
+        best = acc[t];
         bt = t;
       }
-    }
     best_t = bt;
     *tstar = bt;
   }
@@ -759,6 +767,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
         }
       }
     }
+    launch_grain_bounds(*ix, s);
     ix->codes_mask = 1u;
     const uint32_t want = params->codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3));
     if (want) {

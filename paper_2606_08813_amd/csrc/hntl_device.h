@@ -67,15 +67,17 @@ struct WaveTopC {
   uint64_t* best;
   uint64_t* stage;
   uint64_t thr;
+  uint64_t bound;  // keys >= bound are never kept (a threshold known in advance)
   int nstage;
   int C;
 
-  __device__ __forceinline__ void init(uint64_t* lds, int C_) {
+  __device__ __forceinline__ void init(uint64_t* lds, int C_, uint64_t bound_ = KEY_NONE) {
     best = lds;
     stage = lds + CAP;
     C = C_;
     nstage = 0;
-    thr = KEY_NONE;
+    bound = bound_;
+    thr = bound_;
     for (int i = lane_id(); i < CAP; i += HNTL_WAVE) best[i] = KEY_NONE;
     wave_sync();
   }
@@ -124,7 +126,8 @@ struct WaveTopC {
       }
       wave_sync();
     }
-    thr = best[C - 1];
+    const uint64_t t = best[C - 1];
+    thr = t < bound ? t : bound;
     nstage = 0;
   }
 
@@ -150,6 +153,124 @@ struct WaveTopC {
     wave_sync();
   }
 };
+
+// ------------------------------------------- register-resident top-64 list
+// The same selection for C <= 64 with the sorted best list held in registers,
+// one key per lane (lane i holds the i-th smallest).  Arrivals are compacted
+// into a 64-entry LDS stage as above; a flush loads the stage one key per lane,
+// sorts it with a bitonic network across the lanes (shuffles, no LDS round
+// trips) and merges it into the register list.  Threshold and stage count
+// are wave-uniform and kept in scalar registers.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  const uint32_t lo = __shfl((uint32_t)v, src, 64);
+  const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one key per lane.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = shfl_xor_u64(key, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const uint64_t mn = key < other ? key : other;
+      const uint64_t mx = key < other ? other : key;
+      key = (up == lower) ? mn : mx;
+    }
+  return key;
+}
+
+struct WaveTop64 {
+  uint64_t* stage;  // 64 keys of LDS
+  uint64_t best;    // this lane's entry of the sorted list
+  uint64_t thr;     // uniform
+  uint64_t bound;   // uniform
+  int nstage;       // uniform
+  int C;
+
+  __device__ __forceinline__ void init(uint64_t* lds, int C_, uint64_t bound_ = KEY_NONE) {
+    stage = lds;
+    C = C_;
+    nstage = 0;
+    bound = bound_;
+    thr = bound_;
+    best = KEY_NONE;
+  }
+
+  __device__ __forceinline__ void flush() {
+    if (nstage == 0) return;
+    const int lane = lane_id();
+    wave_sync();
+    uint64_t k = lane < nstage ? stage[lane] : KEY_NONE;
+    wave_sync();
+    k = wave_sort64(k);
+    // half-cleaner of (best ascending, arrivals descending), then bitonic merge
+    const uint64_t rev = shfl_u64(k, 63 - lane);
+    uint64_t m = best < rev ? best : rev;
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) {
+      const uint64_t other = shfl_xor_u64(m, j);
+      const bool lower = (lane & j) == 0;
+      const uint64_t mn = m < other ? m : other;
+      const uint64_t mx = m < other ? other : m;
+      m = lower ? mn : mx;
+    }
+    best = m;
+    const uint64_t t = uniform_u64(shfl_u64(best, C - 1));
+    thr = t < bound ? t : bound;
+    nstage = 0;
+  }
+
+  __device__ __forceinline__ void offer(uint64_t key, bool valid) {
+    bool pass = valid && key < thr;
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    if (nstage + cnt > 64) {
+      flush();
+      pass = valid && key < thr;
+      m = __ballot(pass);
+      if (m == 0) return;
+      cnt = __popcll(m);
+    }
+    if (pass) stage[nstage + mbcnt64(m)] = key;
+    nstage += cnt;
+  }
+
+  // After finish(), lane i holds the i-th smallest key (KEY_NONE padded).
+  __device__ __forceinline__ void finish() { flush(); }
+};
+
+// ------------------------------------------------------------- work items
+// Grain of work item `item` of a list whose items per grain have the exclusive
+// prefix ioff[0..G] (the largest g with ioff[g] <= item); false past the end.
+__device__ __forceinline__ bool item_grain(const int32_t* __restrict__ ioff, int G, int item, int& g) {
+  if (item >= ioff[G]) return false;
+  int lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ioff[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  g = lo;
+  return true;
+}
 
 // ------------------------------------------------------------------- MFMA
 // v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16] and B[l/16][l%16] of a

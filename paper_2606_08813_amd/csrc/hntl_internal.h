@@ -44,6 +44,9 @@ struct Index {
   float* scales = nullptr;         // G fp8 scales
   uint16_t* basis_bf16 = nullptr;  // G x r x d (bf16 bits)
   float* X = nullptr;          // N x d, original row order
+  float* blo = nullptr;        // G x rp: per-grain minimum of each code coordinate
+  float* bhi = nullptr;        // G x rp: per-grain maximum
+  float* emin = nullptr;       // G: per-grain minimum eps_i
 
   std::vector<int64_t> offsets_h;
   std::vector<int32_t> boff_h;
@@ -114,25 +117,40 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 // top-P per row of D; with A and Bm given, the winners are re-scored by exact
 // direct differences (routing)
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
-                      const float* A = nullptr, const float* Bm = nullptr, int d = 0);
+                      const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
+                      const float* bn = nullptr, int d = 0);
 
-// grain bucketing of (query, probe) pairs
-struct Buckets {
-  int32_t* gcount;   // G
-  int32_t* gstart;   // G
-  int32_t* cursor;   // G
-  int32_t* order;    // npairs: pair ids grouped by grain
-  int32_t* items;    // 2 * max_items: (grain, start) tiles
-  int32_t* nitems;   // 1
-  int max_items;
-  int tile;
+// grain bucketing of (query, probe) pairs; work-item lists cut from it
+enum { LIST_SLOT0 = 0, LIST_REST = 1, LIST_ALL = 2 };
+struct ItemLists {
+  int32_t* ioff[3];    // G + 1 each: exclusive prefix of items per grain
+  int32_t* lstart[3];  // G each: first position of the list's pairs of grain g in `order`
+  int32_t* lcount[3];  // G each: number of the list's pairs of grain g
+  int tile[3];         // pairs per work item
 };
-void launch_bucket(const int32_t* probes, int64_t npairs, int G, Buckets& b, hipStream_t s);
+struct Buckets {
+  int32_t* gcount;   // G: pairs per grain
+  int32_t* gcount0;  // G: probe-slot-0 pairs per grain
+  int32_t* gstart;   // G
+  int32_t* cur0;     // G
+  int32_t* cur1;     // G
+  int32_t* order;    // npairs: pair ids grouped by grain, slot-0 pairs first
+  ItemLists lists;
+  int max_items[3];  // upper bounds of the item counts (grid sizes)
+  int G;
+};
+void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s);
 
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
-                    hipStream_t s);
+                    hipStream_t s);  // over LIST_ALL
+// Scan of the bucketed pairs.  With `bound_lists` (the lists of probe slot 0,
+// already written into part), each pair starts from its query's C-th key of
+// slot 0 as threshold and, when `prune`, is skipped outright if an exact
+// lower bound of eq. 6 over its grain exceeds that threshold.
 void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, int P, int C,
-                 const Buckets& b, uint64_t* part, hipStream_t s);
+                 const Buckets& b, int list, uint64_t* part, const uint64_t* bound_lists, bool prune,
+                 unsigned long long* scored, hipStream_t s);
+void launch_grain_bounds(Index& ix, hipStream_t s);
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k,
                          const int32_t* probes, const uint64_t* part, const int32_t* pool_in, int32_t* pool_out,
                          float* pool_D_out, int32_t* ids, float* dist, hipStream_t s);

@@ -7,10 +7,9 @@
 //                                         columns, ||q' - W_g z_q||^2 equals
 //                                         ||q'||^2 - ||z_q||^2)
 //
-// One wave handles one work item: up to 16 pairs of one grain.  The centred
-// query rows (16 x 64 chunk) and the basis rows (r x 64 chunk) are staged in
-// LDS and fed to the MFMA; ||q'||^2 is accumulated by direct squares while
-// staging.  Outputs are pair-major: T[pair][r], epsq[pair], pair = q * P + slot.
+// One wave handles 16 pairs of one grain; ||q'||^2 is
+// accumulated by direct squares of the centred values fed to the MFMA.
+// Outputs are pair-major: T[pair][r], epsq[pair], pair = q * P + slot.
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -18,124 +17,141 @@ namespace hntl {
 
 namespace {
 
-constexpr int PT = 16;     // pairs per work item
-constexpr int KC = 64;     // depth chunk
-constexpr int LDK = KC + 1;
+constexpr int PT = 16;    // pairs per wave (rows of one 16x16 MFMA tile)
+constexpr int TILE = 128; // pairs per work item (8 waves)
+constexpr int KS = 8;       // consecutive depth values per lane and chunk
+constexpr int KC = 4 * KS;  // depth chunk: KS MFMA steps of K = 4
 
-__global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ Q, int d, int P,
-                                                      const float* __restrict__ centroids,
-                                                      const float* __restrict__ basis, int r,
-                                                      const int32_t* __restrict__ items,
-                                                      const int32_t* __restrict__ nitems,
-                                                      const int32_t* __restrict__ gcount,
-                                                      const int32_t* __restrict__ gstart,
-                                                      const int32_t* __restrict__ order, float* __restrict__ T,
-                                                      float* __restrict__ epsq) {
-  extern __shared__ float smem[];
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int item = blockIdx.x * 2 + wave;
-  if (item >= *nitems) return;
-  const int g = items[2 * item], start = items[2 * item + 1];
-  const int cnt = min(PT, gcount[g] - start);
-  const int nct = (r + 15) >> 4;  // column tiles of 16
-  float* As = smem + wave * ((PT + 64) * LDK);
-  float* Bs = As + PT * LDK;
-
-  int qrow[PT];
+// Loads KS consecutive floats src[0..KS) (zero from `lim` on) into v.
+template <bool VEC>
+__device__ __forceinline__ void load_ks(float (&v)[KS], const float* __restrict__ src, int lim) {
+  if (VEC) {
 #pragma unroll
-  for (int i = 0; i < PT; ++i) {
-    const int p = i < cnt ? order[gstart[g] + start + i] : 0;
-    qrow[i] = p / P;
+    for (int e = 0; e < KS; e += 4) {
+      float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < lim) t = *reinterpret_cast<const float4*>(src + e);
+      v[e] = t.x;
+      v[e + 1] = t.y;
+      v[e + 2] = t.z;
+      v[e + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < KS; ++e) v[e] = e < lim ? src[e] : 0.f;
   }
+}
+
+// One wave per 16 pairs.  The MFMA sums over the four K slots of each
+// instruction; lane (i = lane % 16, kq = lane / 16) feeds slot kq with depth
+// k0 + KS kq + e in step e, for the A operand (centred query row i) and the B
+// operand (basis row c * 16 + i) alike, so each lane reads KS contiguous floats
+// per operand and chunk straight from global memory.  NCT = ceil(r / 16)
+// column tiles.
+template <bool VEC, int NCT>
+__global__ __launch_bounds__(64 * (TILE / PT)) void project_kernel(
+    const float* __restrict__ Q, int d, int P, const float* __restrict__ centroids, const float* __restrict__ basis,
+    int r, const int32_t* __restrict__ ioff, const int32_t* __restrict__ lstart, const int32_t* __restrict__ lcount,
+    int G, const int32_t* __restrict__ order, float* __restrict__ T, float* __restrict__ epsq) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  // a work item holds up to TILE pairs of one grain; wave w projects rows
+  // 16 w .. 16 w + 15, and the waves share the grain's basis through L2
+  int g;
+  if (!item_grain(ioff, G, blockIdx.x, g)) return;
+  const int first = (blockIdx.x - ioff[g]) * TILE + PT * wave;  // within the grain's pairs
+  const int cnt = min(PT, lcount[g] - first);
+  if (cnt <= 0) return;  // no workgroup barrier in this kernel
+  const int32_t* pairs = order + lstart[g] + first;
+  const int i = lane & 15, kq = lane >> 4;
+  const int qrow = i < cnt ? pairs[i] / P : -1;
   const float* mu = centroids + (size_t)g * d;
   const float* Wg = basis + (size_t)g * r * d;
+  const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
 
-  floatx4 acc[4];
+  floatx4 acc[NCT];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  float sq[PT];
-#pragma unroll
-  for (int i = 0; i < PT; ++i) sq[i] = 0.f;
+  for (int c = 0; c < NCT; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float sq = 0.f;
 
   for (int k0 = 0; k0 < d; k0 += KC) {
-    const int kk = k0 + lane;
-    const bool in = kk < d;
-    const float m = in ? mu[kk] : 0.f;
-    float qv[PT];
+    const int kb = k0 + KS * kq;
+    const int lim = d - kb;  // valid floats from kb (may be <= 0)
+    float a[KS], m[KS], b[NCT][KS];
+    load_ks<VEC>(m, mu + kb, lim);
+    load_ks<VEC>(a, qp + kb, qrow >= 0 ? lim : 0);
 #pragma unroll
-    for (int i = 0; i < PT; ++i) qv[i] = (i < cnt && in) ? Q[(size_t)qrow[i] * d + kk] : 0.f;
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const float v = (i < cnt && in) ? qv[i] - m : 0.f;
-      As[i * LDK + lane] = v;
-      sq[i] = fmaf(v, v, sq[i]);
+    for (int c = 0; c < NCT; ++c) {
+      const int j = c * 16 + i;
+      load_ks<VEC>(b[c], Wg + (size_t)(j < r ? j : 0) * d + kb, j < r ? lim : 0);
     }
-    // basis rows: issue every load of the chunk before the LDS stores
-    float wv[64];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) wv[j] = (j < r && in) ? Wg[(size_t)j * d + kk] : 0.f;
-#pragma unroll
-    for (int j = 0; j < 64; ++j)
-      if (j < nct * 16) Bs[j * LDK + lane] = wv[j];
-    wave_sync();
-#pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      const int kr = 4 * s + (lane >> 4);
-      const float a = As[(lane & 15) * LDK + kr];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < nct) acc[c] = mfma16x16x4(a, Bs[(c * 16 + (lane & 15)) * LDK + kr], acc[c]);
+    for (int e = 0; e < KS; ++e) {
+      a[e] = qrow >= 0 ? a[e] - m[e] : 0.f;
+      sq = fmaf(a[e], a[e], sq);
     }
-    wave_sync();
+#pragma unroll
+    for (int e = 0; e < KS; ++e)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) acc[c] = mfma16x16x4(a[e], b[c][e], acc[c]);
   }
 
-  // ||q'||^2 per row, ||z||^2 per row
-  float qn[PT];
+  // ||q'||^2 of row i: the four K slots of the row
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+  // ||z||^2 per output row (MFMA layout: row 4 * (lane >> 4) + t, column lane & 15)
 #pragma unroll
-  for (int i = 0; i < PT; ++i) qn[i] = wave_sum(sq[i]);
-  float zn[4];
+  for (int t = 0; t < 4; ++t) {
+    const int row = 4 * (lane >> 4) + t;
+    float zz = 0.f;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float t = 0.f;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCT; ++c) {
       const int col = c * 16 + (lane & 15);
-      if (c < nct && col < r) t = fmaf(acc[c][i], acc[c][i], t);
+      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
     }
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) t += __shfl_xor(t, o, 64);
-    zn[i] = t;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = 4 * (lane >> 4) + i;
+    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    const float q2 = __shfl(sq, row, 64);  // lane `row` holds row `row`'s ||q'||^2
     if (row < cnt) {
-      const int p = order[gstart[g] + start + row];
+      const int p = pairs[row];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < NCT; ++c) {
         const int col = c * 16 + (lane & 15);
-        if (c < nct && col < r) T[(size_t)p * r + col] = acc[c][i];
+        if (col < r) T[(size_t)p * r + col] = acc[c][t];
       }
-      if ((lane & 15) == 0) {
-        float q2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < PT; ++j)
-          if (j == row) q2 = qn[j];
-        epsq[p] = fmaxf(q2 - zn[i], 0.f);
-      }
+      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
     }
   }
 }
 
 }  // namespace
 
+template <bool VEC, int NCT>
+void launch_project_t(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                      hipStream_t s) {
+  const ItemLists& L = b.lists;
+  hipLaunchKernelGGL((project_kernel<VEC, NCT>), dim3((unsigned)b.max_items[LIST_ALL]), dim3(64 * (TILE / PT)), 0,
+                     s, Q, (int)ix.d, P, ix.centroids, ix.basis, (int)ix.r, L.ioff[LIST_ALL], L.lstart[LIST_ALL],
+                     L.lcount[LIST_ALL], (int)ix.G, b.order, T, epsq);
+}
+
+template <bool VEC>
+void launch_project_v(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                      hipStream_t s) {
+  switch ((ix.r + 15) / 16) {
+    case 1: launch_project_t<VEC, 1>(ix, Q, P, b, T, epsq, s); break;
+    case 2: launch_project_t<VEC, 2>(ix, Q, P, b, T, epsq, s); break;
+    case 3: launch_project_t<VEC, 3>(ix, Q, P, b, T, epsq, s); break;
+    default: launch_project_t<VEC, 4>(ix, Q, P, b, T, epsq, s); break;
+  }
+}
+
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
                     hipStream_t s) {
-  const size_t shmem = 2 * (PT + 64) * LDK * sizeof(float);
-  const unsigned grid = (unsigned)((b.max_items + 1) / 2);
-  if (grid == 0) return;
-  hipLaunchKernelGGL(project_kernel, dim3(grid), dim3(128), shmem, s, Q, (int)ix.d, P, ix.centroids, ix.basis,
-                     (int)ix.r, b.items, b.nitems, b.gcount, b.gstart, b.order, T, epsq);
+  if (b.max_items[LIST_ALL] <= 0) return;
+  if (b.lists.tile[LIST_ALL] != TILE) throw ArgError{HNTL_EDEVICE, "projection tile mismatch"};
+  if ((ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0)
+    launch_project_v<true>(ix, Q, P, b, T, epsq, s);
+  else
+    launch_project_v<false>(ix, Q, P, b, T, epsq, s);
   HIP_TRY(hipGetLastError());
 }
 

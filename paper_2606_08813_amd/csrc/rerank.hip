@@ -5,8 +5,9 @@
 //      smallest (D, id) over the union of the probed grains.  This is exact
 //      because the global top-C is contained in the union of per-grain top-Cs.
 //   2. all waves gather the raw float32 rows of the pool (HBM-resident copy of
-//      the corpus) and compute ||q - x||^2 by direct differences in FP32,
-//      16-byte loads, one row per wave at a time.
+//      the corpus) and compute ||q - x||^2 by direct differences in FP32:
+//      16-byte non-temporal loads (each row is used once), two rows per wave
+//      at a time (measured faster than one or four on MI355X).
 //   3. wave 0 keeps the k smallest (distance, id).
 #include "hntl_device.h"
 #include "hntl_internal.h"
@@ -15,7 +16,7 @@ namespace hntl {
 
 namespace {
 
-template <int CAP>
+template <int CAP, int RR, bool NT>
 __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restrict__ Q, int d, int P, int C, int k,
                                                            int G, int64_t N, const int32_t* __restrict__ probes,
                                                            const uint64_t* __restrict__ part,
@@ -30,7 +31,27 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   const int64_t q = blockIdx.x;
 
   if (pool_in == nullptr) {
-    if (wave == 0) {
+    if constexpr (CAP == 64) {
+      if (wave == 0) {
+        WaveTop64 L;
+        L.init(lst, C);
+        const uint64_t* src = part + (size_t)q * P * C;
+        for (int s = 0; s < P; ++s) {
+          const int g = probes[q * P + s];
+          if (g < 0 || g >= G) continue;                 // invalid probe: its list was never written
+          if (src[(size_t)s * C] == KEY_NONE) continue;  // empty (or pruned) list
+          const uint64_t key = lane < C ? src[(size_t)s * C + lane] : KEY_NONE;
+          L.offer(key, key != KEY_NONE);
+        }
+        L.finish();
+        if (lane < C) {
+          const int32_t id = L.best == KEY_NONE ? -1 : (int32_t)key_id(L.best);
+          pool[lane] = id;
+          if (pool_out) pool_out[q * C + lane] = id;
+          if (pool_D_out) pool_D_out[q * C + lane] = L.best == KEY_NONE ? __builtin_inff() : key_dist(L.best);
+        }
+      }
+    } else if (wave == 0) {
       WaveTopC<CAP> L;
       L.init(lst, C);
       const uint64_t* src = part + (size_t)q * P * C;
@@ -38,6 +59,9 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         const int g = probes[q * P + s];
         if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
         for (int c0 = 0; c0 < C; c0 += HNTL_WAVE) {
+          // lists are ascending with KEY_NONE padding (a pruned grain's list
+          // holds a single KEY_NONE): stop at the first padding key
+          if (src[(size_t)s * C + c0] == KEY_NONE) break;
           const int c = c0 + lane;
           const uint64_t key = c < C ? src[(size_t)s * C + c] : KEY_NONE;
           L.offer(key, key != KEY_NONE);
@@ -60,36 +84,74 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   }
   __syncthreads();
 
+  // each wave gathers RR pool rows at a time
   const float* qv = Q + (size_t)q * d;
-  for (int c = wave; c < C; c += 4) {
-    const int32_t id = pool[c];
-    if (id < 0) {
-      if (lane == 0) delta[c] = __builtin_inff();
-      continue;
+  for (int c0 = wave * RR; c0 < C; c0 += 4 * RR) {
+    int32_t id[RR];
+    const float* x[RR];
+    float acc[RR];
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      id[u] = c0 + u < C ? pool[c0 + u] : -1;
+      x[u] = X + (size_t)(id[u] < 0 ? 0 : id[u]) * d;
+      acc[u] = 0.f;
     }
-    const float* x = X + (size_t)id * d;
-    float acc = 0.f;
     if (vec4) {
       for (int j = lane * 4; j < d; j += 4 * HNTL_WAVE) {
-        const float4 a = *reinterpret_cast<const float4*>(x + j);
         const float4 b = *reinterpret_cast<const float4*>(qv + j);
-        const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-        acc = fmaf(d0, d0, acc);
-        acc = fmaf(d1, d1, acc);
-        acc = fmaf(d2, d2, acc);
-        acc = fmaf(d3, d3, acc);
+        float4 a[RR];
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+          if (id[u] < 0) {
+            a[u] = b;
+          } else if (NT) {
+            const float4* src = reinterpret_cast<const float4*>(x[u] + j);
+            a[u] = make_float4(__builtin_nontemporal_load(&src->x), __builtin_nontemporal_load(&src->y),
+                               __builtin_nontemporal_load(&src->z), __builtin_nontemporal_load(&src->w));
+          } else {
+            a[u] = *reinterpret_cast<const float4*>(x[u] + j);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+          const float d0 = a[u].x - b.x, d1 = a[u].y - b.y, d2 = a[u].z - b.z, d3 = a[u].w - b.w;
+          acc[u] = fmaf(d0, d0, acc[u]);
+          acc[u] = fmaf(d1, d1, acc[u]);
+          acc[u] = fmaf(d2, d2, acc[u]);
+          acc[u] = fmaf(d3, d3, acc[u]);
+        }
       }
     } else {
       for (int j = lane; j < d; j += HNTL_WAVE) {
-        const float df = x[j] - qv[j];
-        acc = fmaf(df, df, acc);
+        const float b = qv[j];
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+          const float df = id[u] >= 0 ? x[u][j] - b : 0.f;
+          acc[u] = fmaf(df, df, acc[u]);
+        }
       }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) delta[c] = acc;
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+      const float t = wave_sum(acc[u]);
+      if (lane == 0 && c0 + u < C) delta[c0 + u] = id[u] >= 0 ? t : __builtin_inff();
+    }
   }
   __syncthreads();
 
+  if constexpr (CAP == 64) {
+    if (wave == 0) {
+      // top k of at most 64 exact distances: one bitonic sort across the lanes
+      const bool ok = lane < C && pool[lane] >= 0;
+      uint64_t key = ok ? make_key(delta[lane], (uint32_t)pool[lane]) : KEY_NONE;
+      key = wave_sort64(key);
+      if (lane < k) {
+        ids[q * k + lane] = key == KEY_NONE ? -1 : (int32_t)key_id(key);
+        dist[q * k + lane] = key == KEY_NONE ? __builtin_inff() : key_dist(key);
+      }
+    }
+    return;
+  }
   if (wave == 0) {
     WaveTopC<CAP> L;
     L.init(lst, k);
@@ -119,7 +181,7 @@ void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int
   const int cap = pow2_at_least(C < 64 ? 64 : C);
   dim3 grid((unsigned)nq);
 #define HNTL_MR(CAPV)                                                                                             \
-  hipLaunchKernelGGL(merge_rerank_kernel<CAPV>, grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
+  hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 2, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
                      (int64_t)ix.N, probes, part, pool_in, ix.X,                                                  \
                      pool_out, pool_D_out, ids, dist, vec4)
   if (cap == 64)

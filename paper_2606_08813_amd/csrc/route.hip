@@ -205,18 +205,29 @@ __global__ __launch_bounds__(256) void argmin_rows_kernel(const float* __restric
 // distances carry direct-difference accuracy; the FP32 expansion error (about
 // 1e-4 relative at these magnitudes) is far below the gap that 16 extra ranks
 // open between the P-th and M-th centroid.
-template <int CAP>
+// Expansion error bound used to decide which shortlist entries can still
+// reach the top P: ERR * (||a||^2 + ||b||^2) is several times the FP32
+// rounding error of a 768-term dot product at these magnitudes.
+constexpr float ERR = 5e-5f;
+
+// Top-P per row, shortlist of M <= 64 held in registers (lane j = j-th entry).
+// Without A/Bm: the P smallest entries of D.  With them (routing): the
+// shortlist entries that can still reach the top P are re-scored by direct
+// differences ||a - b||^2 in FP32 and the P smallest exact distances are kept,
+// so probe order and reported distances carry direct-difference accuracy.
 __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
                                                         int M, const float* __restrict__ A,
-                                                        const float* __restrict__ Bm, int d,
+                                                        const float* __restrict__ an,
+                                                        const float* __restrict__ Bm,
+                                                        const float* __restrict__ bn, int d,
                                                         int32_t* __restrict__ idx, float* __restrict__ val) {
-  __shared__ uint64_t lists[4][2 * CAP];
+  __shared__ uint64_t stage[4][64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= rows) return;
-  WaveTopC<CAP> L;
   const bool exact = A != nullptr;
-  L.init(lists[wave], exact ? M : P);
+  WaveTop64 L;
+  L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
   for (int c0 = 0; c0 < cols; c0 += HNTL_WAVE) {
     const int c = c0 + lane;
@@ -225,49 +236,53 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
     L.offer(make_key(v, (uint32_t)c), ok);
   }
   L.finish();
-  if (exact) {
-    // re-score the shortlist exactly, then sort it by (exact distance, column)
-    const float* a = A + row * d;
-    constexpr int RB = 8;  // shortlist entries re-scored together
-    for (int j0 = 0; j0 < M; j0 += RB) {
-      int cs[RB];
-      const float* bp[RB];
-      float acc[RB];
-#pragma unroll
-      for (int u = 0; u < RB; ++u) {
-        cs[u] = j0 + u < M ? (int)key_id(L.best[j0 + u]) : (int)key_id(L.best[j0]);
-        bp[u] = Bm + (size_t)cs[u] * d;
-        acc[u] = 0.f;
-      }
-      for (int t = lane; t < d; t += HNTL_WAVE) {
-        const float av = a[t];
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-          const float df = av - bp[u][t];
-          acc[u] = fmaf(df, df, acc[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < RB; ++u) {
-        const float tot = wave_sum(acc[u]);
-        if (lane == 0 && j0 + u < M) L.stage[j0 + u] = make_key(tot, (uint32_t)cs[u]);
-      }
-    }
-    wave_sync();
-    for (int j = M + lane; j < CAP; j += HNTL_WAVE) L.stage[j] = KEY_NONE;
-    wave_sync();
-    L.sort_stage();
-    for (int j = lane; j < P; j += HNTL_WAVE) {
-      const uint64_t kk = L.stage[j];
-      idx[row * P + j] = (int32_t)key_id(kk);
-      if (val) val[row * P + j] = key_dist(kk);
+  if (!exact) {
+    if (lane < P) {
+      idx[row * P + lane] = L.best == KEY_NONE ? -1 : (int32_t)key_id(L.best);
+      if (val) val[row * P + lane] = L.best == KEY_NONE ? __builtin_inff() : key_dist(L.best);
     }
     return;
   }
-  for (int j = lane; j < P; j += HNTL_WAVE) {
-    const uint64_t kk = L.best[j];
-    idx[row * P + j] = kk == KEY_NONE ? -1 : (int32_t)key_id(kk);
-    if (val) val[row * P + j] = kk == KEY_NONE ? __builtin_inff() : key_dist(kk);
+  // entries j >= P qualify while expansion(j) - bound(j) <= expansion(P-1) + bound(P-1)
+  const float arow = an[row];
+  const uint64_t mine = L.best;
+  const uint64_t kp = shfl_u64(mine, P - 1);
+  const float hiP = key_dist(kp) + ERR * (arow + bn[key_id(kp)]);
+  const bool in = lane >= P && lane < M && key_dist(mine) - ERR * (arow + bn[key_id(mine)]) <= hiP;
+  const uint64_t qual = __ballot(in);
+  const int Mr = qual ? 64 - __clzll(qual) : P;  // re-score the prefix [0, Mr)
+  const float* a = A + row * d;
+  constexpr int RB = 8;  // shortlist entries re-scored together
+  uint64_t ex = KEY_NONE;
+  for (int j0 = 0; j0 < Mr; j0 += RB) {
+    int cs[RB];
+    const float* bp[RB];
+    float acc[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int j = j0 + u < Mr ? j0 + u : j0;
+      cs[u] = (int)key_id(shfl_u64(mine, j));
+      bp[u] = Bm + (size_t)cs[u] * d;
+      acc[u] = 0.f;
+    }
+    for (int t = lane; t < d; t += HNTL_WAVE) {
+      const float av = a[t];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const float df = av - bp[u][t];
+        acc[u] = fmaf(df, df, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const float tot = wave_sum(acc[u]);
+      if (lane == j0 + u && lane < Mr) ex = make_key(tot, (uint32_t)cs[u]);
+    }
+  }
+  ex = wave_sort64(ex);
+  if (lane < P) {
+    idx[row * P + lane] = (int32_t)key_id(ex);
+    if (val) val[row * P + lane] = key_dist(ex);
   }
 }
 
@@ -298,14 +313,12 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 }
 
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
-                      const float* A, const float* Bm, int d) {
+                      const float* A, const float* an, const float* Bm, const float* bn, int d) {
   if (rows <= 0) return;
+  if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + 3) / 4));
   const int M = A ? std::min(cols, P + 16) : P;
-  if (M <= 64)
-    hipLaunchKernelGGL(topk_rows_kernel<64>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, Bm, d, idx, val);
-  else
-    hipLaunchKernelGGL(topk_rows_kernel<128>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, Bm, d, idx, val);
+  hipLaunchKernelGGL(topk_rows_kernel, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val);
   HIP_TRY(hipGetLastError());
 }
 

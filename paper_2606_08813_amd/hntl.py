@@ -19,9 +19,9 @@ LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 
 HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
-HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE = 1, 2, 4
+HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE = 1, 2, 4, 8
 STAGES = ("route", "bucket", "project", "scan", "rerank")
-HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 64, 64
+HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 48, 64
 CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3}
 
 
@@ -64,7 +64,7 @@ EXPORTS = {
                               C.c_void_p, C.c_void_p]),
     "hntl_search_stages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params)]
                            + [C.c_void_p] * 13),
-    "hntl_profile_read": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "hntl_profile_read": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "hntl_last_error": (C.c_char_p, []),
     "hntl_version": (C.c_char_p, []),
 }
@@ -232,11 +232,13 @@ def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0,
 
 
 def hntl_profile_read():
-    """Summed per-stage milliseconds of profiled searches since the last read, and their count."""
+    """Summed per-stage milliseconds of profiled searches since the last read, their
+    count, and the number of eq. 6 scores they computed."""
     ms = np.zeros(len(STAGES), np.float64)
     calls = C.c_uint32(0)
-    _check(lib().hntl_profile_read(ms.ctypes.data, len(STAGES), C.byref(calls)))
-    return dict(zip(STAGES, ms.tolist())), calls.value
+    scored = C.c_uint64(0)
+    _check(lib().hntl_profile_read(ms.ctypes.data, len(STAGES), C.byref(calls), C.byref(scored)))
+    return dict(zip(STAGES, ms.tolist())), calls.value, scored.value
 
 
 def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=HNTL_FLAG_SYNC,

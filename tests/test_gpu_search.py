@@ -180,3 +180,22 @@ def test_export_roundtrip(small):
     ex = hntl.hntl_index_export(small["ix"])
     for key in ("centroids", "basis", "offsets", "perm", "codes", "eps"):
         np.testing.assert_array_equal(ex[key], small["stored"][key].astype(ex[key].dtype), err_msg=key)
+
+
+def test_pruned_scan_equals_full_scan(small):
+    """The slot-0 bound and the grain lower-bound pruning change no pool entry
+    and no result (bitwise), and scan strictly fewer members."""
+    announce("pruned vs full scan, 1000 queries")
+    W, hntl, torch = small["W"], small["hntl"], small["torch"]
+    for P, C in ((W.P, W.C), (8, 64), (16, 100)):
+        a = hntl.hntl_search_stages(small["ix"], small["Qd"], P, C, W.k,
+                                    flags=hntl.HNTL_FLAG_SYNC | hntl.HNTL_FLAG_PROFILE)
+        _, _, scored_a = hntl.hntl_profile_read()
+        b = hntl.hntl_search_stages(small["ix"], small["Qd"], P, C, W.k,
+                                    flags=hntl.HNTL_FLAG_SYNC | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_PROFILE)
+        _, _, scored_b = hntl.hntl_profile_read()
+        for key in ("pool_ids", "pool_D", "ids", "dist"):
+            assert torch.equal(a[key], b[key]), (P, C, key)
+        sizes = np.diff(small["stored"]["offsets"])
+        assert scored_b == int(sizes[b["probes"].cpu().numpy()].sum())
+        assert scored_a < scored_b
