@@ -29,6 +29,7 @@ METRIC = "queries/sec and ns/vector scanned at Recall@10≥0.95; scan HBM GB/s v
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP32_VALU_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -46,6 +47,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=400, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-stage HIP event records")
     ap.add_argument("--no-prune", action="store_true", help="scan every member of every probed grain")
+    ap.add_argument("--fp32-project", action="store_true",
+                    help="with --codes bf16/fp8, keep the FP32 projection (default: BF16 MFMA projection)")
+    ap.add_argument("--error-sample", type=int, default=100,
+                    help="queries for the reduced-precision error report against the FP64 oracle")
     return ap.parse_args()
 
 
@@ -86,6 +91,9 @@ def main():
     flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
     if args.no_prune:
         flags |= hntl.HNTL_FLAG_NO_PRUNE
+    bf16_project = args.codes != "fp32" and not args.fp32_project
+    if bf16_project:
+        flags |= hntl.HNTL_FLAG_PROJECT_BF16
     for _ in range(args.warmup):
         hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, flags=flags & ~hntl.HNTL_FLAG_PROFILE,
                          out=(ids, dist))
@@ -110,7 +118,8 @@ def main():
         f"{qps:,.0f} queries/s; stages {stage_avg}")
 
     # work accounting from one staged run (probes -> vectors scanned per step)
-    o = hntl.hntl_search_stages(ix, Q, W.P, W.C, W.k, codes=args.codes)
+    o = hntl.hntl_search_stages(ix, Q, W.P, W.C, W.k, codes=args.codes,
+                                flags=hntl.HNTL_FLAG_SYNC | (flags & hntl.HNTL_FLAG_PROJECT_BF16))
     probes = o["probes"].cpu().numpy()
     ex = hntl.hntl_index_export(ix)
     sizes = np.diff(ex["offsets"])
@@ -125,13 +134,45 @@ def main():
     recall = osr.recall(ids_h[rs], gt, W.k)
     log(f"[bench] Recall@10 on {len(rs)} sampled queries: {recall:.4f} (brute force {time.time() - t0:.1f}s)")
 
+    # reduced-precision error report against the FP64 oracle (eq. 6 scores of
+    # the GPU's pool entries and final distances, on a query sample)
+    precision = None
+    if args.codes != "fp32" and args.error_sample > 0:
+        es = np.random.default_rng(13).choice(W.nq, size=min(args.error_sample, W.nq), replace=False)
+        probes_s = probes[es]
+        zq64, eq64 = osr.project(queries.X[es], probes_s, ex)
+        pool_ids = o["pool_ids"].cpu().numpy()[es]
+        pool_D = o["pool_D"].cpu().numpy()[es].astype(np.float64)
+        rel = []
+        for i in range(len(es)):
+            m = {}
+            for sl in range(W.P):
+                gi, gd = osr.grain_scores(zq64[i, sl], eq64[i, sl], int(probes_s[i, sl]), ex)
+                m.update(zip(gi.tolist(), gd.tolist()))
+            for pid, pd in zip(pool_ids[i], pool_D[i]):
+                if pid >= 0:
+                    ref = m[int(pid)]
+                    rel.append(abs(pd - ref) / max(ref, 1e-12))
+        rel = np.array(rel)
+        fd = dist.cpu().numpy()[es].astype(np.float64)
+        fi = ids_h[es]
+        exact = ((corpus.X[fi].astype(np.float64) - queries.X[es][:, None, :].astype(np.float64)) ** 2).sum(-1)
+        frel = np.abs(fd - exact) / np.maximum(exact, 1e-12)
+        precision = {"codes": args.codes, "projection": "bf16" if bf16_project else "fp32",
+                     "sample_queries": len(es),
+                     "scan_score_rel_err_vs_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                                    "max": float(rel.max())},
+                     "final_dist_rel_err_vs_fp64": {"median": float(np.median(frel)), "max": float(frel.max())}}
+        log(f"[bench] precision report: {precision}")
+
     # rooflines per stage (algorithmic work per launch / average stage time)
     npairs = W.nq * W.P
     rp = (W.r + 7) // 8 * 8
     code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1}[args.codes]
     per_stage = {
         "route": dict(bound="mfma", work=2.0 * W.nq * W.G * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
-        "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
+        "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s",
+                        peak=BF16_MFMA_PEAK_TFLOPS if bf16_project else FP32_MFMA_PEAK_TFLOPS),
         "scan": dict(bound="alu", work=3.0 * W.r * (scored or scanned), unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
         "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * W.P * W.C * 8, unit="GB/s",
                        peak=HBM_PEAK_GBS),
@@ -178,7 +219,8 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.codes],
         "data": "synthetic",
         "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
-                   "P": W.P, "C": W.C, "k": W.k, "codes": args.codes},
+                   "P": W.P, "C": W.C, "k": W.k, "codes": args.codes,
+                   "projection": "bf16" if bf16_project else "fp32"},
         "recall_at_10": round(recall, 4),
         "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
         "scan_ns_per_vector_scored": round(scan_ms * 1e6 / scored, 5) if (scan_ms and scored) else None,
@@ -192,6 +234,7 @@ def main():
         "roofline": dict(roof.get(dominant, {}), kernel=dominant, traffic=None) if dominant else None,
         "stage_rooflines": roof,
         "cpu_baseline": cpu,
+        "precision": precision,
     }
     print(json.dumps(out), flush=True)
 

@@ -73,6 +73,9 @@ typedef enum hntl_codes {
 #define HNTL_FLAG_CHECK_Q 2u    /* reject non-finite query values with HNTL_EINVAL (implies a sync) */
 #define HNTL_FLAG_PROFILE 4u    /* record HIP events around each stage on the call's stream (see hntl_profile_read) */
 #define HNTL_FLAG_NO_PRUNE 8u   /* scan every member of every probed grain (see below) */
+#define HNTL_FLAG_PROJECT_BF16 16u /* projection on BF16 MFMA: q - mu_g (FP32) and W_g rounded to BF16 (nearest
+                                      even), FP32 accumulation; eps_q stays FP32.  Needs an index with a
+                                      reduced-precision code form (the BF16 bases are built with it) and d % 8 == 0 */
 /*
  * Exact pruning.  By default the nearest probed grain of each query is scanned
  * first; its C-th best (D, id) key then bounds the other probed grains: their
@@ -142,6 +145,15 @@ hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, co
  */
 hntl_status hntl_index_export(const hntl_index* index, float* centroids, float* basis, int64_t* offsets,
                               int32_t* perm, float* codes, float* eps, float* scales);
+
+/*
+ * hntl_index_export_codes - the reduced-precision codes of an index, unpacked to
+ * N x r in grain order: uint16 BF16 bit patterns (codes = HNTL_CODES_BF16) or
+ * uint8 E4M3fn bit patterns (codes = HNTL_CODES_FP8_E4M3, value = code * scales[g]).
+ * out and scales (G floats, FP8 only) are host or device and may be NULL.
+ * Errors: EINVAL (FP32 requested), ESTATE (form not built).  Synchronous.
+ */
+hntl_status hntl_index_export_codes(const hntl_index* index, uint32_t codes, void* out, float* scales);
 
 typedef struct hntl_index_info {
   uint64_t N;

@@ -46,7 +46,7 @@ def fp8_e4m3_round(x) -> np.ndarray:
     q = np.rint(a / quantum) * quantum
     out = np.where(nz, q, 0.0)
     out = np.minimum(out, FP8_MAX)
-    return s * out
+    return np.copysign(out, v)  # the sign survives rounding to zero
 
 
 def fp8_e4m3_values() -> np.ndarray:
@@ -66,7 +66,8 @@ def fp8_e4m3_values() -> np.ndarray:
 def fp8_encode_byte(x) -> np.ndarray:
     """E4M3fn bit pattern (uint8) of already-rounded values."""
     v = np.asarray(x, dtype=np.float64)
-    sign = (v < 0).astype(np.uint8) << 7
+    # rounding keeps the sign: a negative value that rounds to zero is -0 (0x80)
+    sign = np.signbit(v).astype(np.uint8) << 7
     a = np.abs(v)
     out = np.zeros(a.shape, dtype=np.uint8)
     sub = a < 2.0 ** -6
@@ -88,13 +89,47 @@ def fp8_decode_byte(b) -> np.ndarray:
 
 
 def grain_fp8_scales(codes: np.ndarray, offsets: np.ndarray) -> np.ndarray:
-    """Per-grain FP32 scale amax/448 (1.0 for an empty or all-zero grain)."""
+    """Per-grain FP32 scale amax/448 computed as a float32 division (1.0 for an
+    empty or all-zero grain)."""
     G = len(offsets) - 1
     sc = np.ones(G, dtype=np.float32)
     for g in range(G):
         a, b = int(offsets[g]), int(offsets[g + 1])
         if b > a:
-            amax = float(np.abs(codes[a:b]).max())
+            amax = np.abs(np.asarray(codes[a:b], dtype=np.float32)).max()
             if amax > 0:
-                sc[g] = np.float32(amax / FP8_MAX)
+                sc[g] = np.float32(amax) / np.float32(FP8_MAX)
     return sc
+
+
+def fp8_grain_codes(codes: np.ndarray, offsets: np.ndarray):
+    """FP8 code values (float64, exact E4M3fn values) of z / s_g with the
+    quotient formed in float32, and the scales."""
+    z = np.asarray(codes, dtype=np.float32)
+    sc = grain_fp8_scales(z, offsets)
+    out = np.zeros(z.shape, dtype=np.float64)
+    for g in range(len(offsets) - 1):
+        a, b = int(offsets[g]), int(offsets[g + 1])
+        if b > a:
+            out[a:b] = fp8_e4m3_round(z[a:b] / sc[g])
+    return out, sc
+
+
+def decoded_codes(codes: np.ndarray, offsets: np.ndarray, form: str) -> np.ndarray:
+    """The code values a scan of the given form reads, as float64:
+    fp32 - the stored values; bf16 - their BF16 rounding; fp8 - the float32
+    product fl32(e4m3(z / s_g) * s_g)."""
+    z = np.asarray(codes, dtype=np.float32)
+    if form == "fp32":
+        return z.astype(np.float64)
+    if form == "bf16":
+        return bf16_round(z).astype(np.float64)
+    if form == "fp8":
+        c, sc = fp8_grain_codes(z, offsets)
+        out = np.zeros(z.shape, dtype=np.float32)
+        for g in range(len(offsets) - 1):
+            a, b = int(offsets[g]), int(offsets[g + 1])
+            if b > a:
+                out[a:b] = c[a:b].astype(np.float32) * sc[g]
+        return out.astype(np.float64)
+    raise ValueError(form)

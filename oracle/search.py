@@ -20,13 +20,23 @@ can be checked on its own.  The quantisation envelope filter of Section 2.3
 prunes grains whose int16 query coordinates saturate; float32 query
 coordinates never saturate, so it is the identity here.
 
+Reduced-precision form: the scan reads BF16 or FP8 (per-grain scale) code
+values and the projection may run on BF16 inputs; ``project(bf16=True)`` and
+``scan_pool(form=...)`` emulate those rounding points exactly and sum in
+float64.
+
 Parity: pinned by brute force on tiny inputs (P = G and C = N give the exact
 k-NN), by the r = d identity (scan score equals the exact distance), and by
-the isotropic rows of the paper's recall table.
+the isotropic rows of the paper's recall table.  The reduced-precision
+emulation is pinned by the format tests of ``quant`` and by the identity that
+BF16 / FP8 scans of codes that are already exactly representable equal the
+FP32 scan.
 """
 from __future__ import annotations
 
 import numpy as np
+
+from . import quant
 
 INF = np.inf
 
@@ -57,10 +67,18 @@ def route(Q: np.ndarray, centroids: np.ndarray, P: int):
     return probes, pdist
 
 
-def project(Q: np.ndarray, probes: np.ndarray, stored: dict):
-    """Tangent coordinates z_q (nq, P, r) and residual energies eps_q (nq, P)."""
-    Q = np.asarray(Q, dtype=np.float64)
+def project(Q: np.ndarray, probes: np.ndarray, stored: dict, bf16: bool = False):
+    """Tangent coordinates z_q (nq, P, r) and residual energies eps_q (nq, P).
+
+    bf16=True emulates the reduced-precision projection: q' = q - mu_g formed in
+    float32, q' and W_g rounded to BF16 (nearest even), products summed in
+    float64 (exact BF16 products, so only summation order differs from an FP32
+    accumulator), and eps_q = max(0, ||q'||^2 - ||z_q||^2) with the unrounded q'.
+    """
+    Q32 = np.asarray(Q, dtype=np.float32)
+    Q = Q32.astype(np.float64)
     M = stored["centroids"].astype(np.float64)
+    M32 = stored["centroids"].astype(np.float32)
     B = stored["basis"]
     nq, P = probes.shape
     r = B.shape[1]
@@ -71,6 +89,14 @@ def project(Q: np.ndarray, probes: np.ndarray, stored: dict):
             g = int(probes[i, s])
             if g < 0:
                 continue
+            if bf16:
+                qp32 = Q32[i] - M32[g]                                   # eq. (1) in float32
+                Wb = quant.bf16_round(B[g]).astype(np.float64)           # (r, d)
+                z = Wb @ quant.bf16_round(qp32).astype(np.float64)       # eq. (2)
+                qn = float((qp32.astype(np.float64) ** 2).sum())
+                zq[i, s] = z
+                epsq[i, s] = max(0.0, qn - float(z @ z))                 # eq. (3)-(4), Pythagoras
+                continue
             W = B[g].astype(np.float64).T          # (d, r)
             qp = Q[i] - M[g]                       # eq. (1)
             z = W.T @ qp                           # eq. (2)
@@ -80,17 +106,20 @@ def project(Q: np.ndarray, probes: np.ndarray, stored: dict):
     return zq, epsq
 
 
-def grain_scores(zq: np.ndarray, epsq: float, g: int, stored: dict):
-    """eq. (6) for every member of grain g: returns (original ids, D)."""
+def grain_scores(zq: np.ndarray, epsq: float, g: int, stored: dict, codes=None):
+    """eq. (6) for every member of grain g: returns (original ids, D).  `codes`
+    optionally replaces the stored codes (decoded reduced-precision values)."""
     a, b = int(stored["offsets"][g]), int(stored["offsets"][g + 1])
-    Z = stored["codes"][a:b].astype(np.float64)
+    Z = (stored["codes"] if codes is None else codes)[a:b].astype(np.float64)
     ei = stored["eps"][a:b].astype(np.float64)
     D = ((zq[None, :] - Z) ** 2).sum(axis=1) + epsq + ei
     return stored["perm"][a:b].astype(np.int64), D
 
 
-def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict, C: int):
-    """Candidate pool (nq, C) ids and scores over the union of the probed grains."""
+def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict, C: int, form: str = "fp32"):
+    """Candidate pool (nq, C) ids and scores over the union of the probed grains,
+    scanning the code values of the given form (fp32, bf16, fp8)."""
+    codes = None if form == "fp32" else quant.decoded_codes(stored["codes"], stored["offsets"], form)
     nq, P = probes.shape
     pool_ids = np.full((nq, C), -1, dtype=np.int64)
     pool_D = np.full((nq, C), INF)
@@ -100,7 +129,7 @@ def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict
             g = int(probes[i, s])
             if g < 0:
                 continue
-            gi, gd = grain_scores(zq[i, s], epsq[i, s], g, stored)
+            gi, gd = grain_scores(zq[i, s], epsq[i, s], g, stored, codes)
             ids.append(gi)
             Ds.append(gd)
         if ids:
@@ -125,7 +154,7 @@ def rerank(Q: np.ndarray, pool_ids: np.ndarray, X: np.ndarray, k: int):
 
 
 def search(Q, stored: dict, X, P: int, C: int, k: int, probes=None, zq=None, epsq=None,
-           pool_ids=None):
+           pool_ids=None, form: str = "fp32", bf16_project: bool = False):
     """The whole lifecycle; any stage's input may be supplied to check later stages."""
     G = stored["centroids"].shape[0]
     if not (1 <= P <= G) or k < 1 or C < k:
@@ -136,10 +165,10 @@ def search(Q, stored: dict, X, P: int, C: int, k: int, probes=None, zq=None, eps
         out["pdist"] = pdist
     out["probes"] = probes
     if zq is None or epsq is None:
-        zq, epsq = project(Q, probes, stored)
+        zq, epsq = project(Q, probes, stored, bf16=bf16_project)
     out["zq"], out["epsq"] = zq, epsq
     if pool_ids is None:
-        pool_ids, pool_D = scan_pool(zq, epsq, probes, stored, C)
+        pool_ids, pool_D = scan_pool(zq, epsq, probes, stored, C, form)
         out["pool_D"] = pool_D
     out["pool_ids"] = pool_ids
     out["ids"], out["dist"] = rerank(Q, pool_ids, X, k)

@@ -301,6 +301,38 @@ hntl_status hntl_index_export(const hntl_index* index, float* centroids, float* 
   });
 }
 
+hntl_status hntl_index_export_codes(const hntl_index* index, uint32_t codes, void* out, float* scales) {
+  g_last_error.clear();
+  if (!index) return fail(HNTL_EINVAL, "index is NULL");
+  const Index& ix = index->ix;
+  if (codes != HNTL_CODES_BF16 && codes != HNTL_CODES_FP8_E4M3) return fail(HNTL_EINVAL, "codes must be BF16 or FP8");
+  if (!(ix.codes_mask & (1u << codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
+  return guarded([&] {
+    const uint32_t G = ix.G, r = ix.r, rp = ix.rp;
+    if (scales && codes == HNTL_CODES_FP8_E4M3)
+      HIP_TRY(hipMemcpy(scales, ix.scales, sizeof(float) * G, hipMemcpyDefault));
+    if (!out) return;
+    const int per = codes == HNTL_CODES_BF16 ? 2 : 4;  // values per 32-bit word
+    auto words = to_host(codes == HNTL_CODES_BF16 ? ix.codes_bf16 : ix.codes_fp8, (size_t)ix.nblocks * (rp / per) * B);
+    const size_t esz = codes == HNTL_CODES_BF16 ? 2 : 1;
+    std::vector<uint8_t> o((size_t)ix.N * r * esz);
+    for (uint32_t g = 0; g < G; ++g) {
+      const int64_t a = ix.offsets_h[g], n = ix.offsets_h[g + 1] - a;
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t blkid = ix.boff_h[g] + i / B, lane = i % B;
+        for (uint32_t j = 0; j < r; ++j) {
+          const uint32_t w = words[((size_t)blkid * (rp / per) + j / per) * B + lane];
+          const uint32_t v = (w >> ((j % per) * (32 / per))) & (per == 2 ? 0xFFFFu : 0xFFu);
+          const size_t at = ((size_t)(a + i) * r + j) * esz;
+          o[at] = (uint8_t)v;
+          if (esz == 2) o[at + 1] = (uint8_t)(v >> 8);
+        }
+      }
+    }
+    HIP_TRY(hipMemcpy(out, o.data(), o.size(), hipMemcpyDefault));
+  });
+}
+
 hntl_status hntl_index_info_get(const hntl_index* index, hntl_index_info* out) {
   g_last_error.clear();
   if (!index || !out) return fail(HNTL_EINVAL, "null pointer");
@@ -419,7 +451,7 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
         clk.at(HNTL_STAGE_PROJECT);
         float* To = tangent_out ? tangent_out : sc.get<float>((size_t)npairs * ix.r);
         float* eo = epsq_out ? epsq_out : sc.get<float>(npairs);
-        launch_project(ix, Q, (int)P, b, To, eo, s);
+        launch_project(ix, Q, (int)P, b, To, eo, (sp->flags & HNTL_FLAG_PROJECT_BF16) != 0, s);
         T = To;
         eq = eo;
       }

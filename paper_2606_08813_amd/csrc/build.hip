@@ -8,8 +8,9 @@
 //     (seeding on a few rows per grain often merges clusters)
 //   * seeding: greedy k-means++ on the device: per centroid, 16 candidates
 //     drawn by D^2 sampling, the one lowering the potential most is
-//     kept (sample / evaluate / choose / apply kernels; uniforms come from a
-//     counter-based SplitMix64 hash, so no host round trip is needed)
+//     kept (candidate distances on the MFMA distance kernel; sample /
+//     potential / choose / apply kernels; uniforms come from a counter-based
+//     SplitMix64 hash, so no host round trip is needed)
 //   * Lloyd: nearest-centroid assignment on FP32 MFMA (ties to the lower
 //     grain), centroid = FP64 mean of its members summed in a fixed order, an
 //     empty grain re-seeded with the training row farthest from its centroid
@@ -20,7 +21,7 @@
 // (delta_g = 1e-6 trace(S_g) keeps every iterate full rank without moving
 // eigenvectors) with Cholesky-QR2 re-orthonormalisation, and a final
 // Rayleigh-Ritz step (Jacobi eigensolver on the small projected matrix).  The
-// batched FP64 GEMM/SYRK/TRSM are library calls (rocBLAS), as are the batched
+// batched FP64 GEMM/TRSM are library calls (rocBLAS), as are the batched
 // Cholesky and the small Jacobi eigensolver (rocSOLVER).
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -85,39 +86,24 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, int d, const int
 // centroid; partial[blk] = sum of closest over 256-row blocks (FP64).
 constexpr int KPP_MAXL = 16;
 
-// dcand[i][t] = ||x_i - x_cand[t]||^2 and per-block potentials
-// potpart[blk][t] = sum_i min(closest[i], dcand[i][t]).
-__global__ __launch_bounds__(256) void kpp_eval_kernel(const float* __restrict__ Xs, int64_t n, int d,
-                                                       const int32_t* __restrict__ cand, int L,
-                                                       const float* __restrict__ closest, int first,
-                                                       float* __restrict__ dcand, double* __restrict__ potpart) {
+// Per-block potentials potpart[blk][t] = sum_i min(closest[i], dcand[i][t])
+// over 256-row blocks, from the candidate distances dcand (n x L, computed by
+// the MFMA distance kernel).
+__global__ __launch_bounds__(256) void kpp_pot_kernel(int64_t n, int L, const float* __restrict__ dcand,
+                                                      const float* __restrict__ closest, int first,
+                                                      double* __restrict__ potpart) {
   __shared__ double red[4][KPP_MAXL];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  double pot[KPP_MAXL];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float ci = (i < n && !first) ? closest[i] : __builtin_inff();
 #pragma unroll
-  for (int t = 0; t < KPP_MAXL; ++t) pot[t] = 0.0;
-  for (int rr = 0; rr < 64; ++rr) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + wave * 64 + rr;
-    if (i >= n) break;
-    const float* x = Xs + (size_t)i * d;
-    const float ci = first ? __builtin_inff() : closest[i];
-#pragma unroll
-    for (int t = 0; t < KPP_MAXL; ++t) {
-      if (t < L) {
-        const float* c = Xs + (size_t)cand[t] * d;
-        float acc = 0.f;
-        for (int j = lane; j < d; j += HNTL_WAVE) {
-          const float df = x[j] - c[j];
-          acc = fmaf(df, df, acc);
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) dcand[(size_t)i * L + t] = acc;
-        pot[t] += (double)fminf(ci, acc);
-      }
+  for (int t = 0; t < KPP_MAXL; ++t) {
+    if (t < L) {
+      const double v = i < n ? (double)fminf(ci, dcand[(size_t)i * L + t]) : 0.0;
+      const double w = wave_sum_d(v);
+      if (lane == 0) red[wave][t] = w;
     }
   }
-  if (lane == 0)
-    for (int t = 0; t < KPP_MAXL; ++t) red[wave][t] = pot[t];
   __syncthreads();
   if ((int)threadIdx.x < L)
     potpart[(size_t)blockIdx.x * L + threadIdx.x] =
@@ -536,16 +522,25 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       // first centroid: a uniformly drawn seeding row
       const int32_t first = (int32_t)std::min<int64_t>(n_seed - 1, (int64_t)(uh[0] * (double)n_seed));
       HIP_TRY(hipMemcpyAsync(cand, &first, sizeof(int32_t), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(kpp_eval_kernel, dim3(nblk), dim3(256), 0, s, Xt, n_seed, (int)d, cand, 1, closest, 1, dcand,
-                         potpart);
+      float* cand_rows = dev_alloc<float>(nullptr, (size_t)KPP_MAXL * d);
+      float* cand_norm = dev_alloc<float>(nullptr, KPP_MAXL);
+      tmp.p.insert(tmp.p.end(), {cand_rows, cand_norm});
+      // candidate distances on the MFMA distance kernel, then potentials
+      auto evaluate = [&](int Lc, int first_step) {
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(Lc), dim3(256), 0, s, Xt, (int)d, cand, (int64_t)Lc, cand_rows);
+        launch_row_norms(cand_rows, Lc, (int)d, cand_norm, s);
+        launch_dist_matrix(Xt, xtn, n_seed, cand_rows, cand_norm, Lc, (int)d, dcand, s);
+        hipLaunchKernelGGL(kpp_pot_kernel, dim3(nblk), dim3(256), 0, s, n_seed, Lc, dcand, closest, first_step,
+                           potpart);
+      };
+      evaluate(1, 1);
       hipLaunchKernelGGL(kpp_choose_kernel, dim3(1), dim3(64), 0, s, Xt, (int)d, cand, 1, potpart, nblk, tstar,
                          ix->centroids, 0);
       hipLaunchKernelGGL(kpp_apply_kernel, dim3(nblk), dim3(256), 0, s, n_seed, 1, dcand, tstar, 1, closest, partial);
       for (uint32_t step = 1; step < G; ++step) {
         hipLaunchKernelGGL(kpp_sample_kernel, dim3(1), dim3(64), 0, s, n_seed, closest, partial, nblk,
                            uu + (size_t)step * KPP_MAXL, L, cand);
-        hipLaunchKernelGGL(kpp_eval_kernel, dim3(nblk), dim3(256), 0, s, Xt, n_seed, (int)d, cand, L, closest, 0,
-                           dcand, potpart);
+        evaluate(L, 0);
         hipLaunchKernelGGL(kpp_choose_kernel, dim3(1), dim3(64), 0, s, Xt, (int)d, cand, L, potpart, nblk, tstar,
                            ix->centroids, (int)step);
         hipLaunchKernelGGL(kpp_apply_kernel, dim3(nblk), dim3(256), 0, s, n_seed, L, dcand, tstar, 0, closest,
@@ -688,9 +683,9 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
         const rocblas_stride sS = (rocblas_stride)d * d, sV = (rocblas_stride)d * bsz, sM = (rocblas_stride)bsz * bsz;
         auto cholqr = [&](double* Yp) {
           for (int rep = 0; rep < 2; ++rep) {
-            rb(rocblas_dsyrk_strided_batched(blas.h, rocblas_fill_upper, rocblas_operation_transpose, bsz, (int)d,
-                                             &one, Yp, (int)d, sV, &zero, M, bsz, sM, gc),
-               "dsyrk");
+            rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_transpose, rocblas_operation_none, bsz, bsz,
+                                             (int)d, &one, Yp, (int)d, sV, Yp, (int)d, sV, &zero, M, bsz, sM, gc),
+               "dgemm Y^T*Y");
             rb(rocsolver_dpotrf_strided_batched(blas.h, rocblas_fill_upper, bsz, M, bsz, sM, info, gc), "dpotrf");
             rb(rocblas_dtrsm_strided_batched(blas.h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                                              rocblas_diagonal_non_unit, (int)d, bsz, &one, M, bsz, sM, Yp, (int)d, sV,

@@ -39,8 +39,8 @@ struct Index {
   int32_t* perm = nullptr;     // N
   float* codes = nullptr;      // nblocks x rp x B
   float* eps = nullptr;        // nblocks x B
-  uint16_t* codes_bf16 = nullptr;  // nblocks x rp x B (bf16 bits)
-  uint8_t* codes_fp8 = nullptr;    // nblocks x rp x B (e4m3fn bits)
+  uint32_t* codes_bf16 = nullptr;  // nblocks x (rp / 2) x B words, 2 bf16 per word
+  uint32_t* codes_fp8 = nullptr;   // nblocks x (rp / 4) x B words, 4 e4m3fn per word
   float* scales = nullptr;         // G fp8 scales
   uint16_t* basis_bf16 = nullptr;  // G x r x d (bf16 bits)
   float* X = nullptr;          // N x d, original row order
@@ -141,7 +141,7 @@ struct Buckets {
 };
 void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s);
 
-void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
                     hipStream_t s);  // over LIST_ALL
 // Scan of the bucketed pairs.  With `bound_lists` (the lists of probe slot 0,
 // already written into part), each pair starts from its query's C-th key of

@@ -2,6 +2,11 @@
 // E4M3 codes with one FP32 scale per grain, derived from the FP32 Block-SoA
 // codes; plus a BF16 copy of the bases for the BF16 projection.
 //
+// Packed Block-SoA layouts (one 32-bit word per lane and row, so that a row
+// of a block is still one coalesced 256-byte load):
+//   BF16: word[blk][j2][lane] holds dims 2 j2 (low half) and 2 j2 + 1 (high half)
+//   FP8:  word[blk][j4][lane] holds dims 4 j4 + i in byte i
+//
 // BF16: round-to-nearest-even of the FP32 bit pattern (drop 16 mantissa bits).
 // FP8 E4M3 "fn" (OCP 8-bit float specification): bias 7, 3 mantissa bits,
 // largest finite 448, no infinities.  Code = e4m3(z / s_g) rounded to nearest
@@ -50,6 +55,19 @@ __global__ void bf16_kernel(const float* __restrict__ in, int64_t n, uint16_t* _
   if (i < n) out[i] = f32_to_bf16_rne(in[i]);
 }
 
+// codes [blk][rp][64] f32 -> words [blk][rp / 2][64]
+__global__ void bf16_pack_kernel(const float* __restrict__ codes, int rp, int64_t nblocks,
+                                 uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // word index
+  const int64_t per = (int64_t)(rp / 2) * B;
+  if (i >= nblocks * per) return;
+  const int64_t blk = i / per, rem = i % per, j2 = rem / B, lane = rem % B;
+  const float* c = codes + (size_t)blk * rp * B;
+  const uint32_t lo = f32_to_bf16_rne(c[(2 * j2) * B + lane]);
+  const uint32_t hi = f32_to_bf16_rne(c[(2 * j2 + 1) * B + lane]);
+  out[i] = lo | (hi << 16);
+}
+
 // one workgroup per grain: amax over valid members and j < r
 __global__ __launch_bounds__(256) void grain_scale_kernel(const float* __restrict__ codes, int rp, int r,
                                                           const int32_t* __restrict__ goff,
@@ -72,27 +90,35 @@ __global__ __launch_bounds__(256) void grain_scale_kernel(const float* __restric
   if (threadIdx.x == 0) scales[g] = red[0] > 0.f ? red[0] / 448.f : 1.f;
 }
 
-__global__ void fp8_kernel(const float* __restrict__ codes, int rp, const int32_t* __restrict__ block_grain,
-                           const float* __restrict__ scales, int64_t nblocks, uint8_t* __restrict__ out) {
+// codes [blk][rp][64] f32 -> words [blk][rp / 4][64] of e4m3(z / s_g)
+__global__ void fp8_pack_kernel(const float* __restrict__ codes, int rp, const int32_t* __restrict__ block_grain,
+                                const float* __restrict__ scales, int64_t nblocks, uint32_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nblocks * rp * B) return;
-  const int64_t blk = i / (rp * B);
+  const int64_t per = (int64_t)(rp / 4) * B;
+  if (i >= nblocks * per) return;
+  const int64_t blk = i / per, rem = i % per, j4 = rem / B, lane = rem % B;
   const float s = scales[block_grain[blk]];
-  out[i] = f32_to_e4m3_rne_sat(codes[i] / s);
+  const float* c = codes + (size_t)blk * rp * B;
+  uint32_t w = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) w |= (uint32_t)f32_to_e4m3_rne_sat(c[(4 * j4 + t) * B + lane] / s) << (8 * t);
+  out[i] = w;
 }
 
 }  // namespace
 
 void launch_derive_lowp(Index& ix, hipStream_t s) {
-  const int64_t n = (int64_t)ix.nblocks * ix.rp * B;
+  const int64_t nw2 = (int64_t)ix.nblocks * (ix.rp / 2) * B;
+  const int64_t nw4 = (int64_t)ix.nblocks * (ix.rp / 4) * B;
   if (ix.codes_mask & (1u << HNTL_CODES_BF16)) {
-    if (!ix.codes_bf16) ix.codes_bf16 = dev_alloc<uint16_t>(&ix, n);
-    hipLaunchKernelGGL(bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ix.codes, n, ix.codes_bf16);
+    if (!ix.codes_bf16) ix.codes_bf16 = dev_alloc<uint32_t>(&ix, nw2);
+    hipLaunchKernelGGL(bf16_pack_kernel, dim3((unsigned)((nw2 + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp,
+                       (int64_t)ix.nblocks, ix.codes_bf16);
     HIP_TRY(hipGetLastError());
   }
   if (ix.codes_mask & (1u << HNTL_CODES_FP8_E4M3)) {
     if (!ix.scales) ix.scales = dev_alloc<float>(&ix, ix.G);
-    if (!ix.codes_fp8) ix.codes_fp8 = dev_alloc<uint8_t>(&ix, n);
+    if (!ix.codes_fp8) ix.codes_fp8 = dev_alloc<uint32_t>(&ix, nw4);
     hipLaunchKernelGGL(grain_scale_kernel, dim3(ix.G), dim3(256), 0, s, ix.codes, (int)ix.rp, (int)ix.r, ix.goff,
                        ix.boff, ix.scales);
     std::vector<int32_t> bg(ix.nblocks);
@@ -101,8 +127,8 @@ void launch_derive_lowp(Index& ix, hipStream_t s) {
     int32_t* d_bg = nullptr;
     HIP_TRY(hipMalloc((void**)&d_bg, sizeof(int32_t) * std::max<size_t>(1, bg.size())));
     HIP_TRY(hipMemcpy(d_bg, bg.data(), sizeof(int32_t) * bg.size(), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(fp8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp, d_bg,
-                       ix.scales, (int64_t)ix.nblocks, ix.codes_fp8);
+    hipLaunchKernelGGL(fp8_pack_kernel, dim3((unsigned)((nw4 + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp,
+                       d_bg, ix.scales, (int64_t)ix.nblocks, ix.codes_fp8);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipFree(d_bg));

@@ -122,6 +122,92 @@ __global__ __launch_bounds__(64 * (TILE / PT)) void project_kernel(
   }
 }
 
+// BF16 projection (the precision form): q' = q - mu_g is formed in FP32 and
+// rounded to BF16 (nearest even), the basis is the BF16 copy, and
+// v_mfma_f32_16x16x32_bf16 accumulates the exact BF16 products in FP32.
+// ||q'||^2 comes from the unrounded FP32 q', as in the FP32 kernel.  Lane
+// (i, kq) feeds depths k0 + 8 kq .. + 7 of row / column i in every MFMA.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+template <int NCT>
+__global__ __launch_bounds__(64 * (TILE / PT)) void project_bf16_kernel(
+    const float* __restrict__ Q, int d, int P, const float* __restrict__ centroids,
+    const uint16_t* __restrict__ basis16, int r, const int32_t* __restrict__ ioff, const int32_t* __restrict__ lstart,
+    const int32_t* __restrict__ lcount, int G, const int32_t* __restrict__ order, float* __restrict__ T,
+    float* __restrict__ epsq) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int g;
+  if (!item_grain(ioff, G, blockIdx.x, g)) return;
+  const int first = (blockIdx.x - ioff[g]) * TILE + PT * wave;
+  const int cnt = min(PT, lcount[g] - first);
+  if (cnt <= 0) return;  // no workgroup barrier in this kernel
+  const int32_t* pairs = order + lstart[g] + first;
+  const int i = lane & 15, kq = lane >> 4;
+  const int qrow = i < cnt ? pairs[i] / P : -1;
+  const float* mu = centroids + (size_t)g * d;
+  const uint16_t* Wg = basis16 + (size_t)g * r * d;
+  const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
+
+  floatx4 acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float sq = 0.f;
+  for (int k0 = 0; k0 < d; k0 += 32) {
+    const int kb = k0 + 8 * kq;
+    const bool in = kb < d;  // d is a multiple of 8 on this path: whole 8-runs are in or out
+    float a[8], m[8];
+    load_ks<true>(m, mu + kb, in ? 8 : 0);
+    load_ks<true>(a, qp + kb, (in && qrow >= 0) ? 8 : 0);
+    u32x4 av;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const float v0 = qrow >= 0 ? a[e] - m[e] : 0.f;
+      const float v1 = qrow >= 0 ? a[e + 1] - m[e + 1] : 0.f;
+      sq = fmaf(v0, v0, fmaf(v1, v1, sq));
+      av[e / 2] = bf16_rne_bits(v0) | (bf16_rne_bits(v1) << 16);
+    }
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int j = c * 16 + i;
+      u32x4 bv = {0u, 0u, 0u, 0u};
+      if (j < r && in) bv = *reinterpret_cast<const u32x4*>(Wg + (size_t)j * d + kb);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                        acc[c], 0, 0, 0);
+    }
+  }
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int row = 4 * (lane >> 4) + t;
+    float zz = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c * 16 + (lane & 15);
+      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    const float q2 = __shfl(sq, row, 64);
+    if (row < cnt) {
+      const int p = pairs[row];
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = c * 16 + (lane & 15);
+        if (col < r) T[(size_t)p * r + col] = acc[c][t];
+      }
+      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
+    }
+  }
+}
+
 }  // namespace
 
 template <bool VEC, int NCT>
@@ -144,9 +230,31 @@ void launch_project_v(const Index& ix, const float* Q, int P, const Buckets& b, 
   }
 }
 
-void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+template <int NCT>
+void launch_project_bf16_t(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                           hipStream_t s) {
+  const ItemLists& L = b.lists;
+  hipLaunchKernelGGL((project_bf16_kernel<NCT>), dim3((unsigned)b.max_items[LIST_ALL]), dim3(64 * (TILE / PT)), 0, s,
+                     Q, (int)ix.d, P, ix.centroids, ix.basis_bf16, (int)ix.r, L.ioff[LIST_ALL], L.lstart[LIST_ALL],
+                     L.lcount[LIST_ALL], (int)ix.G, b.order, T, epsq);
+}
+
+void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
                     hipStream_t s) {
   if (b.max_items[LIST_ALL] <= 0) return;
+  if (bf16) {
+    if (!ix.basis_bf16) throw ArgError{HNTL_ESTATE, "BF16 projection needs the BF16 basis (build a reduced-precision code form)"};
+    if ((ix.d % 8) != 0 || ((uintptr_t)Q % 16) != 0)
+      throw ArgError{HNTL_EUNSUPPORTED, "BF16 projection needs d % 8 == 0 and 16-byte aligned queries"};
+    switch ((ix.r + 15) / 16) {
+      case 1: launch_project_bf16_t<1>(ix, Q, P, b, T, epsq, s); break;
+      case 2: launch_project_bf16_t<2>(ix, Q, P, b, T, epsq, s); break;
+      case 3: launch_project_bf16_t<3>(ix, Q, P, b, T, epsq, s); break;
+      default: launch_project_bf16_t<4>(ix, Q, P, b, T, epsq, s); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return;
+  }
   if (b.lists.tile[LIST_ALL] != TILE) throw ArgError{HNTL_EDEVICE, "projection tile mismatch"};
   if ((ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0)
     launch_project_v<true>(ix, Q, P, b, T, epsq, s);

@@ -1,0 +1,244 @@
+// Block-SoA tangent scan kernels (included by one translation unit per code
+// form).  Block-SoA tangent scan with per-pair top-C selection (paper eq. 6, Section
+// 2.1 step 3, layout of Section 2.4).
+//
+// For a work item (grain g, up to 16 query pairs probing g) one wave streams
+// the grain's blocks: lane b of the wave owns vector b of the block and loads
+// its rp coordinates as rp coalesced 256-byte rows plus its eps.  The query
+// tangents of the tile sit in LDS and are read as broadcasts.  For every pair
+// t of the tile and every member i:
+//
+//   D_i = sum_j (z_q[t][j] - z_i[j])^2 + eps_q[t] + eps_i
+//
+// in FP32 as direct differences (the expansion through ||z||^2 loses the
+// relative accuracy the candidate ranking needs), then offered to pair t's
+// wave top-C list.  Keys carry the grain-order position, whose order inside a
+// grain equals original-id order, so (D, position) ranks like (D, id).  The C
+// winners are written as (D, original id) keys: part[pair][0..C).
+#pragma once
+
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+namespace scan_detail {
+
+constexpr int ITEM = 16;  // pairs per scan work item (tile of LIST_SLOT0 and LIST_REST)
+constexpr float PRUNE_SLACK = 1e-4f;  // relative margin on the FP32 lower bound
+
+template <int CAP>
+struct ListOf {
+  using type = WaveTopC<CAP>;
+  static constexpr int lds = 2 * CAP;  // keys of LDS per list
+};
+template <>
+struct ListOf<64> {
+  using type = WaveTop64;
+  static constexpr int lds = 64;
+};
+
+// One workgroup per work item; its 16 / QT waves take QT pairs each and all
+// stream the same grain (the repeated code reads hit in L1/L2).
+// CT: code form (0 FP32, 1 BF16 packed in pairs, 2 FP8 E4M3 packed in fours
+// with a per-grain scale; the decoded value of an FP8 code is fl32(code * s_g)).
+template <int RP, int CT>
+__device__ __forceinline__ void load_block(float (&c)[RP], const void* __restrict__ codes, size_t blk, int lane,
+                                           float s) {
+  if constexpr (CT == 0) {
+    const float* cb = reinterpret_cast<const float*>(codes) + blk * RP * B;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) c[j] = cb[j * B + lane];
+  } else if constexpr (CT == 1) {
+    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
+#pragma unroll
+    for (int j = 0; j < RP / 2; ++j) {
+      const uint32_t w = wb[j * B + lane];
+      c[2 * j] = __uint_as_float(w << 16);
+      c[2 * j + 1] = __uint_as_float(w & 0xFFFF0000u);
+    }
+  } else {
+    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 4) * B;
+#pragma unroll
+    for (int j = 0; j < RP / 4; ++j) {
+      const int w = (int)wb[j * B + lane];
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);  // bytes 0, 1
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);   // bytes 2, 3
+      c[4 * j] = lo[0] * s;
+      c[4 * j + 1] = lo[1] * s;
+      c[4 * j + 2] = hi[0] * s;
+      c[4 * j + 3] = hi[1] * s;
+    }
+  }
+}
+
+template <int RP, int CAP, int QT, int CT>
+__global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
+    const void* __restrict__ codes, const float* __restrict__ scales, const float* __restrict__ eps, const int32_t* __restrict__ goff,
+    const int32_t* __restrict__ boff, const int32_t* __restrict__ perm, int r, const float* __restrict__ T,
+    const float* __restrict__ epsq, int P, int C, const int32_t* __restrict__ ioff,
+    const int32_t* __restrict__ lstart, const int32_t* __restrict__ lcount, int G,
+    const int32_t* __restrict__ order, uint64_t* __restrict__ part, const uint64_t* __restrict__ bound_lists,
+    int prune, const float* __restrict__ blo, const float* __restrict__ bhi, const float* __restrict__ emin,
+    unsigned long long* __restrict__ scored) {
+  using List = typename ListOf<CAP>::type;
+  constexpr int NW = ITEM / QT;
+  __shared__ float zq_all[NW][QT][RP];
+  __shared__ float eq_all[NW][QT];
+  __shared__ uint64_t lists_all[NW][QT][ListOf<CAP>::lds];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  float (*zq)[RP] = zq_all[wave];
+  float* eq = eq_all[wave];
+  int g;
+  if (!item_grain(ioff, G, blockIdx.x, g)) return;
+  const int first = (blockIdx.x - ioff[g]) * ITEM;
+  const int total = min(ITEM, lcount[g] - first);
+  const int sub = wave * QT;
+  if (sub >= total) return;  // no workgroup barrier below: idle waves may leave
+  const int32_t* pairs = order + lstart[g] + first + sub;
+  const int cnt = min(QT, total - sub);
+  const int pos0 = goff[g];
+  const int ng = goff[g + 1] - pos0;
+  const int b0 = boff[g];
+  const int nb = boff[g + 1] - b0;
+
+  // stage the query tangents of this wave's pairs (zero beyond r and cnt)
+  for (int idx = lane; idx < QT * RP; idx += HNTL_WAVE) {
+    const int t = idx / RP, j = idx % RP;
+    float v = 0.f;
+    if (t < cnt && j < r) v = T[(size_t)pairs[t] * r + j];
+    zq[t][j] = v;
+  }
+  if (lane < QT) eq[lane] = lane < cnt ? epsq[pairs[lane]] : 0.f;
+  wave_sync();
+
+  List L[QT];
+  bool live[QT];
+  int nlive = 0;
+  const float sg = CT == 2 ? scales[g] : 1.f;
+  // this lane's coordinate of the grain's code bounding box (lanes >= r idle),
+  // widened by the largest rounding error of the code form so that it holds
+  // the decoded values the scan uses: BF16 half-ulp 2^-9 relative; FP8 E4M3
+  // half-ulp 2^-4 relative plus the subnormal quantum 2^-10 s_g
+  float lo = (bound_lists && prune && lane < r) ? blo[(size_t)g * RP + lane] : 0.f;
+  float hi = (bound_lists && prune && lane < r) ? bhi[(size_t)g * RP + lane] : 0.f;
+  if (CT != 0) {
+    const float amax = fmaxf(fabsf(lo), fabsf(hi));
+    const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
+    lo -= 1.0001f * w;
+    hi += 1.0001f * w;
+  }
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    uint64_t bnd = KEY_NONE;
+    live[t] = t < cnt;
+    if (live[t] && bound_lists) {
+      const int p = pairs[t];
+      bnd = bound_lists[((size_t)(p / P) * P) * C + C - 1];  // C-th key of the query's probe-0 list
+      if (prune && bnd != KEY_NONE) {
+        // eq. 6 lower bound over the grain: squared distance from z_q to the
+        // code bounding box, plus eps_q, plus the grain's smallest eps_i
+        const float v = lane < r ? zq[t][lane] : 0.f;
+        const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
+        const float lb = wave_sum(dd * dd) + eq[t] + emin[g];
+        if (lb * (1.f - PRUNE_SLACK) > key_dist(bnd)) {
+          live[t] = false;
+          if (lane == 0) part[(size_t)p * C] = KEY_NONE;  // empty list
+        }
+      }
+    }
+    L[t].init(lists_all[wave][t], C, bnd);
+    nlive += live[t] ? 1 : 0;
+  }
+  wave_sync();
+  if (scored && lane == 0 && nlive > 0) atomicAdd(scored, (unsigned long long)nlive * (unsigned long long)ng);
+
+  if (nlive > 0) {
+    for (int b = 0; b < nb; ++b) {
+      float c[RP];
+      load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
+      const float ei = eps[(size_t)(b0 + b) * B + lane];
+      const bool valid = b * B + lane < ng;
+      const uint32_t pos = (uint32_t)(pos0 + b * B + lane);
+#pragma unroll
+      for (int t = 0; t < QT; ++t) {
+        if (live[t]) {
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < RP; ++j) {
+            const float df = zq[t][j] - c[j];
+            acc = fmaf(df, df, acc);
+          }
+          L[t].offer(make_key(acc + eq[t] + ei, pos), valid);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    if (live[t]) {
+      L[t].finish();
+      uint64_t* out = part + (size_t)pairs[t] * C;
+      if constexpr (CAP == 64) {
+        const uint64_t k = L[t].best;
+        if (lane < C) out[lane] = (k == KEY_NONE) ? KEY_NONE : make_key(key_dist(k), (uint32_t)perm[key_id(k)]);
+      } else {
+        for (int i = lane; i < C; i += HNTL_WAVE) {
+          const uint64_t k = L[t].best[i];
+          out[i] = (k == KEY_NONE) ? KEY_NONE : make_key(key_dist(k), (uint32_t)perm[key_id(k)]);
+        }
+      }
+    }
+  }
+}
+
+template <int RP, int CAP, int CT>
+void launch_rp_cap(const Index& ix, const float* T, const float* epsq, int P, int C, const Buckets& b, int list,
+                   uint64_t* part, const uint64_t* bound_lists, bool prune, unsigned long long* scored, hipStream_t s) {
+  // unbounded lists (nearest grain) insert often: 4 pairs per wave for more
+  // waves in flight; bounded lists insert rarely: 16 pairs share every code load
+  constexpr int QT_WIDE = CAP <= 128 ? 16 : 8;
+  const dim3 grid((unsigned)b.max_items[list]);
+  const void* codes = CT == 0 ? (const void*)ix.codes : CT == 1 ? (const void*)ix.codes_bf16 : (const void*)ix.codes_fp8;
+  const ItemLists& Ls = b.lists;
+  if (bound_lists == nullptr)
+    hipLaunchKernelGGL((scan_f32_kernel<RP, CAP, 4, CT>), grid, dim3(64 * (ITEM / 4)), 0, s, codes, ix.scales, ix.eps,
+                       ix.goff,
+                       ix.boff, ix.perm, (int)ix.r, T, epsq, P, C, Ls.ioff[list], Ls.lstart[list], Ls.lcount[list],
+                       (int)ix.G, b.order, part, bound_lists, prune ? 1 : 0, ix.blo, ix.bhi, ix.emin, scored);
+  else
+    hipLaunchKernelGGL((scan_f32_kernel<RP, CAP, QT_WIDE, CT>), grid, dim3(64 * (ITEM / QT_WIDE)), 0, s, codes,
+                       ix.scales, ix.eps, ix.goff, ix.boff, ix.perm, (int)ix.r, T, epsq, P, C, Ls.ioff[list], Ls.lstart[list],
+                       Ls.lcount[list], (int)ix.G, b.order, part, bound_lists, prune ? 1 : 0, ix.blo, ix.bhi, ix.emin, scored);
+}
+
+template <int RP, int CT>
+void launch_rp(const Index& ix, const float* T, const float* epsq, int P, int C, const Buckets& b, int list,
+               uint64_t* part,
+               const uint64_t* bound_lists, bool prune, unsigned long long* scored, hipStream_t s) {
+  const int cap = pow2_at_least(C < 64 ? 64 : C);
+  if (cap == 64)
+    launch_rp_cap<RP, 64, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
+  else if (cap == 128)
+    launch_rp_cap<RP, 128, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
+  else
+    launch_rp_cap<RP, 256, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
+}
+
+template <int CT>
+void launch_ct(const Index& ix, const float* T, const float* epsq, int P, int C, const Buckets& b, int list,
+               uint64_t* part, const uint64_t* bound_lists, bool prune, unsigned long long* scored, hipStream_t s) {
+  switch (ix.rp) {
+    case 8: launch_rp<8, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 16: launch_rp<16, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 24: launch_rp<24, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 32: launch_rp<32, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 40: launch_rp<40, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 48: launch_rp<48, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 56: launch_rp<56, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    case 64: launch_rp<64, CT>(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s); break;
+    default: throw ArgError{HNTL_EUNSUPPORTED, "padded rank must be a multiple of 8 up to 64"};
+  }
+}
+
+}  // namespace scan_detail
+}  // namespace hntl

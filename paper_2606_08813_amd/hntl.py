@@ -19,7 +19,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 
 HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
-HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE = 1, 2, 4, 8
+HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
 STAGES = ("route", "bucket", "project", "scan", "rerank")
 HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 48, 64
 CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3}
@@ -57,6 +57,7 @@ EXPORTS = {
     "hntl_index_create": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32] + [C.c_void_p] * 7
                           + [C.c_uint32, C.POINTER(C.c_void_p)]),
     "hntl_index_export": (C.c_int, [C.c_void_p] * 8),
+    "hntl_index_export_codes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "hntl_index_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_index_info)]),
     "hntl_index_captured": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hntl_index_free": (None, [C.c_void_p]),
@@ -191,6 +192,18 @@ def hntl_index_export(index: Index, with_scales=False) -> dict:
     if with_scales:
         o["scales"] = sc
     return o
+
+
+def hntl_index_export_codes(index: Index, codes: str):
+    """Reduced-precision codes (N x r bit patterns, grain order) and, for FP8, the per-grain scales."""
+    if codes == "bf16":
+        out = np.empty((index.N, index.r), np.uint16)
+        _check(lib().hntl_index_export_codes(index.handle, HNTL_CODES_BF16, out.ctypes.data, None))
+        return out, None
+    out = np.empty((index.N, index.r), np.uint8)
+    sc = np.empty(index.G, np.float32)
+    _check(lib().hntl_index_export_codes(index.handle, HNTL_CODES_FP8_E4M3, out.ctypes.data, sc.ctypes.data))
+    return out, sc
 
 
 def hntl_index_info_get(index: Index) -> dict:

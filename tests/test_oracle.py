@@ -242,7 +242,7 @@ def test_planted_dropped_residual_term_fails_isotropic_pin(monkeypatch):
     Q = pm.isotropic(200, 768, 12)
     st = oi.build(X, 1, 32, 0, labels=np.zeros(10000, dtype=int)).stored()
 
-    def bad_scores(zq, epsq, g, stored):
+    def bad_scores(zq, epsq, g, stored, codes=None):
         a, b = int(stored["offsets"][g]), int(stored["offsets"][g + 1])
         Z = stored["codes"][a:b].astype(np.float64)
         return stored["perm"][a:b].astype(np.int64), ((zq[None, :] - Z) ** 2).sum(1)
@@ -345,3 +345,59 @@ def test_gelu_matches_definition_and_softmax_ce_minimum():
     y = np.eye(4)[[1]]
     _, g = router.loss_and_dlogits(np.array([[0.0, 50.0, 0.0, 0.0]]), y)
     assert np.abs(g).max() < 1e-20
+
+
+# ------------------------------------------------- reduced-precision emulation
+
+def test_lowp_emulation_is_identity_on_representable_values():
+    """When every code is already a BF16 value (resp. an FP8 value times a
+    power-of-two scale that leaves the quotient exact), the reduced-precision
+    scans read exactly the FP32 codes, so pools are identical."""
+    X = pm.uniform_rows(300, 16, seed=21)
+    Q = pm.uniform_rows(12, 16, seed=22)
+    st = oi.build(X, 3, 4, seed=23).stored()
+    st_b = dict(st, codes=quant.bf16_round(st["codes"]))
+    zq, epsq = osr.project(Q, osr.route(Q, st["centroids"], 2)[0], st_b)
+    probes = osr.route(Q, st["centroids"], 2)[0]
+    a = osr.scan_pool(zq, epsq, probes, st_b, 40, "fp32")
+    b = osr.scan_pool(zq, epsq, probes, st_b, 40, "bf16")
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    # FP8: codes on the E4M3 grid scaled so that each grain's amax is exactly 448 * 2^-3
+    vals = quant.fp8_e4m3_values()
+    rng = np.random.default_rng(3)
+    z8 = rng.choice(np.concatenate([vals, -vals]), size=st["codes"].shape) * 2.0 ** -3
+    for g in range(3):
+        a0, b0 = st["offsets"][g], st["offsets"][g + 1]
+        z8[a0] = 448 * 2.0 ** -3
+    st_8 = dict(st, codes=z8.astype(np.float32))
+    c, sc = quant.fp8_grain_codes(st_8["codes"], st_8["offsets"])
+    assert np.all(sc == np.float32(2.0 ** -3))
+    np.testing.assert_array_equal(quant.decoded_codes(st_8["codes"], st_8["offsets"], "fp8"),
+                                  st_8["codes"].astype(np.float64))
+
+
+def test_bf16_projection_emulation_bounds():
+    """BF16 rounding moves each coordinate by at most the rounding of q' and W:
+    |z_bf16 - z| <= 2^-8 * sum_k |W_jk q'_k| (two half-ulp relative roundings)."""
+    X = pm.uniform_rows(400, 32, seed=31)
+    Q = pm.uniform_rows(10, 32, seed=32)
+    st = oi.build(X, 2, 6, seed=33).stored()
+    probes = osr.route(Q, st["centroids"], 2)[0]
+    z, e = osr.project(Q, probes, st)
+    zb, eb = osr.project(Q, probes, st, bf16=True)
+    for i in range(len(Q)):
+        for s in range(2):
+            g = probes[i, s]
+            qp = Q[i].astype(np.float64) - st["centroids"][g].astype(np.float64)
+            bound = 2.0 ** -8 * (np.abs(st["basis"][g].astype(np.float64)) @ np.abs(qp)) + 1e-12
+            assert (np.abs(zb[i, s] - z[i, s]) <= bound).all()
+    assert (eb >= 0).all()
+
+
+def test_fp8_negative_underflow_keeps_sign():
+    """IEEE-style rounding keeps the sign of a value that rounds to zero:
+    E4M3 encodes it as negative zero (0x80)."""
+    v = quant.fp8_e4m3_round(np.array([-1e-5, 1e-5, -0.0]))
+    assert (v == 0).all()
+    np.testing.assert_array_equal(quant.fp8_encode_byte(v), [0x80, 0x00, 0x80])
