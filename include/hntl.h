@@ -224,6 +224,111 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
  */
 hntl_status hntl_profile_read(double* ms, uint32_t n, uint32_t* calls, uint64_t* scored);
 
+/* ------------------------------------------------------------------------
+ * Batching form: persistent fused search plans
+ * ------------------------------------------------------------------------
+ * A plan fixes (index, search params, largest batch max_nq, schedule) and owns
+ * every device buffer of the search, allocated once: the query, result and
+ * scratch arrays.  Running a plan allocates nothing.  Steps 2-3 run as one
+ * persistent fused project-scan-select kernel whose workgroups take work
+ * items from a device queue, largest grain first; large grains are split into
+ * block ranges, and every query shares one running bound on its pool between
+ * the items (exact pruning, see HNTL_FLAG_NO_PRUNE).  With HNTL_PLAN_GRAPH the
+ * plan captures its whole launch sequence (reset, routing, bucketing, fused
+ * kernel, merge + rerank) into a HIP graph once, at creation, and every run
+ * replays it: the batch size is read from device memory, so replays of one
+ * plan need no host work beyond the launch.  Results equal those of
+ * hntl_search with the same parameters (the pool is the exact top C of the
+ * probed grains in both).
+ *
+ * A plan reads its index until it is freed; free every plan before its index.
+ * Runs of one plan on different streams must not overlap (they share the
+ * plan's buffers); different plans may run concurrently.
+ */
+typedef struct hntl_plan hntl_plan; /* opaque */
+
+/* Work schedule of the fused kernel (picked by hntl_tune or given). */
+typedef struct hntl_schedule {
+  uint32_t qt;     /* pairs per wave in a scan item: 1, 2 or 4 */
+  uint32_t nw;     /* waves per workgroup, 1..8: a scan item holds nw * qt pairs of one grain */
+  uint32_t range;  /* blocks of 64 vectors per scan item (0 = whole grain); larger grains
+                      give one item per range, whose lists the merge joins */
+  uint32_t grid;   /* workgroups of the persistent launch (0 = as many as are resident at once) */
+} hntl_schedule;
+
+#define HNTL_PLAN_GRAPH 1u /* capture a HIP graph at creation; runs replay it */
+
+/*
+ * hntl_plan_create - a plan for batches of up to max_nq queries.
+ *   index   the index (must outlive the plan); needs d % 8 == 0 and a padded rank
+ *           8 * ceil(r / 8) of 16, 32, 48 or 64
+ *   sp      search parameters as for hntl_search (flags: HNTL_FLAG_PROJECT_BF16,
+ *           HNTL_FLAG_NO_PRUNE are honoured; HNTL_FLAG_SYNC applies to every run)
+ *   sched   NULL = a default chosen from the batch shape
+ *   stream  stream used for the one-time setup (and for graph capture through a
+ *           private stream)
+ * Errors: EINVAL, ESTATE, EUNSUPPORTED (shape outside the compiled kernels, or a
+ * schedule whose workgroup needs more than 64 KiB of LDS), ENOMEM, EDEVICE.
+ */
+hntl_status hntl_plan_create(hntl_index* index, const hntl_search_params* sp, uint32_t max_nq,
+                             const hntl_schedule* sched, uint32_t plan_flags, void* stream, hntl_plan** out);
+
+/*
+ * hntl_plan_buffers - the plan's own device buffers: Q (max_nq x d float32),
+ * ids (max_nq x k int32), dist (max_nq x k float32).  Writing queries into Q and
+ * calling hntl_plan_run avoids the copies of hntl_plan_search.  Any pointer may be NULL.
+ */
+hntl_status hntl_plan_buffers(hntl_plan* plan, float** Q, int32_t** ids, float** dist);
+
+/*
+ * hntl_plan_run - search the first nq rows of the plan's Q buffer (nq <= max_nq);
+ * results land in the plan's ids / dist buffers (rows >= nq hold -1 / +inf).
+ * Asynchronous on `stream` unless HNTL_FLAG_SYNC was given; then a wait that gave up
+ * inside the fused kernel is reported as EDEVICE.
+ */
+hntl_status hntl_plan_run(hntl_plan* plan, uint32_t nq, void* stream);
+
+/*
+ * hntl_plan_search - copy nq queries (device) into the plan, run it, copy the
+ * results out (device ids nq x k, dist nq x k).  Q, ids and dist may also be the
+ * plan's own buffers (no copy then).
+ */
+hntl_status hntl_plan_search(hntl_plan* plan, const float* Q, uint32_t nq, int32_t* ids, float* dist,
+                             void* stream);
+
+typedef struct hntl_plan_info {
+  uint32_t max_nq;
+  hntl_schedule sched;     /* the schedule in use (grid resolved) */
+  uint32_t graph;          /* 1 if runs replay a captured graph */
+  uint64_t device_bytes;   /* the plan's device buffers */
+  uint64_t list_slots;     /* capacity of per-(pair, range) candidate lists */
+  uint32_t wait_errors;    /* waits that gave up since creation (0 in a healthy run) */
+} hntl_plan_info;
+
+/* hntl_plan_info_get - plan facts; synchronises the plan's last stream to read wait_errors. */
+hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out);
+
+void hntl_plan_free(hntl_plan* plan);
+
+/*
+ * hntl_tune - the autotuner.  Times every candidate schedule of the fused kernel
+ * (qt in {1, 2, 4} x nw in {1, 2, 4, 8} x range in {0, 4, 8, 16, 32, 64}, those whose
+ * LDS fits) on the nq given queries (device, nq x d) and returns the fastest in *best
+ * (*best_ms its median device time of one run).  With db_path != NULL the result is
+ * also stored in that text file, one line per (device, index shape, search params,
+ * batch size), replacing an older line of the same key; hntl_schedule_lookup reads it.
+ */
+hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const float* Q, uint32_t nq,
+                      const char* db_path, hntl_schedule* best, float* best_ms, void* stream);
+
+/*
+ * hntl_schedule_lookup - the schedule stored by hntl_tune for this device, index
+ * shape, search params and batch size max_nq.  ESTATE if the file has no such entry
+ * (or does not exist).
+ */
+hntl_status hntl_schedule_lookup(const hntl_index* index, const hntl_search_params* sp, uint32_t max_nq,
+                                 const char* db_path, hntl_schedule* out);
+
 /* Last error message of the calling thread ("" if none). */
 const char* hntl_last_error(void);
 

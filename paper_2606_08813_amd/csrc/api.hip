@@ -21,7 +21,7 @@ hntl_status fail(hntl_status s, const std::string& msg) {
 
 Index::~Index() {
   void* ptrs[] = {centroids, cnorm, basis, goff, boff, perm, codes, eps, codes_bf16, codes_fp8, scales, basis_bf16, X,
-                  blo, bhi, emin};
+                  blo, bhi, emin, gorder};
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);

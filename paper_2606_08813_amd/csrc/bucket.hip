@@ -87,16 +87,24 @@ __device__ int block_exclusive_scan(int v, int* tmp /* >= 16 ints */, int& total
 }
 
 // Single workgroup: grain ranges, the three lists' ranges and item offsets.
+// Grains are visited in the order `gorder` (rank -> grain; identity if null)
+// and ioff is indexed by that rank, so items come out in that order; lstart and
+// lcount stay indexed by grain.  With `nsplit`, a grain's slot-0 and rest
+// tiles each become nsplit[g] items (one per block range of the grain).
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __restrict__ gcount,
                                                            const int32_t* __restrict__ gcount0, int G,
+                                                           const int32_t* __restrict__ gorder,
+                                                           const int32_t* __restrict__ nsplit,
                                                            int32_t* __restrict__ gstart, int32_t* __restrict__ cur0,
                                                            int32_t* __restrict__ cur1, ItemLists lists) {
   __shared__ int tmp[32];
   int carry_p = 0, carry[3] = {0, 0, 0};
   for (int base = 0; base < G; base += 1024) {
-    const int g = base + (int)threadIdx.x;
+    const int rank = base + (int)threadIdx.x;
+    const int g = rank < G ? (gorder ? gorder[rank] : rank) : G;
     const int c = g < G ? gcount[g] : 0;
     const int c0 = g < G ? gcount0[g] : 0;
+    const int split = (g < G && nsplit) ? nsplit[g] : 1;
     int tot;
     const int sp = block_exclusive_scan(c, tmp, tot);
     const int st = carry_p + sp;
@@ -106,11 +114,11 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
       const int tile = lists.tile[L];
-      const int nt = (lc[L] + tile - 1) / tile;
+      const int nt = (lc[L] + tile - 1) / tile * (L == LIST_ALL ? 1 : split);
       int tt;
       const int so = block_exclusive_scan(nt, tmp, tt);
       if (g < G) {
-        lists.ioff[L][g] = carry[L] + so;
+        lists.ioff[L][rank] = carry[L] + so;
         lists.lstart[L][g] = ls[L];
         lists.lcount[L][g] = lc[L];
       }
@@ -183,20 +191,72 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const int32_t* __re
   }
 }
 
+// Per-pair list slots when grains are split into block ranges: pair
+// (q, slot) of grain g owns the nsplit[g] consecutive lists from lbase[pair];
+// a query's lists are contiguous, qoff[q] .. qoff[q + 1] (single workgroup).
+__global__ __launch_bounds__(1024) void pair_lists_kernel(const int32_t* __restrict__ probes, int64_t nq, int P,
+                                                          int G, const int32_t* __restrict__ nsplit,
+                                                          int32_t* __restrict__ lbase, int32_t* __restrict__ qoff) {
+  __shared__ int tmp[32];
+  int carry = 0;
+  for (int64_t base = 0; base < nq; base += 1024) {
+    const int64_t q = base + threadIdx.x;
+    int tot = 0;
+    if (q < nq)
+      for (int sl = 0; sl < P; ++sl) {
+        const int g = probes[q * P + sl];
+        tot += (g >= 0 && g < G) ? nsplit[g] : 0;
+      }
+    int all;
+    const int ex = carry + block_exclusive_scan(tot, tmp, all);
+    if (q < nq) {
+      qoff[q] = ex;
+      int run = ex;
+      for (int sl = 0; sl < P; ++sl) {
+        const int g = probes[q * P + sl];
+        lbase[q * P + sl] = run;
+        run += (g >= 0 && g < G) ? nsplit[g] : 0;
+      }
+    }
+    carry += all;
+  }
+  if (threadIdx.x == 0) qoff[nq] = carry;
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
 
-void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s) {
+// Fill with a kernel rather than hipMemsetAsync, so that captured graphs hold
+// only kernel nodes.
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  HIP_TRY(hipGetLastError());
+}
+
+void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
+                       int32_t* qoff, hipStream_t s) {
+  hipLaunchKernelGGL(pair_lists_kernel, dim3(1), dim3(1024), 0, s, probes, nq, P, G, nsplit, lbase, qoff);
+  HIP_TRY(hipGetLastError());
+}
+
+void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s,
+                   const int32_t* gorder, const int32_t* nsplit) {
   const int64_t npairs = nq * P;
-  HIP_TRY(hipMemsetAsync(b.gcount, 0, sizeof(int32_t) * G, s));
-  HIP_TRY(hipMemsetAsync(b.gcount0, 0, sizeof(int32_t) * G, s));
+  launch_fill_i32(b.gcount, G, 0, s);
+  launch_fill_i32(b.gcount0, G, 0, s);
   const unsigned nb = (unsigned)((npairs + CHUNK - 1) / CHUNK);
   if (npairs > 0) {
     hipLaunchKernelGGL(bucket_hist_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G ? 2 * G * sizeof(int) : 0, s,
                        probes, npairs, P, G, b.gcount, b.gcount0);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, b.gcount, b.gcount0, G, b.gstart, b.cur0, b.cur1,
-                     b.lists);
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, b.gcount, b.gcount0, G, gorder, nsplit, b.gstart,
+                     b.cur0, b.cur1, b.lists);
   HIP_TRY(hipGetLastError());
   if (npairs > 0) {
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G / 2 ? 4 * G * sizeof(int) : 0, s,

@@ -27,7 +27,10 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <limits>
 #include <numeric>
 
@@ -419,6 +422,28 @@ struct KMeansOut {
   int iters = 0;
 };
 
+// Phase timings on stderr when HNTL_VERBOSE is set to a positive number (each
+// report waits for the stream, so timings are off unless asked for).
+struct PhaseLog {
+  bool on;
+  hipStream_t s;
+  std::chrono::steady_clock::time_point t0, t;
+  explicit PhaseLog(hipStream_t s_) : s(s_) {
+    const char* v = std::getenv("HNTL_VERBOSE");
+    on = v && std::atoi(v) > 0;
+    t0 = t = std::chrono::steady_clock::now();
+  }
+  void operator()(const char* what) {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    const auto n = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[hntl_build] %-26s %8.2f s  (total %.2f s)\n", what,
+                 std::chrono::duration<double>(n - t).count(), std::chrono::duration<double>(n - t0).count());
+    std::fflush(stderr);
+    t = n;
+  }
+};
+
 std::vector<int64_t> counting_sort(const std::vector<int32_t>& lab, int G, std::vector<int32_t>& order) {
   std::vector<int64_t> off(G + 1, 0);
   for (int32_t l : lab) off[l + 1]++;
@@ -464,6 +489,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
     ix->G = G;
     ix->r = r;
     ix->rp = (r + 7) / 8 * 8;
+    PhaseLog plog(s);
     ix->X = dev_alloc<float>(ix, (size_t)N * d);
     HIP_TRY(hipMemcpyAsync(ix->X, X, sizeof(float) * N * d, hipMemcpyDefault, s));
     ix->centroids = dev_alloc<float>(ix, (size_t)G * d);
@@ -549,6 +575,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       HIP_TRY(hipGetLastError());
     }
 
+    plog("k-means++ seeding");
     // ---------------- Lloyd iterations on the training rows
     std::vector<int32_t> lab_h(n_train), prev(n_train, -1), order_h;
     std::vector<float> dmin_h(n_train);
@@ -593,6 +620,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       if (changed == 0) break;
     }
     ix->kmeans_iters_run = std::min(it, max_iter);
+    plog("Lloyd iterations");
 
     // ---------------- final assignment of every row, exact member means
     {
@@ -617,6 +645,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       launch_row_norms(ix->centroids, G, (int)d, ix->cnorm, s);
     }
 
+    plog("final assignment + means");
     // ---------------- block layout
     {
       ix->boff_h.assign(G + 1, 0);
@@ -762,6 +791,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
         }
       }
     }
+    plog("covariance, eigensolve, codes");
     launch_grain_bounds(*ix, s);
     ix->codes_mask = 1u;
     const uint32_t want = params->codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3));
@@ -770,6 +800,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       launch_derive_lowp(*ix, s);
     }
     HIP_TRY(hipStreamSynchronize(s));
+    plog("bounds + reduced-precision codes");
   } catch (const ArgError& e) {
     delete h;
     return fail(e.code, e.msg);

@@ -1,0 +1,330 @@
+// Persistent fused project-scan-select kernel: the batching form of the
+// search (paper Section 2.1 steps 2-3 and eq. 1-6) for batches of uneven size
+// over grains of very uneven size.
+//
+// One launch runs a fixed number of workgroups (as many as fit the device);
+// every wave of them is an independent worker that takes work items from one
+// device ticket counter until the items run out (no workgroup barriers).
+// The items come in three runs, each ordered largest grain first so that the
+// long items start early:
+//
+//   1. projection items: 16 (query, grain) pairs of one grain, whose tangents
+//      z_q and eps_q the wave computes on the MFMA units (the same wave
+//      routine as the grain-major projection kernel), then counts the item
+//      as done for its grain (release);
+//   2. scan items of probe slot 0 (each query's nearest grain);
+//   3. scan items of the other probe slots.
+//
+// A scan item holds QT pairs of one grain and one block range of it (R
+// blocks, or the whole grain for R = 0).  Consecutive tickets are the tiles
+// of one range, so waves that run them together read the same blocks (L2
+// hits).  Before it reads tangents, a scan item waits until every projection
+// item of its grain is done (acquire).  The wait cannot deadlock: tickets are
+// handed out in item order, so every projection item was taken earlier by a
+// running wave that never waits itself; a spin limit still bounds it and
+// flags an error.
+//
+// Exact shared pruning.  Every query keeps one bound in device memory, the
+// smallest C-th distance of any of its lists that already holds C
+// candidates.  The query's final pool (the C smallest (D, id) over all its
+// probed grains) cannot contain a candidate whose distance exceeds that
+// bound, so a list may drop such candidates, and a whole pair is skipped when
+// the exact lower bound of eq. 6 over its grain (box distance of z_q to the
+// grain's code bounding box + eps_q + the grain's smallest eps_i) exceeds it.
+// Lists publish their C-th distance (atomic min) and re-read the bound every
+// REFRESH blocks.  Which candidates a list drops depends on timing; the merged
+// pool does not, since it is the exact top C in every case.
+#pragma once
+
+#include <algorithm>
+
+#include "project_impl.h"
+#include "scan_impl.h"
+
+namespace hntl {
+namespace fused_detail {
+
+using proj_detail::project_wave;
+using proj_detail::project_wave_bf16;
+using scan_detail::ListOf;
+using scan_detail::load_block;
+using scan_detail::PRUNE_SLACK;
+
+constexpr int REFRESH = 16;                 // blocks between bound exchanges
+constexpr long long SPIN_LIMIT = 1ll << 26;  // wait polls before giving up
+
+constexpr uint32_t NO_BOUND = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int find_rank(const int32_t* __restrict__ ioff, int G, int item) {
+  int lo = 0, hi = G;  // largest rank with ioff[rank] <= item (ioff[G] > item)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ioff[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// A bound on the distance part only: the list keys carry grain positions,
+// which do not order like the original ids across grains, so every candidate
+// at the bound's distance is kept and the merge settles exact ties.
+__device__ __forceinline__ uint64_t bound_key(uint32_t ord) {
+  return ord == NO_BOUND ? KEY_NONE : (((uint64_t)ord << 32) | 0xFFFFFFFFull);
+}
+
+template <int RP, int QT, int LK>
+constexpr size_t wave_lds_bytes() {
+  return (size_t)QT * LK * 8 + (((size_t)QT * RP + QT) * 4 + 7) / 8 * 8;
+}
+
+// One wave's part of a scan item: its cnt (<= QT) pairs of grain g against
+// block range `range` of the grain (no workgroup barrier inside).
+template <int RP, int CAP, int QT, int CT>
+__device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int L, int g, int range,
+                                          const int32_t* __restrict__ pairs, int cnt) {
+  using List = typename ListOf<CAP>::type;
+  constexpr int LK = ListOf<CAP>::lds;
+  const int lane = lane_id();
+  const int P = a.P, C = a.C, r = a.r;
+  uint64_t* lists_lds = my;
+  float(*zq)[RP] = reinterpret_cast<float(*)[RP]>(my + QT * LK);
+  float* eq = reinterpret_cast<float*>(my + QT * LK) + QT * RP;
+  const int pos0 = a.goff[g];
+  const int ng = a.goff[g + 1] - pos0;
+  const int b0 = a.boff[g];
+  const int nb = a.boff[g + 1] - b0;
+  const int rb0 = a.R ? range * a.R : 0;
+  const int rb1 = a.R ? min(nb, rb0 + a.R) : nb;
+
+  for (int idx = lane; idx < QT * RP; idx += HNTL_WAVE) {
+    const int t = idx / RP, j = idx % RP;
+    zq[t][j] = (t < cnt && j < r) ? a.T[(size_t)pairs[t] * r + j] : 0.f;
+  }
+  if (lane < QT) eq[lane] = lane < cnt ? a.epsq[pairs[lane]] : 0.f;
+  wave_sync();
+
+  const float sg = CT == 2 ? a.scales[g] : 1.f;
+  float lo = (a.prune && lane < r) ? a.blo[(size_t)g * RP + lane] : 0.f;
+  float hi = (a.prune && lane < r) ? a.bhi[(size_t)g * RP + lane] : 0.f;
+  if (CT != 0) {  // the box must hold the decoded values the scan uses
+    const float amax = fmaxf(fabsf(lo), fabsf(hi));
+    const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
+    lo -= 1.0001f * w;
+    hi += 1.0001f * w;
+  }
+  List Ls[QT];
+  bool live[QT];
+  int nlive = 0;
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    live[t] = t < cnt;
+    uint64_t bnd = KEY_NONE;
+    if (live[t]) {
+      const int p = pairs[t];
+      const uint32_t ob = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&a.qbound[p / P], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      bnd = bound_key(ob);
+      if (a.prune && ob != NO_BOUND) {
+        const float v = lane < r ? zq[t][lane] : 0.f;
+        const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
+        const float lb = wave_sum(dd * dd) + eq[t] + a.emin[g];
+        if (__builtin_amdgcn_readfirstlane(lb * (1.f - PRUNE_SLACK) > ord2f(ob) ? 1 : 0)) {
+          live[t] = false;
+          const int64_t slot = (a.lbase ? (int64_t)a.lbase[p] : (int64_t)p) + range;
+          if (lane == 0) a.part[(size_t)slot * C] = KEY_NONE;  // empty list
+        }
+      }
+    }
+    Ls[t].init(lists_lds + t * LK, C, bnd);
+    nlive += live[t] ? 1 : 0;
+  }
+  wave_sync();
+  if (nlive == 0) return;
+  if (a.scored && lane == 0) {
+    const int nvec = min(ng, rb1 * B) - rb0 * B;
+    if (nvec > 0) atomicAdd(a.scored, (unsigned long long)nlive * (unsigned long long)nvec);
+  }
+
+  const void* codes = a.codes;
+  for (int b = rb0; b < rb1; ++b) {
+    if (b > rb0 && ((b - rb0) % REFRESH) == 0) {
+      // exchange bounds: publish each list's C-th distance, adopt the query's
+#pragma unroll
+      for (int t = 0; t < QT; ++t) {
+        if (live[t]) {
+          const int q = pairs[t] / P;
+          const uint64_t own = Ls[t].cth();
+          if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[q], (uint32_t)(own >> 32));
+          const uint32_t ob = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(&a.qbound[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          Ls[t].tighten(bound_key(ob));
+        }
+      }
+    }
+    // one block of codes in registers per wave; the loads of the other waves
+    // on the CU cover the HBM latency
+    float c[RP];
+    load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
+    const float e = a.eps[(size_t)(b0 + b) * B + lane];
+    const bool valid = b * B + lane < ng;
+    const uint32_t pos = (uint32_t)(pos0 + b * B + lane);
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      if (live[t]) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          const float df = zq[t][j] - c[j];
+          acc = fmaf(df, df, acc);
+        }
+        Ls[t].offer(make_key(acc + eq[t] + e, pos), valid);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    if (live[t]) {
+      Ls[t].finish();
+      const int p = pairs[t];
+      const uint64_t own = Ls[t].cth();
+      if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[p / P], (uint32_t)(own >> 32));
+      const int64_t slot = (a.lbase ? (int64_t)a.lbase[p] : (int64_t)p) + range;
+      uint64_t* out = a.part + (size_t)slot * C;
+      if constexpr (CAP == 64) {
+        const uint64_t kk = Ls[t].best;
+        if (lane < C) out[lane] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
+      } else {
+        for (int i = lane; i < C; i += HNTL_WAVE) {
+          const uint64_t kk = Ls[t].best[i];
+          out[i] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
+        }
+      }
+    }
+  }
+}
+
+template <int RP, int CAP, int QT, int CT>
+__global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict__ ap) {
+  const FusedArgs& a = *ap;
+  constexpr int LK = ListOf<CAP>::lds;
+  constexpr int NCT = (RP + 15) / 16;
+  extern __shared__ uint64_t smem[];
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t* my = smem + (size_t)wave * (wave_lds_bytes<RP, QT, LK>() / 8);
+  const int G = a.G;
+  const int nP = __builtin_amdgcn_readfirstlane(a.ioff[LIST_ALL][G]);
+  const int n0 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_SLOT0][G]);
+  const int n1 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_REST][G]);
+  const int total = nP + n0 + n1;
+
+  // Each wave is its own worker: it takes tickets until they run out.  The
+  // fetch is one atomic for the wave (lane 0 adds 1, the others 0) whose
+  // lane-0 result is broadcast; nothing in the loop synchronises waves.
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(atomicAdd(a.ticket, lane == 0 ? 1 : 0));
+    if (it >= total) break;
+    if (it < nP) {  // ---------------------------------------- projection
+      const int rank = find_rank(a.ioff[LIST_ALL], G, it);
+      const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
+      const int first = (it - a.ioff[LIST_ALL][rank]) * 16;
+      const int cnt = __builtin_amdgcn_readfirstlane(min(16, a.lcount[LIST_ALL][g] - first));
+      const int32_t* pairs = a.order + a.lstart[LIST_ALL][g] + first;
+      if (a.proj_bf16)
+        project_wave_bf16<NCT>(a.Q, a.d, a.P, a.centroids, a.basis16, a.r, g, pairs, cnt, a.T, a.epsq);
+      else
+        project_wave<true, NCT>(a.Q, a.d, a.P, a.centroids, a.basis, a.r, g, pairs, cnt, a.T, a.epsq);
+      // release: the tangents of this item are visible before the count is
+      __hip_atomic_fetch_add(&a.proj_done[g], lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {  // ----------------------------------------------------- scan
+      const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
+      const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
+      const int rank = find_rank(a.ioff[L], G, li);
+      const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
+      const int lc = __builtin_amdgcn_readfirstlane(a.lcount[L][g]);
+      const int ntiles = (lc + QT - 1) / QT;
+      const int k = li - __builtin_amdgcn_readfirstlane(a.ioff[L][rank]);
+      const int range = k / ntiles, tile = k % ntiles;  // range-major: a range's tiles run together
+      // wait until every projection item of the grain has finished (acquire)
+      const int need = (__builtin_amdgcn_readfirstlane(a.lcount[LIST_ALL][g]) + 15) / 16;
+      for (long long spin = 0;; ++spin) {
+        const int done = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&a.proj_done[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        if (done >= need) break;
+        if (spin > SPIN_LIMIT) {
+          atomicOr(a.err, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      const int first = tile * QT;
+      const int cnt = min(QT, lc - first);
+      scan_tile<RP, CAP, QT, CT>(a, my, L, g, range, a.order + a.lstart[L][g] + first, cnt);
+    }
+  }
+}
+
+template <int RP, int CAP, int QT, int CT>
+struct Inst {
+  static constexpr size_t lds_per_wave = wave_lds_bytes<RP, QT, ListOf<CAP>::lds>();
+  static int resident(int nw) {
+    static int cache[9] = {0};
+    if (nw < 1 || nw > 8) return 0;
+    if (cache[nw] == 0) {
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_kernel<RP, CAP, QT, CT>, 64 * nw,
+                                                       lds_per_wave * nw) != hipSuccess)
+        per_cu = 1;
+      int dev = 0, ncu = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      cache[nw] = std::max(1, per_cu) * std::max(1, ncu);
+    }
+    return cache[nw];
+  }
+  static void launch(const FusedArgs* a, int nw, int grid, hipStream_t s) {
+    if (grid <= 0) grid = resident(nw);
+    hipLaunchKernelGGL((fused_kernel<RP, CAP, QT, CT>), dim3((unsigned)grid), dim3(64 * nw), lds_per_wave * nw, s, a);
+  }
+};
+
+// Dispatch over (rp, cap, qt) for one code form; F(Inst) is called with the
+// matching instantiation.  Returns false for combinations not compiled.
+template <int CT, class F>
+bool dispatch(int rp, int C, int qt, F&& f) {
+  const int cap = pow2_at_least(C < 64 ? 64 : C);
+#define HNTL_FQ(RPV, CAPV)                               \
+  if (rp == RPV && cap == CAPV) {                        \
+    if (qt == 1) return f(Inst<RPV, CAPV, 1, CT>{}), true; \
+    if (qt == 2) return f(Inst<RPV, CAPV, 2, CT>{}), true; \
+    if (qt == 4) return f(Inst<RPV, CAPV, 4, CT>{}), true; \
+    return false;                                        \
+  }
+#define HNTL_FR(RPV) HNTL_FQ(RPV, 64) HNTL_FQ(RPV, 128) HNTL_FQ(RPV, 256)
+  HNTL_FR(16)
+  HNTL_FR(32)
+  HNTL_FR(48)
+  HNTL_FR(64)
+#undef HNTL_FR
+#undef HNTL_FQ
+  return false;
+}
+
+}  // namespace fused_detail
+}  // namespace hntl
+
+// Defines the per-code-form entry points of one translation unit.
+#define HNTL_FUSED_TU(CT)                                                                                      \
+  namespace hntl {                                                                                             \
+  bool launch_fused_ct##CT(const FusedArgs* a, int rp, int C, int qt, int nw, int grid, hipStream_t s) {       \
+    return fused_detail::dispatch<CT>(rp, C, qt, [&](auto inst) { decltype(inst)::launch(a, nw, grid, s); }); \
+  }                                                                                                            \
+  int fused_resident_ct##CT(int rp, int C, int qt, int nw) {                                                   \
+    int n = 0;                                                                                                 \
+    fused_detail::dispatch<CT>(rp, C, qt, [&](auto inst) { n = decltype(inst)::resident(nw); });              \
+    return n;                                                                                                  \
+  }                                                                                                            \
+  }

@@ -152,6 +152,14 @@ struct WaveTopC {
     flush();
     wave_sync();
   }
+
+  // Lowers the bound to b (a threshold learned while scanning).
+  __device__ __forceinline__ void tighten(uint64_t b) {
+    if (b < bound) bound = b;
+    if (b < thr) thr = b;
+  }
+  // The C-th smallest key merged so far (KEY_NONE while fewer than C).
+  __device__ __forceinline__ uint64_t cth() const { return best[C - 1]; }
 };
 
 // ------------------------------------------- register-resident top-64 list
@@ -253,6 +261,12 @@ struct WaveTop64 {
 
   // After finish(), lane i holds the i-th smallest key (KEY_NONE padded).
   __device__ __forceinline__ void finish() { flush(); }
+
+  __device__ __forceinline__ void tighten(uint64_t b) {
+    if (b < bound) bound = b;
+    if (b < thr) thr = b;
+  }
+  __device__ __forceinline__ uint64_t cth() const { return uniform_u64(shfl_u64(best, C - 1)); }
 };
 
 // ------------------------------------------------------------- work items

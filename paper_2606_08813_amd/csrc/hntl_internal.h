@@ -47,6 +47,7 @@ struct Index {
   float* blo = nullptr;        // G x rp: per-grain minimum of each code coordinate
   float* bhi = nullptr;        // G x rp: per-grain maximum
   float* emin = nullptr;       // G: per-grain minimum eps_i
+  int32_t* gorder = nullptr;   // G: grains by size, largest first (made by the first search plan)
 
   std::vector<int64_t> offsets_h;
   std::vector<int32_t> boff_h;
@@ -110,15 +111,18 @@ struct Scratch {
 // ----------------------------------------------------------- launchers
 // routing / k-means distances: D[i][j] = ||a_i||^2 + ||b_j||^2 - 2 a_i . b_j
 void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream_t s);
+// With nlim (device), rows from *nlim - row_base on are skipped (batches whose
+// size lives in device memory).
 void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
-                        int cols, int d, float* D, hipStream_t s);
+                        int cols, int d, float* D, hipStream_t s, const int32_t* nlim = nullptr,
+                        int64_t row_base = 0);
 void launch_argmin_rows(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
                         int cols, int d, int32_t* label, float* dmin, hipStream_t s);
 // top-P per row of D; with A and Bm given, the winners are re-scored by exact
-// direct differences (routing)
+// direct differences (routing).  Rows beyond *nlim - row_base get probes -1.
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
-                      const float* bn = nullptr, int d = 0);
+                      const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0);
 
 // grain bucketing of (query, probe) pairs; work-item lists cut from it
 enum { LIST_SLOT0 = 0, LIST_REST = 1, LIST_ALL = 2 };
@@ -139,7 +143,11 @@ struct Buckets {
   int max_items[3];  // upper bounds of the item counts (grid sizes)
   int G;
 };
-void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s);
+void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s,
+                   const int32_t* gorder = nullptr, const int32_t* nsplit = nullptr);
+void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
+                       int32_t* qoff, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
                     hipStream_t s);  // over LIST_ALL
@@ -153,7 +161,52 @@ void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, 
 void launch_grain_bounds(Index& ix, hipStream_t s);
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k,
                          const int32_t* probes, const uint64_t* part, const int32_t* pool_in, int32_t* pool_out,
-                         float* pool_D_out, int32_t* ids, float* dist, hipStream_t s);
+                         float* pool_D_out, int32_t* ids, float* dist, hipStream_t s,
+                         const int32_t* qoff = nullptr);
+
+// Persistent fused project-scan-select kernel (the batching form).  Its
+// waves take work items from one device ticket counter, in three runs:
+// projection items (LIST_ALL, 16 pairs), then scan items of probe slot 0,
+// then scan items of the other slots (QT pairs, one item per block range of
+// R blocks; R = 0 scans whole grains).  Inside each run items follow the
+// grain order `gorder` (largest grain first).
+struct FusedArgs {
+  // index
+  const void* codes;
+  const float* scales;
+  const float* eps;
+  const int32_t* goff;
+  const int32_t* boff;
+  const int32_t* perm;
+  const float* blo;
+  const float* bhi;
+  const float* emin;
+  const float* centroids;
+  const float* basis;
+  const uint16_t* basis16;
+  int d, r, G, P, C;
+  // batch
+  const float* Q;
+  // work items
+  const int32_t* ioff[3];  // indexed by grain rank
+  const int32_t* lstart[3];
+  const int32_t* lcount[3];
+  const int32_t* gorder;
+  const int32_t* order;
+  const int32_t* lbase;  // per pair: first list slot (null: the pair id)
+  int R;
+  // shared state (reset before every launch)
+  int32_t* ticket;     // 1
+  int32_t* proj_done;  // G: finished projection items per grain
+  uint32_t* qbound;    // per query: order image of the smallest known C-th distance
+  int32_t* err;        // 1: set if a wait gave up
+  float* T;            // npairs x r tangents
+  float* epsq;         // npairs
+  uint64_t* part;      // lists x C keys
+  unsigned long long* scored;
+  int proj_bf16;
+  int prune;
+};
 
 // build helpers
 void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);

@@ -1,0 +1,200 @@
+// Projection of queries onto the local PCA bases of their probed grains
+// (paper Section 2.2, eq. 1-4), one wave per 16 (query, grain) pairs:
+//
+//   q'    = q - mu_g                    (eq. 1, centred first, in FP32)
+//   z_q   = W_g^T q'                    (eq. 2, MFMA)
+//   eps_q = max(0, ||q'||^2 - ||z_q||^2) (eq. 3-4: since W_g has orthonormal
+//                                         columns, ||q' - W_g z_q||^2 equals
+//                                         ||q'||^2 - ||z_q||^2)
+//
+// ||q'||^2 is accumulated by direct squares of the centred values fed to the
+// MFMA.  Outputs are pair-major: T[pair][r], epsq[pair], pair = q * P + slot.
+// Used by the grain-major projection kernel and by the fused persistent kernel.
+#pragma once
+
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+namespace proj_detail {
+
+constexpr int PT = 16;    // pairs per wave (rows of one 16x16 MFMA tile)
+constexpr int KS = 8;       // consecutive depth values per lane and chunk
+constexpr int KC = 4 * KS;  // depth chunk: KS MFMA steps of K = 4
+
+// Loads KS consecutive floats src[0..KS) (zero from `lim` on) into v.
+template <bool VEC>
+__device__ __forceinline__ void load_ks(float (&v)[KS], const float* __restrict__ src, int lim) {
+  if (VEC) {
+#pragma unroll
+    for (int e = 0; e < KS; e += 4) {
+      float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < lim) t = *reinterpret_cast<const float4*>(src + e);
+      v[e] = t.x;
+      v[e + 1] = t.y;
+      v[e + 2] = t.z;
+      v[e + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < KS; ++e) v[e] = e < lim ? src[e] : 0.f;
+  }
+}
+
+// The MFMA sums over the four K slots of each
+// instruction; lane (i = lane % 16, kq = lane / 16) feeds slot kq with depth
+// k0 + KS kq + e in step e, for the A operand (centred query row i) and the B
+// operand (basis row c * 16 + i) alike, so each lane reads KS contiguous floats
+// per operand and chunk straight from global memory.  NCT = ceil(r / 16)
+// column tiles.
+// Projects the cnt (<= 16) pairs pairs[0..cnt) of grain g with one wave.
+template <bool VEC, int NCT>
+__device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d, int P,
+                                             const float* __restrict__ centroids, const float* __restrict__ basis,
+                                             int r, int g, const int32_t* __restrict__ pairs, int cnt,
+                                             float* __restrict__ T, float* __restrict__ epsq) {
+  const int lane = lane_id();
+  const int i = lane & 15, kq = lane >> 4;
+  const int qrow = i < cnt ? pairs[i] / P : -1;
+  const float* mu = centroids + (size_t)g * d;
+  const float* Wg = basis + (size_t)g * r * d;
+  const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
+
+  floatx4 acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float sq = 0.f;
+
+  for (int k0 = 0; k0 < d; k0 += KC) {
+    const int kb = k0 + KS * kq;
+    const int lim = d - kb;  // valid floats from kb (may be <= 0)
+    float a[KS], m[KS], b[NCT][KS];
+    load_ks<VEC>(m, mu + kb, lim);
+    load_ks<VEC>(a, qp + kb, qrow >= 0 ? lim : 0);
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int j = c * 16 + i;
+      load_ks<VEC>(b[c], Wg + (size_t)(j < r ? j : 0) * d + kb, j < r ? lim : 0);
+    }
+#pragma unroll
+    for (int e = 0; e < KS; ++e) {
+      a[e] = qrow >= 0 ? a[e] - m[e] : 0.f;
+      sq = fmaf(a[e], a[e], sq);
+    }
+#pragma unroll
+    for (int e = 0; e < KS; ++e)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) acc[c] = mfma16x16x4(a[e], b[c][e], acc[c]);
+  }
+
+  // ||q'||^2 of row i: the four K slots of the row
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+  // ||z||^2 per output row (MFMA layout: row 4 * (lane >> 4) + t, column lane & 15)
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int row = 4 * (lane >> 4) + t;
+    float zz = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c * 16 + (lane & 15);
+      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    const float q2 = __shfl(sq, row, 64);  // lane `row` holds row `row`'s ||q'||^2
+    if (row < cnt) {
+      const int p = pairs[row];
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = c * 16 + (lane & 15);
+        if (col < r) T[(size_t)p * r + col] = acc[c][t];
+      }
+      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
+    }
+  }
+}
+
+// BF16 projection (the precision form): q' = q - mu_g is formed in FP32 and
+// rounded to BF16 (nearest even), the basis is the BF16 copy, and
+// v_mfma_f32_16x16x32_bf16 accumulates the exact BF16 products in FP32.
+// ||q'||^2 comes from the unrounded FP32 q', as in the FP32 kernel.  Lane
+// (i, kq) feeds depths k0 + 8 kq .. + 7 of row / column i in every MFMA.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// BF16 form of project_wave (d % 8 == 0, 16-byte aligned query rows).
+template <int NCT>
+__device__ __forceinline__ void project_wave_bf16(const float* __restrict__ Q, int d, int P,
+                                                  const float* __restrict__ centroids,
+                                                  const uint16_t* __restrict__ basis16, int r, int g,
+                                                  const int32_t* __restrict__ pairs, int cnt, float* __restrict__ T,
+                                                  float* __restrict__ epsq) {
+  const int lane = lane_id();
+  const int i = lane & 15, kq = lane >> 4;
+  const int qrow = i < cnt ? pairs[i] / P : -1;
+  const float* mu = centroids + (size_t)g * d;
+  const uint16_t* Wg = basis16 + (size_t)g * r * d;
+  const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
+
+  floatx4 acc[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float sq = 0.f;
+  for (int k0 = 0; k0 < d; k0 += 32) {
+    const int kb = k0 + 8 * kq;
+    const bool in = kb < d;  // d is a multiple of 8 on this path: whole 8-runs are in or out
+    float a[8], m[8];
+    load_ks<true>(m, mu + kb, in ? 8 : 0);
+    load_ks<true>(a, qp + kb, (in && qrow >= 0) ? 8 : 0);
+    u32x4 av;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const float v0 = qrow >= 0 ? a[e] - m[e] : 0.f;
+      const float v1 = qrow >= 0 ? a[e + 1] - m[e + 1] : 0.f;
+      sq = fmaf(v0, v0, fmaf(v1, v1, sq));
+      av[e / 2] = bf16_rne_bits(v0) | (bf16_rne_bits(v1) << 16);
+    }
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int j = c * 16 + i;
+      u32x4 bv = {0u, 0u, 0u, 0u};
+      if (j < r && in) bv = *reinterpret_cast<const u32x4*>(Wg + (size_t)j * d + kb);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                        acc[c], 0, 0, 0);
+    }
+  }
+  sq += __shfl_xor(sq, 16, 64);
+  sq += __shfl_xor(sq, 32, 64);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int row = 4 * (lane >> 4) + t;
+    float zz = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c * 16 + (lane & 15);
+      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    const float q2 = __shfl(sq, row, 64);
+    if (row < cnt) {
+      const int p = pairs[row];
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = c * 16 + (lane & 15);
+        if (col < r) T[(size_t)p * r + col] = acc[c][t];
+      }
+      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
+    }
+  }
+}
+
+}  // namespace proj_detail
+}  // namespace hntl

@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
                                                            const int32_t* __restrict__ pool_in,
                                                            const float* __restrict__ X, int32_t* __restrict__ pool_out,
                                                            float* __restrict__ pool_D_out, int32_t* __restrict__ ids,
-                                                           float* __restrict__ dist, bool vec4) {
+                                                           float* __restrict__ dist, bool vec4,
+                                                           const int32_t* __restrict__ qoff) {
   __shared__ uint64_t lst[2 * CAP];
   __shared__ int32_t pool[CAP];
   __shared__ float delta[CAP];
@@ -35,10 +36,16 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
       if (wave == 0) {
         WaveTop64 L;
         L.init(lst, C);
-        const uint64_t* src = part + (size_t)q * P * C;
-        for (int s = 0; s < P; ++s) {
-          const int g = probes[q * P + s];
-          if (g < 0 || g >= G) continue;                 // invalid probe: its list was never written
+        // the query's lists: one per probe, or (grains split into block
+        // ranges) the contiguous run qoff[q] .. qoff[q + 1]
+        const int64_t l0 = qoff ? qoff[q] : q * P;
+        const int nl = qoff ? qoff[q + 1] - qoff[q] : P;
+        const uint64_t* src = part + (size_t)l0 * C;
+        for (int s = 0; s < nl; ++s) {
+          if (!qoff) {
+            const int g = probes[q * P + s];
+            if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
+          }
           if (src[(size_t)s * C] == KEY_NONE) continue;  // empty (or pruned) list
           const uint64_t key = lane < C ? src[(size_t)s * C + lane] : KEY_NONE;
           L.offer(key, key != KEY_NONE);
@@ -54,10 +61,14 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
     } else if (wave == 0) {
       WaveTopC<CAP> L;
       L.init(lst, C);
-      const uint64_t* src = part + (size_t)q * P * C;
-      for (int s = 0; s < P; ++s) {
-        const int g = probes[q * P + s];
-        if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
+      const int64_t l0 = qoff ? qoff[q] : q * P;
+      const int nl = qoff ? qoff[q + 1] - qoff[q] : P;
+      const uint64_t* src = part + (size_t)l0 * C;
+      for (int s = 0; s < nl; ++s) {
+        if (!qoff) {
+          const int g = probes[q * P + s];
+          if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
+        }
         for (int c0 = 0; c0 < C; c0 += HNTL_WAVE) {
           // lists are ascending with KEY_NONE padding (a pruned grain's list
           // holds a single KEY_NONE): stop at the first padding key
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k, const int32_t* probes,
                          const uint64_t* part,
                          const int32_t* pool_in, int32_t* pool_out, float* pool_D_out, int32_t* ids, float* dist,
-                         hipStream_t s) {
+                         hipStream_t s, const int32_t* qoff) {
   if (nq <= 0) return;
   const bool vec4 = (ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0 && ((uintptr_t)ix.X % 16) == 0;
   const int cap = pow2_at_least(C < 64 ? 64 : C);
@@ -183,7 +194,7 @@ void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int
 #define HNTL_MR(CAPV)                                                                                             \
   hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 2, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
                      (int64_t)ix.N, probes, part, pool_in, ix.X,                                                  \
-                     pool_out, pool_D_out, ids, dist, vec4)
+                     pool_out, pool_D_out, ids, dist, vec4, qoff)
   if (cap == 64)
     HNTL_MR(64);
   else if (cap == 128)

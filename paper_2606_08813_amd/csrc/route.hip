@@ -91,11 +91,17 @@ __device__ __forceinline__ void tile_dot(floatx4 (&acc)[2][2], float (*As)[LDT],
 __global__ __launch_bounds__(256) void dist_matrix_kernel(const float* __restrict__ A, const float* __restrict__ an,
                                                           int64_t rows, const float* __restrict__ Bm,
                                                           const float* __restrict__ bn, int cols, int d,
-                                                          float* __restrict__ D, bool vec4) {
+                                                          float* __restrict__ D, bool vec4,
+                                                          const int32_t* __restrict__ nlim, int64_t row_base) {
   __shared__ float As[TM][LDT];
   __shared__ float Bs[TN][LDT];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * TM;
+  if (nlim) {  // rows from *nlim - row_base on are not part of this batch
+    const int64_t lim = (int64_t)*nlim - row_base;
+    if (row0 >= lim) return;
+    if (lim < rows) rows = lim;
+  }
   const int col0 = blockIdx.y * TN;
   floatx4 acc[2][2];
   tile_dot(acc, As, Bs, A, rows, Bm, cols, d, row0, col0, vec4);
@@ -220,11 +226,19 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
                                                         const float* __restrict__ an,
                                                         const float* __restrict__ Bm,
                                                         const float* __restrict__ bn, int d,
-                                                        int32_t* __restrict__ idx, float* __restrict__ val) {
+                                                        int32_t* __restrict__ idx, float* __restrict__ val,
+                                                        const int32_t* __restrict__ nlim, int64_t row_base) {
   __shared__ uint64_t stage[4][64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= rows) return;
+  if (nlim && row >= (int64_t)*nlim - row_base) {  // not part of this batch: no probes
+    if (lane < P) {
+      idx[row * P + lane] = -1;
+      if (val) val[row * P + lane] = __builtin_inff();
+    }
+    return;
+  }
   const bool exact = A != nullptr;
   WaveTop64 L;
   L.init(stage[wave], exact ? M : P);
@@ -295,11 +309,12 @@ void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream
 }
 
 void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn, int cols,
-                        int d, float* D, hipStream_t s) {
+                        int d, float* D, hipStream_t s, const int32_t* nlim, int64_t row_base) {
   if (rows <= 0 || cols <= 0) return;
   const bool vec4 = (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
   dim3 grid((unsigned)((rows + TM - 1) / TM), (unsigned)((cols + TN - 1) / TN));
-  hipLaunchKernelGGL(dist_matrix_kernel, grid, dim3(256), 0, s, A, an, rows, Bm, bn, cols, d, D, vec4);
+  hipLaunchKernelGGL(dist_matrix_kernel, grid, dim3(256), 0, s, A, an, rows, Bm, bn, cols, d, D, vec4, nlim,
+                     row_base);
   HIP_TRY(hipGetLastError());
 }
 
@@ -313,12 +328,14 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 }
 
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
-                      const float* A, const float* an, const float* Bm, const float* bn, int d) {
+                      const float* A, const float* an, const float* Bm, const float* bn, int d,
+                      const int32_t* nlim, int64_t row_base) {
   if (rows <= 0) return;
   if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + 3) / 4));
   const int M = A ? std::min(cols, P + 16) : P;
-  hipLaunchKernelGGL(topk_rows_kernel, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val);
+  hipLaunchKernelGGL(topk_rows_kernel, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val, nlim,
+                     row_base);
   HIP_TRY(hipGetLastError());
 }
 

@@ -134,6 +134,10 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
     if (live[t] && bound_lists) {
       const int p = pairs[t];
       bnd = bound_lists[((size_t)(p / P) * P) * C + C - 1];  // C-th key of the query's probe-0 list
+      // that key holds an original id while this scan keys by grain position:
+      // keep every candidate whose distance does not exceed the bound's, so an
+      // exact distance tie is settled by the merge, in (distance, id) order
+      if (bnd != KEY_NONE) bnd |= 0xFFFFFFFFull;
       if (prune && bnd != KEY_NONE) {
         // eq. 6 lower bound over the grain: squared distance from z_q to the
         // code bounding box, plus eps_q, plus the grain's smallest eps_i

@@ -43,6 +43,18 @@ class hntl_index_info(C.Structure):
                 ("kmeans_iters_run", C.c_uint32), ("max_grain", C.c_uint32)]
 
 
+class hntl_schedule(C.Structure):
+    _fields_ = [("qt", C.c_uint32), ("nw", C.c_uint32), ("range", C.c_uint32), ("grid", C.c_uint32)]
+
+
+class hntl_plan_info(C.Structure):
+    _fields_ = [("max_nq", C.c_uint32), ("sched", hntl_schedule), ("graph", C.c_uint32),
+                ("device_bytes", C.c_uint64), ("list_slots", C.c_uint64), ("wait_errors", C.c_uint32)]
+
+
+HNTL_PLAN_GRAPH = 1
+
+
 class HNTLError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"hntl status {status}: {msg}")
@@ -66,6 +78,17 @@ EXPORTS = {
     "hntl_search_stages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params)]
                            + [C.c_void_p] * 13),
     "hntl_profile_read": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "hntl_plan_create": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_uint32, C.c_void_p, C.c_uint32,
+                                   C.c_void_p, C.POINTER(C.c_void_p)]),
+    "hntl_plan_buffers": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_void_p)] * 3),
+    "hntl_plan_run": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "hntl_plan_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hntl_plan_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_plan_info)]),
+    "hntl_plan_free": (None, [C.c_void_p]),
+    "hntl_tune": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_void_p, C.c_uint32, C.c_char_p,
+                            C.POINTER(hntl_schedule), C.POINTER(C.c_float), C.c_void_p]),
+    "hntl_schedule_lookup": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_uint32, C.c_char_p,
+                                       C.POINTER(hntl_schedule)]),
     "hntl_last_error": (C.c_char_p, []),
     "hntl_version": (C.c_char_p, []),
 }
@@ -280,3 +303,100 @@ def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", f
         _ptr(tangent_in), _ptr(epsq_in), _ptr(o.get("zq")), _ptr(o.get("epsq")), _ptr(pool_in),
         _ptr(o.get("pool_ids")), _ptr(o.get("pool_D")), _ptr(o["ids"]), _ptr(o["dist"]), _stream(stream)))
     return o
+
+
+# ---------------------------------------------------------------- batching form
+@dataclass
+class Plan:
+    """A search plan handle (freed when garbage collected or by ``hntl_plan_free``).
+    Keeps its index alive."""
+
+    handle: C.c_void_p
+    index: Index
+    max_nq: int
+    k: int
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.hntl_plan_free(self.handle)
+            self.handle = None
+
+
+def _sched(sched):
+    if sched is None:
+        return None
+    if isinstance(sched, hntl_schedule):
+        return sched
+    if isinstance(sched, dict):
+        return hntl_schedule(sched["qt"], sched["nw"], sched["range"], sched.get("grid", 0))
+    return hntl_schedule(*sched)
+
+
+def sched_dict(s: hntl_schedule) -> dict:
+    return {"qt": s.qt, "nw": s.nw, "range": s.range, "grid": s.grid}
+
+
+def hntl_plan_create(index: Index, P: int, C_: int, k: int, max_nq: int, codes="fp32", flags=0, sched=None,
+                     graph=True, stream=None) -> Plan:
+    sp = _params(P, C_, k, codes, flags)
+    sc = _sched(sched)
+    h = C.c_void_p()
+    _check(lib().hntl_plan_create(index.handle, C.byref(sp), max_nq, C.byref(sc) if sc is not None else None,
+                                  HNTL_PLAN_GRAPH if graph else 0, _stream(stream), C.byref(h)))
+    return Plan(h, index, max_nq, k)
+
+
+def hntl_plan_buffers(plan: Plan):
+    """Device addresses (ints) of the plan's Q, ids and dist buffers."""
+    q, i, d = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().hntl_plan_buffers(plan.handle, C.byref(q), C.byref(i), C.byref(d)))
+    return q.value, i.value, d.value
+
+
+def hntl_plan_run(plan: Plan, nq: int, stream=None):
+    _check(lib().hntl_plan_run(plan.handle, nq, _stream(stream)))
+
+
+def hntl_plan_search(plan: Plan, Q, out=None, stream=None):
+    """Search the rows of Q (nq <= max_nq) with the plan; returns (ids, dist) CUDA tensors."""
+    import torch
+    _cuda_f32(Q, "Q")
+    nq = Q.shape[0]
+    if out is None:
+        ids = torch.empty((nq, plan.k), dtype=torch.int32, device=Q.device)
+        dist = torch.empty((nq, plan.k), dtype=torch.float32, device=Q.device)
+    else:
+        ids, dist = out
+    _check(lib().hntl_plan_search(plan.handle, Q.data_ptr(), nq, ids.data_ptr(), dist.data_ptr(), _stream(stream)))
+    return ids, dist
+
+
+def hntl_plan_info_get(plan: Plan) -> dict:
+    info = hntl_plan_info()
+    _check(lib().hntl_plan_info_get(plan.handle, C.byref(info)))
+    return {"max_nq": info.max_nq, "sched": sched_dict(info.sched), "graph": bool(info.graph),
+            "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors}
+
+
+def hntl_plan_free(plan: Plan):
+    if plan.handle:
+        lib().hntl_plan_free(plan.handle)
+        plan.handle = None
+
+
+def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, db_path=None, stream=None):
+    """Autotune the fused kernel's schedule on the batch Q; returns (schedule dict, median ms)."""
+    _cuda_f32(Q, "Q")
+    sp = _params(P, C_, k, codes, flags)
+    best = hntl_schedule()
+    ms = C.c_float(0.0)
+    _check(lib().hntl_tune(index.handle, C.byref(sp), Q.data_ptr(), Q.shape[0],
+                           str(db_path).encode() if db_path else None, C.byref(best), C.byref(ms), _stream(stream)))
+    return sched_dict(best), ms.value
+
+
+def hntl_schedule_lookup(index: Index, P: int, C_: int, k: int, max_nq: int, db_path, codes="fp32", flags=0):
+    sp = _params(P, C_, k, codes, flags)
+    out = hntl_schedule()
+    _check(lib().hntl_schedule_lookup(index.handle, C.byref(sp), max_nq, str(db_path).encode(), C.byref(out)))
+    return sched_dict(out)

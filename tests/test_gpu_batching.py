@@ -1,0 +1,173 @@
+"""GPU tests of the batching form: search plans around the persistent fused
+project-scan-select kernel, HIP-graph replay, and the schedule autotuner.
+
+A plan's pool is the exact top C of (eq. 6 score, id) over the probed grains,
+computed with the same arithmetic as the staged search, so its results must
+equal hntl_search's bit for bit, for every schedule (tile shape, waves per
+workgroup, block ranges), batch size, code form and projection precision.
+The final results are also checked against the oracle on the oracle's own
+index.
+"""
+import numpy as np
+import pytest
+
+from oracle import search as osr
+from tests import parity
+from tests.gpu_common import announce, exact_dist_fn, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    dict(qt=1, nw=1, range=0),
+    dict(qt=1, nw=4, range=1),   # every grain split into one-block ranges
+    dict(qt=2, nw=2, range=2),
+    dict(qt=2, nw=1, range=3),
+    dict(qt=4, nw=4, range=0),
+    dict(qt=4, nw=8, range=1),
+]
+
+
+@pytest.fixture(scope="module")
+def bt(small10k):
+    torch = require_gpu()
+    from paper_2606_08813_amd import hntl
+    st = {k: small10k["stored"][k] for k in ("centroids", "basis", "offsets", "perm", "codes", "eps")}
+    announce("import oracle index 10k x 768 (FP32, BF16, FP8 codes) for plans")
+    ix = hntl.hntl_index_create(st, small10k["X"], codes=("fp32", "bf16", "fp8"))
+    W = small10k["W"]
+    orc = osr.search(small10k["Q"], st, small10k["X"], W.P, W.C, W.k)
+    return dict(small10k, st=st, ix=ix, Qd=to_dev(small10k["Q"]), orc=orc, torch=torch, hntl=hntl)
+
+
+def staged(bt, Q, codes="fp32", flags=0):
+    W, hntl = bt["W"], bt["hntl"]
+    ids, dist = hntl.hntl_search(bt["ix"], Q, W.P, W.C, W.k, codes=codes, flags=flags | hntl.HNTL_FLAG_SYNC)
+    return ids, dist
+
+
+def assert_same(a, b, what):
+    torch = __import__("torch")
+    assert torch.equal(a[0], b[0]), f"{what}: ids differ"
+    assert torch.equal(a[1], b[1]), f"{what}: distances differ"
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: f"qt{s['qt']}-nw{s['nw']}-range{s['range']}")
+def test_plan_equals_staged_search(bt, sched):
+    W, hntl = bt["W"], bt["hntl"]
+    announce(f"plan (eager) {sched} vs staged search, batches 1..1000")
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=sched, graph=False,
+                                 flags=hntl.HNTL_FLAG_SYNC)
+    for nb in (1000, 1, 7, 256):
+        Q = bt["Qd"][:nb].contiguous()
+        assert_same(hntl.hntl_plan_search(plan, Q), staged(bt, Q), f"{sched} nq={nb}")
+    assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
+
+
+@pytest.mark.parametrize("codes,bf16proj", [("bf16", True), ("fp8", True), ("bf16", False), ("fp8", False)])
+def test_plan_reduced_precision_equals_staged(bt, codes, bf16proj):
+    W, hntl = bt["W"], bt["hntl"]
+    fl = hntl.HNTL_FLAG_PROJECT_BF16 if bf16proj else 0
+    announce(f"plan codes={codes} bf16 projection={bf16proj} vs staged search")
+    for sched in (dict(qt=2, nw=4, range=1), dict(qt=4, nw=2, range=0)):
+        plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, codes=codes, flags=fl | hntl.HNTL_FLAG_SYNC,
+                                     sched=sched)
+        assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], codes, fl), f"{codes} {sched}")
+
+
+def test_plan_no_prune_equals_pruned(bt):
+    W, hntl = bt["W"], bt["hntl"]
+    announce("plan with and without exact pruning")
+    sched = dict(qt=2, nw=2, range=1)
+    a = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=sched, flags=hntl.HNTL_FLAG_SYNC)
+    b = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=sched,
+                              flags=hntl.HNTL_FLAG_SYNC | hntl.HNTL_FLAG_NO_PRUNE)
+    assert_same(hntl.hntl_plan_search(a, bt["Qd"]), hntl.hntl_plan_search(b, bt["Qd"]), "prune vs no prune")
+
+
+def test_graph_replays_match_eager(bt):
+    """Replays of one captured graph with different batch sizes, with unrelated
+    eager GPU work and synchronisations between them; every replay must equal
+    the eager result of the same batch."""
+    W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
+    announce("graph replay: 6 replays of one plan, nq 1000/1/333/7/1000/64")
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=dict(qt=2, nw=4, range=2), graph=True)
+    assert hntl.hntl_plan_info_get(plan)["graph"]
+    x = torch.randn(512, 512, device="cuda")
+    for nb in (1000, 1, 333, 7, 1000, 64):
+        Q = bt["Qd"][:nb].contiguous()
+        got = hntl.hntl_plan_search(plan, Q)
+        torch.cuda.synchronize()
+        y = (x @ x).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        assert_same(got, staged(bt, Q), f"replay nq={nb}")
+    assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
+
+
+def test_plan_buffers_run(bt):
+    """Queries written straight into the plan's buffer; results read from its buffers."""
+    W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
+    announce("plan_run on the plan's own buffers")
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=dict(qt=1, nw=2, range=0))
+    qa, ia, da = hntl.hntl_plan_buffers(plan)
+    assert qa and ia and da
+    ref = staged(bt, bt["Qd"][:100].contiguous())
+    ids, dist = hntl.hntl_plan_search(plan, bt["Qd"][:100].contiguous())
+    torch.cuda.synchronize()
+    assert_same((ids, dist), ref, "plan_search")
+    hntl.hntl_plan_run(plan, 100)  # same queries are still in the plan's buffer
+    torch.cuda.synchronize()
+    ids2, dist2 = hntl.hntl_plan_search(plan, bt["Qd"][:100].contiguous())
+    assert_same((ids2, dist2), ref, "plan_run then plan_search")
+
+
+def test_plan_oracle_parity(bt):
+    """Final results of a graph-replayed plan against the oracle (ids up to
+    near-ties within 1e-5 relative, distances within 1e-4 relative)."""
+    W, hntl = bt["W"], bt["hntl"]
+    announce("plan final ids/distances vs oracle")
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=dict(qt=2, nw=4, range=1), graph=True)
+    ids, dist = hntl.hntl_plan_search(plan, bt["Qd"])
+    orc = bt["orc"]
+    nd, n = parity.check_lists(ids.cpu().numpy(), dist.cpu().numpy(), orc["ids"], orc["dist"],
+                               exact_dist_fn(bt["X"], bt["Q"]), what="plan ids")
+    assert nd <= 0.01 * n
+
+
+def test_autotuner_and_lookup(bt, tmp_path):
+    W, hntl = bt["W"], bt["hntl"]
+    announce("autotuner on 256 queries, tuning file round trip")
+    db = tmp_path / "tune.txt"
+    Q = bt["Qd"][:256].contiguous()
+    best, ms = hntl.hntl_tune(bt["ix"], Q, W.P, W.C, W.k, db_path=db)
+    assert ms > 0 and best["qt"] in (1, 2, 4) and 1 <= best["nw"] <= 8
+    assert hntl.hntl_schedule_lookup(bt["ix"], W.P, W.C, W.k, 256, db) == best
+    text = db.read_text()
+    assert text.count("\n") == 1 and "nq=256" in text
+    best2, _ = hntl.hntl_tune(bt["ix"], Q, W.P, W.C, W.k, db_path=db)  # replaces its own line
+    assert db.read_text().count("\n") == 1
+    with pytest.raises(hntl.HNTLError):
+        hntl.hntl_schedule_lookup(bt["ix"], W.P, W.C, W.k, 999, db)
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 256, sched=best2)
+    assert_same(hntl.hntl_plan_search(plan, Q), staged(bt, Q), "tuned schedule")
+
+
+def test_plan_errors(bt):
+    W, hntl = bt["W"], bt["hntl"]
+    announce("plan argument errors")
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 100, sched=dict(qt=3, nw=1, range=0))
+    assert e.value.status == hntl.HNTL_EINVAL
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 100, sched=dict(qt=1, nw=9, range=0))
+    assert e.value.status == hntl.HNTL_EINVAL
+    with pytest.raises(hntl.HNTLError) as e:  # 4 lists x 4 KiB x 8 waves of LDS
+        hntl.hntl_plan_create(bt["ix"], W.P, 256, W.k, 100, sched=dict(qt=4, nw=8, range=0))
+    assert e.value.status == hntl.HNTL_EUNSUPPORTED
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 0)
+    assert e.value.status == hntl.HNTL_EINVAL
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 10)
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_plan_search(plan, bt["Qd"][:11].contiguous())
+    assert e.value.status == hntl.HNTL_EINVAL
