@@ -175,12 +175,21 @@ hntl_status hntl_index_captured(const hntl_index* index, double* out);
 void hntl_index_free(hntl_index* index);
 
 /* Parameters of a search. */
+/* Routing of step 1. */
+typedef enum hntl_route {
+  HNTL_ROUTE_CENTROID = 0, /* the P grains with the closest centroids (Section 2.1 step 1) */
+  HNTL_ROUTE_LEARNED = 1   /* the P grains with the largest learned-router scores (see hntl_router_train) */
+} hntl_route;
+
 typedef struct hntl_search_params {
   uint32_t P;       /* probes per query, 1 <= P <= min(G, HNTL_MAX_P) */
   uint32_t C;       /* candidate pool per query, k <= C <= HNTL_MAX_C */
   uint32_t k;       /* results per query, >= 1 */
   uint32_t codes;   /* hntl_codes form to scan */
   uint32_t flags;   /* HNTL_FLAG_* */
+  uint32_t route;   /* hntl_route; LEARNED needs a trained or imported router (else ESTATE) */
+  float tau;        /* learned routing only: a query whose largest softmax probability over the grains
+                       is below tau is routed by centroids instead (0 = never) */
 } hntl_search_params;
 
 /*
@@ -328,6 +337,80 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
  */
 hntl_status hntl_schedule_lookup(const hntl_index* index, const hntl_search_params* sp, uint32_t max_nq,
                                  const char* db_path, hntl_schedule* out);
+
+/* ------------------------------------------------------------------------
+ * Learned router (an extension: the paper routes by centroid distance,
+ * Section 2.3, and lists learned partitioning as future work, Section 4)
+ * ------------------------------------------------------------------------
+ * An MLP d -> hidden1 -> hidden2 -> G with GELU (exact erf form) maps a
+ * standardised query xh = (q - mean) / std to one score per grain:
+ *   s = W3 gelu(W2 gelu(W1 xh + b1) + b2) + b3.
+ * Weights are FP32 with BF16 copies; the three GEMMs (and those of training)
+ * run on BF16 MFMA with FP32 accumulation; each GEMM operand is rounded to
+ * BF16 (nearest even).  Learned routing probes the P grains of largest score
+ * (ties: lower grain id).
+ */
+#define HNTL_ROUTER_KEEP_WEIGHTS 1u /* continue from the index's current router (no initialisation,
+                                       mean/std kept) */
+#define HNTL_ROUTER_NO_SHUFFLE 2u   /* batches in input order (default: reshuffled every epoch) */
+
+typedef struct hntl_router_params {
+  uint32_t hidden1, hidden2; /* hidden widths (0 = 1024); multiples of 8 */
+  uint32_t epochs;           /* passes over the training queries (0 = 1) */
+  uint32_t batch;            /* rows per Adam step (0 = 1024); a partial last batch is dropped */
+  uint32_t knn;              /* neighbours per training query forming its target (0 = 10, at most 16) */
+  uint32_t flags;            /* HNTL_ROUTER_* */
+  float lr;                  /* Adam step size (0 = 1e-3; beta1 0.9, beta2 0.999, eps 1e-8) */
+  uint64_t seed;             /* initialisation and shuffling (counter-based generator) */
+} hntl_router_params;
+
+/*
+ * hntl_router_train - train the index's router on n queries (device, n x d).
+ * Target of query i: the grain distribution of its exact knn nearest rows of
+ * the index (brute force on the GPU, see hntl_knn), or the given targets
+ * (device, n x knn grain ids, each weighing 1 / knn).  Loss: mean softmax
+ * cross-entropy; Adam on the FP32 masters.  Without HNTL_ROUTER_KEEP_WEIGHTS
+ * the router is (re)initialised (He-style uniform) and mean / std are the
+ * column statistics of the training queries.  epoch_loss (host, epochs floats)
+ * may be NULL.  Synchronous.  Errors: EINVAL (n < batch), EUNSUPPORTED (sizes
+ * not multiples of 8, knn > 16), ENOMEM, EDEVICE.
+ */
+hntl_status hntl_router_train(hntl_index* index, const float* Qtrain, uint32_t n, const int32_t* targets,
+                              const hntl_router_params* params, float* epoch_loss, void* stream);
+
+/*
+ * hntl_router_set / hntl_router_export - import or read the router's FP32
+ * weights: W1 hidden1 x d, b1 hidden1, W2 hidden2 x hidden1, b2 hidden2,
+ * W3 G x hidden2, b3 G (row-major, out x in), mean and std (d).  Pointers are
+ * host or device; export pointers may be NULL.  Synchronous.
+ */
+hntl_status hntl_router_set(hntl_index* index, uint32_t hidden1, uint32_t hidden2, const float* W1, const float* b1,
+                            const float* W2, const float* b2, const float* W3, const float* b3, const float* mean,
+                            const float* std);
+hntl_status hntl_router_export(const hntl_index* index, uint32_t* hidden1, uint32_t* hidden2, float* W1, float* b1,
+                               float* W2, float* b2, float* W3, float* b3, float* mean, float* std);
+
+/* hntl_router_forward - router scores of nq queries (device nq x d) into scores (device nq x G). */
+hntl_status hntl_router_forward(const hntl_index* index, const float* Q, uint32_t nq, float* scores, void* stream);
+
+/*
+ * hntl_router_grad - loss and gradients of the router at its current weights for
+ * the batch X (device, n x d) with targets (device, n x kt grain ids), without
+ * updating it: gW* / gb* (host or device, shaped like the weights; any may be NULL),
+ * *loss (host).  Synchronous.
+ */
+hntl_status hntl_router_grad(hntl_index* index, const float* X, uint32_t n, const int32_t* targets, uint32_t kt,
+                             float* loss, float* gW1, float* gb1, float* gW2, float* gb2, float* gW3, float* gb3,
+                             void* stream);
+
+/*
+ * hntl_knn - exact k nearest raw vectors of the index for nq queries (device),
+ * k <= 16: ids (device nq x k, original row ids, ascending distance, ties to the
+ * lower id) and dist (device nq x k squared L2, may be NULL).  A 32-entry MFMA
+ * expansion shortlist per query is re-scored by direct differences in FP32.
+ */
+hntl_status hntl_knn(const hntl_index* index, const float* Q, uint32_t nq, uint32_t k, int32_t* ids, float* dist,
+                     void* stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char* hntl_last_error(void);

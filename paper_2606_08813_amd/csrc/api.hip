@@ -25,6 +25,7 @@ Index::~Index() {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
+  router.reset();
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   (void)hipSetDevice(prev);
@@ -384,6 +385,9 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
   if (sp->codes > HNTL_CODES_FP8_E4M3) return fail(HNTL_EINVAL, "unknown codes form");
   if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
   if ((tangent_in == nullptr) != (epsq_in == nullptr)) return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
+  if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
+  const bool learned = sp->route == HNTL_ROUTE_LEARNED && !probes_in && !pool_in;
+  if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
   if (nq == 0) return HNTL_OK;
   if (!Q || !ids || !dist) return fail(HNTL_EINVAL, "Q, ids and dist are required");
   hipStream_t s = (hipStream_t)stream;
@@ -411,11 +415,17 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
       if (!probes) {
         clk.at(HNTL_STAGE_ROUTE);
         int32_t* pr = probes_out ? probes_out : sc.get<int32_t>(npairs);
-        float* qn = sc.get<float>(nq);
-        launch_row_norms(Q, nq, (int)ix.d, qn, s);
+        if (learned) {
+          RouterScratch w;
+          char* base = sc.get<char>(w.layout(nullptr, ix, nq, (int)P));
+          w.layout(base, ix, nq, (int)P);
+          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s);
+        }
         const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
-        float* Dm = sc.get<float>((size_t)std::min<int64_t>(chunk, nq) * ix.G);
-        for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+        float* qn = learned ? nullptr : sc.get<float>(nq);
+        float* Dm = learned ? nullptr : sc.get<float>((size_t)std::min<int64_t>(chunk, nq) * ix.G);
+        if (!learned) launch_row_norms(Q, nq, (int)ix.d, qn, s);
+        for (int64_t q0 = 0; q0 < nq && !learned; q0 += chunk) {
           const int64_t rows = std::min<int64_t>(chunk, nq - q0);
           launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
           launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,

@@ -221,11 +221,14 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const int n1 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_REST][G]);
   const int total = nP + n0 + n1;
 
-  // Each wave is its own worker: it takes tickets until they run out.  The
-  // fetch is one atomic for the wave (lane 0 adds 1, the others 0) whose
-  // lane-0 result is broadcast; nothing in the loop synchronises waves.
+  // Each wave is its own worker: it takes tickets until they run out, and
+  // nothing in the loop synchronises waves.  All 64 lanes add 1 to the
+  // counter, so it moves by 64 per fetch (the compiler folds the wave's adds
+  // into one atomic) and lane 0's old value / 64 is the wave's item.
+  int32_t __attribute__((address_space(1)))* ticket = (int32_t __attribute__((address_space(1)))*)a.ticket;
   for (;;) {
-    const int it = __builtin_amdgcn_readfirstlane(atomicAdd(a.ticket, lane == 0 ? 1 : 0));
+    const int it =
+        __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 6;
     if (it >= total) break;
     if (it < nP) {  // ---------------------------------------- projection
       const int rank = find_rank(a.ioff[LIST_ALL], G, it);
@@ -238,7 +241,9 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
       else
         project_wave<true, NCT>(a.Q, a.d, a.P, a.centroids, a.basis, a.r, g, pairs, cnt, a.T, a.epsq);
       // release: the tangents of this item are visible before the count is
-      __hip_atomic_fetch_add(&a.proj_done[g], lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // (every lane adds 1: an item counts 64)
+      __hip_atomic_fetch_add((int32_t __attribute__((address_space(1)))*)(a.proj_done + g), 1, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
     } else {  // ----------------------------------------------------- scan
       const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
       const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
       const int k = li - __builtin_amdgcn_readfirstlane(a.ioff[L][rank]);
       const int range = k / ntiles, tile = k % ntiles;  // range-major: a range's tiles run together
       // wait until every projection item of the grain has finished (acquire)
-      const int need = (__builtin_amdgcn_readfirstlane(a.lcount[LIST_ALL][g]) + 15) / 16;
+      const int need = (__builtin_amdgcn_readfirstlane(a.lcount[LIST_ALL][g]) + 15) / 16 * 64;
       for (long long spin = 0;; ++spin) {
         const int done = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&a.proj_done[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,34 @@ namespace hntl {
 // is padded to rp = 8 * ceil(r / 8) with zero coordinates, and padding lanes
 // of a grain's last block hold eps = +inf.
 constexpr int B = HNTL_BLOCK;
+
+// Learned router: MLP d -> h1 -> h2 -> G (FP32 masters, BF16 copies for the
+// MFMA GEMMs) and the input standardisation.  Layer l: W[l] is out x in,
+// row-major.
+struct Router {
+  int d = 0, h1 = 0, h2 = 0, G = 0;
+  float* W[3] = {};
+  float* b[3] = {};
+  uint16_t* Wb[3] = {};
+  float* mean = nullptr;
+  float* stdv = nullptr;
+  bool trained = false;
+  void alloc(int d, int h1, int h2, int G);
+  int64_t wsize(int l) const;
+  int64_t bsize(int l) const;
+  void refresh_bf16(hipStream_t s);
+  ~Router();
+};
+
+struct Index;
+// Buffers of one learned routing of up to nq queries.
+struct RouterScratch {
+  uint16_t *xh = nullptr, *h1 = nullptr, *h2 = nullptr;
+  float* negS = nullptr;
+  int32_t *fb_rows = nullptr, *fb_count = nullptr, *fb_probes = nullptr;
+  float *fb_Q = nullptr, *fb_qn = nullptr, *fb_pdist = nullptr;
+  size_t layout(char* base, const Index& ix, int64_t nq, int P);
+};
 
 struct Index {
   int device = 0;
@@ -48,6 +77,7 @@ struct Index {
   float* bhi = nullptr;        // G x rp: per-grain maximum
   float* emin = nullptr;       // G: per-grain minimum eps_i
   int32_t* gorder = nullptr;   // G: grains by size, largest first (made by the first search plan)
+  std::unique_ptr<Router> router;  // learned router (trained or imported), else null
 
   std::vector<int64_t> offsets_h;
   std::vector<int32_t> boff_h;
@@ -123,6 +153,11 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
                       const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0);
+
+// exact k nearest rows of B (cols x d) for every row of A (rows x d), k <= 16:
+// MFMA expansion shortlist of 32 per row, re-scored by direct differences
+void launch_knn(const float* A, int64_t rows, const float* Bm, int64_t cols, int d, int k, int32_t* ids, float* dist,
+                hipStream_t s);
 
 // grain bucketing of (query, probe) pairs; work-item lists cut from it
 enum { LIST_SLOT0 = 0, LIST_REST = 1, LIST_ALL = 2 };
@@ -207,6 +242,11 @@ struct FusedArgs {
   int proj_bf16;
   int prune;
 };
+
+// learned routing: probes by descending router score; rows whose largest
+// softmax probability is below tau fall back to centroid routing
+void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr);
 
 // build helpers
 void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);

@@ -112,7 +112,8 @@ std::string tune_key(const Index& ix, const hntl_search_params& sp, uint32_t nq)
   std::ostringstream k;
   k << device_key(ix.device) << " N=" << ix.N << " d=" << ix.d << " G=" << ix.G << " r=" << ix.r
     << " maxgrain=" << ix.max_grain << " P=" << sp.P << " C=" << sp.C << " k=" << sp.k << " codes=" << sp.codes
-    << " flags=" << (sp.flags & (HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE)) << " nq=" << nq;
+    << " flags=" << (sp.flags & (HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE)) << " route=" << sp.route
+    << " nq=" << nq;
   return k.str();
 }
 
@@ -153,6 +154,8 @@ struct Plan {
   float* epsq = nullptr;
   uint64_t* part = nullptr;
   uint64_t list_slots = 0;
+  // learned routing
+  RouterScratch rs;
   // graph
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -210,6 +213,11 @@ struct Plan {
     T = L.take<float>((size_t)np * x.r);
     epsq = L.take<float>(np);
     part = L.take<uint64_t>((size_t)list_slots * sp.C);
+    if (sp.route == HNTL_ROUTE_LEARNED) {
+      const size_t n = rs.layout(nullptr, x, max_nq, (int)sp.P);
+      char* rb = L.take<char>(n);
+      rs.layout(rb, x, max_nq, (int)sp.P);
+    }
     return L.off;
   }
 
@@ -269,8 +277,11 @@ struct Plan {
     launch_fill_i32(ticket, 1, 0, s);
     launch_fill_i32(proj_done, G, 0, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(qbound), max_nq, -1, s);
-    launch_row_norms(Q, max_nq, d, qn, s);
-    for (int64_t q0 = 0; q0 < (int64_t)max_nq; q0 += chunk) {
+    if (sp.route == HNTL_ROUTE_LEARNED)
+      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev);
+    else
+      launch_row_norms(Q, max_nq, d, qn, s);
+    for (int64_t q0 = 0; q0 < (int64_t)max_nq && sp.route != HNTL_ROUTE_LEARNED; q0 += chunk) {
       const int64_t rows = std::min<int64_t>(chunk, (int64_t)max_nq - q0);
       launch_dist_matrix(Q + q0 * d, qn + q0, rows, x.centroids, x.cnorm, G, d, Dm, s, nq_dev, q0);
       launch_topk_rows(Dm, rows, G, P, probes + q0 * P, nullptr, s, Q + q0 * d, qn + q0, x.centroids, x.cnorm, d,
@@ -307,6 +318,9 @@ void check_plan_shape(const Index& ix, const hntl_search_params& sp) {
   if (!(ix.codes_mask & (1u << sp.codes))) throw ArgError{HNTL_ESTATE, "codes form not built for this index"};
   if ((sp.flags & HNTL_FLAG_PROJECT_BF16) && !ix.basis_bf16)
     throw ArgError{HNTL_ESTATE, "BF16 projection needs the BF16 basis (build a reduced-precision code form)"};
+  if (sp.route > HNTL_ROUTE_LEARNED) throw ArgError{HNTL_EINVAL, "unknown route"};
+  if (sp.route == HNTL_ROUTE_LEARNED && !(ix.router && ix.router->trained))
+    throw ArgError{HNTL_ESTATE, "learned routing needs a trained router"};
   if (ix.d % 8 != 0) throw ArgError{HNTL_EUNSUPPORTED, "the fused kernel needs d % 8 == 0"};
   if (ix.rp != 16 && ix.rp != 32 && ix.rp != 48 && ix.rp != 64)
     throw ArgError{HNTL_EUNSUPPORTED, "the fused kernel needs a padded rank of 16, 32, 48 or 64"};
@@ -350,9 +364,6 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   pl->max_nq = max_nq;
   pl->flags = plan_flags;
   pl->device = ix.device;
-  if (sch.grid == 0) sch.grid = (uint32_t)fused_resident((int)sp.codes, (int)ix.rp, (int)sp.C, (int)sch.qt, (int)sch.nw);
-  if (sch.grid == 0) throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
-  pl->sch = sch;
   // list slots: per query at most the sum of its P largest split counts
   std::vector<int32_t> ns(ix.G);
   for (uint32_t g = 0; g < ix.G; ++g) {
@@ -361,6 +372,16 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   }
   std::vector<int32_t> srt(ns);
   std::sort(srt.begin(), srt.end(), std::greater<int32_t>());
+  if (sch.grid == 0) {
+    // as many workgroups as are resident at once, but no more waves than the
+    // largest possible number of work items
+    const uint64_t np = (uint64_t)max_nq * sp.P, gp = std::min<uint64_t>(ix.G, np);
+    const uint64_t items = (np + 15) / 16 + gp + (np / sch.qt + 2 * gp) * (uint64_t)srt[0];
+    const uint64_t res = (uint64_t)fused_resident((int)sp.codes, (int)ix.rp, (int)sp.C, (int)sch.qt, (int)sch.nw);
+    sch.grid = (uint32_t)std::min<uint64_t>(res, (items + sch.nw - 1) / sch.nw);
+  }
+  if (sch.grid == 0) throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
+  pl->sch = sch;
   uint64_t per_q = 0;
   for (uint32_t i = 0; i < sp.P; ++i) per_q += (uint64_t)srt[i];
   pl->list_slots = (uint64_t)max_nq * per_q;

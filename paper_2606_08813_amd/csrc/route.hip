@@ -300,6 +300,106 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
   }
 }
 
+// ------------------------------------------------------- brute-force kNN
+// Exact k nearest rows of B for every row of A (the learned router's training
+// targets).  Pass 1, grid (row tiles of 64, column splits): a workgroup walks
+// its column range in 64-wide tiles of MFMA expansion distances, stages each
+// 64 x 64 tile in LDS, and every wave keeps, for its 16 rows, the KNN_SHORT
+// smallest (distance, column) keys in register lists.  Pass 2 merges the
+// splits' lists per row, re-scores the merged shortlist by direct
+// differences in FP32 and keeps the k smallest exact distances (ties: lower
+// column).
+constexpr int KNN_SHORT = 32;
+
+__global__ __launch_bounds__(256) void knn_partial_kernel(const float* __restrict__ A, const float* __restrict__ an,
+                                                          int64_t rows, const float* __restrict__ Bm,
+                                                          const float* __restrict__ bn, int64_t cols, int d,
+                                                          int64_t per_split, uint64_t* __restrict__ part,
+                                                          bool vec4) {
+  __shared__ float tiles[2 * TM * LDT];  // As and Bs; then the 64 x 64 distance tile
+  __shared__ uint64_t stage[4][16][64];
+  float(*As)[LDT] = reinterpret_cast<float(*)[LDT]>(tiles);
+  float(*Bs)[LDT] = reinterpret_cast<float(*)[LDT]>(tiles + TM * LDT);
+  float(*Dt)[TN + 1] = reinterpret_cast<float(*)[TN + 1]>(tiles);
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * TM;
+  const int64_t c_begin = (int64_t)blockIdx.y * per_split;
+  const int64_t c_end = c_begin + per_split < cols ? c_begin + per_split : cols;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  WaveTop64 L[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) L[r].init(stage[wave][r], KNN_SHORT);
+  for (int64_t col0 = c_begin; col0 < c_end; col0 += TN) {
+    floatx4 acc[2][2];
+    tile_dot(acc, As, Bs, A, rows, Bm, (int)(c_end < cols ? c_end : cols), d, row0, (int)col0, vec4);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rl = wr + rt * 16 + 4 * (lane >> 4) + i;
+          const int cl = wc + ct * 16 + (lane & 15);
+          const int64_t row = row0 + rl, col = col0 + cl;
+          Dt[rl][cl] = (row < rows && col < c_end) ? fmaxf(an[row] + bn[col] - 2.f * acc[rt][ct][i], 0.f)
+                                                   : __builtin_inff();
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float v = Dt[16 * wave + r][lane];
+      const int64_t col = col0 + lane;
+      L[r].offer(make_key(v, (uint32_t)col), col < c_end);
+    }
+    __syncthreads();  // the next tile_dot overwrites the distance tile
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    L[r].finish();
+    const int64_t row = row0 + 16 * wave + r;
+    if (row < rows && lane < KNN_SHORT) part[((size_t)row * gridDim.y + blockIdx.y) * KNN_SHORT + lane] = L[r].best;
+  }
+}
+
+// One wave per row: merge the splits' shortlists, exact re-score, top k.
+__global__ __launch_bounds__(256) void knn_merge_kernel(const float* __restrict__ A, int64_t rows,
+                                                        const float* __restrict__ Bm, int d, int splits,
+                                                        const uint64_t* __restrict__ part, int k,
+                                                        int32_t* __restrict__ ids, float* __restrict__ dist) {
+  __shared__ uint64_t stage[4][64];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= rows) return;
+  WaveTop64 L;
+  L.init(stage[wave], KNN_SHORT);
+  for (int sp = 0; sp < splits; ++sp) {
+    const uint64_t key = lane < KNN_SHORT ? part[((size_t)row * splits + sp) * KNN_SHORT + lane] : KEY_NONE;
+    L.offer(key, key != KEY_NONE);
+  }
+  L.finish();
+  const uint64_t mine = L.best;
+  const float* a = A + row * d;
+  uint64_t ex = KEY_NONE;
+  for (int j = 0; j < KNN_SHORT; ++j) {
+    const uint64_t kj = shfl_u64(mine, j);
+    if (kj == KEY_NONE) break;
+    const uint32_t c = key_id(kj);
+    const float* b = Bm + (size_t)c * d;
+    float acc = 0.f;
+    for (int t = lane; t < d; t += HNTL_WAVE) {
+      const float df = a[t] - b[t];
+      acc = fmaf(df, df, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == j) ex = make_key(acc, c);
+  }
+  ex = wave_sort64(ex);
+  if (lane < k) {
+    ids[row * k + lane] = ex == KEY_NONE ? -1 : (int32_t)key_id(ex);
+    if (dist) dist[row * k + lane] = ex == KEY_NONE ? __builtin_inff() : key_dist(ex);
+  }
+}
+
 }  // namespace
 
 void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream_t s) {
@@ -343,6 +443,38 @@ int pow2_at_least(int x) {
   int p = 1;
   while (p < x) p <<= 1;
   return p;
+}
+
+}  // namespace hntl
+
+namespace hntl {
+
+void launch_knn(const float* A, int64_t rows, const float* Bm, int64_t cols, int d, int k, int32_t* ids, float* dist,
+                hipStream_t s) {
+  if (rows <= 0) return;
+  if (k < 1 || k > 16) throw ArgError{HNTL_EUNSUPPORTED, "brute-force kNN supports 1 <= k <= 16"};
+  if (cols >= (1ll << 31)) throw ArgError{HNTL_EUNSUPPORTED, "brute-force kNN needs fewer than 2^31 rows"};
+  const bool vec4 = (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
+  const int64_t rt = (rows + TM - 1) / TM;
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>((cols + TN - 1) / TN, 2048 / rt));
+  int64_t per = ((cols + splits - 1) / splits + TN - 1) / TN * TN;
+  splits = (cols + per - 1) / per;
+  float *an = nullptr, *bn = nullptr;
+  uint64_t* part = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&an, sizeof(float) * rows, s));
+  HIP_TRY(hipMallocAsync((void**)&bn, sizeof(float) * cols, s));
+  HIP_TRY(hipMallocAsync((void**)&part, sizeof(uint64_t) * rows * splits * KNN_SHORT, s));
+  launch_row_norms(A, rows, d, an, s);
+  launch_row_norms(Bm, cols, d, bn, s);
+  hipLaunchKernelGGL(knn_partial_kernel, dim3((unsigned)rt, (unsigned)splits), dim3(256), 0, s, A, an, rows, Bm, bn,
+                     cols, d, per, part, vec4);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, A, rows, Bm, d,
+                     (int)splits, part, k, ids, dist);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(an, s));
+  HIP_TRY(hipFreeAsync(bn, s));
+  HIP_TRY(hipFreeAsync(part, s));
 }
 
 }  // namespace hntl

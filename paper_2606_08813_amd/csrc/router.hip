@@ -1,0 +1,859 @@
+// Learned router: a small MLP that maps a query to one score per grain, whose
+// top-P grains replace centroid routing.  The paper routes by centroid
+// distance (Section 2.3) and names learned partitioning as future work
+// (Section 4); this is that extension.
+//
+//   xh = bf16((x - mean) / std)                      standardised input
+//   h1 = bf16(gelu(W1 xh + b1)),  h2 = bf16(gelu(W2 h1 + b2))
+//   s  = W3 h2 + b3                                   one score per grain
+//
+// GELU is the exact erf form (Hendrycks & Gimpel), computed with the device
+// erff.  Weights are FP32 masters with BF16 copies; every GEMM takes BF16
+// operands on the MFMA units (v_mfma_f32_16x16x32_bf16) and accumulates in
+// FP32; bias, GELU, softmax, loss and Adam run in FP32.
+//
+// Training (softmax cross-entropy, Adam of Kingma & Ba with bias
+// correction) targets the grain distribution of each training query's exact
+// k nearest neighbours: the fraction of them in each grain.  Backward pass,
+// per batch of B rows (rounding points as the forward: every GEMM operand
+// rounded to BF16):
+//
+//   ds  = (softmax(s) - y) / B;   gW3 = bf16(ds)^T h2,  gb3 = sum_b ds
+//   da2 = (bf16(ds) W3) * gelu'(a2);   gW2 = bf16(da2)^T h1,  gb2 = sum_b da2
+//   da1 = (bf16(da2) W2) * gelu'(a1);  gW1 = bf16(da1)^T xh,  gb1 = sum_b da1
+//
+// The GEMM kernel below is the one contraction of all of this: C = A . B^T in
+// the sense C[m][n] = sum_k A(m, k) B(n, k), with A and B each stored either
+// k-contiguous or (transposed) m- / n-contiguous, staged through LDS.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "hntl_device.h"
+#include "hntl_internal.h"
+
+namespace hntl {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------ GEMM
+constexpr int GM = 128, GN = 128, GK = 32, GLD = GK + 8;  // LDS rows padded by 8 bf16
+
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2, EPI_BIAS_F32 = 3 };
+struct Epi {
+  float* C;            // FP32 output (EPI_F32, EPI_BIAS_F32: the result; EPI_BIAS_GELU: pre-activation, optional)
+  int ldc;
+  const float* bias;   // N
+  uint16_t* H;         // BF16 output (EPI_BIAS_GELU: gelu(z); EPI_GELU_GRAD: bf16(acc * gelu'(z)))
+  int ldh;
+  const float* Z;      // EPI_GELU_GRAD: pre-activation
+  int ldz;
+  float* D;            // EPI_GELU_GRAD: FP32 acc * gelu'(z)
+  int ldd;
+  float scale;         // EPI_BIAS_F32: result = scale * (acc + bias)
+};
+
+// Loads a 128 x 32 tile of X(r, k) (rows r0.., depths k0..) into S[r][k].
+// XT = false: X(r, k) = X[r * ld + k]; XT = true: X(r, k) = X[k * ld + r].
+template <bool XT>
+__device__ __forceinline__ void gemm_load(uint16_t (*S)[GLD], const uint16_t* __restrict__ X, int ld, int R, int K,
+                                          int r0, int k0) {
+  const int t = threadIdx.x;
+  if (!XT) {
+    const int r = t >> 1, kk = (t & 1) * 16;
+    const int gr = r0 + r;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gk = k0 + kk + 8 * h;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gr < R && gk + 8 <= K) {
+        v = *reinterpret_cast<const uint4*>(X + (size_t)gr * ld + gk);
+      } else if (gr < R) {
+        uint16_t e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = gk + u < K ? X[(size_t)gr * ld + gk + u] : 0;
+        memcpy(&v, e, 16);
+      }
+      *reinterpret_cast<uint4*>(&S[r][kk + 8 * h]) = v;
+    }
+  } else {
+    const int k = t >> 3, rr = (t & 7) * 16;  // 32 depths x 8 runs of 16 rows
+    const int gk = k0 + k;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gr = r0 + rr + 8 * h;
+      uint16_t e[8];
+      if (gk < K && gr + 8 <= R) {
+        const uint4 v = *reinterpret_cast<const uint4*>(X + (size_t)gk * ld + gr);
+        memcpy(e, &v, 16);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = (gk < K && gr + u < R) ? X[(size_t)gk * ld + gr + u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S[rr + 8 * h + u][k] = e[u];
+    }
+  }
+}
+
+// One workgroup (4 waves) per 128 x 128 tile of C; wave w owns a 64 x 64
+// quarter as 4 x 4 MFMA 16x16 tiles.  Lane (i = lane % 16, kq = lane / 16)
+// feeds depths 8 kq .. 8 kq + 7 of row / column i to each MFMA and holds
+// C[4 kq + j][i] of each 16 x 16 output.  Rows from *mlim on are skipped.
+template <bool AT, bool BT, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int lda,
+                                                        const uint16_t* __restrict__ B, int ldb, int M, int N, int K,
+                                                        Epi e, const int32_t* __restrict__ mlim) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GM][GLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GN][GLD];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * GM, n0 = blockIdx.x * GN;
+  if (mlim) {
+    const int lim = *mlim;
+    if (m0 >= lim) return;
+    if (lim < M) M = lim;
+  }
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int i = lane & 15, kq = lane >> 4;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    gemm_load<AT>(As, A, lda, M, K, m0, k0);
+    gemm_load<BT>(Bs, B, ldb, N, K, n0, k0);
+    __syncthreads();
+    bf16x8 af[4], bfv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + i][8 * kq]);
+      bfv[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + i][8 * kq]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wm + 16 * a + 4 * kq + j;
+        const int col = n0 + wn + 16 * b + i;
+        if (row >= M || col >= N) continue;
+        const float v = acc[a][b][j];
+        if constexpr (EPI == EPI_F32) {
+          e.C[(size_t)row * e.ldc + col] = v;
+        } else if constexpr (EPI == EPI_BIAS_F32) {
+          e.C[(size_t)row * e.ldc + col] = e.scale * (v + e.bias[col]);
+        } else if constexpr (EPI == EPI_BIAS_GELU) {
+          const float z = v + e.bias[col];
+          if (e.C) e.C[(size_t)row * e.ldc + col] = z;
+          e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
+        } else {
+          const float gz = v * gelu_grad(e.Z[(size_t)row * e.ldz + col]);
+          e.D[(size_t)row * e.ldd + col] = gz;
+          e.H[(size_t)row * e.ldh + col] = to_bf16(gz);
+        }
+      }
+}
+
+template <bool AT, bool BT, int EPI>
+void gemm(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K, const Epi& e, hipStream_t s,
+          const int32_t* mlim = nullptr) {
+  if (M <= 0 || N <= 0) return;
+  const dim3 grid((unsigned)((N + GN - 1) / GN), (unsigned)((M + GM - 1) / GM));
+  hipLaunchKernelGGL((gemm_bf16_kernel<AT, BT, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, e, mlim);
+  HIP_TRY(hipGetLastError());
+}
+
+// ------------------------------------------------------ elementwise kernels
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// xh[r][j] = bf16((X[rows[r]][j] - mean[j]) / std[j]) (rows == null: r itself)
+__global__ void standardize_kernel(const float* __restrict__ X, const int32_t* __restrict__ rows, int64_t n, int d,
+                                   const float* __restrict__ mean, const float* __restrict__ stdv,
+                                   uint16_t* __restrict__ xh, const int32_t* __restrict__ nlim) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int64_t r = i / d;
+  const int j = (int)(i % d);
+  if (nlim && r >= *nlim) return;
+  const int64_t src = rows ? rows[r] : r;
+  xh[i] = to_bf16((X[src * d + j] - mean[j]) / stdv[j]);
+}
+
+// Column mean and standard deviation (FP64 accumulation) of n x d rows.
+__global__ void col_stats_kernel(const float* __restrict__ X, int64_t n, int d, float* __restrict__ mean,
+                                 float* __restrict__ stdv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < n; ++r) s += X[r * d + j];
+  const double mu = s / (double)n;
+  double v = 0.0;
+  for (int64_t r = 0; r < n; ++r) {
+    const double t = X[r * d + j] - mu;
+    v += t * t;
+  }
+  mean[j] = (float)mu;
+  const double sd = sqrt(v / (double)n);
+  stdv[j] = (float)(sd > 1e-12 ? sd : 1.0);
+}
+
+// Softmax cross-entropy of one row of scores against the target distribution
+// of `kt` grain ids (each weighing 1 / kt): ds = (p - y) / B in FP32 and BF16,
+// and the row's loss.  One workgroup of 256 per row.
+__global__ __launch_bounds__(256) void softmax_ce_kernel(const float* __restrict__ S, int G,
+                                                         const int32_t* __restrict__ tgt, int kt, float invB,
+                                                         float* __restrict__ ds, uint16_t* __restrict__ dsb,
+                                                         float* __restrict__ loss) {
+  __shared__ float red[256];
+  const int64_t r = blockIdx.x;
+  const float* s = S + r * G;
+  float m = -__builtin_inff();
+  for (int g = threadIdx.x; g < G; g += 256) m = fmaxf(m, s[g]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  m = red[0];
+  __syncthreads();
+  float z = 0.f;
+  for (int g = threadIdx.x; g < G; g += 256) z += expf(s[g] - m);
+  red[threadIdx.x] = z;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  z = red[0];
+  const float logz = logf(z);
+  const int32_t* t = tgt + r * kt;
+  const float w = 1.f / (float)kt;
+  for (int g = threadIdx.x; g < G; g += 256) {
+    float y = 0.f;
+    for (int q = 0; q < kt; ++q) y += t[q] == g ? w : 0.f;
+    const float p = expf(s[g] - m) / z;
+    const float v = (p - y) * invB;
+    ds[r * G + g] = v;
+    dsb[r * G + g] = to_bf16(v);
+  }
+  if (threadIdx.x == 0) {
+    float l = 0.f;
+    for (int q = 0; q < kt; ++q) {
+      const int g = t[q];
+      if (g >= 0 && g < G) l -= w * (s[g] - m - logz);
+    }
+    atomicAdd(loss, l * invB);
+  }
+}
+
+// out[n] = sum over rows of X[r][n] (bias gradients).
+__global__ void col_sum_kernel(const float* __restrict__ X, int rows, int N, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float acc = 0.f;
+  for (int r = 0; r < rows; ++r) acc += X[(size_t)r * N + n];
+  out[n] = acc;
+}
+
+// One Adam step of a tensor, and its BF16 copy when given.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2, uint16_t* __restrict__ wb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = to_bf16(wi);
+}
+
+// Max softmax probability of each row of negated scores (1 / sum exp(s - max));
+// rows below tau are appended to the fallback list.
+__global__ __launch_bounds__(256) void fallback_select_kernel(const float* __restrict__ negS, int64_t rows, int G,
+                                                              float tau, int32_t* __restrict__ fb_rows,
+                                                              int32_t* __restrict__ fb_count,
+                                                              const int32_t* __restrict__ nlim) {
+  const int lane = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows || (nlim && r >= *nlim)) return;
+  const float* s = negS + r * G;
+  float mn = __builtin_inff();
+  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
+  float z = 0.f;
+  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
+  z = wave_sum(z);
+  if (lane == 0 && 1.f / z < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
+}
+
+// Copies the query rows of the fallback list into a compact block.
+__global__ void gather_rows_kernel(const float* __restrict__ Q, int d, const int32_t* __restrict__ rows,
+                                   const int32_t* __restrict__ count, float* __restrict__ out) {
+  const int r = blockIdx.x;
+  if (r >= *count) return;
+  const float* src = Q + (size_t)rows[r] * d;
+  for (int j = threadIdx.x; j < d; j += blockDim.x) out[(size_t)r * d + j] = src[j];
+}
+
+// Writes the centroid-routing probes of the fallback rows back in place.
+__global__ void scatter_probes_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ count, int P,
+                                      const int32_t* __restrict__ src, const float* __restrict__ srcd,
+                                      int32_t* __restrict__ probes, float* __restrict__ pdist) {
+  const int r = blockIdx.x;
+  if (r >= *count) return;
+  const int q = rows[r];
+  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+    probes[(size_t)q * P + j] = src[(size_t)r * P + j];
+    if (pdist) pdist[(size_t)q * P + j] = srcd ? srcd[(size_t)r * P + j] : 0.f;
+  }
+}
+
+// Grain of every original row: lab[perm[pos]] = grain holding position pos.
+__global__ void row_grain_kernel(const int32_t* __restrict__ perm, const int32_t* __restrict__ goff, int G, int64_t N,
+                                 int32_t* __restrict__ lab) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= N) return;
+  int lo = 0, hi = G;  // largest g with goff[g] <= pos
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (goff[mid] <= pos)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  lab[perm[pos]] = lo;
+}
+
+__global__ void map_ids_kernel(const int32_t* __restrict__ ids, int64_t n, const int32_t* __restrict__ lab,
+                               int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ids[i] >= 0 ? lab[ids[i]] : -1;
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+uint64_t splitmix(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+double uni(uint64_t seed, uint64_t stream, uint64_t i) {
+  return (double)(splitmix(splitmix(seed ^ (stream * 0xD1B54A32D192ED03ull)) + i) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ router
+void Router::alloc(int d_, int h1_, int h2_, int G_) {
+  d = d_;
+  h1 = h1_;
+  h2 = h2_;
+  G = G_;
+  const int64_t n[3] = {(int64_t)h1 * d, (int64_t)h2 * h1, (int64_t)G * h2};
+  const int64_t nb[3] = {h1, h2, G};
+  for (int l = 0; l < 3; ++l) {
+    HIP_TRY(hipMalloc((void**)&W[l], sizeof(float) * n[l]));
+    HIP_TRY(hipMalloc((void**)&b[l], sizeof(float) * nb[l]));
+    HIP_TRY(hipMalloc((void**)&Wb[l], sizeof(uint16_t) * n[l]));
+  }
+  HIP_TRY(hipMalloc((void**)&mean, sizeof(float) * d));
+  HIP_TRY(hipMalloc((void**)&stdv, sizeof(float) * d));
+}
+
+Router::~Router() {
+  for (int l = 0; l < 3; ++l) {
+    if (W[l]) (void)hipFree(W[l]);
+    if (b[l]) (void)hipFree(b[l]);
+    if (Wb[l]) (void)hipFree(Wb[l]);
+  }
+  if (mean) (void)hipFree(mean);
+  if (stdv) (void)hipFree(stdv);
+}
+
+int64_t Router::wsize(int l) const { return l == 0 ? (int64_t)h1 * d : l == 1 ? (int64_t)h2 * h1 : (int64_t)G * h2; }
+int64_t Router::bsize(int l) const { return l == 0 ? h1 : l == 1 ? h2 : G; }
+
+void Router::refresh_bf16(hipStream_t s) {
+  for (int l = 0; l < 3; ++l)
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(wsize(l))), dim3(256), 0, s, W[l], wsize(l), Wb[l]);
+  HIP_TRY(hipGetLastError());
+}
+
+// Learned routing of nq rows of Q: probes (nq x P) by descending score (ties:
+// lower grain), pdist = the negated scores; rows whose largest softmax
+// probability is below tau use centroid routing instead.
+void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim) {
+  const Router& rt = *ix.router;
+  hipLaunchKernelGGL(standardize_kernel, dim3(blocks(nq * rt.d)), dim3(256), 0, s, Q, nullptr, nq, rt.d, rt.mean,
+                     rt.stdv, w.xh, nlim);
+  Epi e{};
+  e.bias = rt.b[0];
+  e.H = w.h1;
+  e.ldh = rt.h1;
+  gemm<false, false, EPI_BIAS_GELU>(w.xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s, nlim);
+  e.bias = rt.b[1];
+  e.H = w.h2;
+  e.ldh = rt.h2;
+  gemm<false, false, EPI_BIAS_GELU>(w.h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s, nlim);
+  Epi o{};
+  o.C = w.negS;
+  o.ldc = rt.G;
+  o.bias = rt.b[2];
+  o.scale = -1.f;
+  gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
+  launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, nlim, 0);
+  if (tau > 0.f) {
+    launch_fill_i32(w.fb_count, 1, 0, s);
+    hipLaunchKernelGGL(fallback_select_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, tau, w.fb_rows,
+                       w.fb_count, nlim);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)nq), dim3(256), 0, s, Q, (int)ix.d, w.fb_rows, w.fb_count,
+                       w.fb_Q);
+    launch_row_norms(w.fb_Q, nq, (int)ix.d, w.fb_qn, s);
+    const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
+    for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+      const int64_t rows = std::min<int64_t>(chunk, nq - q0);
+      launch_dist_matrix(w.fb_Q + q0 * ix.d, w.fb_qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d,
+                         w.negS, s, w.fb_count, q0);  // the scores are no longer needed: reuse as scratch
+      launch_topk_rows(w.negS, rows, (int)ix.G, P, w.fb_probes + q0 * P, w.fb_pdist + q0 * P, s,
+                       w.fb_Q + q0 * ix.d, w.fb_qn + q0, ix.centroids, ix.cnorm, (int)ix.d, w.fb_count, q0);
+    }
+    hipLaunchKernelGGL(scatter_probes_kernel, dim3((unsigned)nq), dim3(64), 0, s, w.fb_rows, w.fb_count, P,
+                       w.fb_probes, w.fb_pdist, probes, pdist);
+    HIP_TRY(hipGetLastError());
+  }
+}
+
+// Buffers of launch_route_learned carved from one block (base == nullptr:
+// sizing pass); returns the bytes used.
+size_t RouterScratch::layout(char* base, const Index& ix, int64_t nq, int P) {
+  const Router& rt = *ix.router;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) / 256 * 256;
+    char* p = base ? base + off : nullptr;
+    off += std::max<size_t>(bytes, 1);
+    return p;
+  };
+  xh = (uint16_t*)take(2 * (size_t)nq * rt.d);
+  h1 = (uint16_t*)take(2 * (size_t)nq * rt.h1);
+  h2 = (uint16_t*)take(2 * (size_t)nq * rt.h2);
+  const int64_t chunk = std::min<int64_t>(nq, std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G));
+  negS = (float*)take(4 * (size_t)std::max<int64_t>(nq * rt.G, chunk * ix.G));
+  fb_rows = (int32_t*)take(4 * (size_t)nq);
+  fb_count = (int32_t*)take(4);
+  fb_Q = (float*)take(4 * (size_t)nq * ix.d);
+  fb_qn = (float*)take(4 * (size_t)nq);
+  fb_probes = (int32_t*)take(4 * (size_t)nq * P);
+  fb_pdist = (float*)take(4 * (size_t)nq * P);
+  return off;
+}
+
+namespace {
+
+// Training state: Adam moments, gradients, activations of one batch.
+struct Trainer {
+  Router& rt;
+  int B;
+  hipStream_t s;
+  std::vector<void*> mem;
+  float* m[6] = {};
+  float* v[6] = {};
+  float* g[6] = {};
+  uint16_t *xh = nullptr, *h1 = nullptr, *h2 = nullptr, *dsb = nullptr, *da2b = nullptr, *da1b = nullptr;
+  float *a1 = nullptr, *a2 = nullptr, *S = nullptr, *ds = nullptr, *da2 = nullptr, *da1 = nullptr, *loss = nullptr;
+  int32_t* rows = nullptr;
+  int32_t* tgt = nullptr;
+  int step = 0;
+
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(T) * std::max<size_t>(n, 1)));
+    mem.push_back(p);
+    return (T*)p;
+  }
+  Trainer(Router& r, int B_, hipStream_t st) : rt(r), B(B_), s(st) {
+    for (int l = 0; l < 3; ++l) {
+      m[2 * l] = alloc<float>(rt.wsize(l));
+      v[2 * l] = alloc<float>(rt.wsize(l));
+      g[2 * l] = alloc<float>(rt.wsize(l));
+      m[2 * l + 1] = alloc<float>(rt.bsize(l));
+      v[2 * l + 1] = alloc<float>(rt.bsize(l));
+      g[2 * l + 1] = alloc<float>(rt.bsize(l));
+      HIP_TRY(hipMemsetAsync(m[2 * l], 0, sizeof(float) * rt.wsize(l), s));
+      HIP_TRY(hipMemsetAsync(v[2 * l], 0, sizeof(float) * rt.wsize(l), s));
+      HIP_TRY(hipMemsetAsync(m[2 * l + 1], 0, sizeof(float) * rt.bsize(l), s));
+      HIP_TRY(hipMemsetAsync(v[2 * l + 1], 0, sizeof(float) * rt.bsize(l), s));
+    }
+    xh = alloc<uint16_t>((size_t)B * rt.d);
+    h1 = alloc<uint16_t>((size_t)B * rt.h1);
+    h2 = alloc<uint16_t>((size_t)B * rt.h2);
+    a1 = alloc<float>((size_t)B * rt.h1);
+    a2 = alloc<float>((size_t)B * rt.h2);
+    S = alloc<float>((size_t)B * rt.G);
+    ds = alloc<float>((size_t)B * rt.G);
+    dsb = alloc<uint16_t>((size_t)B * rt.G);
+    da2 = alloc<float>((size_t)B * rt.h2);
+    da2b = alloc<uint16_t>((size_t)B * rt.h2);
+    da1 = alloc<float>((size_t)B * rt.h1);
+    da1b = alloc<uint16_t>((size_t)B * rt.h1);
+    loss = alloc<float>(1);
+    rows = alloc<int32_t>(B);
+  }
+  ~Trainer() {
+    for (void* p : mem) (void)hipFree(p);
+  }
+
+  // Loss and gradients of the batch X[rows[0..B)] against targets tg (B x kt).
+  void grad(const float* X, const int32_t* d_rows, const int32_t* tg, int kt) {
+    const int d = rt.d, H1 = rt.h1, H2 = rt.h2, G = rt.G;
+    hipLaunchKernelGGL(standardize_kernel, dim3(blocks((int64_t)B * d)), dim3(256), 0, s, X, d_rows, (int64_t)B, d,
+                       rt.mean, rt.stdv, xh, nullptr);
+    Epi e{};
+    e.C = a1;
+    e.ldc = H1;
+    e.bias = rt.b[0];
+    e.H = h1;
+    e.ldh = H1;
+    gemm<false, false, EPI_BIAS_GELU>(xh, d, rt.Wb[0], d, B, H1, d, e, s);
+    e.C = a2;
+    e.ldc = H2;
+    e.bias = rt.b[1];
+    e.H = h2;
+    e.ldh = H2;
+    gemm<false, false, EPI_BIAS_GELU>(h1, H1, rt.Wb[1], H1, B, H2, H1, e, s);
+    Epi o{};
+    o.C = S;
+    o.ldc = G;
+    o.bias = rt.b[2];
+    o.scale = 1.f;
+    gemm<false, false, EPI_BIAS_F32>(h2, H2, rt.Wb[2], H2, B, G, H2, o, s);
+    HIP_TRY(hipMemsetAsync(loss, 0, sizeof(float), s));
+    hipLaunchKernelGGL(softmax_ce_kernel, dim3(B), dim3(256), 0, s, S, G, tg, kt, 1.f / (float)B, ds, dsb, loss);
+    HIP_TRY(hipGetLastError());
+    // layer 3: gW3[g][k] = sum_b ds[b][g] h2[b][k]; dh2 = ds W3, times gelu'(a2)
+    Epi w{};
+    w.C = g[4];
+    w.ldc = H2;
+    gemm<true, true, EPI_F32>(dsb, G, h2, H2, G, H2, B, w, s);
+    hipLaunchKernelGGL(col_sum_kernel, dim3(blocks(G)), dim3(256), 0, s, ds, B, G, g[5]);
+    Epi gg{};
+    gg.Z = a2;
+    gg.ldz = H2;
+    gg.D = da2;
+    gg.ldd = H2;
+    gg.H = da2b;
+    gg.ldh = H2;
+    gemm<false, true, EPI_GELU_GRAD>(dsb, G, rt.Wb[2], H2, B, H2, G, gg, s);
+    // layer 2
+    w.C = g[2];
+    w.ldc = H1;
+    gemm<true, true, EPI_F32>(da2b, H2, h1, H1, H2, H1, B, w, s);
+    hipLaunchKernelGGL(col_sum_kernel, dim3(blocks(H2)), dim3(256), 0, s, da2, B, H2, g[3]);
+    gg.Z = a1;
+    gg.ldz = H1;
+    gg.D = da1;
+    gg.ldd = H1;
+    gg.H = da1b;
+    gg.ldh = H1;
+    gemm<false, true, EPI_GELU_GRAD>(da2b, H2, rt.Wb[1], H1, B, H1, H2, gg, s);
+    // layer 1
+    w.C = g[0];
+    w.ldc = d;
+    gemm<true, true, EPI_F32>(da1b, H1, xh, d, H1, d, B, w, s);
+    hipLaunchKernelGGL(col_sum_kernel, dim3(blocks(H1)), dim3(256), 0, s, da1, B, H1, g[1]);
+    HIP_TRY(hipGetLastError());
+  }
+
+  void adam(float lr) {
+    ++step;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    for (int l = 0; l < 3; ++l) {
+      hipLaunchKernelGGL(adam_kernel, dim3(blocks(rt.wsize(l))), dim3(256), 0, s, rt.W[l], g[2 * l], m[2 * l],
+                         v[2 * l], rt.wsize(l), lr, b1, b2, eps, c1, c2, rt.Wb[l]);
+      hipLaunchKernelGGL(adam_kernel, dim3(blocks(rt.bsize(l))), dim3(256), 0, s, rt.b[l], g[2 * l + 1],
+                         m[2 * l + 1], v[2 * l + 1], rt.bsize(l), lr, b1, b2, eps, c1, c2, (uint16_t*)nullptr);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+};
+
+template <class F>
+hntl_status guarded_r(F&& f) {
+  try {
+    f();
+    return HNTL_OK;
+  } catch (const ArgError& e) {
+    return fail(e.code, e.msg);
+  } catch (const HipError& e) {
+    return fail(e.code == hipErrorOutOfMemory || e.code == hipErrorMemoryAllocation ? HNTL_ENOMEM : HNTL_EDEVICE,
+                e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HNTL_ENOMEM, "host allocation failed");
+  }
+}
+
+void init_router(Index& ix, int h1, int h2) {
+  if (h1 < 1 || h2 < 1) throw ArgError{HNTL_EINVAL, "hidden sizes must be positive"};
+  if (ix.d % 8 || h1 % 8 || h2 % 8 || ix.G % 8)
+    throw ArgError{HNTL_EUNSUPPORTED, "the router needs d, hidden sizes and G to be multiples of 8"};
+  ix.router.reset(new Router());
+  ix.router->alloc((int)ix.d, h1, h2, (int)ix.G);
+}
+
+}  // namespace
+
+}  // namespace hntl
+
+using namespace hntl;
+
+extern "C" {
+
+hntl_status hntl_router_set(hntl_index* index, uint32_t h1, uint32_t h2, const float* W1, const float* b1,
+                            const float* W2, const float* b2, const float* W3, const float* b3, const float* mean,
+                            const float* stdv) {
+  set_error("");
+  if (!index || !W1 || !b1 || !W2 || !b2 || !W3 || !b3 || !mean || !stdv) return fail(HNTL_EINVAL, "null pointer");
+  return guarded_r([&] {
+    Index& ix = index->ix;
+    HIP_TRY(hipSetDevice(ix.device));
+    init_router(ix, (int)h1, (int)h2);
+    Router& rt = *ix.router;
+    const float* Ws[3] = {W1, W2, W3};
+    const float* bs[3] = {b1, b2, b3};
+    for (int l = 0; l < 3; ++l) {
+      HIP_TRY(hipMemcpy(rt.W[l], Ws[l], sizeof(float) * rt.wsize(l), hipMemcpyDefault));
+      HIP_TRY(hipMemcpy(rt.b[l], bs[l], sizeof(float) * rt.bsize(l), hipMemcpyDefault));
+    }
+    HIP_TRY(hipMemcpy(rt.mean, mean, sizeof(float) * ix.d, hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(rt.stdv, stdv, sizeof(float) * ix.d, hipMemcpyDefault));
+    rt.refresh_bf16(nullptr);
+    HIP_TRY(hipDeviceSynchronize());
+    rt.trained = true;
+  });
+}
+
+hntl_status hntl_router_export(const hntl_index* index, uint32_t* h1, uint32_t* h2, float* W1, float* b1, float* W2,
+                               float* b2, float* W3, float* b3, float* mean, float* stdv) {
+  set_error("");
+  if (!index) return fail(HNTL_EINVAL, "null index");
+  const Index& ix = index->ix;
+  if (!ix.router) return fail(HNTL_ESTATE, "the index has no router");
+  return guarded_r([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    const Router& rt = *ix.router;
+    if (h1) *h1 = (uint32_t)rt.h1;
+    if (h2) *h2 = (uint32_t)rt.h2;
+    float* Ws[3] = {W1, W2, W3};
+    float* bs[3] = {b1, b2, b3};
+    HIP_TRY(hipDeviceSynchronize());
+    for (int l = 0; l < 3; ++l) {
+      if (Ws[l]) HIP_TRY(hipMemcpy(Ws[l], rt.W[l], sizeof(float) * rt.wsize(l), hipMemcpyDefault));
+      if (bs[l]) HIP_TRY(hipMemcpy(bs[l], rt.b[l], sizeof(float) * rt.bsize(l), hipMemcpyDefault));
+    }
+    if (mean) HIP_TRY(hipMemcpy(mean, rt.mean, sizeof(float) * ix.d, hipMemcpyDefault));
+    if (stdv) HIP_TRY(hipMemcpy(stdv, rt.stdv, sizeof(float) * ix.d, hipMemcpyDefault));
+  });
+}
+
+hntl_status hntl_router_grad(hntl_index* index, const float* X, uint32_t n, const int32_t* targets, uint32_t kt,
+                             float* loss, float* gW1, float* gb1, float* gW2, float* gb2, float* gW3, float* gb3,
+                             void* stream) {
+  set_error("");
+  if (!index || !X || !targets) return fail(HNTL_EINVAL, "null pointer");
+  Index& ix = index->ix;
+  if (!ix.router) return fail(HNTL_ESTATE, "the index has no router");
+  if (n == 0 || kt == 0) return fail(HNTL_EINVAL, "n and kt must be positive");
+  return guarded_r([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    hipStream_t s = (hipStream_t)stream;
+    Router& rt = *ix.router;
+    Trainer tr(rt, (int)n, s);
+    std::vector<int32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    HIP_TRY(hipMemcpyAsync(tr.rows, idx.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    tr.grad(X, tr.rows, targets, (int)kt);
+    float* outs[6] = {gW1, gb1, gW2, gb2, gW3, gb3};
+    for (int l = 0; l < 3; ++l) {
+      if (outs[2 * l]) HIP_TRY(hipMemcpyAsync(outs[2 * l], tr.g[2 * l], sizeof(float) * rt.wsize(l), hipMemcpyDefault, s));
+      if (outs[2 * l + 1])
+        HIP_TRY(hipMemcpyAsync(outs[2 * l + 1], tr.g[2 * l + 1], sizeof(float) * rt.bsize(l), hipMemcpyDefault, s));
+    }
+    if (loss) HIP_TRY(hipMemcpyAsync(loss, tr.loss, sizeof(float), hipMemcpyDefault, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  });
+}
+
+hntl_status hntl_router_forward(const hntl_index* index, const float* Q, uint32_t nq, float* scores, void* stream) {
+  set_error("");
+  if (!index || !Q || !scores) return fail(HNTL_EINVAL, "null pointer");
+  const Index& ix = index->ix;
+  if (!ix.router) return fail(HNTL_ESTATE, "the index has no router");
+  if (nq == 0) return HNTL_OK;
+  return guarded_r([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    hipStream_t s = (hipStream_t)stream;
+    const Router& rt = *ix.router;
+    Scratch sc(s);
+    uint16_t* xh = sc.get<uint16_t>((size_t)nq * rt.d);
+    uint16_t* h1 = sc.get<uint16_t>((size_t)nq * rt.h1);
+    uint16_t* h2 = sc.get<uint16_t>((size_t)nq * rt.h2);
+    hipLaunchKernelGGL(standardize_kernel, dim3(blocks((int64_t)nq * rt.d)), dim3(256), 0, s, Q, nullptr,
+                       (int64_t)nq, rt.d, rt.mean, rt.stdv, xh, nullptr);
+    Epi e{};
+    e.bias = rt.b[0];
+    e.H = h1;
+    e.ldh = rt.h1;
+    gemm<false, false, EPI_BIAS_GELU>(xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s);
+    e.bias = rt.b[1];
+    e.H = h2;
+    e.ldh = rt.h2;
+    gemm<false, false, EPI_BIAS_GELU>(h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s);
+    Epi o{};
+    o.C = scores;
+    o.ldc = rt.G;
+    o.bias = rt.b[2];
+    o.scale = 1.f;
+    gemm<false, false, EPI_BIAS_F32>(h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s);
+  });
+}
+
+hntl_status hntl_knn(const hntl_index* index, const float* Q, uint32_t nq, uint32_t k, int32_t* ids, float* dist,
+                     void* stream) {
+  set_error("");
+  if (!index || !Q || !ids) return fail(HNTL_EINVAL, "null pointer");
+  if (nq == 0) return HNTL_OK;
+  const Index& ix = index->ix;
+  return guarded_r([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    launch_knn(Q, nq, ix.X, (int64_t)ix.N, (int)ix.d, (int)k, ids, dist, (hipStream_t)stream);
+  });
+}
+
+hntl_status hntl_router_train(hntl_index* index, const float* Qtrain, uint32_t n, const int32_t* targets,
+                              const hntl_router_params* rp, float* epoch_loss, void* stream) {
+  set_error("");
+  if (!index || !Qtrain || !rp) return fail(HNTL_EINVAL, "null pointer");
+  Index& ix = index->ix;
+  const uint32_t B = rp->batch ? rp->batch : 1024;
+  const uint32_t kt = rp->knn ? rp->knn : 10;
+  if (n < B) return fail(HNTL_EINVAL, "need at least one full batch of training queries");
+  if (kt > 16) return fail(HNTL_EUNSUPPORTED, "targets from at most 16 neighbours");
+  return guarded_r([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    hipStream_t s = (hipStream_t)stream;
+    const bool keep = (rp->flags & HNTL_ROUTER_KEEP_WEIGHTS) && ix.router;
+    if (!keep) {
+      init_router(ix, (int)(rp->hidden1 ? rp->hidden1 : 1024), (int)(rp->hidden2 ? rp->hidden2 : 1024));
+      Router& rt = *ix.router;
+      // He-style uniform initialisation from the counter-based generator
+      for (int l = 0; l < 3; ++l) {
+        const int fan_in = l == 0 ? rt.d : l == 1 ? rt.h1 : rt.h2;
+        const double bound = std::sqrt((l < 2 ? 6.0 : 3.0) / fan_in);
+        std::vector<float> w(rt.wsize(l));
+        for (size_t i = 0; i < w.size(); ++i) w[i] = (float)((2.0 * uni(rp->seed, 10 + l, i) - 1.0) * bound);
+        HIP_TRY(hipMemcpy(rt.W[l], w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(rt.b[l], 0, sizeof(float) * rt.bsize(l)));
+      }
+      hipLaunchKernelGGL(col_stats_kernel, dim3(blocks(ix.d)), dim3(256), 0, s, Qtrain, (int64_t)n, (int)ix.d,
+                         rt.mean, rt.stdv);
+      rt.refresh_bf16(s);
+    }
+    Router& rt = *ix.router;
+    // targets: grains of each training query's exact kt nearest neighbours
+    int32_t* tg = nullptr;
+    std::unique_ptr<int32_t, void (*)(int32_t*)> tg_own(nullptr, [](int32_t* p) { (void)hipFree(p); });
+    if (targets) {
+      tg = const_cast<int32_t*>(targets);
+    } else {
+      int32_t *ids = nullptr, *lab = nullptr;
+      HIP_TRY(hipMalloc((void**)&tg, sizeof(int32_t) * (size_t)n * kt));
+      tg_own.reset(tg);
+      HIP_TRY(hipMalloc((void**)&ids, sizeof(int32_t) * (size_t)n * kt));
+      HIP_TRY(hipMalloc((void**)&lab, sizeof(int32_t) * ix.N));
+      launch_knn(Qtrain, n, ix.X, (int64_t)ix.N, (int)ix.d, (int)kt, ids, nullptr, s);
+      hipLaunchKernelGGL(row_grain_kernel, dim3(blocks((int64_t)ix.N)), dim3(256), 0, s, ix.perm, ix.goff, (int)ix.G,
+                         (int64_t)ix.N, lab);
+      hipLaunchKernelGGL(map_ids_kernel, dim3(blocks((int64_t)n * kt)), dim3(256), 0, s, ids, (int64_t)n * kt, lab, tg);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipStreamSynchronize(s));
+      (void)hipFree(ids);
+      (void)hipFree(lab);
+    }
+    Trainer tr(rt, (int)B, s);
+    const uint32_t nb = n / B;  // full batches per epoch
+    const uint32_t epochs = rp->epochs ? rp->epochs : 1;
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    int32_t* d_order = nullptr;
+    int32_t* tgb = nullptr;
+    HIP_TRY(hipMalloc((void**)&d_order, sizeof(int32_t) * n));
+    HIP_TRY(hipMalloc((void**)&tgb, sizeof(int32_t) * (size_t)B * kt));
+    std::unique_ptr<int32_t, void (*)(int32_t*)> o1(d_order, [](int32_t* p) { (void)hipFree(p); });
+    std::unique_ptr<int32_t, void (*)(int32_t*)> o2(tgb, [](int32_t* p) { (void)hipFree(p); });
+    std::vector<int32_t> tg_h((size_t)n * kt);
+    HIP_TRY(hipMemcpyAsync(tg_h.data(), tg, sizeof(int32_t) * tg_h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> tgb_h((size_t)B * kt);
+    for (uint32_t ep = 0; ep < epochs; ++ep) {
+      if (!(rp->flags & HNTL_ROUTER_NO_SHUFFLE))  // Fisher-Yates from the counter-based generator
+        for (uint32_t i = n - 1; i > 0; --i) {
+          const uint32_t j = (uint32_t)(uni(rp->seed, 100 + ep, i) * (double)(i + 1));
+          std::swap(order[i], order[std::min(j, i)]);
+        }
+      HIP_TRY(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+      double eloss = 0.0;
+      for (uint32_t bi = 0; bi < nb; ++bi) {
+        for (uint32_t r = 0; r < B; ++r)
+          std::memcpy(&tgb_h[(size_t)r * kt], &tg_h[(size_t)order[bi * B + r] * kt], sizeof(int32_t) * kt);
+        HIP_TRY(hipMemcpyAsync(tgb, tgb_h.data(), sizeof(int32_t) * tgb_h.size(), hipMemcpyHostToDevice, s));
+        tr.grad(Qtrain, d_order + (size_t)bi * B, tgb, (int)kt);
+        tr.adam(rp->lr > 0 ? rp->lr : 1e-3f);
+        float l = 0.f;
+        HIP_TRY(hipMemcpyAsync(&l, tr.loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));  // also keeps tgb_h from being overwritten early
+        eloss += l;
+      }
+      if (epoch_loss) epoch_loss[ep] = (float)(eloss / nb);
+    }
+    rt.trained = true;
+  });
+}
+
+}  // extern "C"

@@ -20,6 +20,9 @@ LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
+HNTL_ROUTE_CENTROID, HNTL_ROUTE_LEARNED = 0, 1
+HNTL_ROUTER_KEEP_WEIGHTS, HNTL_ROUTER_NO_SHUFFLE = 1, 2
+ROUTES = {"centroid": HNTL_ROUTE_CENTROID, "learned": HNTL_ROUTE_LEARNED}
 STAGES = ("route", "bucket", "project", "scan", "rerank")
 HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 48, 64
 CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3}
@@ -33,7 +36,12 @@ class hntl_build_params(C.Structure):
 
 class hntl_search_params(C.Structure):
     _fields_ = [("P", C.c_uint32), ("C", C.c_uint32), ("k", C.c_uint32), ("codes", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("route", C.c_uint32), ("tau", C.c_float)]
+
+
+class hntl_router_params(C.Structure):
+    _fields_ = [("hidden1", C.c_uint32), ("hidden2", C.c_uint32), ("epochs", C.c_uint32), ("batch", C.c_uint32),
+                ("knn", C.c_uint32), ("flags", C.c_uint32), ("lr", C.c_float), ("seed", C.c_uint64)]
 
 
 class hntl_index_info(C.Structure):
@@ -89,6 +97,14 @@ EXPORTS = {
                             C.POINTER(hntl_schedule), C.POINTER(C.c_float), C.c_void_p]),
     "hntl_schedule_lookup": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_uint32, C.c_char_p,
                                        C.POINTER(hntl_schedule)]),
+    "hntl_router_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(hntl_router_params),
+                                    C.c_void_p, C.c_void_p]),
+    "hntl_router_set": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32] + [C.c_void_p] * 8),
+    "hntl_router_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)] + [C.c_void_p] * 8),
+    "hntl_router_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "hntl_router_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32] + [C.c_void_p] * 7
+                         + [C.c_void_p]),
+    "hntl_knn": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hntl_last_error": (C.c_char_p, []),
     "hntl_version": (C.c_char_p, []),
 }
@@ -247,11 +263,13 @@ def hntl_index_free(index: Index):
         index.handle = None
 
 
-def _params(P, C_, k, codes, flags):
-    return hntl_search_params(P, C_, k, CODES[codes] if isinstance(codes, str) else codes, flags)
+def _params(P, C_, k, codes, flags, route="centroid", tau=0.0):
+    return hntl_search_params(P, C_, k, CODES[codes] if isinstance(codes, str) else codes, flags,
+                              ROUTES[route] if isinstance(route, str) else route, tau)
 
 
-def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None):
+def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None,
+                route="centroid", tau=0.0):
     """Top-k ids (int32) and squared distances (float32) per query, as CUDA tensors."""
     import torch
     _cuda_f32(Q, "Q")
@@ -261,7 +279,7 @@ def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0,
         dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
     else:
         ids, dist = out
-    sp = _params(P, C_, k, codes, flags)
+    sp = _params(P, C_, k, codes, flags, route, tau)
     _check(lib().hntl_search(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
                              _stream(stream)))
     return ids, dist
@@ -278,7 +296,8 @@ def hntl_profile_read():
 
 
 def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=HNTL_FLAG_SYNC,
-                       probes_in=None, tangent_in=None, epsq_in=None, pool_in=None, stream=None):
+                       probes_in=None, tangent_in=None, epsq_in=None, pool_in=None, stream=None,
+                       route="centroid", tau=0.0):
     """Run the lifecycle with stage outputs returned and optional stage inputs (CUDA tensors)."""
     import torch
     _cuda_f32(Q, "Q")
@@ -297,7 +316,7 @@ def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", f
         o["pool_D"] = torch.full((nq, C_), float("nan"), dtype=torch.float32, device=dev)
     o["ids"] = torch.full((nq, k), -7, dtype=torch.int32, device=dev)
     o["dist"] = torch.full((nq, k), float("nan"), dtype=torch.float32, device=dev)
-    sp = _params(P, C_, k, codes, flags)
+    sp = _params(P, C_, k, codes, flags, route, tau)
     _check(lib().hntl_search_stages(
         index.handle, Q.data_ptr(), nq, C.byref(sp), _ptr(probes_in), _ptr(o.get("probes")), _ptr(o.get("pdist")),
         _ptr(tangent_in), _ptr(epsq_in), _ptr(o.get("zq")), _ptr(o.get("epsq")), _ptr(pool_in),
@@ -337,8 +356,8 @@ def sched_dict(s: hntl_schedule) -> dict:
 
 
 def hntl_plan_create(index: Index, P: int, C_: int, k: int, max_nq: int, codes="fp32", flags=0, sched=None,
-                     graph=True, stream=None) -> Plan:
-    sp = _params(P, C_, k, codes, flags)
+                     graph=True, stream=None, route="centroid", tau=0.0) -> Plan:
+    sp = _params(P, C_, k, codes, flags, route, tau)
     sc = _sched(sched)
     h = C.c_void_p()
     _check(lib().hntl_plan_create(index.handle, C.byref(sp), max_nq, C.byref(sc) if sc is not None else None,
@@ -384,10 +403,11 @@ def hntl_plan_free(plan: Plan):
         plan.handle = None
 
 
-def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, db_path=None, stream=None):
+def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, db_path=None, stream=None,
+              route="centroid", tau=0.0):
     """Autotune the fused kernel's schedule on the batch Q; returns (schedule dict, median ms)."""
     _cuda_f32(Q, "Q")
-    sp = _params(P, C_, k, codes, flags)
+    sp = _params(P, C_, k, codes, flags, route, tau)
     best = hntl_schedule()
     ms = C.c_float(0.0)
     _check(lib().hntl_tune(index.handle, C.byref(sp), Q.data_ptr(), Q.shape[0],
@@ -395,8 +415,72 @@ def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, d
     return sched_dict(best), ms.value
 
 
-def hntl_schedule_lookup(index: Index, P: int, C_: int, k: int, max_nq: int, db_path, codes="fp32", flags=0):
-    sp = _params(P, C_, k, codes, flags)
+def hntl_schedule_lookup(index: Index, P: int, C_: int, k: int, max_nq: int, db_path, codes="fp32", flags=0,
+                         route="centroid", tau=0.0):
+    sp = _params(P, C_, k, codes, flags, route, tau)
     out = hntl_schedule()
     _check(lib().hntl_schedule_lookup(index.handle, C.byref(sp), max_nq, str(db_path).encode(), C.byref(out)))
     return sched_dict(out)
+
+
+# ----------------------------------------------------------------- learned router
+def hntl_router_train(index: Index, Qtrain, targets=None, hidden=(1024, 1024), epochs=1, batch=1024, knn=10,
+                      lr=1e-3, seed=0, flags=0, stream=None):
+    """Train the index's router on Qtrain (CUDA float32, n x d); returns the per-epoch mean losses."""
+    _cuda_f32(Qtrain, "Qtrain")
+    rp = hntl_router_params(hidden[0], hidden[1], epochs, batch, knn, flags, lr, seed)
+    losses = np.zeros(max(1, epochs), np.float32)
+    _check(lib().hntl_router_train(index.handle, Qtrain.data_ptr(), Qtrain.shape[0], _ptr(targets), C.byref(rp),
+                                   losses.ctypes.data, _stream(stream)))
+    return losses
+
+
+def hntl_router_set(index: Index, params: dict, mean, std):
+    """Import router weights (numpy float32: W1, b1, W2, b2, W3, b3) and the input standardisation."""
+    a = {k: np.ascontiguousarray(params[k], dtype=np.float32) for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+    m = np.ascontiguousarray(mean, dtype=np.float32)
+    s = np.ascontiguousarray(std, dtype=np.float32)
+    _check(lib().hntl_router_set(index.handle, a["W1"].shape[0], a["W2"].shape[0], *(a[k].ctypes.data for k in
+                                 ("W1", "b1", "W2", "b2", "W3", "b3")), m.ctypes.data, s.ctypes.data))
+
+
+def hntl_router_export(index: Index) -> dict:
+    h1, h2 = C.c_uint32(), C.c_uint32()
+    _check(lib().hntl_router_export(index.handle, C.byref(h1), C.byref(h2), *([None] * 8)))
+    d, G = index.d, index.G
+    out = {"W1": np.empty((h1.value, d), np.float32), "b1": np.empty(h1.value, np.float32),
+           "W2": np.empty((h2.value, h1.value), np.float32), "b2": np.empty(h2.value, np.float32),
+           "W3": np.empty((G, h2.value), np.float32), "b3": np.empty(G, np.float32),
+           "mean": np.empty(d, np.float32), "std": np.empty(d, np.float32)}
+    _check(lib().hntl_router_export(index.handle, None, None, *(out[k].ctypes.data for k in
+                                    ("W1", "b1", "W2", "b2", "W3", "b3", "mean", "std"))))
+    return out
+
+
+def hntl_router_forward(index: Index, Q, stream=None):
+    import torch
+    _cuda_f32(Q, "Q")
+    s = torch.empty((Q.shape[0], index.G), dtype=torch.float32, device=Q.device)
+    _check(lib().hntl_router_forward(index.handle, Q.data_ptr(), Q.shape[0], s.data_ptr(), _stream(stream)))
+    return s
+
+
+def hntl_router_grad(index: Index, X, targets):
+    """Loss and gradients (numpy float32 dict) of the router at its current weights."""
+    _cuda_f32(X, "X")
+    w = hntl_router_export(index)
+    g = {k: np.empty_like(w[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+    loss = np.zeros(1, np.float32)
+    _check(lib().hntl_router_grad(index.handle, X.data_ptr(), X.shape[0], targets.data_ptr(), targets.shape[1],
+                                  loss.ctypes.data, *(g[k].ctypes.data for k in ("W1", "b1", "W2", "b2", "W3", "b3")),
+                                  _stream(None)))
+    return float(loss[0]), g
+
+
+def hntl_knn(index: Index, Q, k: int, stream=None):
+    import torch
+    _cuda_f32(Q, "Q")
+    ids = torch.empty((Q.shape[0], k), dtype=torch.int32, device=Q.device)
+    dist = torch.empty((Q.shape[0], k), dtype=torch.float32, device=Q.device)
+    _check(lib().hntl_knn(index.handle, Q.data_ptr(), Q.shape[0], k, ids.data_ptr(), dist.data_ptr(), _stream(stream)))
+    return ids, dist
