@@ -5,6 +5,15 @@ index G = 1,024 k-means grains, r = 32; one batch of 10,000 queries; P = 8,
 C = 64, k = 10; FP32.  A step is one full search of the batch (route, bucket,
 project, scan + select, merge + rerank), inputs resident in HBM.
 
+Other forms (same JSON line; --workload zipf10M_d768_G8192_r48 is the 10M-vector
+Zipf-grain batching workload, 16,384 queries per step, P = 16, C = 100):
+  --form plan      the persistent fused project-scan-select kernel inside an
+                   autotuned search plan whose launch sequence replays as a HIP
+                   graph; stage times come from an eager profiled run
+  --route learned  the learned router, trained first on --router-train
+                   generated queries with brute-force kNN targets
+  --codes bf16|fp8 reduced-precision codes (BF16 MFMA projection by default)
+
 Prints one JSON line: queries/s (whole job), ns per vector scanned,
 Recall@10 against exact brute force on a query sample, per-stage device times
 from HIP events recorded by the library on its stream during the timed steps,
@@ -51,6 +60,16 @@ def parse():
                     help="with --codes bf16/fp8, keep the FP32 projection (default: BF16 MFMA projection)")
     ap.add_argument("--error-sample", type=int, default=100,
                     help="queries for the reduced-precision error report against the FP64 oracle")
+    ap.add_argument("--form", choices=("staged", "plan"), default="staged",
+                    help="staged: hntl_search; plan: the persistent fused kernel in an autotuned, graph-replayed plan")
+    ap.add_argument("--route", choices=("centroid", "learned"), default="centroid",
+                    help="learned: train the router first (router-train queries, brute-force kNN targets)")
+    ap.add_argument("--P", type=int, default=0, help="probes per query (0 = the workload's)")
+    ap.add_argument("--tau", type=float, default=0.0, help="learned routing: centroid fallback below this max prob")
+    ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
+    ap.add_argument("--router-epochs", type=int, default=8)
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="run one plain device copy of this many GiB first (calibrates HBM counters)")
     return ap.parse_args()
 
 
@@ -65,6 +84,16 @@ def main():
     from paper_2606_08813_amd import hntl
 
     W = WORKLOADS[args.workload]
+    if args.copy_gib > 0:  # a copy of known size: n bytes read, n bytes written
+        n = int(args.copy_gib * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {n * 4} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
     t0 = time.time()
     corpus = W.corpus()
     queries = W.queries()
@@ -86,6 +115,20 @@ def main():
     torch.cuda.empty_cache()
 
     stream = torch.cuda.current_stream()
+    P = args.P or W.P
+    router = None
+    if args.route == "learned":
+        from workloads.configs import ROUTER_TRAIN_SEED
+        t0 = time.time()
+        Qtr = torch.from_numpy(W.queries(nq=args.router_train, query_seed=ROUTER_TRAIN_SEED).X).to(dev)
+        losses = hntl.hntl_router_train(ix, Qtr, hidden=(1024, 1024), epochs=args.router_epochs, batch=1024, knn=10,
+                                        lr=1e-3, seed=1)
+        torch.cuda.synchronize()
+        router = {"train_queries": args.router_train, "epochs": args.router_epochs, "hidden": [1024, 1024],
+                  "train_s": round(time.time() - t0, 1), "epoch_loss": [round(float(x), 4) for x in losses],
+                  "tau": args.tau}
+        log(f"[bench] router trained in {router['train_s']}s, losses {router['epoch_loss']}")
+        del Qtr
     ids = torch.empty((W.nq, W.k), dtype=torch.int32, device=dev)
     dist = torch.empty((W.nq, W.k), dtype=torch.float32, device=dev)
     flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
@@ -94,32 +137,56 @@ def main():
     bf16_project = args.codes != "fp32" and not args.fp32_project
     if bf16_project:
         flags |= hntl.HNTL_FLAG_PROJECT_BF16
-    for _ in range(args.warmup):
-        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, flags=flags & ~hntl.HNTL_FLAG_PROFILE,
-                         out=(ids, dist))
-    torch.cuda.synchronize()
-    hntl.hntl_profile_read()  # drop warm-up records
+    rkw = dict(route=args.route, tau=args.tau)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=args.codes, flags=flags, out=(ids, dist))
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    stage_ms, calls, scored_total = hntl.hntl_profile_read()
-    stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
-    scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
+    sched = None
+    if args.form == "staged":
+        for _ in range(args.warmup):
+            hntl.hntl_search(ix, Q, P, W.C, W.k, codes=args.codes, flags=flags & ~hntl.HNTL_FLAG_PROFILE,
+                             out=(ids, dist), **rkw)
+        torch.cuda.synchronize()
+        hntl.hntl_profile_read()  # drop warm-up records
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            hntl.hntl_search(ix, Q, P, W.C, W.k, codes=args.codes, flags=flags, out=(ids, dist), **rkw)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_per_step = ev0.elapsed_time(ev1) / args.steps
+        stage_ms, calls, scored_total = hntl.hntl_profile_read()
+        stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
+        scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
+    else:
+        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE)
+        t0 = time.time()
+        sched, tuned_ms = hntl.hntl_tune(ix, Q, P, W.C, W.k, codes=args.codes, flags=pflags, **rkw)
+        log(f"[bench] autotuned schedule {sched} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
+        plan = hntl.hntl_plan_create(ix, P, W.C, W.k, W.nq, codes=args.codes, flags=pflags, sched=sched,
+                                     graph=True, **rkw)
+        for _ in range(args.warmup):
+            hntl.hntl_plan_search(plan, Q, out=(ids, dist))
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            hntl.hntl_plan_search(plan, Q, out=(ids, dist))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_per_step = ev0.elapsed_time(ev1) / args.steps
+        stage_avg, scored = hntl.hntl_plan_profile(plan, W.nq, reps=3)
+        stage_avg = {("scan" if k == "fused" else k): v for k, v in stage_avg.items()}
+        assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
     qps = W.nq / (ms_per_step / 1e3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
         f"{qps:,.0f} queries/s; stages {stage_avg}")
 
     # work accounting from one staged run (probes -> vectors scanned per step)
-    o = hntl.hntl_search_stages(ix, Q, W.P, W.C, W.k, codes=args.codes,
-                                flags=hntl.HNTL_FLAG_SYNC | (flags & hntl.HNTL_FLAG_PROJECT_BF16))
+    o = hntl.hntl_search_stages(ix, Q, P, W.C, W.k, codes=args.codes,
+                                flags=hntl.HNTL_FLAG_SYNC | (flags & hntl.HNTL_FLAG_PROJECT_BF16), **rkw)
     probes = o["probes"].cpu().numpy()
     ex = hntl.hntl_index_export(ix)
     sizes = np.diff(ex["offsets"])
@@ -146,7 +213,7 @@ def main():
         rel = []
         for i in range(len(es)):
             m = {}
-            for sl in range(W.P):
+            for sl in range(P):
                 gi, gd = osr.grain_scores(zq64[i, sl], eq64[i, sl], int(probes_s[i, sl]), ex)
                 m.update(zip(gi.tolist(), gd.tolist()))
             for pid, pd in zip(pool_ids[i], pool_D[i]):
@@ -166,15 +233,18 @@ def main():
         log(f"[bench] precision report: {precision}")
 
     # rooflines per stage (algorithmic work per launch / average stage time)
-    npairs = W.nq * W.P
+    npairs = W.nq * P
     rp = (W.r + 7) // 8 * 8
     code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1}[args.codes]
+    route_work = (2.0 * W.nq * (W.d * 1024 + 1024 * 1024 + 1024 * W.G) if args.route == "learned"
+                  else 2.0 * W.nq * W.G * W.d)
     per_stage = {
-        "route": dict(bound="mfma", work=2.0 * W.nq * W.G * W.d, unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS),
+        "route": dict(bound="mfma", work=route_work, unit="TFLOP/s",
+                      peak=BF16_MFMA_PEAK_TFLOPS if args.route == "learned" else FP32_MFMA_PEAK_TFLOPS),
         "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s",
                         peak=BF16_MFMA_PEAK_TFLOPS if bf16_project else FP32_MFMA_PEAK_TFLOPS),
         "scan": dict(bound="alu", work=3.0 * W.r * (scored or scanned), unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
-        "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * W.P * W.C * 8, unit="GB/s",
+        "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * P * W.C * 8, unit="GB/s",
                        peak=HBM_PEAK_GBS),
     }
     roof = {}
@@ -197,7 +267,7 @@ def main():
         cs = np.random.default_rng(11).choice(W.nq, size=min(args.cpu_sample, W.nq), replace=False)
         with threadpool_limits(1):
             t0 = time.time()
-            osr.search(queries.X[cs], ex, corpus.X, W.P, W.C, W.k)
+            osr.search(queries.X[cs], ex, corpus.X, P, W.C, W.k)
             el = time.time() - t0
         cpu = {"value": round(len(cs) / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
                "sample": f"{len(cs)} of the {W.nq} queries, full lifecycle in float64 (numpy, 1 thread), "
@@ -219,8 +289,9 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.codes],
         "data": "synthetic",
         "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
-                   "P": W.P, "C": W.C, "k": W.k, "codes": args.codes,
-                   "projection": "bf16" if bf16_project else "fp32"},
+                   "P": P, "C": W.C, "k": W.k, "codes": args.codes,
+                   "projection": "bf16" if bf16_project else "fp32", "form": args.form, "route": args.route,
+                   "schedule": sched},
         "recall_at_10": round(recall, 4),
         "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
         "scan_ns_per_vector_scored": round(scan_ms * 1e6 / scored, 5) if (scan_ms and scored) else None,
@@ -235,6 +306,7 @@ def main():
         "stage_rooflines": roof,
         "cpu_baseline": cpu,
         "precision": precision,
+        "router": router,
     }
     print(json.dumps(out), flush=True)
 

@@ -317,6 +317,17 @@ typedef struct hntl_plan_info {
 /* hntl_plan_info_get - plan facts; synchronises the plan's last stream to read wait_errors. */
 hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out);
 
+/*
+ * hntl_plan_profile - run the plan reps times without its graph, with HIP events
+ * between its stages on `stream`, and return the mean device milliseconds per stage
+ * in stage_ms[0..4): routing, bucketing (with the resets), the fused
+ * project-scan-select kernel, merge + rerank.  *scored (may be NULL) receives the
+ * eq. 6 scores the last run computed.  The queries are the first nq rows of the
+ * plan's Q buffer.  Synchronous.
+ */
+hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, double* stage_ms, uint64_t* scored,
+                              void* stream);
+
 void hntl_plan_free(hntl_plan* plan);
 
 /*

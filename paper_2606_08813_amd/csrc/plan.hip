@@ -154,6 +154,7 @@ struct Plan {
   float* epsq = nullptr;
   uint64_t* part = nullptr;
   uint64_t list_slots = 0;
+  unsigned long long* scored = nullptr;  // eq. 6 scores of the last run
   // learned routing
   RouterScratch rs;
   // graph
@@ -213,6 +214,7 @@ struct Plan {
     T = L.take<float>((size_t)np * x.r);
     epsq = L.take<float>(np);
     part = L.take<uint64_t>((size_t)list_slots * sp.C);
+    scored = L.take<unsigned long long>(1);
     if (sp.route == HNTL_ROUTE_LEARNED) {
       const size_t n = rs.layout(nullptr, x, max_nq, (int)sp.P);
       char* rb = L.take<char>(n);
@@ -264,17 +266,21 @@ struct Plan {
     a.T = T;
     a.epsq = epsq;
     a.part = part;
-    a.scored = nullptr;
+    a.scored = scored;
     a.proj_bf16 = (sp.flags & HNTL_FLAG_PROJECT_BF16) ? 1 : 0;
     a.prune = (sp.flags & HNTL_FLAG_NO_PRUNE) ? 0 : 1;
     return a;
   }
 
-  // The launch sequence of one run (batch size already in nq_dev).
-  void enqueue(hipStream_t s) {
+  // The launch sequence of one run (batch size already in nq_dev).  With
+  // `ev` (5 events) the stage boundaries are recorded: route, bucketing,
+  // fused kernel, merge + rerank.
+  void enqueue(hipStream_t s, hipEvent_t* ev = nullptr) {
     const Index& x = *ix;
     const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     launch_fill_i32(ticket, 1, 0, s);
+    launch_fill_i32(reinterpret_cast<int32_t*>(scored), 2, 0, s);
     launch_fill_i32(proj_done, G, 0, s);
     launch_fill_i32(reinterpret_cast<int32_t*>(qbound), max_nq, -1, s);
     if (sp.route == HNTL_ROUTE_LEARNED)
@@ -287,13 +293,17 @@ struct Plan {
       launch_topk_rows(Dm, rows, G, P, probes + q0 * P, nullptr, s, Q + q0 * d, qn + q0, x.centroids, x.cnorm, d,
                        nq_dev, q0);
     }
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (!fused_launch((int)sp.codes, args_dev, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid, s))
       throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
     HIP_TRY(hipGetLastError());
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     launch_merge_rerank(x, Q, max_nq, P, (int)sp.C, (int)sp.k, probes, part, nullptr, nullptr, nullptr, ids, dist, s,
                         sch.range ? qoff : nullptr);
+    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
   }
 
   void run(uint32_t nq, hipStream_t s) {
@@ -536,6 +546,43 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out) {
     out->device_bytes = pl.arena_bytes;
     out->list_slots = pl.list_slots;
     out->wait_errors = read_wait_errors(pl);
+  });
+}
+
+hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, double* stage_ms, uint64_t* scored,
+                              void* stream) {
+  set_error("");
+  if (!plan || !stage_ms) return fail(HNTL_EINVAL, "null pointer");
+  Plan& pl = *plan->p;
+  if (nq > pl.max_nq) return fail(HNTL_EINVAL, "nq exceeds the plan's max_nq");
+  if (reps == 0) return fail(HNTL_EINVAL, "reps must be positive");
+  return guarded_call([&] {
+    HIP_TRY(hipSetDevice(pl.device));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    std::vector<double> acc(4, 0.0);
+    unsigned long long sc = 0;
+    try {
+      for (uint32_t rep = 0; rep < reps; ++rep) {
+        hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl.nq_dev, (int32_t)nq);
+        pl.enqueue(s, ev);
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        for (int i = 0; i < 4; ++i) {
+          float t = 0.f;
+          HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+          acc[i] += t;
+        }
+        HIP_TRY(hipMemcpy(&sc, pl.scored, sizeof(sc), hipMemcpyDeviceToHost));
+      }
+    } catch (...) {
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i] / reps;
+    if (scored) *scored = sc;
+    pl.last_stream = s;
   });
 }
 

@@ -93,6 +93,7 @@ EXPORTS = {
     "hntl_plan_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hntl_plan_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_plan_info)]),
     "hntl_plan_free": (None, [C.c_void_p]),
+    "hntl_plan_profile": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hntl_tune": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_void_p, C.c_uint32, C.c_char_p,
                             C.POINTER(hntl_schedule), C.POINTER(C.c_float), C.c_void_p]),
     "hntl_schedule_lookup": (C.c_int, [C.c_void_p, C.POINTER(hntl_search_params), C.c_uint32, C.c_char_p,
@@ -395,6 +396,18 @@ def hntl_plan_info_get(plan: Plan) -> dict:
     _check(lib().hntl_plan_info_get(plan.handle, C.byref(info)))
     return {"max_nq": info.max_nq, "sched": sched_dict(info.sched), "graph": bool(info.graph),
             "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors}
+
+
+PLAN_STAGES = ("route", "bucket", "fused", "rerank")
+
+
+def hntl_plan_profile(plan: Plan, nq: int, reps=3, stream=None):
+    """Mean device ms per plan stage over reps eager runs of the queries already in
+    the plan's buffer, and the eq. 6 scores of the last run."""
+    ms = np.zeros(4, np.float64)
+    sc = C.c_uint64(0)
+    _check(lib().hntl_plan_profile(plan.handle, nq, reps, ms.ctypes.data, C.byref(sc), _stream(stream)))
+    return dict(zip(PLAN_STAGES, ms.tolist())), sc.value
 
 
 def hntl_plan_free(plan: Plan):
