@@ -9,6 +9,8 @@
 // them: per list L and grain g, lstart[L][g] / lcount[L][g] give the pairs, and
 // the exclusive prefix ioff[L][g] of ceil(lcount / tile_L) numbers its items;
 // a kernel finds the grain of item i by binary search in ioff.
+#include <algorithm>
+
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -86,52 +88,99 @@ __device__ int block_exclusive_scan(int v, int* tmp /* >= 16 ints */, int& total
   return wsum + x - v;
 }
 
+// Exclusive scan of four values per thread of a 1024-thread workgroup.
+__device__ void block_exclusive_scan4(const int (&v)[4], int (&ex)[4], int (&total)[4], int (*tmp)[4]) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int x[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    x[c] = v[c];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x[c], o, 64);
+      if (lane >= o) x[c] += y;
+    }
+  }
+  if (lane == 63)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tmp[wave][c] = x[c];
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int wsum = 0, all = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int t = tmp[w][c];
+      if (w < wave) wsum += t;
+      all += t;
+    }
+    ex[c] = wsum + x[c] - v[c];
+    total[c] = all;
+  }
+  __syncthreads();
+}
+
 // Single workgroup: grain ranges, the three lists' ranges and item offsets.
 // Grains are visited in the order `gorder` (rank -> grain; identity if null)
 // and ioff is indexed by that rank, so items come out in that order; lstart and
 // lcount stay indexed by grain.  With `nsplit`, a grain's slot-0 and rest
 // tiles each become nsplit[g] items (one per block range of the grain).
+// Thread t owns the consecutive ranks t * per .. t * per + per - 1: a local
+// pass sums its pairs and items, one workgroup scan turns the sums into
+// offsets, a second local pass writes them.
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __restrict__ gcount,
                                                            const int32_t* __restrict__ gcount0, int G,
                                                            const int32_t* __restrict__ gorder,
                                                            const int32_t* __restrict__ nsplit,
                                                            int32_t* __restrict__ gstart, int32_t* __restrict__ cur0,
                                                            int32_t* __restrict__ cur1, ItemLists lists) {
-  __shared__ int tmp[32];
-  int carry_p = 0, carry[3] = {0, 0, 0};
-  for (int base = 0; base < G; base += 1024) {
-    const int rank = base + (int)threadIdx.x;
-    const int g = rank < G ? (gorder ? gorder[rank] : rank) : G;
-    const int c = g < G ? gcount[g] : 0;
-    const int c0 = g < G ? gcount0[g] : 0;
-    const int split = (g < G && nsplit) ? nsplit[g] : 1;
-    int tot;
-    const int sp = block_exclusive_scan(c, tmp, tot);
-    const int st = carry_p + sp;
-    carry_p += tot;
-    const int lc[3] = {c0, c - c0, c};
-    const int ls[3] = {st, st + c0, st};
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-      const int tile = lists.tile[L];
-      const int nt = (lc[L] + tile - 1) / tile * (L == LIST_ALL ? 1 : split);
-      int tt;
-      const int so = block_exclusive_scan(nt, tmp, tt);
-      if (g < G) {
-        lists.ioff[L][rank] = carry[L] + so;
-        lists.lstart[L][g] = ls[L];
-        lists.lcount[L][g] = lc[L];
-      }
-      carry[L] += tt;
-    }
-    if (g < G) {
-      gstart[g] = st;
-      cur0[g] = 0;
-      cur1[g] = 0;
-    }
+  __shared__ int tmp[16][4];
+  const int per = (G + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int r0 = (int)threadIdx.x * per;
+  const int t0 = lists.tile[LIST_SLOT0], t1 = lists.tile[LIST_REST], t2 = lists.tile[LIST_ALL];
+  int loc[4] = {0, 0, 0, 0};  // pairs, items of slot 0, of the rest, of all
+  for (int i = 0; i < per; ++i) {
+    const int rank = r0 + i;
+    if (rank >= G) break;
+    const int g = gorder ? gorder[rank] : rank;
+    const int c = gcount[g], c0 = gcount0[g];
+    const int split = nsplit ? nsplit[g] : 1;
+    loc[0] += c;
+    loc[1] += (c0 + t0 - 1) / t0 * split;
+    loc[2] += (c - c0 + t1 - 1) / t1 * split;
+    loc[3] += (c + t2 - 1) / t2;
   }
-  if (threadIdx.x == 0)
-    for (int L = 0; L < 3; ++L) lists.ioff[L][G] = carry[L];
+  int run[4], tot[4];
+  block_exclusive_scan4(loc, run, tot, tmp);
+  for (int i = 0; i < per; ++i) {
+    const int rank = r0 + i;
+    if (rank >= G) break;
+    const int g = gorder ? gorder[rank] : rank;
+    const int c = gcount[g], c0 = gcount0[g];
+    const int split = nsplit ? nsplit[g] : 1;
+    const int st = run[0];
+    gstart[g] = st;
+    cur0[g] = 0;
+    cur1[g] = 0;
+    lists.ioff[LIST_SLOT0][rank] = run[1];
+    lists.ioff[LIST_REST][rank] = run[2];
+    lists.ioff[LIST_ALL][rank] = run[3];
+    lists.lstart[LIST_SLOT0][g] = st;
+    lists.lcount[LIST_SLOT0][g] = c0;
+    lists.lstart[LIST_REST][g] = st + c0;
+    lists.lcount[LIST_REST][g] = c - c0;
+    lists.lstart[LIST_ALL][g] = st;
+    lists.lcount[LIST_ALL][g] = c;
+    run[0] += c;
+    run[1] += (c0 + t0 - 1) / t0 * split;
+    run[2] += (c - c0 + t1 - 1) / t1 * split;
+    run[3] += (c + t2 - 1) / t2;
+  }
+  if (threadIdx.x == 0) {
+    lists.ioff[LIST_SLOT0][G] = tot[1];
+    lists.ioff[LIST_REST][G] = tot[2];
+    lists.ioff[LIST_ALL][G] = tot[3];
+  }
 }
 
 // Scatter pair ids into their grain's range (slot 0 first): each workgroup
@@ -228,6 +277,12 @@ __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void fill_multi_kernel(FillList L) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < L.n; ++k)
+    if (i < L.seg[k].n) L.seg[k].p[i] = L.seg[k].v;
+}
+
 }  // namespace
 
 // Fill with a kernel rather than hipMemsetAsync, so that captured graphs hold
@@ -238,6 +293,14 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   HIP_TRY(hipGetLastError());
 }
 
+void launch_fill_multi(const FillList& L, hipStream_t s) {
+  int64_t n = 0;
+  for (int k = 0; k < L.n; ++k) n = std::max<int64_t>(n, L.seg[k].n);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_multi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L);
+  HIP_TRY(hipGetLastError());
+}
+
 void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
                        int32_t* qoff, hipStream_t s) {
   hipLaunchKernelGGL(pair_lists_kernel, dim3(1), dim3(1024), 0, s, probes, nq, P, G, nsplit, lbase, qoff);
@@ -245,10 +308,15 @@ void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const in
 }
 
 void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s,
-                   const int32_t* gorder, const int32_t* nsplit) {
+                   const int32_t* gorder, const int32_t* nsplit, bool counts_zeroed) {
   const int64_t npairs = nq * P;
-  launch_fill_i32(b.gcount, G, 0, s);
-  launch_fill_i32(b.gcount0, G, 0, s);
+  if (!counts_zeroed) {
+    FillList f{};
+    f.seg[0] = FillSeg{b.gcount, G, 0};
+    f.seg[1] = FillSeg{b.gcount0, G, 0};
+    f.n = 2;
+    launch_fill_multi(f, s);
+  }
   const unsigned nb = (unsigned)((npairs + CHUNK - 1) / CHUNK);
   if (npairs > 0) {
     hipLaunchKernelGGL(bucket_hist_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G ? 2 * G * sizeof(int) : 0, s,

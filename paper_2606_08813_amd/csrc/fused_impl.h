@@ -193,14 +193,11 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
       if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[p / P], (uint32_t)(own >> 32));
       const int64_t slot = (a.lbase ? (int64_t)a.lbase[p] : (int64_t)p) + range;
       uint64_t* out = a.part + (size_t)slot * C;
-      if constexpr (CAP == 64) {
-        const uint64_t kk = Ls[t].best;
-        if (lane < C) out[lane] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
-      } else {
-        for (int i = lane; i < C; i += HNTL_WAVE) {
-          const uint64_t kk = Ls[t].best[i];
-          out[i] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
-        }
+#pragma unroll
+      for (int rr = 0; rr < CAP / 64; ++rr) {
+        const int i = rr * 64 + lane;
+        const uint64_t kk = Ls[t].best[rr];
+        if (i < C) out[i] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
       }
     }
   }

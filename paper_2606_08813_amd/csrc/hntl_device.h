@@ -54,121 +54,17 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// ------------------------------------------------------- wave top-C selection
-// One wave keeps the C smallest keys of a stream in LDS.  Layout: best[CAP]
-// (sorted ascending) followed by stage[CAP] (unsorted arrivals).  A key is
-// staged only if it beats the current threshold (the C-th best key); when the
-// stage would overflow it is bitonic-sorted and merged into best.  CAP is a
-// power of two >= max(C, 64).  This is the threshold + buffer + merging
-// network scheme of GPU k-selection (Johnson, Douze, Jegou, "Billion-scale
-// similarity search with GPUs"), laid out for 64-wide waves and LDS.
-template <int CAP>
-struct WaveTopC {
-  uint64_t* best;
-  uint64_t* stage;
-  uint64_t thr;
-  uint64_t bound;  // keys >= bound are never kept (a threshold known in advance)
-  int nstage;
-  int C;
-
-  __device__ __forceinline__ void init(uint64_t* lds, int C_, uint64_t bound_ = KEY_NONE) {
-    best = lds;
-    stage = lds + CAP;
-    C = C_;
-    nstage = 0;
-    bound = bound_;
-    thr = bound_;
-    for (int i = lane_id(); i < CAP; i += HNTL_WAVE) best[i] = KEY_NONE;
-    wave_sync();
-  }
-
-  __device__ __forceinline__ static void cas(uint64_t* s, int i, int p, bool up) {
-    uint64_t a = s[i], b = s[p];
-    if ((a > b) == up) {
-      s[i] = b;
-      s[p] = a;
-    }
-  }
-
-  __device__ void sort_stage() {
-    const int lane = lane_id();
-#pragma unroll 1
-    for (int k = 2; k <= CAP; k <<= 1) {
-#pragma unroll 1
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = lane; t < CAP / 2; t += HNTL_WAVE) {
-          int i = 2 * t - (t & (j - 1));
-          cas(stage, i, i + j, (i & k) == 0);
-        }
-        wave_sync();
-      }
-    }
-  }
-
-  __device__ void flush() {
-    if (nstage == 0) return;
-    const int lane = lane_id();
-    for (int i = nstage + lane; i < CAP; i += HNTL_WAVE) stage[i] = KEY_NONE;
-    wave_sync();
-    sort_stage();
-    // half-cleaner: min of ascending best and descending stage is bitonic and
-    // holds the CAP smallest of the union
-    for (int i = lane; i < CAP; i += HNTL_WAVE) {
-      uint64_t a = best[i], b = stage[CAP - 1 - i];
-      best[i] = a < b ? a : b;
-    }
-    wave_sync();
-#pragma unroll 1
-    for (int j = CAP >> 1; j > 0; j >>= 1) {
-      for (int t = lane; t < CAP / 2; t += HNTL_WAVE) {
-        int i = 2 * t - (t & (j - 1));
-        cas(best, i, i + j, true);
-      }
-      wave_sync();
-    }
-    const uint64_t t = best[C - 1];
-    thr = t < bound ? t : bound;
-    nstage = 0;
-  }
-
-  // Every lane offers one key (valid == false: no candidate from this lane).
-  __device__ __forceinline__ void offer(uint64_t key, bool valid) {
-    bool pass = valid && key < thr;
-    uint64_t m = __ballot(pass);
-    if (m == 0) return;
-    int cnt = __popcll(m);
-    if (nstage + cnt > CAP) {
-      flush();
-      pass = valid && key < thr;
-      m = __ballot(pass);
-      if (m == 0) return;
-      cnt = __popcll(m);
-    }
-    if (pass) stage[nstage + mbcnt64(m)] = key;
-    nstage += cnt;
-  }
-
-  __device__ __forceinline__ void finish() {
-    flush();
-    wave_sync();
-  }
-
-  // Lowers the bound to b (a threshold learned while scanning).
-  __device__ __forceinline__ void tighten(uint64_t b) {
-    if (b < bound) bound = b;
-    if (b < thr) thr = b;
-  }
-  // The C-th smallest key merged so far (KEY_NONE while fewer than C).
-  __device__ __forceinline__ uint64_t cth() const { return best[C - 1]; }
-};
-
 // ------------------------------------------- register-resident top-64 list
-// The same selection for C <= 64 with the sorted best list held in registers,
-// one key per lane (lane i holds the i-th smallest).  Arrivals are compacted
-// into a 64-entry LDS stage as above; a flush loads the stage one key per lane,
-// sorts it with a bitonic network across the lanes (shuffles, no LDS round
-// trips) and merges it into the register list.  Threshold and stage count
-// are wave-uniform and kept in scalar registers.
+// One wave keeps the C <= 64 smallest keys of a stream, the sorted list held
+// in registers, one key per lane (lane i holds the i-th smallest).  A key is
+// staged only if it beats the current threshold (the C-th best key); arrivals
+// are compacted into a 64-entry LDS stage, and when the stage would overflow
+// a flush loads it one key per lane, sorts it with a bitonic network across
+// the lanes (shuffles, no LDS round trips) and merges it into the register
+// list.  Threshold and stage count are wave-uniform (scalar registers).  This
+// is the threshold + buffer + merging-network scheme of GPU k-selection
+// (Johnson, Douze, Jegou, "Billion-scale similarity search with GPUs"), laid
+// out for 64-wide waves.
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
   const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
@@ -267,6 +163,102 @@ struct WaveTop64 {
     if (b < thr) thr = b;
   }
   __device__ __forceinline__ uint64_t cth() const { return uniform_u64(shfl_u64(best, C - 1)); }
+};
+
+// ------------------------------------- register-resident top-(64 NR) list
+// WaveTop64 widened to C <= 64 NR: the sorted list is NR keys per lane, list
+// element r * 64 + lane in best[r].  A flush sorts the (at most 64) staged
+// arrivals across the lanes, folds them into the last register block with a
+// half-cleaner against the reversed arrivals (the elementwise minimum of the
+// ascending list and the descending arrivals is bitonic and holds the 64 NR
+// smallest of both), then sorts that bitonic sequence: compare-exchanges
+// between register blocks for strides of 64 and more, lane shuffles below.
+template <int NR>
+struct WaveTopR {
+  uint64_t* stage;   // 64 keys of LDS
+  uint64_t best[NR];
+  uint64_t thr;      // uniform
+  uint64_t bound;    // uniform
+  int nstage;        // uniform
+  int C;
+
+  __device__ __forceinline__ void init(uint64_t* lds, int C_, uint64_t bound_ = KEY_NONE) {
+    stage = lds;
+    C = C_;
+    nstage = 0;
+    bound = bound_;
+    thr = bound_;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) best[r] = KEY_NONE;
+  }
+
+  __device__ __forceinline__ void flush() {
+    if (nstage == 0) return;
+    const int lane = lane_id();
+    wave_sync();
+    uint64_t k = lane < nstage ? stage[lane] : KEY_NONE;
+    wave_sync();
+    k = wave_sort64(k);
+    const uint64_t rev = shfl_u64(k, 63 - lane);
+    best[NR - 1] = best[NR - 1] < rev ? best[NR - 1] : rev;
+#pragma unroll
+    for (int st = NR / 2; st >= 1; st >>= 1)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if ((r & st) == 0) {
+          const uint64_t a = best[r], b = best[r + st];
+          best[r] = a < b ? a : b;
+          best[r + st] = a < b ? b : a;
+        }
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) {
+      const bool lower = (lane & j) == 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint64_t m = best[r];
+        const uint64_t other = shfl_xor_u64(m, j);
+        const uint64_t mn = m < other ? m : other;
+        const uint64_t mx = m < other ? other : m;
+        best[r] = lower ? mn : mx;
+      }
+    }
+    const uint64_t t = cth();
+    thr = t < bound ? t : bound;
+    nstage = 0;
+  }
+
+  __device__ __forceinline__ void offer(uint64_t key, bool valid) {
+    bool pass = valid && key < thr;
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    if (nstage + cnt > 64) {
+      flush();
+      pass = valid && key < thr;
+      m = __ballot(pass);
+      if (m == 0) return;
+      cnt = __popcll(m);
+    }
+    if (pass) stage[nstage + mbcnt64(m)] = key;
+    nstage += cnt;
+  }
+
+  // After finish(), list element r * 64 + lane is best[r] (KEY_NONE padded).
+  __device__ __forceinline__ void finish() { flush(); }
+
+  __device__ __forceinline__ void tighten(uint64_t b) {
+    if (b < bound) bound = b;
+    if (b < thr) thr = b;
+  }
+  // The C-th smallest key merged so far (KEY_NONE while fewer than C).
+  __device__ __forceinline__ uint64_t cth() const {
+    const int e = C - 1;
+    uint64_t v = best[0];
+#pragma unroll
+    for (int r = 1; r < NR; ++r)
+      if ((e >> 6) == r) v = best[r];
+    return uniform_u64(shfl_u64(v, e & 63));
+  }
 };
 
 // ------------------------------------------------------------- work items

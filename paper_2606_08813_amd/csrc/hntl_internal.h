@@ -179,7 +179,18 @@ struct Buckets {
   int G;
 };
 void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, hipStream_t s,
-                   const int32_t* gorder = nullptr, const int32_t* nsplit = nullptr);
+                   const int32_t* gorder = nullptr, const int32_t* nsplit = nullptr, bool counts_zeroed = false);
+// up to 8 fills in one launch (graph-friendly resets)
+struct FillSeg {
+  int32_t* p;
+  int64_t n;
+  int32_t v;
+};
+struct FillList {
+  FillSeg seg[8];
+  int n;
+};
+void launch_fill_multi(const FillList& L, hipStream_t s);
 void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
                        int32_t* qoff, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

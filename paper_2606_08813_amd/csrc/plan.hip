@@ -63,8 +63,8 @@ int fused_resident(int codes, int rp, int C, int qt, int nw) {
 
 // Bytes of per-wave LDS of the fused kernel (lists + staged tangents).
 size_t lds_per_wave(int rp, int C, int qt) {
-  const int cap = pow2_at_least(C < 64 ? 64 : C);
-  const size_t lk = cap == 64 ? 64 : 2 * (size_t)cap;
+  (void)C;
+  const size_t lk = 64;  // the arrival stage of a register-resident list
   return (size_t)qt * lk * 8 + (((size_t)qt * rp + qt) * 4 + 7) / 8 * 8;
 }
 
@@ -279,10 +279,15 @@ struct Plan {
     const Index& x = *ix;
     const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    launch_fill_i32(ticket, 1, 0, s);
-    launch_fill_i32(reinterpret_cast<int32_t*>(scored), 2, 0, s);
-    launch_fill_i32(proj_done, G, 0, s);
-    launch_fill_i32(reinterpret_cast<int32_t*>(qbound), max_nq, -1, s);
+    FillList f{};
+    f.seg[0] = FillSeg{ticket, 1, 0};
+    f.seg[1] = FillSeg{reinterpret_cast<int32_t*>(scored), 2, 0};
+    f.seg[2] = FillSeg{proj_done, G, 0};
+    f.seg[3] = FillSeg{reinterpret_cast<int32_t*>(qbound), (int64_t)max_nq, -1};
+    f.seg[4] = FillSeg{b.gcount, G, 0};
+    f.seg[5] = FillSeg{b.gcount0, G, 0};
+    f.n = 6;
+    launch_fill_multi(f, s);
     if (sp.route == HNTL_ROUTE_LEARNED)
       launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev);
     else
@@ -294,7 +299,7 @@ struct Plan {
                        nq_dev, q0);
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit);
+    launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (!fused_launch((int)sp.codes, args_dev, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid, s))

@@ -41,14 +41,23 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         const int64_t l0 = qoff ? qoff[q] : q * P;
         const int nl = qoff ? qoff[q + 1] - qoff[q] : P;
         const uint64_t* src = part + (size_t)l0 * C;
-        for (int s = 0; s < nl; ++s) {
-          if (!qoff) {
-            const int g = probes[q * P + s];
-            if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
+        constexpr int U = 4;  // lists loaded together
+        for (int s0 = 0; s0 < nl; s0 += U) {
+          uint64_t key[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int s = s0 + u;
+            bool ok = s < nl;
+            if (ok && !qoff) {
+              const int g = probes[q * P + s];
+              ok = g >= 0 && g < G;  // invalid probe: its list was never written
+            }
+            key[u] = (ok && lane < C) ? src[(size_t)s * C + lane] : KEY_NONE;
           }
-          if (src[(size_t)s * C] == KEY_NONE) continue;  // empty (or pruned) list
-          const uint64_t key = lane < C ? src[(size_t)s * C + lane] : KEY_NONE;
-          L.offer(key, key != KEY_NONE);
+          // a pruned list holds one KEY_NONE and nothing else written: skip it whole
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (shfl_u64(key[u], 0) != KEY_NONE) L.offer(key[u], key[u] != KEY_NONE);
         }
         L.finish();
         if (lane < C) {
@@ -59,28 +68,42 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         }
       }
     } else if (wave == 0) {
-      WaveTopC<CAP> L;
+      WaveTopR<CAP / 64> L;
       L.init(lst, C);
       const int64_t l0 = qoff ? qoff[q] : q * P;
       const int nl = qoff ? qoff[q + 1] - qoff[q] : P;
       const uint64_t* src = part + (size_t)l0 * C;
-      for (int s = 0; s < nl; ++s) {
-        if (!qoff) {
-          const int g = probes[q * P + s];
-          if (g < 0 || g >= G) continue;  // invalid probe: its list was never written
+      constexpr int NR = CAP / 64, U = 2;  // lists loaded together
+      for (int s0 = 0; s0 < nl; s0 += U) {
+        uint64_t key[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int s = s0 + u;
+          bool ok = s < nl;
+          if (ok && !qoff) {
+            const int g = probes[q * P + s];
+            ok = g >= 0 && g < G;  // invalid probe: its list was never written
+          }
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const int c = r * 64 + lane;
+            key[u][r] = (ok && c < C) ? src[(size_t)s * C + c] : KEY_NONE;
+          }
         }
-        for (int c0 = 0; c0 < C; c0 += HNTL_WAVE) {
-          // lists are ascending with KEY_NONE padding (a pruned grain's list
-          // holds a single KEY_NONE): stop at the first padding key
-          if (src[(size_t)s * C + c0] == KEY_NONE) break;
-          const int c = c0 + lane;
-          const uint64_t key = c < C ? src[(size_t)s * C + c] : KEY_NONE;
-          L.offer(key, key != KEY_NONE);
-        }
+        // lists are ascending and KEY_NONE-padded; a pruned list holds one
+        // KEY_NONE and nothing else written: skip it whole
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (shfl_u64(key[u][0], 0) != KEY_NONE)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) L.offer(key[u][r], key[u][r] != KEY_NONE);
       }
       L.finish();
-      for (int c = lane; c < C; c += HNTL_WAVE) {
-        const uint64_t key = L.best[c];
+#pragma unroll
+      for (int rr = 0; rr < CAP / 64; ++rr) {
+        const int c = rr * 64 + lane;
+        if (c >= C) continue;
+        const uint64_t key = L.best[rr];
         const int32_t id = key == KEY_NONE ? -1 : (int32_t)key_id(key);
         pool[c] = id;
         if (pool_out) pool_out[q * C + c] = id;
@@ -164,7 +187,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
     return;
   }
   if (wave == 0) {
-    WaveTopC<CAP> L;
+    WaveTopR<CAP / 64> L;
     L.init(lst, k);
     for (int c0 = 0; c0 < C; c0 += HNTL_WAVE) {
       const int c = c0 + lane;
@@ -173,8 +196,11 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
       L.offer(key, ok);
     }
     L.finish();
-    for (int j = lane; j < k; j += HNTL_WAVE) {
-      const uint64_t key = L.best[j];
+#pragma unroll
+    for (int rr = 0; rr < CAP / 64; ++rr) {
+      const int j = rr * 64 + lane;
+      if (j >= k) continue;
+      const uint64_t key = L.best[rr];
       ids[q * k + j] = key == KEY_NONE ? -1 : (int32_t)key_id(key);
       dist[q * k + j] = key == KEY_NONE ? __builtin_inff() : key_dist(key);
     }

@@ -243,11 +243,19 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
   WaveTop64 L;
   L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
-  for (int c0 = 0; c0 < cols; c0 += HNTL_WAVE) {
-    const int c = c0 + lane;
-    const bool ok = c < cols;
-    const float v = ok ? drow[c] : 0.f;
-    L.offer(make_key(v, (uint32_t)c), ok);
+  constexpr int U = 8;  // chunks of 64 loaded together (memory-level parallelism for one row)
+  for (int c0 = 0; c0 < cols; c0 += U * HNTL_WAVE) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * HNTL_WAVE + lane;
+      v[u] = c < cols ? drow[c] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * HNTL_WAVE + lane;
+      L.offer(make_key(v[u], (uint32_t)c), c < cols);
+    }
   }
   L.finish();
   if (!exact) {

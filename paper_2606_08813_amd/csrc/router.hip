@@ -53,7 +53,7 @@ __device__ __forceinline__ float gelu_grad(float x) {
 }
 
 // ------------------------------------------------------------------ GEMM
-constexpr int GM = 128, GN = 128, GK = 32, GLD = GK + 8;  // LDS rows padded by 8 bf16
+constexpr int GM = 128, GN = 128, GK = 64, GLD = GK + 8;  // LDS rows padded by 8 bf16
 
 enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2, EPI_BIAS_F32 = 3 };
 struct Epi {
@@ -69,19 +69,26 @@ struct Epi {
   float scale;         // EPI_BIAS_F32: result = scale * (acc + bias)
 };
 
-// Loads a 128 x 32 tile of X(r, k) (rows r0.., depths k0..) into S[r][k].
-// XT = false: X(r, k) = X[r * ld + k]; XT = true: X(r, k) = X[k * ld + r].
+// One thread's share of a 128 x 64 tile of X(r, k) (rows r0.., depths k0..):
+// 32 bf16 in four 16-byte words.  XT = false: X(r, k) = X[r * ld + k], the
+// thread holds row t / 2, depths 32 (t % 2) .. + 31; XT = true:
+// X(r, k) = X[k * ld + r], the thread holds depth t / 4, rows 32 (t % 4) .. + 31.
+struct Frag {
+  uint4 v[4];
+};
+
 template <bool XT>
-__device__ __forceinline__ void gemm_load(uint16_t (*S)[GLD], const uint16_t* __restrict__ X, int ld, int R, int K,
-                                          int r0, int k0) {
+__device__ __forceinline__ void gemm_fetch(Frag& f, const uint16_t* __restrict__ X, int ld, int R, int K, int r0,
+                                           int k0) {
   const int t = threadIdx.x;
-  if (!XT) {
-    const int r = t >> 1, kk = (t & 1) * 16;
-    const int gr = r0 + r;
+  const int a = XT ? (t >> 2) : (t >> 1);       // depth (XT) or row
+  const int b0 = XT ? (t & 3) * 32 : (t & 1) * 32;  // first row (XT) or depth of the run
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int gk = k0 + kk + 8 * h;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  for (int h = 0; h < 4; ++h) {
+    const int gr = XT ? r0 + b0 + 8 * h : r0 + a;  // row of element 0 of this word
+    const int gk = XT ? k0 + a : k0 + b0 + 8 * h;  // depth of element 0
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (!XT) {
       if (gr < R && gk + 8 <= K) {
         v = *reinterpret_cast<const uint4*>(X + (size_t)gr * ld + gk);
       } else if (gr < R) {
@@ -90,22 +97,33 @@ __device__ __forceinline__ void gemm_load(uint16_t (*S)[GLD], const uint16_t* __
         for (int u = 0; u < 8; ++u) e[u] = gk + u < K ? X[(size_t)gr * ld + gk + u] : 0;
         memcpy(&v, e, 16);
       }
-      *reinterpret_cast<uint4*>(&S[r][kk + 8 * h]) = v;
-    }
-  } else {
-    const int k = t >> 3, rr = (t & 7) * 16;  // 32 depths x 8 runs of 16 rows
-    const int gk = k0 + k;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int gr = r0 + rr + 8 * h;
-      uint16_t e[8];
+    } else {
       if (gk < K && gr + 8 <= R) {
-        const uint4 v = *reinterpret_cast<const uint4*>(X + (size_t)gk * ld + gr);
-        memcpy(e, &v, 16);
-      } else {
+        v = *reinterpret_cast<const uint4*>(X + (size_t)gk * ld + gr);
+      } else if (gk < K) {
+        uint16_t e[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) e[u] = (gk < K && gr + u < R) ? X[(size_t)gk * ld + gr + u] : 0;
+        for (int u = 0; u < 8; ++u) e[u] = gr + u < R ? X[(size_t)gk * ld + gr + u] : 0;
+        memcpy(&v, e, 16);
       }
+    }
+    f.v[h] = v;
+  }
+}
+
+template <bool XT>
+__device__ __forceinline__ void gemm_store(uint16_t (*S)[GLD], const Frag& f) {
+  const int t = threadIdx.x;
+  if (!XT) {
+    const int r = t >> 1, kk = (t & 1) * 32;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) *reinterpret_cast<uint4*>(&S[r][kk + 8 * h]) = f.v[h];
+  } else {
+    const int k = t >> 2, rr = (t & 3) * 32;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      uint16_t e[8];
+      memcpy(e, &f.v[h], 16);
 #pragma unroll
       for (int u = 0; u < 8; ++u) S[rr + 8 * h + u][k] = e[u];
     }
@@ -115,7 +133,9 @@ __device__ __forceinline__ void gemm_load(uint16_t (*S)[GLD], const uint16_t* __
 // One workgroup (4 waves) per 128 x 128 tile of C; wave w owns a 64 x 64
 // quarter as 4 x 4 MFMA 16x16 tiles.  Lane (i = lane % 16, kq = lane / 16)
 // feeds depths 8 kq .. 8 kq + 7 of row / column i to each MFMA and holds
-// C[4 kq + j][i] of each 16 x 16 output.  Rows from *mlim on are skipped.
+// C[4 kq + j][i] of each 16 x 16 output.  The next depth tile is fetched into
+// registers while the MFMAs of the current one run.  Rows from *mlim on are
+// skipped.
 template <bool AT, bool BT, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int lda,
                                                         const uint16_t* __restrict__ B, int ldb, int M, int N, int K,
@@ -136,20 +156,31 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  Frag fa, fb;
+  gemm_fetch<AT>(fa, A, lda, M, K, m0, 0);
+  gemm_fetch<BT>(fb, B, ldb, N, K, n0, 0);
   for (int k0 = 0; k0 < K; k0 += GK) {
-    gemm_load<AT>(As, A, lda, M, K, m0, k0);
-    gemm_load<BT>(Bs, B, ldb, N, K, n0, k0);
+    gemm_store<AT>(As, fa);
+    gemm_store<BT>(Bs, fb);
     __syncthreads();
-    bf16x8 af[4], bfv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + i][8 * kq]);
-      bfv[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + i][8 * kq]);
+    if (k0 + GK < K) {
+      gemm_fetch<AT>(fa, A, lda, M, K, m0, k0 + GK);
+      gemm_fetch<BT>(fb, B, ldb, N, K, n0, k0 + GK);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int ks = 0; ks < GK; ks += 32) {
+      bf16x8 af[4], bfv[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + i][ks + 8 * kq]);
+        bfv[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + i][ks + 8 * kq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
+    }
     __syncthreads();
   }
 #pragma unroll

@@ -28,13 +28,8 @@ constexpr float PRUNE_SLACK = 1e-4f;  // relative margin on the FP32 lower bound
 
 template <int CAP>
 struct ListOf {
-  using type = WaveTopC<CAP>;
-  static constexpr int lds = 2 * CAP;  // keys of LDS per list
-};
-template <>
-struct ListOf<64> {
-  using type = WaveTop64;
-  static constexpr int lds = 64;
+  using type = WaveTopR<CAP / 64>;  // the sorted list in registers, NR = CAP / 64 keys per lane
+  static constexpr int lds = 64;    // keys of LDS per list (the arrival stage)
 };
 
 // One workgroup per work item; its 16 / QT waves take QT pairs each and all
@@ -182,14 +177,11 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
     if (live[t]) {
       L[t].finish();
       uint64_t* out = part + (size_t)pairs[t] * C;
-      if constexpr (CAP == 64) {
-        const uint64_t k = L[t].best;
-        if (lane < C) out[lane] = (k == KEY_NONE) ? KEY_NONE : make_key(key_dist(k), (uint32_t)perm[key_id(k)]);
-      } else {
-        for (int i = lane; i < C; i += HNTL_WAVE) {
-          const uint64_t k = L[t].best[i];
-          out[i] = (k == KEY_NONE) ? KEY_NONE : make_key(key_dist(k), (uint32_t)perm[key_id(k)]);
-        }
+#pragma unroll
+      for (int rr = 0; rr < CAP / 64; ++rr) {
+        const int i = rr * 64 + lane;
+        const uint64_t k = L[t].best[rr];
+        if (i < C) out[i] = (k == KEY_NONE) ? KEY_NONE : make_key(key_dist(k), (uint32_t)perm[key_id(k)]);
       }
     }
   }

@@ -161,8 +161,8 @@ def test_plan_errors(bt):
     with pytest.raises(hntl.HNTLError) as e:
         hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 100, sched=dict(qt=1, nw=9, range=0))
     assert e.value.status == hntl.HNTL_EINVAL
-    with pytest.raises(hntl.HNTLError) as e:  # 4 lists x 4 KiB x 8 waves of LDS
-        hntl.hntl_plan_create(bt["ix"], W.P, 256, W.k, 100, sched=dict(qt=4, nw=8, range=0))
+    with pytest.raises(hntl.HNTLError) as e:  # C beyond the compiled pool size
+        hntl.hntl_plan_create(bt["ix"], W.P, 512, W.k, 100, sched=dict(qt=4, nw=8, range=0))
     assert e.value.status == hntl.HNTL_EUNSUPPORTED
     with pytest.raises(hntl.HNTLError) as e:
         hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 0)
