@@ -258,11 +258,14 @@ typedef struct hntl_plan hntl_plan; /* opaque */
 
 /* Work schedule of the fused kernel (picked by hntl_tune or given). */
 typedef struct hntl_schedule {
-  uint32_t qt;     /* pairs per wave in a scan item: 1, 2 or 4 */
+  uint32_t qt;     /* pairs per wave in a scan item: 1, 2, 4 or 8 */
   uint32_t nw;     /* waves per workgroup, 1..8: a scan item holds nw * qt pairs of one grain */
   uint32_t range;  /* blocks of 64 vectors per scan item (0 = whole grain); larger grains
                       give one item per range, whose lists the merge joins */
   uint32_t grid;   /* workgroups of the persistent launch (0 = as many as are resident at once) */
+  uint32_t passes; /* 1: every item in one launch; 2: projection and probe-slot-0 items in a first launch,
+                      the other slots in a second one, which then start from each query's slot-0 bound
+                      (0 = 1) */
 } hntl_schedule;
 
 #define HNTL_PLAN_GRAPH 1u /* capture a HIP graph at creation; runs replay it */
@@ -332,7 +335,7 @@ void hntl_plan_free(hntl_plan* plan);
 
 /*
  * hntl_tune - the autotuner.  Times every candidate schedule of the fused kernel
- * (qt in {1, 2, 4} x nw in {1, 2, 4, 8} x range in {0, 4, 8, 16, 32, 64}, those whose
+ * (passes in {1, 2} x qt in {1, 2, 4, 8} x nw in {1, 2, 4, 8} x range in {0, 8, 32, 64}, those whose
  * LDS fits) on the nq given queries (device, nq x d) and returns the fastest in *best
  * (*best_ms its median device time of one run).  With db_path != NULL the result is
  * also stored in that text file, one line per (device, index shape, search params,

@@ -135,3 +135,19 @@ def route_learned(params, x, mean, std, P, bf16=True):
     G = s.shape[1]
     order = np.lexsort((np.broadcast_to(np.arange(G), s.shape), -s), axis=1)[:, :P]
     return order, np.take_along_axis(s, order, 1)
+
+
+def route_with_fallback(params, x, mean, std, centroids, P, tau, bf16=True):
+    """Learned routing with the centroid fallback: a query whose largest softmax
+    probability over the grains is below tau takes the P nearest centroids
+    (ties to the lower grain) instead of the router's top-P."""
+    from .search import route
+    s, _ = forward(params, x, mean, std, bf16)
+    pmax = 1.0 / np.exp(s - s.max(axis=1, keepdims=True)).sum(axis=1)
+    probes, _ = route_learned(params, x, mean, std, P, bf16)
+    low = pmax < tau
+    if low.any():
+        cp, _ = route(np.asarray(x)[low], centroids, P)
+        probes = probes.copy()
+        probes[low] = cp
+    return probes, pmax

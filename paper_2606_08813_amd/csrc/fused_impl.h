@@ -24,6 +24,11 @@
 // running wave that never waits itself; a spin limit still bounds it and
 // flags an error.
 //
+// Two passes (a schedule option): the launch with phase 1 runs only the
+// projection and slot-0 items, a second launch with phase 2 the other slots,
+// which then start from the bound of each query's nearest grain, as in the
+// staged search; phase 0 runs all items in one launch.
+//
 // Exact shared pruning.  Every query keeps one bound in device memory, the
 // smallest C-th distance of any of its lists that already holds C
 // candidates.  The query's final pool (the C smallest (D, id) over all its
@@ -148,26 +153,21 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   }
 
   const void* codes = a.codes;
-  for (int b = rb0; b < rb1; ++b) {
-    if (b > rb0 && ((b - rb0) % REFRESH) == 0) {
-      // exchange bounds: publish each list's C-th distance, adopt the query's
+  auto exchange = [&]() {
+    // publish each list's C-th distance, adopt the query's bound
 #pragma unroll
-      for (int t = 0; t < QT; ++t) {
-        if (live[t]) {
-          const int q = pairs[t] / P;
-          const uint64_t own = Ls[t].cth();
-          if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[q], (uint32_t)(own >> 32));
-          const uint32_t ob = __builtin_amdgcn_readfirstlane(
-              __hip_atomic_load(&a.qbound[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-          Ls[t].tighten(bound_key(ob));
-        }
+    for (int t = 0; t < QT; ++t) {
+      if (live[t]) {
+        const int q = pairs[t] / P;
+        const uint64_t own = Ls[t].cth();
+        if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[q], (uint32_t)(own >> 32));
+        const uint32_t ob = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&a.qbound[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        Ls[t].tighten(bound_key(ob));
       }
     }
-    // one block of codes in registers per wave; the loads of the other waves
-    // on the CU cover the HBM latency
-    float c[RP];
-    load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
-    const float e = a.eps[(size_t)(b0 + b) * B + lane];
+  };
+  auto score = [&](const float(&c)[RP], float e, int b) {
     const bool valid = b * B + lane < ng;
     const uint32_t pos = (uint32_t)(pos0 + b * B + lane);
 #pragma unroll
@@ -181,6 +181,39 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
         }
         Ls[t].offer(make_key(acc + eq[t] + e, pos), valid);
       }
+    }
+  };
+  if constexpr (QT == 1) {
+    // one pair per wave (small batches, latency-bound): two register buffers,
+    // the next block loads while this one scores
+    float ca[RP], cb[RP];
+    float ea = 0.f, eb = 0.f;
+    if (rb0 < rb1) {
+      load_block<RP, CT>(ca, codes, (size_t)(b0 + rb0), lane, sg);
+      ea = a.eps[(size_t)(b0 + rb0) * B + lane];
+    }
+    for (int b = rb0; b < rb1; b += 2) {
+      if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
+      const bool has_b = b + 1 < rb1;
+      if (has_b) {
+        load_block<RP, CT>(cb, codes, (size_t)(b0 + b + 1), lane, sg);
+        eb = a.eps[(size_t)(b0 + b + 1) * B + lane];
+      }
+      score(ca, ea, b);
+      if (b + 2 < rb1) {
+        load_block<RP, CT>(ca, codes, (size_t)(b0 + b + 2), lane, sg);
+        ea = a.eps[(size_t)(b0 + b + 2) * B + lane];
+      }
+      if (has_b) score(cb, eb, b + 1);
+    }
+  } else {
+    // one block of codes in registers per wave; the loads of the other waves
+    // on the CU cover the HBM latency
+    for (int b = rb0; b < rb1; ++b) {
+      if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
+      float c[RP];
+      load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
+      score(c, a.eps[(size_t)(b0 + b) * B + lane], b);
     }
   }
 
@@ -217,6 +250,8 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const int n0 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_SLOT0][G]);
   const int n1 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_REST][G]);
   const int total = nP + n0 + n1;
+  const int lo = a.phase == 2 ? nP + n0 : 0;             // first item of this launch
+  const int hi = a.phase == 1 ? nP + n0 : total;         // one past its last
 
   // Each wave is its own worker: it takes tickets until they run out, and
   // nothing in the loop synchronises waves.  All 64 lanes add 1 to the
@@ -224,9 +259,10 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   // into one atomic) and lane 0's old value / 64 is the wave's item.
   int32_t __attribute__((address_space(1)))* ticket = (int32_t __attribute__((address_space(1)))*)a.ticket;
   for (;;) {
-    const int it =
-        __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 6;
-    if (it >= total) break;
+    const int it = lo + (__builtin_amdgcn_readfirstlane(
+                             __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
+                         6);
+    if (it >= hi) break;
     if (it < nP) {  // ---------------------------------------- projection
       const int rank = find_rank(a.ioff[LIST_ALL], G, it);
       const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
@@ -264,7 +300,8 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
       }
       const int first = tile * QT;
       const int cnt = min(QT, lc - first);
-      scan_tile<RP, CAP, QT, CT>(a, my, L, g, range, a.order + a.lstart[L][g] + first, cnt);
+      const int32_t* pairs = a.order + a.lstart[L][g] + first;
+      scan_tile<RP, CAP, QT, CT>(a, my, L, g, range, pairs, cnt);
     }
   }
 }
@@ -303,6 +340,7 @@ bool dispatch(int rp, int C, int qt, F&& f) {
     if (qt == 1) return f(Inst<RPV, CAPV, 1, CT>{}), true; \
     if (qt == 2) return f(Inst<RPV, CAPV, 2, CT>{}), true; \
     if (qt == 4) return f(Inst<RPV, CAPV, 4, CT>{}), true; \
+    if (qt == 8) return f(Inst<RPV, CAPV, 8, CT>{}), true; \
     return false;                                        \
   }
 #define HNTL_FR(RPV) HNTL_FQ(RPV, 64) HNTL_FQ(RPV, 128) HNTL_FQ(RPV, 256)

@@ -241,6 +241,7 @@ struct FusedArgs {
   const int32_t* order;
   const int32_t* lbase;  // per pair: first list slot (null: the pair id)
   int R;
+  int phase;  // 0: every item; 1: projection + slot-0 items; 2: the other slots
   // shared state (reset before every launch)
   int32_t* ticket;     // 1
   int32_t* proj_done;  // G: finished projection items per grain

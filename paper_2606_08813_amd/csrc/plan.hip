@@ -206,8 +206,8 @@ struct Plan {
     nsplit = L.take<int32_t>(x.G);
     lbase = L.take<int32_t>(np);
     qoff = L.take<int32_t>((size_t)max_nq + 1);
-    args_dev = L.take<FusedArgs>(1);
-    ticket = L.take<int32_t>(1);
+    args_dev = L.take<FusedArgs>(3);  // phases 0, 1, 2
+    ticket = L.take<int32_t>(2);      // one counter per launch
     proj_done = L.take<int32_t>(x.G);
     qbound = L.take<uint32_t>(max_nq);
     err = L.take<int32_t>(1);
@@ -280,7 +280,7 @@ struct Plan {
     const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     FillList f{};
-    f.seg[0] = FillSeg{ticket, 1, 0};
+    f.seg[0] = FillSeg{ticket, 2, 0};
     f.seg[1] = FillSeg{reinterpret_cast<int32_t*>(scored), 2, 0};
     f.seg[2] = FillSeg{proj_done, G, 0};
     f.seg[3] = FillSeg{reinterpret_cast<int32_t*>(qbound), (int64_t)max_nq, -1};
@@ -302,9 +302,12 @@ struct Plan {
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    if (!fused_launch((int)sp.codes, args_dev, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid, s))
-      throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
-    HIP_TRY(hipGetLastError());
+    for (int ph = sch.passes == 2 ? 1 : 0; ph <= (sch.passes == 2 ? 2 : 0); ++ph) {
+      if (!fused_launch((int)sp.codes, args_dev + ph, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid,
+                        s))
+        throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
+      HIP_TRY(hipGetLastError());
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     launch_merge_rerank(x, Q, max_nq, P, (int)sp.C, (int)sp.k, probes, part, nullptr, nullptr, nullptr, ids, dist, s,
                         sch.range ? qoff : nullptr);
@@ -361,6 +364,7 @@ hntl_schedule default_schedule(const Index& ix, const hntl_search_params& sp, ui
   }
   while (s.nw > 1 && lds_per_wave((int)ix.rp, (int)sp.C, (int)s.qt) * s.nw > LDS_LIMIT) s.nw /= 2;
   s.grid = 0;
+  s.passes = per_grain >= 8.0 ? 2 : 1;  // many pairs per grain: bound the other slots by slot 0 first
   return s;
 }
 
@@ -368,8 +372,11 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
                 uint32_t plan_flags, hipStream_t s) {
   check_plan_shape(ix, sp);
   hntl_schedule sch = sch_in;
-  if (!(sch.qt == 1 || sch.qt == 2 || sch.qt == 4)) throw ArgError{HNTL_EINVAL, "schedule qt must be 1, 2 or 4"};
+  if (!(sch.qt == 1 || sch.qt == 2 || sch.qt == 4 || sch.qt == 8))
+    throw ArgError{HNTL_EINVAL, "schedule qt must be 1, 2, 4 or 8"};
   if (sch.nw < 1 || sch.nw > 8) throw ArgError{HNTL_EINVAL, "schedule nw must be 1..8"};
+  if (sch.passes == 0) sch.passes = 1;
+  if (sch.passes > 2) throw ArgError{HNTL_EINVAL, "schedule passes must be 1 or 2"};
   if (lds_per_wave((int)ix.rp, (int)sp.C, (int)sch.qt) * sch.nw > LDS_LIMIT)
     throw ArgError{HNTL_EUNSUPPORTED, "schedule needs more than 64 KiB of LDS per workgroup"};
   ensure_grain_order(ix);
@@ -408,8 +415,13 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   HIP_TRY(hipMemsetAsync(pl->Q, 0, sizeof(float) * (size_t)max_nq * ix.d, s));
   HIP_TRY(hipMemsetAsync(pl->err, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemcpyAsync(pl->nsplit, ns.data(), sizeof(int32_t) * ix.G, hipMemcpyHostToDevice, s));
-  const FusedArgs a = pl->make_args();
-  HIP_TRY(hipMemcpyAsync(pl->args_dev, &a, sizeof(FusedArgs), hipMemcpyHostToDevice, s));
+  FusedArgs a[3];
+  for (int ph = 0; ph < 3; ++ph) {
+    a[ph] = pl->make_args();
+    a[ph].phase = ph;
+    a[ph].ticket = pl->ticket + (ph == 2 ? 1 : 0);
+  }
+  HIP_TRY(hipMemcpyAsync(pl->args_dev, a, sizeof(a), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (plan_flags & HNTL_PLAN_GRAPH) {
     HIP_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
@@ -615,12 +627,13 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
     float bms = 0.f;
     hntl_schedule bs{};
     bool have = false;
-    const uint32_t qts[] = {1, 2, 4}, nws[] = {1, 2, 4, 8}, ranges[] = {0, 4, 8, 16, 32, 64};
+    const uint32_t qts[] = {1, 2, 4, 8}, nws[] = {1, 2, 4, 8}, ranges[] = {0, 8, 32, 64};
+    for (uint32_t passes = 1; passes <= 2; ++passes)
     for (uint32_t qt : qts)
       for (uint32_t nw : nws)
         for (uint32_t R : ranges) {
           if (lds_per_wave((int)ix.rp, (int)spp.C, (int)qt) * nw > LDS_LIMIT) continue;
-          hntl_schedule c{qt, nw, R, 0};
+          hntl_schedule c{qt, nw, R, 0, passes};
           std::unique_ptr<Plan> pl;
           try {
             pl.reset(make_plan(ix, spp, nq, c, 0, s));
@@ -671,7 +684,8 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
           if (!line.empty() && line.rfind(key + " |", 0) != 0) lines.push_back(line);
       }
       char buf[160];
-      std::snprintf(buf, sizeof buf, " | qt=%u nw=%u range=%u | %.4f ms", bs.qt, bs.nw, bs.range, bms);
+      std::snprintf(buf, sizeof buf, " | qt=%u nw=%u range=%u passes=%u | %.4f ms", bs.qt, bs.nw, bs.range,
+                    bs.passes, bms);
       lines.push_back(key + buf);
       std::ofstream o(db_path, std::ios::trunc);
       if (!o) throw ArgError{HNTL_EINVAL, std::string("cannot write tuning file ") + db_path};
@@ -693,7 +707,8 @@ hntl_status hntl_schedule_lookup(const hntl_index* index, const hntl_search_para
     while (std::getline(in, line)) {
       if (line.rfind(key + " |", 0) != 0) continue;
       hntl_schedule s{};
-      if (std::sscanf(line.c_str() + key.size(), " | qt=%u nw=%u range=%u", &s.qt, &s.nw, &s.range) == 3) {
+      if (std::sscanf(line.c_str() + key.size(), " | qt=%u nw=%u range=%u passes=%u", &s.qt, &s.nw, &s.range,
+                      &s.passes) == 4) {
         s.grid = 0;
         *out = s;
         return;

@@ -65,10 +65,10 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
   for (int c = 0; c < NCT; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
   float sq = 0.f;
 
-  for (int k0 = 0; k0 < d; k0 += KC) {
+  // two register sets: the next depth chunk loads while this one multiplies
+  auto load = [&](float (&a)[KS], float (&m)[KS], float (&b)[NCT][KS], int k0) {
     const int kb = k0 + KS * kq;
-    const int lim = d - kb;  // valid floats from kb (may be <= 0)
-    float a[KS], m[KS], b[NCT][KS];
+    const int lim = d - kb;  // valid floats from kb (may be <= 0: zeros)
     load_ks<VEC>(m, mu + kb, lim);
     load_ks<VEC>(a, qp + kb, qrow >= 0 ? lim : 0);
 #pragma unroll
@@ -76,6 +76,8 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
       const int j = c * 16 + i;
       load_ks<VEC>(b[c], Wg + (size_t)(j < r ? j : 0) * d + kb, j < r ? lim : 0);
     }
+  };
+  auto mult = [&](float (&a)[KS], const float (&m)[KS], const float (&b)[NCT][KS]) {
 #pragma unroll
     for (int e = 0; e < KS; ++e) {
       a[e] = qrow >= 0 ? a[e] - m[e] : 0.f;
@@ -85,6 +87,17 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
     for (int e = 0; e < KS; ++e)
 #pragma unroll
       for (int c = 0; c < NCT; ++c) acc[c] = mfma16x16x4(a[e], b[c][e], acc[c]);
+  };
+  float a0[KS], m0[KS], b0[NCT][KS], a1[KS], m1[KS], b1[NCT][KS];
+  load(a0, m0, b0, 0);
+  for (int k0 = 0; k0 < d; k0 += 2 * KC) {
+    const bool second = k0 + KC < d;
+    if (second) load(a1, m1, b1, k0 + KC);
+    mult(a0, m0, b0);
+    if (second) {
+      if (k0 + 2 * KC < d) load(a0, m0, b0, k0 + 2 * KC);
+      mult(a1, m1, b1);
+    }
   }
 
   // ||q'||^2 of row i: the four K slots of the row

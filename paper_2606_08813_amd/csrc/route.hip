@@ -31,34 +31,47 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const float* __restrict_
   if (lane == 0) out[row] = acc;
 }
 
-// Loads a TM x TK tile of row-major M (rows x d) starting at (r0, k0) into LDS.
-__device__ __forceinline__ void load_tile(float (*S)[LDT], const float* __restrict__ M, int64_t nrows, int d,
-                                          int64_t r0, int k0, bool vec4) {
+// One thread's 8 floats of a TM x TK tile of row-major M (rows x d) at
+// (r0, k0): row tid / 4, depths 8 (tid % 4) .. + 7 (zero outside M).
+__device__ __forceinline__ void fetch_tile(float4 (&v)[2], const float* __restrict__ M, int64_t nrows, int d,
+                                           int64_t r0, int k0, bool vec4) {
   const int tid = threadIdx.x;
   const int rr = tid >> 2, cc = (tid & 3) * 8;
   const int64_t gr = r0 + rr;
   if (vec4) {
 #pragma unroll
-    for (int u = 0; u < 8; u += 4) {
-      const int gk = k0 + cc + u;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < nrows && gk < d) v = *reinterpret_cast<const float4*>(M + gr * d + gk);
-      S[rr][cc + u] = v.x;
-      S[rr][cc + u + 1] = v.y;
-      S[rr][cc + u + 2] = v.z;
-      S[rr][cc + u + 3] = v.w;
+    for (int u = 0; u < 2; ++u) {
+      const int gk = k0 + cc + 4 * u;
+      v[u] = (gr < nrows && gk < d) ? *reinterpret_cast<const float4*>(M + gr * d + gk)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   } else {
+    float e[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int gk = k0 + cc + u;
-      S[rr][cc + u] = (gr < nrows && gk < d) ? M[gr * d + gk] : 0.f;
+      e[u] = (gr < nrows && gk < d) ? M[gr * d + gk] : 0.f;
     }
+    v[0] = make_float4(e[0], e[1], e[2], e[3]);
+    v[1] = make_float4(e[4], e[5], e[6], e[7]);
+  }
+}
+
+__device__ __forceinline__ void store_tile(float (*S)[LDT], const float4 (&v)[2]) {
+  const int tid = threadIdx.x;
+  const int rr = tid >> 2, cc = (tid & 3) * 8;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    S[rr][cc + 4 * u] = v[u].x;
+    S[rr][cc + 4 * u + 1] = v[u].y;
+    S[rr][cc + 4 * u + 2] = v[u].z;
+    S[rr][cc + 4 * u + 3] = v[u].w;
   }
 }
 
 // One 64 x 64 tile of A.B^T accumulated over the full depth d; each of the 4
-// waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 tiles.
+// waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 tiles.  The next depth
+// tile is fetched into registers while the MFMAs of the current one run.
 __device__ __forceinline__ void tile_dot(floatx4 (&acc)[2][2], float (*As)[LDT], float (*Bs)[LDT],
                                          const float* __restrict__ A, int64_t rows, const float* __restrict__ Bm,
                                          int cols, int d, int64_t row0, int col0, bool vec4) {
@@ -68,10 +81,17 @@ __device__ __forceinline__ void tile_dot(floatx4 (&acc)[2][2], float (*As)[LDT],
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float4 fa[2], fb[2];
+  fetch_tile(fa, A, rows, d, row0, 0, vec4);
+  fetch_tile(fb, Bm, cols, d, col0, 0, vec4);
   for (int k0 = 0; k0 < d; k0 += TK) {
-    load_tile(As, A, rows, d, row0, k0, vec4);
-    load_tile(Bs, Bm, cols, d, col0, k0, vec4);
+    store_tile(As, fa);
+    store_tile(Bs, fb);
     __syncthreads();
+    if (k0 + TK < d) {
+      fetch_tile(fa, A, rows, d, row0, k0 + TK, vec4);
+      fetch_tile(fb, Bm, cols, d, col0, k0 + TK, vec4);
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -119,6 +139,46 @@ __global__ __launch_bounds__(256) void dist_matrix_kernel(const float* __restric
           D[row * cols + col] = fmaxf(v, 0.f);
         }
       }
+}
+
+// Small batches (<= 16 rows): exact distances by direct differences, one
+// wave per column (centroid) held in registers (d <= 1024), every row of A
+// against it.  Reads each centroid once instead of staging mostly empty
+// 64-row MFMA tiles.
+constexpr int DIRECT_ROWS = 16;
+__global__ __launch_bounds__(256) void dist_direct_kernel(const float* __restrict__ A, int64_t rows,
+                                                          const float* __restrict__ Bm, int cols, int d,
+                                                          float* __restrict__ D, const int32_t* __restrict__ nlim,
+                                                          int64_t row_base) {
+  const int lane = lane_id();
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= cols) return;
+  int64_t nr = rows;
+  if (nlim) {
+    const int64_t lim = (int64_t)*nlim - row_base;
+    if (lim < nr) nr = lim;
+  }
+  const float* b = Bm + (size_t)col * d;
+  float bv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int j = u * HNTL_WAVE + lane;
+    bv[u] = j < d ? b[j] : 0.f;
+  }
+  for (int64_t r = 0; r < nr; ++r) {
+    const float* a = A + r * d;
+    float acc = 0.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = u * HNTL_WAVE + lane;
+      if (j < d) {
+        const float df = a[j] - bv[u];
+        acc = fmaf(df, df, acc);
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) D[r * cols + col] = acc;
+  }
 }
 
 __global__ __launch_bounds__(256) void argmin_rows_kernel(const float* __restrict__ A, const float* __restrict__ an,
@@ -419,6 +479,12 @@ void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream
 void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn, int cols,
                         int d, float* D, hipStream_t s, const int32_t* nlim, int64_t row_base) {
   if (rows <= 0 || cols <= 0) return;
+  if (rows <= DIRECT_ROWS && d <= 16 * HNTL_WAVE) {
+    hipLaunchKernelGGL(dist_direct_kernel, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, s, A, rows, Bm, cols, d, D,
+                       nlim, row_base);
+    HIP_TRY(hipGetLastError());
+    return;
+  }
   const bool vec4 = (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
   dim3 grid((unsigned)((rows + TM - 1) / TM), (unsigned)((cols + TN - 1) / TN));
   hipLaunchKernelGGL(dist_matrix_kernel, grid, dim3(256), 0, s, A, an, rows, Bm, bn, cols, d, D, vec4, nlim,

@@ -24,6 +24,10 @@ SCHEDULES = [
     dict(qt=2, nw=1, range=3),
     dict(qt=4, nw=4, range=0),
     dict(qt=4, nw=8, range=1),
+    dict(qt=8, nw=2, range=0),
+    dict(qt=8, nw=1, range=2),
+    dict(qt=4, nw=4, range=0, passes=2),
+    dict(qt=2, nw=2, range=1, passes=2),
 ]
 
 
@@ -51,7 +55,8 @@ def assert_same(a, b, what):
     assert torch.equal(a[1], b[1]), f"{what}: distances differ"
 
 
-@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: f"qt{s['qt']}-nw{s['nw']}-range{s['range']}")
+@pytest.mark.parametrize("sched", SCHEDULES,
+                         ids=lambda s: f"qt{s['qt']}-nw{s['nw']}-range{s['range']}-passes{s.get('passes', 1)}")
 def test_plan_equals_staged_search(bt, sched):
     W, hntl = bt["W"], bt["hntl"]
     announce(f"plan (eager) {sched} vs staged search, batches 1..1000")
@@ -140,7 +145,7 @@ def test_autotuner_and_lookup(bt, tmp_path):
     db = tmp_path / "tune.txt"
     Q = bt["Qd"][:256].contiguous()
     best, ms = hntl.hntl_tune(bt["ix"], Q, W.P, W.C, W.k, db_path=db)
-    assert ms > 0 and best["qt"] in (1, 2, 4) and 1 <= best["nw"] <= 8
+    assert ms > 0 and best["qt"] in (1, 2, 4, 8) and 1 <= best["nw"] <= 8
     assert hntl.hntl_schedule_lookup(bt["ix"], W.P, W.C, W.k, 256, db) == best
     text = db.read_text()
     assert text.count("\n") == 1 and "nq=256" in text

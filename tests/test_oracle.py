@@ -401,3 +401,25 @@ def test_fp8_negative_underflow_keeps_sign():
     v = quant.fp8_e4m3_round(np.array([-1e-5, 1e-5, -0.0]))
     assert (v == 0).all()
     np.testing.assert_array_equal(quant.fp8_encode_byte(v), [0x80, 0x00, 0x80])
+
+
+def test_router_fallback_reduces_to_its_two_routes():
+    """tau = 0 is pure learned routing, tau above 1 is pure centroid routing,
+    and a tau between splits the queries by their largest probability."""
+    rng = np.random.default_rng(4)
+    d, G, P = 12, 9, 3
+    params = router.init_params((d, 16, 16, G), seed=2)
+    x = rng.normal(size=(40, d))
+    cents = rng.normal(size=(G, d))
+    mean, std = x.mean(0), x.std(0)
+    lp, _ = router.route_learned(params, x, mean, std, P)
+    cp, _ = osr.route(x, cents, P)
+    p0, pmax = router.route_with_fallback(params, x, mean, std, cents, P, 0.0)
+    np.testing.assert_array_equal(p0, lp)
+    p1, _ = router.route_with_fallback(params, x, mean, std, cents, P, 1.01)
+    np.testing.assert_array_equal(p1, cp)
+    tau = float(np.median(pmax))
+    pm, _ = router.route_with_fallback(params, x, mean, std, cents, P, tau)
+    np.testing.assert_array_equal(pm[pmax < tau], cp[pmax < tau])
+    np.testing.assert_array_equal(pm[pmax >= tau], lp[pmax >= tau])
+    assert ((pmax > 0) & (pmax <= 1)).all()
