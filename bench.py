@@ -41,6 +41,27 @@ FP32_VALU_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
+# HBM traffic of the default workload's dominant kernel (merge + rerank) from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
+# scaled by its reading for a plain 1 GiB device copy; valid while the kernel
+# source is unchanged (sha1 below).  Recorded in
+# profiles/merge_rerank_patch1M_d768_G1024_r32_hbm_counters.md.
+TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "staged", "codes": "fp32", "P": 8,
+           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "938da111e599658521b22f1cfa58d049755d1c3d",
+           "fetch_kib": 995046.0, "fetch_scale": 1048576.0 / 524308.125, "write_kib": 1250.0, "write_scale": 1.0}
+
+
+def measured_traffic(stage, workload, form, codes, P):
+    import hashlib
+    t = TRAFFIC
+    if (stage, workload, form, codes, P) != (t["stage"], t["workload"], t["form"], t["codes"], t["P"]):
+        return None
+    src = ROOT / t["src"]
+    if not src.exists() or hashlib.sha1(src.read_bytes()).hexdigest() != t["sha1"]:
+        return None  # the kernel changed since the counters were taken
+    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -302,7 +323,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "build_s": round(build_s, 2),
         "captured_variance": round(info["captured_variance"], 5),
-        "roofline": dict(roof.get(dominant, {}), kernel=dominant, traffic=None) if dominant else None,
+        "roofline": dict(roof.get(dominant, {}), kernel=dominant,
+                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P)) if dominant else None,
         "stage_rooflines": roof,
         "cpu_baseline": cpu,
         "precision": precision,
