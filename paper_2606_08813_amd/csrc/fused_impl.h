@@ -59,6 +59,8 @@ constexpr int REFRESH = 16;                 // blocks between bound exchanges
 constexpr long long SPIN_LIMIT = 1ll << 26;  // wait polls before giving up
 
 constexpr uint32_t NO_BOUND = 0xFFFFFFFFu;
+constexpr int NCTR = 8;          // scan-item ticket counters (classes of workgroups)
+constexpr int CTR_STRIDE = 64;   // ints between counters (256 bytes)
 
 __device__ __forceinline__ int find_rank(const int32_t* __restrict__ ioff, int G, int item) {
   int lo = 0, hi = G;  // largest rank with ioff[rank] <= item (ioff[G] > item)
@@ -250,20 +252,27 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const int n0 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_SLOT0][G]);
   const int n1 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_REST][G]);
   const int total = nP + n0 + n1;
-  const int lo = a.phase == 2 ? nP + n0 : 0;             // first item of this launch
-  const int hi = a.phase == 1 ? nP + n0 : total;         // one past its last
 
   // Each wave is its own worker: it takes tickets until they run out, and
-  // nothing in the loop synchronises waves.  All 64 lanes add 1 to the
-  // counter, so it moves by 64 per fetch (the compiler folds the wave's adds
-  // into one atomic) and lane 0's old value / 64 is the wave's item.
-  int32_t __attribute__((address_space(1)))* ticket = (int32_t __attribute__((address_space(1)))*)a.ticket;
-  for (;;) {
-    const int it = lo + (__builtin_amdgcn_readfirstlane(
-                             __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
-                         6);
-    if (it >= hi) break;
-    if (it < nP) {  // ---------------------------------------- projection
+  // nothing in the loop synchronises waves.  All 64 lanes add 1 to a counter,
+  // so it moves by 64 per fetch (the compiler folds the wave's adds into one
+  // atomic) and lane 0's old value / 64 is the ticket.  Projection items come
+  // from one counter (checked with a plain load before any atomic, so waves
+  // that find it exhausted cost no atomic); scan items are interleaved over
+  // NCTR counters, one per class of workgroups, so tickets are not all taken
+  // from one address.  A wave reaches the scan items only after every
+  // projection ticket has been handed out.
+  using gptr = int32_t __attribute__((address_space(1)))*;
+  if (a.phase != 2) {
+    const gptr pctr = (gptr)a.ticket;
+    for (;;) {
+      if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(pctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >=
+          nP * 64)
+        break;
+      const int it =
+          __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(pctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
+          6;
+      if (it >= nP) break;
       const int rank = find_rank(a.ioff[LIST_ALL], G, it);
       const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
       const int first = (it - a.ioff[LIST_ALL][rank]) * 16;
@@ -275,9 +284,20 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
         project_wave<true, NCT>(a.Q, a.d, a.P, a.centroids, a.basis, a.r, g, pairs, cnt, a.T, a.epsq);
       // release: the tangents of this item are visible before the count is
       // (every lane adds 1: an item counts 64)
-      __hip_atomic_fetch_add((int32_t __attribute__((address_space(1)))*)(a.proj_done + g), 1, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    } else {  // ----------------------------------------------------- scan
+      __hip_atomic_fetch_add((gptr)(a.proj_done + g), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  const int kc = (int)(blockIdx.x % NCTR);
+  const gptr sctr = (gptr)(a.ticket + CTR_STRIDE * (1 + kc));
+  const int slo = a.phase == 2 ? nP + n0 : nP;     // scan items of this launch
+  const int shi = a.phase == 1 ? nP + n0 : total;
+  for (;;) {
+    const int t =
+        __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
+        6;
+    const int it = slo + t * NCTR + kc;
+    if (it >= shi) break;
+    {  // ----------------------------------------------------------- scan
       const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
       const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
       const int rank = find_rank(a.ioff[L], G, li);

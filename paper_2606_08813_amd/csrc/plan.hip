@@ -69,6 +69,9 @@ size_t lds_per_wave(int rp, int C, int qt) {
 }
 
 constexpr size_t LDS_LIMIT = 64 * 1024;
+// one projection counter and 8 scan counters per launch, 256 bytes apart
+constexpr int TICKET_INTS = 9 * 64;
+constexpr int MIN_GRID = 8;  // every class of scan counters needs a workgroup
 constexpr uint64_t MAX_LIST_BYTES = 4ull << 30;  // candidate-list storage of one plan
 
 // Bump allocation over one block (base == nullptr: sizing pass).
@@ -207,7 +210,7 @@ struct Plan {
     lbase = L.take<int32_t>(np);
     qoff = L.take<int32_t>((size_t)max_nq + 1);
     args_dev = L.take<FusedArgs>(3);  // phases 0, 1, 2
-    ticket = L.take<int32_t>(2);      // one counter per launch
+    ticket = L.take<int32_t>(2 * TICKET_INTS);  // counters of each launch (phases 0/1 and 2)
     proj_done = L.take<int32_t>(x.G);
     qbound = L.take<uint32_t>(max_nq);
     err = L.take<int32_t>(1);
@@ -280,7 +283,7 @@ struct Plan {
     const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     FillList f{};
-    f.seg[0] = FillSeg{ticket, 2, 0};
+    f.seg[0] = FillSeg{ticket, 2 * TICKET_INTS, 0};
     f.seg[1] = FillSeg{reinterpret_cast<int32_t*>(scored), 2, 0};
     f.seg[2] = FillSeg{proj_done, G, 0};
     f.seg[3] = FillSeg{reinterpret_cast<int32_t*>(qbound), (int64_t)max_nq, -1};
@@ -394,21 +397,23 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   }
   std::vector<int32_t> srt(ns);
   std::sort(srt.begin(), srt.end(), std::greater<int32_t>());
-  if (sch.grid == 0) {
-    // as many workgroups as are resident at once, but no more waves than the
-    // largest possible number of work items
-    const uint64_t np = (uint64_t)max_nq * sp.P, gp = std::min<uint64_t>(ix.G, np);
-    const uint64_t items = (np + 15) / 16 + gp + (np / sch.qt + 2 * gp) * (uint64_t)srt[0];
-    const uint64_t res = (uint64_t)fused_resident((int)sp.codes, (int)ix.rp, (int)sp.C, (int)sch.qt, (int)sch.nw);
-    sch.grid = (uint32_t)std::min<uint64_t>(res, (items + sch.nw - 1) / sch.nw);
-  }
-  if (sch.grid == 0) throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
-  pl->sch = sch;
   uint64_t per_q = 0;
   for (uint32_t i = 0; i < sp.P; ++i) per_q += (uint64_t)srt[i];
   pl->list_slots = (uint64_t)max_nq * per_q;
   if (pl->list_slots >= (1ull << 31) || pl->list_slots * sp.C * sizeof(uint64_t) > MAX_LIST_BYTES)
     throw ArgError{HNTL_EUNSUPPORTED, "too many candidate lists for this schedule and batch size"};
+  const uint64_t res = (uint64_t)fused_resident((int)sp.codes, (int)ix.rp, (int)sp.C, (int)sch.qt, (int)sch.nw);
+  if (res == 0) throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
+  if (sch.grid == 0) {
+    // as many workgroups as are resident at once, but no more waves than the
+    // largest possible number of work items:
+    // projection items + at most one scan item per (pair, block range)
+    const uint64_t np = (uint64_t)max_nq * sp.P, gp = std::min<uint64_t>(ix.G, np);
+    const uint64_t items = (np + 15) / 16 + gp + pl->list_slots;
+    sch.grid = (uint32_t)std::min<uint64_t>(res, (items + sch.nw - 1) / sch.nw);
+  }
+  sch.grid = std::max<uint32_t>(sch.grid, MIN_GRID);
+  pl->sch = sch;
   pl->arena_bytes = pl->layout(nullptr);
   HIP_TRY(hipMalloc((void**)&pl->arena, pl->arena_bytes));
   pl->layout(pl->arena);
@@ -419,7 +424,7 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   for (int ph = 0; ph < 3; ++ph) {
     a[ph] = pl->make_args();
     a[ph].phase = ph;
-    a[ph].ticket = pl->ticket + (ph == 2 ? 1 : 0);
+    a[ph].ticket = pl->ticket + (ph == 2 ? TICKET_INTS : 0);
   }
   HIP_TRY(hipMemcpyAsync(pl->args_dev, a, sizeof(a), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
