@@ -66,7 +66,7 @@ __device__ __forceinline__ int find_rank(const int32_t* __restrict__ ioff, int G
   int lo = 0, hi = G;  // largest rank with ioff[rank] <= item (ioff[G] > item)
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (ioff[mid] <= item)
+    if (ldg(ioff + mid) <= item)
       lo = mid;
     else
       hi = mid;
@@ -98,23 +98,23 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   uint64_t* lists_lds = my;
   float(*zq)[RP] = reinterpret_cast<float(*)[RP]>(my + QT * LK);
   float* eq = reinterpret_cast<float*>(my + QT * LK) + QT * RP;
-  const int pos0 = a.goff[g];
-  const int ng = a.goff[g + 1] - pos0;
-  const int b0 = a.boff[g];
-  const int nb = a.boff[g + 1] - b0;
+  const int pos0 = ldg(a.goff + g);
+  const int ng = ldg(a.goff + g + 1) - pos0;
+  const int b0 = ldg(a.boff + g);
+  const int nb = ldg(a.boff + g + 1) - b0;
   const int rb0 = a.R ? range * a.R : 0;
   const int rb1 = a.R ? min(nb, rb0 + a.R) : nb;
 
   for (int idx = lane; idx < QT * RP; idx += HNTL_WAVE) {
     const int t = idx / RP, j = idx % RP;
-    zq[t][j] = (t < cnt && j < r) ? a.T[(size_t)pairs[t] * r + j] : 0.f;
+    zq[t][j] = (t < cnt && j < r) ? ldg(a.T + (size_t)ldg(pairs + t) * r + j) : 0.f;
   }
-  if (lane < QT) eq[lane] = lane < cnt ? a.epsq[pairs[lane]] : 0.f;
+  if (lane < QT) eq[lane] = lane < cnt ? ldg(a.epsq + ldg(pairs + lane)) : 0.f;
   wave_sync();
 
-  const float sg = CT == 2 ? a.scales[g] : 1.f;
-  float lo = (a.prune && lane < r) ? a.blo[(size_t)g * RP + lane] : 0.f;
-  float hi = (a.prune && lane < r) ? a.bhi[(size_t)g * RP + lane] : 0.f;
+  const float sg = CT == 2 ? ldg(a.scales + g) : 1.f;
+  float lo = (a.prune && lane < r) ? ldg(a.blo + (size_t)g * RP + lane) : 0.f;
+  float hi = (a.prune && lane < r) ? ldg(a.bhi + (size_t)g * RP + lane) : 0.f;
   if (CT != 0) {  // the box must hold the decoded values the scan uses
     const float amax = fmaxf(fabsf(lo), fabsf(hi));
     const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
@@ -129,18 +129,18 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     live[t] = t < cnt;
     uint64_t bnd = KEY_NONE;
     if (live[t]) {
-      const int p = pairs[t];
+      const int p = ldg(pairs + t);
       const uint32_t ob = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&a.qbound[p / P], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          __hip_atomic_load(gptr(a.qbound + p / P), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       bnd = bound_key(ob);
       if (a.prune && ob != NO_BOUND) {
         const float v = lane < r ? zq[t][lane] : 0.f;
         const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
-        const float lb = wave_sum(dd * dd) + eq[t] + a.emin[g];
+        const float lb = wave_sum(dd * dd) + eq[t] + ldg(a.emin + g);
         if (__builtin_amdgcn_readfirstlane(lb * (1.f - PRUNE_SLACK) > ord2f(ob) ? 1 : 0)) {
           live[t] = false;
-          const int64_t slot = (a.lbase ? (int64_t)a.lbase[p] : (int64_t)p) + range;
-          if (lane == 0) a.part[(size_t)slot * C] = KEY_NONE;  // empty list
+          const int64_t slot = (a.lbase ? (int64_t)ldg(a.lbase + p) : (int64_t)p) + range;
+          if (lane == 0) stg(a.part + (size_t)slot * C, KEY_NONE);  // empty list
         }
       }
     }
@@ -151,7 +151,9 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   if (nlive == 0) return;
   if (a.scored && lane == 0) {
     const int nvec = min(ng, rb1 * B) - rb0 * B;
-    if (nvec > 0) atomicAdd(a.scored, (unsigned long long)nlive * (unsigned long long)nvec);
+    if (nvec > 0)
+      __hip_atomic_fetch_add(gptr(a.scored), (unsigned long long)nlive * (unsigned long long)nvec, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 
   const void* codes = a.codes;
@@ -160,11 +162,12 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       if (live[t]) {
-        const int q = pairs[t] / P;
+        const int q = ldg(pairs + t) / P;
         const uint64_t own = Ls[t].cth();
-        if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[q], (uint32_t)(own >> 32));
+        if (own != KEY_NONE && lane == 0)
+          __hip_atomic_fetch_min(gptr(a.qbound + q), (uint32_t)(own >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t ob = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&a.qbound[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            __hip_atomic_load(gptr(a.qbound + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         Ls[t].tighten(bound_key(ob));
       }
     }
@@ -192,19 +195,19 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     float ea = 0.f, eb = 0.f;
     if (rb0 < rb1) {
       load_block<RP, CT>(ca, codes, (size_t)(b0 + rb0), lane, sg);
-      ea = a.eps[(size_t)(b0 + rb0) * B + lane];
+      ea = ldg(a.eps + (size_t)(b0 + rb0) * B + lane);
     }
     for (int b = rb0; b < rb1; b += 2) {
       if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
       const bool has_b = b + 1 < rb1;
       if (has_b) {
         load_block<RP, CT>(cb, codes, (size_t)(b0 + b + 1), lane, sg);
-        eb = a.eps[(size_t)(b0 + b + 1) * B + lane];
+        eb = ldg(a.eps + (size_t)(b0 + b + 1) * B + lane);
       }
       score(ca, ea, b);
       if (b + 2 < rb1) {
         load_block<RP, CT>(ca, codes, (size_t)(b0 + b + 2), lane, sg);
-        ea = a.eps[(size_t)(b0 + b + 2) * B + lane];
+        ea = ldg(a.eps + (size_t)(b0 + b + 2) * B + lane);
       }
       if (has_b) score(cb, eb, b + 1);
     }
@@ -215,7 +218,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
       if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
       float c[RP];
       load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
-      score(c, a.eps[(size_t)(b0 + b) * B + lane], b);
+      score(c, ldg(a.eps + (size_t)(b0 + b) * B + lane), b);
     }
   }
 
@@ -223,16 +226,17 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   for (int t = 0; t < QT; ++t) {
     if (live[t]) {
       Ls[t].finish();
-      const int p = pairs[t];
+      const int p = ldg(pairs + t);
       const uint64_t own = Ls[t].cth();
-      if (own != KEY_NONE && lane == 0) atomicMin(&a.qbound[p / P], (uint32_t)(own >> 32));
-      const int64_t slot = (a.lbase ? (int64_t)a.lbase[p] : (int64_t)p) + range;
+      if (own != KEY_NONE && lane == 0)
+        __hip_atomic_fetch_min(gptr(a.qbound + p / P), (uint32_t)(own >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int64_t slot = (a.lbase ? (int64_t)ldg(a.lbase + p) : (int64_t)p) + range;
       uint64_t* out = a.part + (size_t)slot * C;
 #pragma unroll
       for (int rr = 0; rr < CAP / 64; ++rr) {
         const int i = rr * 64 + lane;
         const uint64_t kk = Ls[t].best[rr];
-        if (i < C) out[i] = (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)a.perm[key_id(kk)]);
+        if (i < C) stg(out + i, (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)ldg(a.perm + key_id(kk))));
       }
     }
   }
@@ -248,9 +252,9 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint64_t* my = smem + (size_t)wave * (wave_lds_bytes<RP, QT, LK>() / 8);
   const int G = a.G;
-  const int nP = __builtin_amdgcn_readfirstlane(a.ioff[LIST_ALL][G]);
-  const int n0 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_SLOT0][G]);
-  const int n1 = __builtin_amdgcn_readfirstlane(a.ioff[LIST_REST][G]);
+  const int nP = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_ALL] + G));
+  const int n0 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_SLOT0] + G));
+  const int n1 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_REST] + G));
   const int total = nP + n0 + n1;
 
   // Each wave is its own worker: it takes tickets until they run out, and
@@ -274,17 +278,16 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
           6;
       if (it >= nP) break;
       const int rank = find_rank(a.ioff[LIST_ALL], G, it);
-      const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
-      const int first = (it - a.ioff[LIST_ALL][rank]) * 16;
-      const int cnt = __builtin_amdgcn_readfirstlane(min(16, a.lcount[LIST_ALL][g] - first));
-      const int32_t* pairs = a.order + a.lstart[LIST_ALL][g] + first;
+      const int g = __builtin_amdgcn_readfirstlane(ldg(a.gorder + rank));
+      const int first = (it - ldg(a.ioff[LIST_ALL] + rank)) * 16;
+      const int cnt = __builtin_amdgcn_readfirstlane(min(16, ldg(a.lcount[LIST_ALL] + g) - first));
+      const int32_t* pairs = a.order + ldg(a.lstart[LIST_ALL] + g) + first;
       if (a.proj_bf16)
         project_wave_bf16<NCT>(a.Q, a.d, a.P, a.centroids, a.basis16, a.r, g, pairs, cnt, a.T, a.epsq);
       else
         project_wave<true, NCT>(a.Q, a.d, a.P, a.centroids, a.basis, a.r, g, pairs, cnt, a.T, a.epsq);
-      // release: the tangents of this item are visible before the count is
-      // (every lane adds 1: an item counts 64)
-      __hip_atomic_fetch_add((gptr)(a.proj_done + g), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      // release: the tangents of this item are visible before its flag is
+      __hip_atomic_store((gptr)(a.proj_done + it), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   const int kc = (int)(blockIdx.x % NCTR);
@@ -301,26 +304,33 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
       const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
       const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
       const int rank = find_rank(a.ioff[L], G, li);
-      const int g = __builtin_amdgcn_readfirstlane(a.gorder[rank]);
-      const int lc = __builtin_amdgcn_readfirstlane(a.lcount[L][g]);
+      const int g = __builtin_amdgcn_readfirstlane(ldg(a.gorder + rank));
+      const int lc = __builtin_amdgcn_readfirstlane(ldg(a.lcount[L] + g));
       const int ntiles = (lc + QT - 1) / QT;
-      const int k = li - __builtin_amdgcn_readfirstlane(a.ioff[L][rank]);
+      const int k = li - __builtin_amdgcn_readfirstlane(ldg(a.ioff[L] + rank));
       const int range = k / ntiles, tile = k % ntiles;  // range-major: a range's tiles run together
-      // wait until every projection item of the grain has finished (acquire)
-      const int need = (__builtin_amdgcn_readfirstlane(a.lcount[LIST_ALL][g]) + 15) / 16 * 64;
-      for (long long spin = 0;; ++spin) {
-        const int done = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&a.proj_done[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-        if (done >= need) break;
-        if (spin > SPIN_LIMIT) {
-          atomicOr(a.err, 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
       const int first = tile * QT;
       const int cnt = min(QT, lc - first);
-      const int32_t* pairs = a.order + a.lstart[L][g] + first;
+      // wait (acquire) for the projection items that hold this tile's pairs:
+      // a grain's projection list is its slot-0 pairs followed by the others,
+      // in 16-pair items, so the tile spans items c0 .. c1 (at most two)
+      {
+        const int base = (L == LIST_SLOT0 ? 0 : __builtin_amdgcn_readfirstlane(ldg(a.lcount[LIST_SLOT0] + g))) + first;
+        const int pi0 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_ALL] + rank));
+        for (int c = pi0 + base / 16; c <= pi0 + (base + cnt - 1) / 16; ++c) {
+          for (long long spin = 0;; ++spin) {
+            const int done = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(gptr(a.proj_done + c), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            if (done != 0) break;
+            if (spin > SPIN_LIMIT) {
+              __hip_atomic_fetch_or(gptr(a.err), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+      }
+      const int32_t* pairs = a.order + ldg(a.lstart[L] + g) + first;
       scan_tile<RP, CAP, QT, CT>(a, my, L, g, range, pairs, cnt);
     }
   }

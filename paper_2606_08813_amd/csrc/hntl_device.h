@@ -29,6 +29,28 @@ __device__ __forceinline__ float key_dist(uint64_t k) { return ord2f((uint32_t)(
 __device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)k; }
 constexpr uint64_t KEY_NONE = ~0ull;
 
+// ------------------------------------------------------- global accesses
+// Loads and stores through global (address space 1) pointers.  A pointer read
+// from a struct in device memory is a generic pointer, and accesses through it
+// compile to flat instructions, which count against the LDS wait counter as
+// well: a wait for a shuffle or an LDS read would then also wait for every
+// load in flight.  These helpers give global_load / global_store instead.
+// T must be a scalar or a clang vector type (a class type would be copied
+// through a generic reference).
+#define HNTL_AS1 __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const T HNTL_AS1*)p;
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(T HNTL_AS1*)p = v;
+}
+template <class T>
+__device__ __forceinline__ T HNTL_AS1* gptr(T* p) {
+  return (T HNTL_AS1*)p;
+}
+
 // ---------------------------------------------------------------- wave utils
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -43,11 +65,6 @@ __device__ __forceinline__ int mbcnt64(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -65,11 +82,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // is the threshold + buffer + merging-network scheme of GPU k-selection
 // (Johnson, Douze, Jegou, "Billion-scale similarity search with GPUs"), laid
 // out for 64-wide waves.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   const uint32_t lo = __shfl((uint32_t)v, src, 64);
   const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
@@ -80,20 +92,109 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return ((uint64_t)hi << 32) | lo;
 }
+// Lane `src` (wave-uniform) of v, read into scalar registers.
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
 
-// Ascending bitonic sort of one key per lane.
+// ------------------------------------------ lane exchanges without the LDS
+// The value of lane (lane ^ J).  J <= 8 stays inside a row of 16 lanes and is
+// one or two DPP moves (quad permutations for 1 and 2, a rotation by 8 for 8,
+// shifts by 4 up and down for 4); J = 16 and 32 use the gfx950 permlane swaps
+// of odd / even rows and of the two wave halves.  None of them goes through
+// the LDS, so a sorting network built on them waits on no LDS round trip.
+constexpr int DPP_QP_1032 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QP_2301 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int DPP_FROM_UP4 = 0x104;  // row_shl:4, lane i reads lane i + 4 of its row
+constexpr int DPP_FROM_DN4 = 0x114;  // row_shr:4, lane i reads lane i - 4 of its row
+constexpr int DPP_ROR8 = 0x128;      // row_ror:8, lane i reads lane i ^ 8 of its row
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  const int lane = lane_id();
+  if constexpr (J == 1) {
+    return dpp_mov<DPP_QP_1032>(v);
+  } else if constexpr (J == 2) {
+    return dpp_mov<DPP_QP_2301>(v);
+  } else if constexpr (J == 4) {
+    const uint32_t up = dpp_mov<DPP_FROM_UP4>(v), dn = dpp_mov<DPP_FROM_DN4>(v);
+    return (lane & 4) ? dn : up;
+  } else if constexpr (J == 8) {
+    return dpp_mov<DPP_ROR8>(v);
+  } else if constexpr (J == 16) {
+    // result 0: odd rows replaced by the even rows below them; result 1: even
+    // rows replaced by the odd rows above them
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? p[0] : p[1];
+  } else {
+    static_assert(J == 32, "lane_xor: J must be a power of two below 64");
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? p[0] : p[1];
+  }
+}
+
+// Compare-exchange of one key per lane with lane (lane ^ J): the smaller of
+// the two where keep_min, the larger elsewhere.
+template <int J>
+__device__ __forceinline__ uint64_t cmpx_t(uint64_t key, bool keep_min) {
+  const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+  uint64_t a, b;
+  if constexpr (J == 16 || J == 32) {
+    // the swap leaves {own, partner} in its two results (their order depends
+    // on the lane, which min / max do not care about)
+    const auto pl = J == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = J == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = ((uint64_t)ph[0] << 32) | pl[0];
+    b = ((uint64_t)ph[1] << 32) | pl[1];
+  } else {
+    a = key;
+    b = ((uint64_t)lane_xor<J>(hi) << 32) | lane_xor<J>(lo);
+  }
+  return (a < b) == keep_min ? a : b;
+}
+// j is a compile-time constant once the callers' loops are unrolled.
+__device__ __forceinline__ uint64_t cmpx(uint64_t key, int j, bool keep_min) {
+  switch (j) {
+    case 1: return cmpx_t<1>(key, keep_min);
+    case 2: return cmpx_t<2>(key, keep_min);
+    case 4: return cmpx_t<4>(key, keep_min);
+    case 8: return cmpx_t<8>(key, keep_min);
+    case 16: return cmpx_t<16>(key, keep_min);
+    default: return cmpx_t<32>(key, keep_min);
+  }
+}
+
+// Sum over the wave (butterfly: every lane ends with the same total).
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __uint_as_float(lane_xor<32>(__float_as_uint(v)));
+  v += __uint_as_float(lane_xor<16>(__float_as_uint(v)));
+  v += __uint_as_float(lane_xor<8>(__float_as_uint(v)));
+  v += __uint_as_float(lane_xor<4>(__float_as_uint(v)));
+  v += __uint_as_float(lane_xor<2>(__float_as_uint(v)));
+  v += __uint_as_float(lane_xor<1>(__float_as_uint(v)));
+  return v;
+}
+
+// Bitonic sort of one key per lane, ascending (DESC = false) or descending.
+template <bool DESC = false>
 __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 2; k <= 64; k <<= 1)
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t other = shfl_xor_u64(key, j);
       const bool up = (lane & k) == 0;
       const bool lower = (lane & j) == 0;
-      const uint64_t mn = key < other ? key : other;
-      const uint64_t mx = key < other ? other : key;
-      key = (up == lower) ? mn : mx;
+      key = cmpx(key, j, (up == lower) != DESC);
     }
   return key;
 }
@@ -121,20 +222,13 @@ struct WaveTop64 {
     wave_sync();
     uint64_t k = lane < nstage ? stage[lane] : KEY_NONE;
     wave_sync();
-    k = wave_sort64(k);
+    k = wave_sort64<true>(k);
     // half-cleaner of (best ascending, arrivals descending), then bitonic merge
-    const uint64_t rev = shfl_u64(k, 63 - lane);
-    uint64_t m = best < rev ? best : rev;
+    uint64_t m = best < k ? best : k;
 #pragma unroll
-    for (int j = 32; j > 0; j >>= 1) {
-      const uint64_t other = shfl_xor_u64(m, j);
-      const bool lower = (lane & j) == 0;
-      const uint64_t mn = m < other ? m : other;
-      const uint64_t mx = m < other ? other : m;
-      m = lower ? mn : mx;
-    }
+    for (int j = 32; j > 0; j >>= 1) m = cmpx(m, j, (lane & j) == 0);
     best = m;
-    const uint64_t t = uniform_u64(shfl_u64(best, C - 1));
+    const uint64_t t = lane_u64(best, C - 1);
     thr = t < bound ? t : bound;
     nstage = 0;
   }
@@ -162,7 +256,7 @@ struct WaveTop64 {
     if (b < bound) bound = b;
     if (b < thr) thr = b;
   }
-  __device__ __forceinline__ uint64_t cth() const { return uniform_u64(shfl_u64(best, C - 1)); }
+  __device__ __forceinline__ uint64_t cth() const { return lane_u64(best, C - 1); }
 };
 
 // ------------------------------------- register-resident top-(64 NR) list
@@ -198,9 +292,8 @@ struct WaveTopR {
     wave_sync();
     uint64_t k = lane < nstage ? stage[lane] : KEY_NONE;
     wave_sync();
-    k = wave_sort64(k);
-    const uint64_t rev = shfl_u64(k, 63 - lane);
-    best[NR - 1] = best[NR - 1] < rev ? best[NR - 1] : rev;
+    k = wave_sort64<true>(k);  // descending: the half-cleaner pairs it with the ascending list
+    best[NR - 1] = best[NR - 1] < k ? best[NR - 1] : k;
 #pragma unroll
     for (int st = NR / 2; st >= 1; st >>= 1)
 #pragma unroll
@@ -214,13 +307,7 @@ struct WaveTopR {
     for (int j = 32; j > 0; j >>= 1) {
       const bool lower = (lane & j) == 0;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint64_t m = best[r];
-        const uint64_t other = shfl_xor_u64(m, j);
-        const uint64_t mn = m < other ? m : other;
-        const uint64_t mx = m < other ? other : m;
-        best[r] = lower ? mn : mx;
-      }
+      for (int r = 0; r < NR; ++r) best[r] = cmpx(best[r], j, lower);
     }
     const uint64_t t = cth();
     thr = t < bound ? t : bound;
@@ -257,7 +344,7 @@ struct WaveTopR {
 #pragma unroll
     for (int r = 1; r < NR; ++r)
       if ((e >> 6) == r) v = best[r];
-    return uniform_u64(shfl_u64(v, e & 63));
+    return lane_u64(v, e & 63);
   }
 };
 

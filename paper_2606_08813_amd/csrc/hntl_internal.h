@@ -244,7 +244,7 @@ struct FusedArgs {
   int phase;  // 0: every item; 1: projection + slot-0 items; 2: the other slots
   // shared state (reset before every launch)
   int32_t* ticket;     // 1
-  int32_t* proj_done;  // G: finished projection items per grain
+  int32_t* proj_done;  // one flag per projection item: 1 once its tangents are written
   uint32_t* qbound;    // per query: order image of the smallest known C-th distance
   int32_t* err;        // 1: set if a wait gave up
   float* T;            // npairs x r tangents

@@ -150,7 +150,8 @@ struct Plan {
   // fused kernel state
   FusedArgs* args_dev = nullptr;
   int32_t* ticket = nullptr;
-  int32_t* proj_done = nullptr;
+  int32_t* proj_done = nullptr;  // one flag per projection item
+  int64_t proj_items = 0;
   uint32_t* qbound = nullptr;
   int32_t* err = nullptr;
   float* T = nullptr;
@@ -211,7 +212,8 @@ struct Plan {
     qoff = L.take<int32_t>((size_t)max_nq + 1);
     args_dev = L.take<FusedArgs>(3);  // phases 0, 1, 2
     ticket = L.take<int32_t>(2 * TICKET_INTS);  // counters of each launch (phases 0/1 and 2)
-    proj_done = L.take<int32_t>(x.G);
+    proj_items = (int64_t)((np + 15) / 16) + x.G;  // at most sum over grains of ceil(pairs / 16)
+    proj_done = L.take<int32_t>(proj_items);
     qbound = L.take<uint32_t>(max_nq);
     err = L.take<int32_t>(1);
     T = L.take<float>((size_t)np * x.r);
@@ -285,7 +287,7 @@ struct Plan {
     FillList f{};
     f.seg[0] = FillSeg{ticket, 2 * TICKET_INTS, 0};
     f.seg[1] = FillSeg{reinterpret_cast<int32_t*>(scored), 2, 0};
-    f.seg[2] = FillSeg{proj_done, G, 0};
+    f.seg[2] = FillSeg{proj_done, proj_items, 0};
     f.seg[3] = FillSeg{reinterpret_cast<int32_t*>(qbound), (int64_t)max_nq, -1};
     f.seg[4] = FillSeg{b.gcount, G, 0};
     f.seg[5] = FillSeg{b.gcount0, G, 0};

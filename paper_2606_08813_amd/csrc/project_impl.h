@@ -28,16 +28,16 @@ __device__ __forceinline__ void load_ks(float (&v)[KS], const float* __restrict_
   if (VEC) {
 #pragma unroll
     for (int e = 0; e < KS; e += 4) {
-      float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < lim) t = *reinterpret_cast<const float4*>(src + e);
-      v[e] = t.x;
-      v[e + 1] = t.y;
-      v[e + 2] = t.z;
-      v[e + 3] = t.w;
+      floatx4 t = {0.f, 0.f, 0.f, 0.f};
+      if (e < lim) t = ldg(reinterpret_cast<const floatx4*>(src + e));
+      v[e] = t[0];
+      v[e + 1] = t[1];
+      v[e + 2] = t[2];
+      v[e + 3] = t[3];
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < KS; ++e) v[e] = e < lim ? src[e] : 0.f;
+    for (int e = 0; e < KS; ++e) v[e] = e < lim ? ldg(src + e) : 0.f;
   }
 }
 
@@ -55,7 +55,7 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
                                              float* __restrict__ T, float* __restrict__ epsq) {
   const int lane = lane_id();
   const int i = lane & 15, kq = lane >> 4;
-  const int qrow = i < cnt ? pairs[i] / P : -1;
+  const int qrow = i < cnt ? ldg(pairs + i) / P : -1;
   const float* mu = centroids + (size_t)g * d;
   const float* Wg = basis + (size_t)g * r * d;
   const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
@@ -101,8 +101,8 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
   }
 
   // ||q'||^2 of row i: the four K slots of the row
-  sq += __shfl_xor(sq, 16, 64);
-  sq += __shfl_xor(sq, 32, 64);
+  sq += __uint_as_float(lane_xor<16>(__float_as_uint(sq)));
+  sq += __uint_as_float(lane_xor<32>(__float_as_uint(sq)));
   // ||z||^2 per output row (MFMA layout: row 4 * (lane >> 4) + t, column lane & 15)
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -113,17 +113,19 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
       const int col = c * 16 + (lane & 15);
       if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
     }
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    zz += __uint_as_float(lane_xor<1>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<2>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<4>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<8>(__float_as_uint(zz)));
     const float q2 = __shfl(sq, row, 64);  // lane `row` holds row `row`'s ||q'||^2
     if (row < cnt) {
-      const int p = pairs[row];
+      const int p = ldg(pairs + row);
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
         const int col = c * 16 + (lane & 15);
-        if (col < r) T[(size_t)p * r + col] = acc[c][t];
+        if (col < r) stg(T + (size_t)p * r + col, acc[c][t]);
       }
-      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
+      if ((lane & 15) == 0) stg(epsq + p, fmaxf(q2 - zz, 0.f));
     }
   }
 }
@@ -151,7 +153,7 @@ __device__ __forceinline__ void project_wave_bf16(const float* __restrict__ Q, i
                                                   float* __restrict__ epsq) {
   const int lane = lane_id();
   const int i = lane & 15, kq = lane >> 4;
-  const int qrow = i < cnt ? pairs[i] / P : -1;
+  const int qrow = i < cnt ? ldg(pairs + i) / P : -1;
   const float* mu = centroids + (size_t)g * d;
   const uint16_t* Wg = basis16 + (size_t)g * r * d;
   const float* qp = Q + (size_t)(qrow < 0 ? 0 : qrow) * d;
@@ -178,13 +180,13 @@ __device__ __forceinline__ void project_wave_bf16(const float* __restrict__ Q, i
     for (int c = 0; c < NCT; ++c) {
       const int j = c * 16 + i;
       u32x4 bv = {0u, 0u, 0u, 0u};
-      if (j < r && in) bv = *reinterpret_cast<const u32x4*>(Wg + (size_t)j * d + kb);
+      if (j < r && in) bv = ldg(reinterpret_cast<const u32x4*>(Wg + (size_t)j * d + kb));
       acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
                                                         acc[c], 0, 0, 0);
     }
   }
-  sq += __shfl_xor(sq, 16, 64);
-  sq += __shfl_xor(sq, 32, 64);
+  sq += __uint_as_float(lane_xor<16>(__float_as_uint(sq)));
+  sq += __uint_as_float(lane_xor<32>(__float_as_uint(sq)));
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int row = 4 * (lane >> 4) + t;
@@ -194,17 +196,19 @@ __device__ __forceinline__ void project_wave_bf16(const float* __restrict__ Q, i
       const int col = c * 16 + (lane & 15);
       if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
     }
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) zz += __shfl_xor(zz, o, 64);
+    zz += __uint_as_float(lane_xor<1>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<2>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<4>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<8>(__float_as_uint(zz)));
     const float q2 = __shfl(sq, row, 64);
     if (row < cnt) {
-      const int p = pairs[row];
+      const int p = ldg(pairs + row);
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
         const int col = c * 16 + (lane & 15);
-        if (col < r) T[(size_t)p * r + col] = acc[c][t];
+        if (col < r) stg(T + (size_t)p * r + col, acc[c][t]);
       }
-      if ((lane & 15) == 0) epsq[p] = fmaxf(q2 - zz, 0.f);
+      if ((lane & 15) == 0) stg(epsq + p, fmaxf(q2 - zz, 0.f));
     }
   }
 }

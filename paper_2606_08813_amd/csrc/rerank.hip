@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
           // a pruned list holds one KEY_NONE and nothing else written: skip it whole
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (shfl_u64(key[u], 0) != KEY_NONE) L.offer(key[u], key[u] != KEY_NONE);
+            if (lane_u64(key[u], 0) != KEY_NONE) L.offer(key[u], key[u] != KEY_NONE);
         }
         L.finish();
         if (lane < C) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         // KEY_NONE and nothing else written: skip it whole
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (shfl_u64(key[u][0], 0) != KEY_NONE)
+          if (lane_u64(key[u][0], 0) != KEY_NONE)
 #pragma unroll
             for (int r = 0; r < NR; ++r) L.offer(key[u][r], key[u][r] != KEY_NONE);
       }

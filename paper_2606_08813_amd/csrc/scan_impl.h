@@ -42,12 +42,12 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
   if constexpr (CT == 0) {
     const float* cb = reinterpret_cast<const float*>(codes) + blk * RP * B;
 #pragma unroll
-    for (int j = 0; j < RP; ++j) c[j] = cb[j * B + lane];
+    for (int j = 0; j < RP; ++j) c[j] = ldg(cb + j * B + lane);
   } else if constexpr (CT == 1) {
     const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
 #pragma unroll
     for (int j = 0; j < RP / 2; ++j) {
-      const uint32_t w = wb[j * B + lane];
+      const uint32_t w = ldg(wb + j * B + lane);
       c[2 * j] = __uint_as_float(w << 16);
       c[2 * j + 1] = __uint_as_float(w & 0xFFFF0000u);
     }
@@ -55,7 +55,7 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
     const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 4) * B;
 #pragma unroll
     for (int j = 0; j < RP / 4; ++j) {
-      const int w = (int)wb[j * B + lane];
+      const int w = (int)ldg(wb + j * B + lane);
       const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);  // bytes 0, 1
       const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);   // bytes 2, 3
       c[4 * j] = lo[0] * s;
