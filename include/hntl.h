@@ -266,6 +266,9 @@ typedef struct hntl_schedule {
   uint32_t passes; /* 1: every item in one launch; 2: projection and probe-slot-0 items in a first launch,
                       the other slots in a second one, which then start from each query's slot-0 bound
                       (0 = 1) */
+  uint32_t proj;   /* 0: projection items run inside the fused kernel; 1: a grain-major projection
+                      launch (128 pairs of one grain per workgroup) runs before it and the fused
+                      kernel only scans and selects */
 } hntl_schedule;
 
 #define HNTL_PLAN_GRAPH 1u /* capture a HIP graph at creation; runs replay it */
@@ -324,7 +327,8 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out);
  * hntl_plan_profile - run the plan reps times without its graph, with HIP events
  * between its stages on `stream`, and return the mean device milliseconds per stage
  * in stage_ms[0..4): routing, bucketing (with the resets), the fused
- * project-scan-select kernel, merge + rerank.  *scored (may be NULL) receives the
+ * project-scan-select kernel (with schedule proj = 1, the projection launch and the
+ * fused kernel), merge + rerank.  *scored (may be NULL) receives the
  * eq. 6 scores the last run computed.  The queries are the first nq rows of the
  * plan's Q buffer.  Synchronous.
  */
@@ -335,8 +339,8 @@ void hntl_plan_free(hntl_plan* plan);
 
 /*
  * hntl_tune - the autotuner.  Times every candidate schedule of the fused kernel
- * (passes in {1, 2} x qt in {1, 2, 4, 8} x nw in {1, 2, 4, 8} x range in {0, 8, 32, 64}, those whose
- * LDS fits) on the nq given queries (device, nq x d) and returns the fastest in *best
+ * (proj in {0, 1} x passes in {1, 2} x qt in {1, 2, 4, 8} x nw in {1, 2, 4, 8} x range in
+ * {0, 8, 32, 64}, those whose LDS fits) on the nq given queries (device, nq x d) and returns the fastest in *best
  * (*best_ms its median device time of one run).  With db_path != NULL the result is
  * also stored in that text file, one line per (device, index shape, search params,
  * batch size), replacing an older line of the same key; hntl_schedule_lookup reads it.

@@ -444,7 +444,7 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
       b.cur0 = sc.get<int32_t>(ix.G);
       b.cur1 = sc.get<int32_t>(ix.G);
       b.order = sc.get<int32_t>(npairs);
-      const int tiles[3] = {16, 16, 128};
+      const int tiles[3] = {16, 16, PROJECT_TILE};
       const int64_t np[3] = {(int64_t)nq, (int64_t)nq * (P - 1), npairs};
       for (int L = 0; L < 3; ++L) {
         b.lists.tile[L] = tiles[L];
@@ -461,7 +461,7 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
         clk.at(HNTL_STAGE_PROJECT);
         float* To = tangent_out ? tangent_out : sc.get<float>((size_t)npairs * ix.r);
         float* eo = epsq_out ? epsq_out : sc.get<float>(npairs);
-        launch_project(ix, Q, (int)P, b, To, eo, (sp->flags & HNTL_FLAG_PROJECT_BF16) != 0, s);
+        launch_project(ix, Q, (int)P, b, To, eo, (sp->flags & HNTL_FLAG_PROJECT_BF16) != 0, nullptr, s);
         T = To;
         eq = eo;
       }

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   // from one address.  A wave reaches the scan items only after every
   // projection ticket has been handed out.
   using gptr = int32_t __attribute__((address_space(1)))*;
-  if (a.phase != 2) {
+  if (a.phase != 2 && !a.proj_ext) {
     const gptr pctr = (gptr)a.ticket;
     for (;;) {
       if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(pctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >=
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
       // wait (acquire) for the projection items that hold this tile's pairs:
       // a grain's projection list is its slot-0 pairs followed by the others,
       // in 16-pair items, so the tile spans items c0 .. c1 (at most two)
-      {
+      if (!a.proj_ext) {
         const int base = (L == LIST_SLOT0 ? 0 : __builtin_amdgcn_readfirstlane(ldg(a.lcount[LIST_SLOT0] + g))) + first;
         const int pi0 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_ALL] + rank));
         for (int c = pi0 + base / 16; c <= pi0 + (base + cnt - 1) / 16; ++c) {

@@ -195,8 +195,10 @@ void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const in
                        int32_t* qoff, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
+constexpr int PROJECT_TILE = 128;  // pairs per workgroup of the grain-major projection kernel
+// gorder: the rank -> grain map when the buckets were built in that order (ioff by rank), else null
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
-                    hipStream_t s);  // over LIST_ALL
+                    const int32_t* gorder, hipStream_t s);  // over LIST_ALL
 // Scan of the bucketed pairs.  With `bound_lists` (the lists of probe slot 0,
 // already written into part), each pair starts from its query's C-th key of
 // slot 0 as threshold and, when `prune`, is skipped outright if an exact
@@ -252,6 +254,7 @@ struct FusedArgs {
   uint64_t* part;      // lists x C keys
   unsigned long long* scored;
   int proj_bf16;
+  int proj_ext;  // 1: tangents come from a separate projection launch (no projection items, no waits)
   int prune;
 };
 

@@ -206,7 +206,10 @@ struct Plan {
       b.lists.lcount[l] = L.take<int32_t>(x.G);
     }
     b.lists.tile[LIST_SLOT0] = b.lists.tile[LIST_REST] = (int)sch.qt;  // scan item: qt pairs (one wave)
-    b.lists.tile[LIST_ALL] = 16;                                       // projection item: 16 pairs (one wave)
+    // projection item: 16 pairs (one wave of the fused kernel), or a workgroup
+    // of the separate projection launch
+    b.lists.tile[LIST_ALL] = sch.proj ? PROJECT_TILE : 16;
+    b.max_items[LIST_ALL] = (int)(np / b.lists.tile[LIST_ALL] + std::min<int64_t>(x.G, np) + 1);
     nsplit = L.take<int32_t>(x.G);
     lbase = L.take<int32_t>(np);
     qoff = L.take<int32_t>((size_t)max_nq + 1);
@@ -273,6 +276,7 @@ struct Plan {
     a.part = part;
     a.scored = scored;
     a.proj_bf16 = (sp.flags & HNTL_FLAG_PROJECT_BF16) ? 1 : 0;
+    a.proj_ext = sch.proj ? 1 : 0;
     a.prune = (sp.flags & HNTL_FLAG_NO_PRUNE) ? 0 : 1;
     return a;
   }
@@ -307,6 +311,7 @@ struct Plan {
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (sch.proj) launch_project(x, Q, P, b, T, epsq, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0, x.gorder, s);
     for (int ph = sch.passes == 2 ? 1 : 0; ph <= (sch.passes == 2 ? 2 : 0); ++ph) {
       if (!fused_launch((int)sp.codes, args_dev + ph, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid,
                         s))
@@ -382,6 +387,7 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   if (sch.nw < 1 || sch.nw > 8) throw ArgError{HNTL_EINVAL, "schedule nw must be 1..8"};
   if (sch.passes == 0) sch.passes = 1;
   if (sch.passes > 2) throw ArgError{HNTL_EINVAL, "schedule passes must be 1 or 2"};
+  if (sch.proj > 1) throw ArgError{HNTL_EINVAL, "schedule proj must be 0 or 1"};
   if (lds_per_wave((int)ix.rp, (int)sp.C, (int)sch.qt) * sch.nw > LDS_LIMIT)
     throw ArgError{HNTL_EUNSUPPORTED, "schedule needs more than 64 KiB of LDS per workgroup"};
   ensure_grain_order(ix);
@@ -635,12 +641,13 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
     hntl_schedule bs{};
     bool have = false;
     const uint32_t qts[] = {1, 2, 4, 8}, nws[] = {1, 2, 4, 8}, ranges[] = {0, 8, 32, 64};
+    for (uint32_t proj = 0; proj <= 1; ++proj)
     for (uint32_t passes = 1; passes <= 2; ++passes)
     for (uint32_t qt : qts)
       for (uint32_t nw : nws)
         for (uint32_t R : ranges) {
           if (lds_per_wave((int)ix.rp, (int)spp.C, (int)qt) * nw > LDS_LIMIT) continue;
-          hntl_schedule c{qt, nw, R, 0, passes};
+          hntl_schedule c{qt, nw, R, 0, passes, proj};
           std::unique_ptr<Plan> pl;
           try {
             pl.reset(make_plan(ix, spp, nq, c, 0, s));
@@ -691,8 +698,8 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
           if (!line.empty() && line.rfind(key + " |", 0) != 0) lines.push_back(line);
       }
       char buf[160];
-      std::snprintf(buf, sizeof buf, " | qt=%u nw=%u range=%u passes=%u | %.4f ms", bs.qt, bs.nw, bs.range,
-                    bs.passes, bms);
+      std::snprintf(buf, sizeof buf, " | qt=%u nw=%u range=%u passes=%u proj=%u | %.4f ms", bs.qt, bs.nw,
+                    bs.range, bs.passes, bs.proj, bms);
       lines.push_back(key + buf);
       std::ofstream o(db_path, std::ios::trunc);
       if (!o) throw ArgError{HNTL_EINVAL, std::string("cannot write tuning file ") + db_path};
@@ -714,8 +721,9 @@ hntl_status hntl_schedule_lookup(const hntl_index* index, const hntl_search_para
     while (std::getline(in, line)) {
       if (line.rfind(key + " |", 0) != 0) continue;
       hntl_schedule s{};
-      if (std::sscanf(line.c_str() + key.size(), " | qt=%u nw=%u range=%u passes=%u", &s.qt, &s.nw, &s.range,
-                      &s.passes) == 4) {
+      const int nf = std::sscanf(line.c_str() + key.size(), " | qt=%u nw=%u range=%u passes=%u proj=%u", &s.qt,
+                                 &s.nw, &s.range, &s.passes, &s.proj);
+      if (nf == 4 || nf == 5) {  // lines written before the proj field count as proj = 0
         s.grid = 0;
         *out = s;
         return;

@@ -9,17 +9,19 @@ namespace {
 
 using namespace proj_detail;
 
-constexpr int TILE = 128;  // pairs per work item (8 waves of 16)
+constexpr int TILE = PROJECT_TILE;  // pairs per work item (8 waves of 16)
 
 template <bool VEC, int NCT>
 __global__ __launch_bounds__(64 * (TILE / PT)) void project_kernel(
     const float* __restrict__ Q, int d, int P, const float* __restrict__ centroids, const float* __restrict__ basis,
     int r, const int32_t* __restrict__ ioff, const int32_t* __restrict__ lstart, const int32_t* __restrict__ lcount,
-    int G, const int32_t* __restrict__ order, float* __restrict__ T, float* __restrict__ epsq) {
+    int G, const int32_t* __restrict__ gorder, const int32_t* __restrict__ order, float* __restrict__ T,
+    float* __restrict__ epsq) {
   const int wave = threadIdx.x >> 6;
-  int g;
-  if (!item_grain(ioff, G, blockIdx.x, g)) return;
-  const int first = (blockIdx.x - ioff[g]) * TILE + PT * wave;  // within the grain's pairs
+  int rank;
+  if (!item_grain(ioff, G, blockIdx.x, rank)) return;
+  const int g = gorder ? gorder[rank] : rank;
+  const int first = (blockIdx.x - ioff[rank]) * TILE + PT * wave;  // within the grain's pairs
   const int cnt = min(PT, lcount[g] - first);
   if (cnt <= 0) return;  // no workgroup barrier in this kernel
   project_wave<VEC, NCT>(Q, d, P, centroids, basis, r, g, order + lstart[g] + first, cnt, T, epsq);
@@ -29,12 +31,13 @@ template <int NCT>
 __global__ __launch_bounds__(64 * (TILE / PT)) void project_bf16_kernel(
     const float* __restrict__ Q, int d, int P, const float* __restrict__ centroids,
     const uint16_t* __restrict__ basis16, int r, const int32_t* __restrict__ ioff, const int32_t* __restrict__ lstart,
-    const int32_t* __restrict__ lcount, int G, const int32_t* __restrict__ order, float* __restrict__ T,
-    float* __restrict__ epsq) {
+    const int32_t* __restrict__ lcount, int G, const int32_t* __restrict__ gorder, const int32_t* __restrict__ order,
+    float* __restrict__ T, float* __restrict__ epsq) {
   const int wave = threadIdx.x >> 6;
-  int g;
-  if (!item_grain(ioff, G, blockIdx.x, g)) return;
-  const int first = (blockIdx.x - ioff[g]) * TILE + PT * wave;
+  int rank;
+  if (!item_grain(ioff, G, blockIdx.x, rank)) return;
+  const int g = gorder ? gorder[rank] : rank;
+  const int first = (blockIdx.x - ioff[rank]) * TILE + PT * wave;
   const int cnt = min(PT, lcount[g] - first);
   if (cnt <= 0) return;  // no workgroup barrier in this kernel
   project_wave_bf16<NCT>(Q, d, P, centroids, basis16, r, g, order + lstart[g] + first, cnt, T, epsq);
@@ -44,34 +47,38 @@ __global__ __launch_bounds__(64 * (TILE / PT)) void project_bf16_kernel(
 
 template <bool VEC, int NCT>
 void launch_project_t(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                      const int32_t* gorder,
                       hipStream_t s) {
   const ItemLists& L = b.lists;
   hipLaunchKernelGGL((project_kernel<VEC, NCT>), dim3((unsigned)b.max_items[LIST_ALL]), dim3(64 * (TILE / PT)), 0,
                      s, Q, (int)ix.d, P, ix.centroids, ix.basis, (int)ix.r, L.ioff[LIST_ALL], L.lstart[LIST_ALL],
-                     L.lcount[LIST_ALL], (int)ix.G, b.order, T, epsq);
+                     L.lcount[LIST_ALL], (int)ix.G, gorder, b.order, T, epsq);
 }
 
 template <bool VEC>
 void launch_project_v(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                      const int32_t* gorder,
                       hipStream_t s) {
   switch ((ix.r + 15) / 16) {
-    case 1: launch_project_t<VEC, 1>(ix, Q, P, b, T, epsq, s); break;
-    case 2: launch_project_t<VEC, 2>(ix, Q, P, b, T, epsq, s); break;
-    case 3: launch_project_t<VEC, 3>(ix, Q, P, b, T, epsq, s); break;
-    default: launch_project_t<VEC, 4>(ix, Q, P, b, T, epsq, s); break;
+    case 1: launch_project_t<VEC, 1>(ix, Q, P, b, T, epsq, gorder, s); break;
+    case 2: launch_project_t<VEC, 2>(ix, Q, P, b, T, epsq, gorder, s); break;
+    case 3: launch_project_t<VEC, 3>(ix, Q, P, b, T, epsq, gorder, s); break;
+    default: launch_project_t<VEC, 4>(ix, Q, P, b, T, epsq, gorder, s); break;
   }
 }
 
 template <int NCT>
 void launch_project_bf16_t(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq,
+                      const int32_t* gorder,
                            hipStream_t s) {
   const ItemLists& L = b.lists;
   hipLaunchKernelGGL((project_bf16_kernel<NCT>), dim3((unsigned)b.max_items[LIST_ALL]), dim3(64 * (TILE / PT)), 0, s,
                      Q, (int)ix.d, P, ix.centroids, ix.basis_bf16, (int)ix.r, L.ioff[LIST_ALL], L.lstart[LIST_ALL],
-                     L.lcount[LIST_ALL], (int)ix.G, b.order, T, epsq);
+                     L.lcount[LIST_ALL], (int)ix.G, gorder, b.order, T, epsq);
 }
 
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
+                    const int32_t* gorder,
                     hipStream_t s) {
   if (b.max_items[LIST_ALL] <= 0) return;
   if (bf16) {
@@ -79,19 +86,19 @@ void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, fl
     if ((ix.d % 8) != 0 || ((uintptr_t)Q % 16) != 0)
       throw ArgError{HNTL_EUNSUPPORTED, "BF16 projection needs d % 8 == 0 and 16-byte aligned queries"};
     switch ((ix.r + 15) / 16) {
-      case 1: launch_project_bf16_t<1>(ix, Q, P, b, T, epsq, s); break;
-      case 2: launch_project_bf16_t<2>(ix, Q, P, b, T, epsq, s); break;
-      case 3: launch_project_bf16_t<3>(ix, Q, P, b, T, epsq, s); break;
-      default: launch_project_bf16_t<4>(ix, Q, P, b, T, epsq, s); break;
+      case 1: launch_project_bf16_t<1>(ix, Q, P, b, T, epsq, gorder, s); break;
+      case 2: launch_project_bf16_t<2>(ix, Q, P, b, T, epsq, gorder, s); break;
+      case 3: launch_project_bf16_t<3>(ix, Q, P, b, T, epsq, gorder, s); break;
+      default: launch_project_bf16_t<4>(ix, Q, P, b, T, epsq, gorder, s); break;
     }
     HIP_TRY(hipGetLastError());
     return;
   }
   if (b.lists.tile[LIST_ALL] != TILE) throw ArgError{HNTL_EDEVICE, "projection tile mismatch"};
   if ((ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0)
-    launch_project_v<true>(ix, Q, P, b, T, epsq, s);
+    launch_project_v<true>(ix, Q, P, b, T, epsq, gorder, s);
   else
-    launch_project_v<false>(ix, Q, P, b, T, epsq, s);
+    launch_project_v<false>(ix, Q, P, b, T, epsq, gorder, s);
   HIP_TRY(hipGetLastError());
 }
 

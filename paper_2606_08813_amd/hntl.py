@@ -53,7 +53,7 @@ class hntl_index_info(C.Structure):
 
 class hntl_schedule(C.Structure):
     _fields_ = [("qt", C.c_uint32), ("nw", C.c_uint32), ("range", C.c_uint32), ("grid", C.c_uint32),
-                ("passes", C.c_uint32)]
+                ("passes", C.c_uint32), ("proj", C.c_uint32)]
 
 
 class hntl_plan_info(C.Structure):
@@ -349,12 +349,13 @@ def _sched(sched):
     if isinstance(sched, hntl_schedule):
         return sched
     if isinstance(sched, dict):
-        return hntl_schedule(sched["qt"], sched["nw"], sched["range"], sched.get("grid", 0), sched.get("passes", 1))
+        return hntl_schedule(sched["qt"], sched["nw"], sched["range"], sched.get("grid", 0), sched.get("passes", 1),
+                             sched.get("proj", 0))
     return hntl_schedule(*sched)
 
 
 def sched_dict(s: hntl_schedule) -> dict:
-    return {"qt": s.qt, "nw": s.nw, "range": s.range, "grid": s.grid, "passes": s.passes}
+    return {"qt": s.qt, "nw": s.nw, "range": s.range, "grid": s.grid, "passes": s.passes, "proj": s.proj}
 
 
 def hntl_plan_create(index: Index, P: int, C_: int, k: int, max_nq: int, codes="fp32", flags=0, sched=None,

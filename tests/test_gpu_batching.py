@@ -28,6 +28,9 @@ SCHEDULES = [
     dict(qt=8, nw=1, range=2),
     dict(qt=4, nw=4, range=0, passes=2),
     dict(qt=2, nw=2, range=1, passes=2),
+    dict(qt=4, nw=4, range=0, proj=1),           # separate projection launch
+    dict(qt=2, nw=2, range=1, passes=2, proj=1),
+    dict(qt=1, nw=8, range=3, proj=1),
 ]
 
 
@@ -56,7 +59,8 @@ def assert_same(a, b, what):
 
 
 @pytest.mark.parametrize("sched", SCHEDULES,
-                         ids=lambda s: f"qt{s['qt']}-nw{s['nw']}-range{s['range']}-passes{s.get('passes', 1)}")
+                         ids=lambda s: f"qt{s['qt']}-nw{s['nw']}-range{s['range']}-passes{s.get('passes', 1)}"
+                                       f"-proj{s.get('proj', 0)}")
 def test_plan_equals_staged_search(bt, sched):
     W, hntl = bt["W"], bt["hntl"]
     announce(f"plan (eager) {sched} vs staged search, batches 1..1000")
@@ -73,7 +77,7 @@ def test_plan_reduced_precision_equals_staged(bt, codes, bf16proj):
     W, hntl = bt["W"], bt["hntl"]
     fl = hntl.HNTL_FLAG_PROJECT_BF16 if bf16proj else 0
     announce(f"plan codes={codes} bf16 projection={bf16proj} vs staged search")
-    for sched in (dict(qt=2, nw=4, range=1), dict(qt=4, nw=2, range=0)):
+    for sched in (dict(qt=2, nw=4, range=1), dict(qt=4, nw=2, range=0), dict(qt=4, nw=2, range=0, proj=1)):
         plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, codes=codes, flags=fl | hntl.HNTL_FLAG_SYNC,
                                      sched=sched)
         assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], codes, fl), f"{codes} {sched}")
@@ -145,7 +149,7 @@ def test_autotuner_and_lookup(bt, tmp_path):
     db = tmp_path / "tune.txt"
     Q = bt["Qd"][:256].contiguous()
     best, ms = hntl.hntl_tune(bt["ix"], Q, W.P, W.C, W.k, db_path=db)
-    assert ms > 0 and best["qt"] in (1, 2, 4, 8) and 1 <= best["nw"] <= 8
+    assert ms > 0 and best["qt"] in (1, 2, 4, 8) and 1 <= best["nw"] <= 8 and best["proj"] in (0, 1)
     assert hntl.hntl_schedule_lookup(bt["ix"], W.P, W.C, W.k, 256, db) == best
     text = db.read_text()
     assert text.count("\n") == 1 and "nq=256" in text
@@ -176,3 +180,22 @@ def test_plan_errors(bt):
     with pytest.raises(hntl.HNTLError) as e:
         hntl.hntl_plan_search(plan, bt["Qd"][:11].contiguous())
     assert e.value.status == hntl.HNTL_EINVAL
+
+
+def test_plan_unequal_grains(bt):
+    """An index built on the GPU with G = 100 grains over 64 patches: grain sizes
+    differ, so the plans' size-ordered item lists (rank -> grain map) are not
+    the identity; every schedule form must still equal the staged search."""
+    W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
+    announce("G=100 GPU-built index: plans (fused and separate projection) vs staged search")
+    ix = hntl.hntl_build(torch.from_numpy(bt["X"]).cuda(), 100, 32, seed=11, codes=("fp32", "bf16"))
+    sizes = np.diff(hntl.hntl_index_export(ix)["offsets"])
+    assert len(set(sizes.tolist())) > 1
+    Q = bt["Qd"]
+    for codes, fl in (("fp32", 0), ("bf16", hntl.HNTL_FLAG_PROJECT_BF16)):
+        ref = hntl.hntl_search(ix, Q, W.P, W.C, W.k, codes=codes, flags=fl | hntl.HNTL_FLAG_SYNC)
+        for sched in (dict(qt=4, nw=2, range=0), dict(qt=4, nw=2, range=0, proj=1),
+                      dict(qt=2, nw=4, range=1, passes=2, proj=1), dict(qt=1, nw=8, range=2)):
+            plan = hntl.hntl_plan_create(ix, W.P, W.C, W.k, 1000, codes=codes, flags=fl, sched=sched)
+            assert_same(hntl.hntl_plan_search(plan, Q), ref, f"G=100 {codes} {sched}")
+            assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
