@@ -209,10 +209,162 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
       }
 }
 
+// Epilogue of one output element (row < M, col < N checked by the caller).
+template <int EPI>
+__device__ __forceinline__ void epi_store(const Epi& e, int row, int col, float v) {
+  if constexpr (EPI == EPI_F32) {
+    e.C[(size_t)row * e.ldc + col] = v;
+  } else if constexpr (EPI == EPI_BIAS_F32) {
+    e.C[(size_t)row * e.ldc + col] = e.scale * (v + e.bias[col]);
+  } else if constexpr (EPI == EPI_BIAS_GELU) {
+    const float z = v + e.bias[col];
+    if (e.C) e.C[(size_t)row * e.ldc + col] = z;
+    e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
+  } else {
+    const float gz = v * gelu_grad(e.Z[(size_t)row * e.ldz + col]);
+    e.D[(size_t)row * e.ldd + col] = gz;
+    e.H[(size_t)row * e.ldh + col] = to_bf16(gz);
+  }
+}
+
+// ---------------------------------------------- large-tile GEMM, both k-contiguous
+// C = A B^T with A (M x K) and B (N x K) both row-major (k contiguous, K % 8
+// == 0), the shape of every forward product.  One workgroup of 8 waves per
+// 256 x 128 tile of C; wave w owns rows 64 (w / 2) .. + 63 and columns
+// 64 (w % 2) .. + 63 as 4 x 4 MFMA 16x16x32 tiles.  Depth tiles of 64 go
+// global -> registers -> LDS into two LDS buffers: tile k + 1 loads while
+// tile k feeds the MFMAs, one barrier per depth tile.  Tiles are handed to the
+// 8 XCDs in contiguous runs (workgroup ids go round-robin over the XCDs), so
+// the workgroups of one XCD share A row blocks in their L2.
+constexpr int NM = 256, NN = 128, NK = 64, NLD = NK + 8;
+
+struct NFrag {
+  uint4 a[4];  // A: row t / 2, depths 32 (t % 2) + 8 h
+  uint4 b[2];  // B: row t / 4, depths 16 (t % 4) + 8 h
+};
+
+// 8 consecutive bf16 of row r from depth k (K % 8 == 0: a run is wholly in or out).
+__device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ X, int ld, int R, int K, int r, int k) {
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (r < R && k < K) v = *reinterpret_cast<const uint4*>(X + (size_t)r * ld + k);
+  return v;
+}
+
+__device__ __forceinline__ void nfetch(NFrag& f, const uint16_t* __restrict__ A, int lda, int M,
+                                       const uint16_t* __restrict__ B, int ldb, int N, int K, int m0, int n0, int k0) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) f.a[h] = load8(A, lda, M, K, m0 + (t >> 1), k0 + (t & 1) * 32 + 8 * h);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) f.b[h] = load8(B, ldb, N, K, n0 + (t >> 2), k0 + (t & 3) * 16 + 8 * h);
+}
+
+__device__ __forceinline__ void nstore(uint16_t (*As)[NLD], uint16_t (*Bs)[NLD], const NFrag& f) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) *reinterpret_cast<uint4*>(&As[t >> 1][(t & 1) * 32 + 8 * h]) = f.a[h];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) *reinterpret_cast<uint4*>(&Bs[t >> 2][(t & 3) * 16 + 8 * h]) = f.b[h];
+}
+
+template <int EPI>
+__global__ __launch_bounds__(512) void gemm_nn_kernel(const uint16_t* __restrict__ A, int lda,
+                                                      const uint16_t* __restrict__ B, int ldb, int M, int N, int K,
+                                                      Epi e, const int32_t* __restrict__ mlim, int tiles_n,
+                                                      int ntiles) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t nsm[];
+  uint16_t(*As0)[NLD] = reinterpret_cast<uint16_t(*)[NLD]>(nsm);
+  uint16_t(*Bs0)[NLD] = reinterpret_cast<uint16_t(*)[NLD]>(nsm + NM * NLD);
+  uint16_t(*As1)[NLD] = reinterpret_cast<uint16_t(*)[NLD]>(nsm + (NM + NN) * NLD);
+  uint16_t(*Bs1)[NLD] = reinterpret_cast<uint16_t(*)[NLD]>(nsm + (2 * NM + NN) * NLD);
+  // XCD-contiguous tile order: workgroup b runs on XCD b % 8
+  const int nb = (int)gridDim.x, per = nb / 8;
+  const int bid = (int)blockIdx.x;
+  const int tile = (nb % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
+  if (tile >= ntiles) return;
+  const int m0 = (tile / tiles_n) * NM, n0 = (tile % tiles_n) * NN;
+  if (mlim) {
+    const int lim = *mlim;
+    if (m0 >= lim) return;
+    if (lim < M) M = lim;
+  }
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int i = lane & 15, kq = lane >> 4;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (K + NK - 1) / NK;
+  auto mma = [&](uint16_t (*As)[NLD], uint16_t (*Bs)[NLD]) {
+#pragma unroll
+    for (int ks = 0; ks < NK; ks += 32) {
+      bf16x8 af[4], bfv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + i][ks + 8 * kq]);
+        bfv[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + i][ks + 8 * kq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  NFrag f;
+  nfetch(f, A, lda, M, B, ldb, N, K, m0, n0, 0);
+  nstore(As0, Bs0, f);
+  __syncthreads();
+  // LDS buffer k % 2 holds depth tile k while tile k + 1 loads into registers;
+  // the buffer written in a step was last read in the step before, which the
+  // barrier closed
+  for (int k = 0; k < nk; k += 2) {
+    if (k + 1 < nk) nfetch(f, A, lda, M, B, ldb, N, K, m0, n0, (k + 1) * NK);
+    mma(As0, Bs0);
+    if (k + 1 < nk) nstore(As1, Bs1, f);
+    __syncthreads();
+    if (k + 1 >= nk) break;
+    if (k + 2 < nk) nfetch(f, A, lda, M, B, ldb, N, K, m0, n0, (k + 2) * NK);
+    mma(As1, Bs1);
+    if (k + 2 < nk) nstore(As0, Bs0, f);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wm + 16 * a + 4 * kq + j;
+        const int col = n0 + wn + 16 * b + i;
+        if (row < M && col < N) epi_store<EPI>(e, row, col, acc[a][b][j]);
+      }
+}
+constexpr size_t NN_LDS = (size_t)2 * (NM + NN) * NLD * sizeof(uint16_t);
+
 template <bool AT, bool BT, int EPI>
 void gemm(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K, const Epi& e, hipStream_t s,
           const int32_t* mlim = nullptr) {
   if (M <= 0 || N <= 0) return;
+  if constexpr (!AT && !BT) {
+    if ((K % 8) == 0 && (lda % 8) == 0 && (ldb % 8) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0) {
+      const int tn = (N + NN - 1) / NN, tm = (M + NM - 1) / NM;
+      const int nt = tn * tm;
+      const int grid = (nt + 7) / 8 * 8;  // a multiple of 8 for the XCD-contiguous order
+      static bool lds_set = false;        // more than 64 KiB of dynamic LDS
+      if (!lds_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)gemm_nn_kernel<EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)NN_LDS));
+        lds_set = true;
+      }
+      hipLaunchKernelGGL((gemm_nn_kernel<EPI>), dim3((unsigned)grid), dim3(512), NN_LDS, s, A, lda, B, ldb, M, N, K, e,
+                         mlim, tn, nt);
+      HIP_TRY(hipGetLastError());
+      return;
+    }
+  }
   const dim3 grid((unsigned)((N + GN - 1) / GN), (unsigned)((M + GM - 1) / GM));
   hipLaunchKernelGGL((gemm_bf16_kernel<AT, BT, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, e, mlim);
   HIP_TRY(hipGetLastError());
