@@ -267,8 +267,8 @@ typedef struct hntl_schedule {
                       the other slots in a second one, which then start from each query's slot-0 bound
                       (0 = 1) */
   uint32_t proj;   /* 0: projection items run inside the fused kernel; 1: a grain-major projection
-                      launch (128 pairs of one grain per workgroup) runs before it and the fused
-                      kernel only scans and selects */
+                      launch (16 pairs of one grain per single-wave workgroup) runs before it and
+                      the fused kernel only scans and selects */
 } hntl_schedule;
 
 #define HNTL_PLAN_GRAPH 1u /* capture a HIP graph at creation; runs replay it */
