@@ -3,13 +3,15 @@
 Workload (default): 1,000,000 patch-mixture vectors, d = 768, 1,024 patches;
 index G = 1,024 k-means grains, r = 32; one batch of 10,000 queries; P = 8,
 C = 64, k = 10; FP32.  A step is one full search of the batch (route, bucket,
-project, scan + select, merge + rerank), inputs resident in HBM.
+project, scan + select, merge + rerank), inputs resident in HBM, run by an
+autotuned search plan (the persistent fused project-scan-select kernel, launch
+sequence replayed as a HIP graph; stage times come from an eager profiled run).
 
 Other forms (same JSON line; --workload zipf10M_d768_G8192_r48 is the 10M-vector
 Zipf-grain batching workload, 16,384 queries per step, P = 16, C = 100):
-  --form plan      the persistent fused project-scan-select kernel inside an
-                   autotuned search plan whose launch sequence replays as a HIP
-                   graph; stage times come from an eager profiled run
+  --form staged    hntl_search: one launch per stage, stage times from the
+                   library's HIP events during the timed steps
+  --sched ...      a fixed plan schedule instead of the autotuner's
   --route learned  the learned router, trained first on --router-train
                    generated queries with brute-force kNN targets
   --codes bf16|fp8 reduced-precision codes (BF16 MFMA projection by default)
@@ -46,9 +48,9 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # scaled by its reading for a plain 1 GiB device copy; valid while the kernel
 # source is unchanged (sha1 below).  Recorded in
 # profiles/merge_rerank_patch1M_d768_G1024_r32_hbm_counters.md.
-TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "staged", "codes": "fp32", "P": 8,
-           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "938da111e599658521b22f1cfa58d049755d1c3d",
-           "fetch_kib": 995046.0, "fetch_scale": 1048576.0 / 524308.125, "write_kib": 1250.0, "write_scale": 1.0}
+TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "plan", "codes": "fp32", "P": 8,
+           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "f6e9612345c74c5b52f217f275ed940a00260033",
+           "fetch_kib": 995029.1, "fetch_scale": 1048576.0 / 524307.8125, "write_kib": 1250.0, "write_scale": 1.0}
 
 
 def measured_traffic(stage, workload, form, codes, P):
@@ -81,8 +83,10 @@ def parse():
                     help="with --codes bf16/fp8, keep the FP32 projection (default: BF16 MFMA projection)")
     ap.add_argument("--error-sample", type=int, default=100,
                     help="queries for the reduced-precision error report against the FP64 oracle")
-    ap.add_argument("--form", choices=("staged", "plan"), default="staged",
+    ap.add_argument("--form", choices=("staged", "plan"), default="plan",
                     help="staged: hntl_search; plan: the persistent fused kernel in an autotuned, graph-replayed plan")
+    ap.add_argument("--sched", default="",
+                    help="plan schedule instead of autotuning, e.g. qt=4,nw=2,range=0,passes=2,proj=1")
     ap.add_argument("--route", choices=("centroid", "learned"), default="centroid",
                     help="learned: train the router first (router-train queries, brute-force kNN targets)")
     ap.add_argument("--P", type=int, default=0, help="probes per query (0 = the workload's)")
@@ -183,8 +187,13 @@ def main():
     else:
         pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE)
         t0 = time.time()
-        sched, tuned_ms = hntl.hntl_tune(ix, Q, P, W.C, W.k, codes=args.codes, flags=pflags, **rkw)
-        log(f"[bench] autotuned schedule {sched} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
+        if args.sched:
+            sched = {k: int(v) for k, v in (kv.split("=") for kv in args.sched.split(","))}
+            sched = hntl.sched_dict(hntl._sched(dict({"grid": 0, "passes": 1, "proj": 0}, **sched)))
+            log(f"[bench] given schedule {sched}")
+        else:
+            sched, tuned_ms = hntl.hntl_tune(ix, Q, P, W.C, W.k, codes=args.codes, flags=pflags, **rkw)
+            log(f"[bench] autotuned schedule {sched} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
         plan = hntl.hntl_plan_create(ix, P, W.C, W.k, W.nq, codes=args.codes, flags=pflags, sched=sched,
                                      graph=True, **rkw)
         for _ in range(args.warmup):
