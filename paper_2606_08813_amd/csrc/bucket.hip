@@ -242,34 +242,52 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const int32_t* __re
 
 // Per-pair list slots when grains are split into block ranges: pair
 // (q, slot) of grain g owns the nsplit[g] consecutive lists from lbase[pair];
-// a query's lists are contiguous, qoff[q] .. qoff[q + 1] (single workgroup).
-__global__ __launch_bounds__(1024) void pair_lists_kernel(const int32_t* __restrict__ probes, int64_t nq, int P,
+// a query's lists are contiguous, qoff[q] .. qoff[q + 1].  Three passes: the
+// lists of each query (one thread per query), an exclusive scan over the
+// queries (one workgroup, each thread a contiguous run), the per-slot bases
+// (one thread per query).
+__global__ __launch_bounds__(256) void query_lists_kernel(const int32_t* __restrict__ probes, int64_t nq, int P,
                                                           int G, const int32_t* __restrict__ nsplit,
-                                                          int32_t* __restrict__ lbase, int32_t* __restrict__ qoff) {
-  __shared__ int tmp[32];
-  int carry = 0;
-  for (int64_t base = 0; base < nq; base += 1024) {
-    const int64_t q = base + threadIdx.x;
-    int tot = 0;
-    if (q < nq)
-      for (int sl = 0; sl < P; ++sl) {
-        const int g = probes[q * P + sl];
-        tot += (g >= 0 && g < G) ? nsplit[g] : 0;
-      }
-    int all;
-    const int ex = carry + block_exclusive_scan(tot, tmp, all);
-    if (q < nq) {
-      qoff[q] = ex;
-      int run = ex;
-      for (int sl = 0; sl < P; ++sl) {
-        const int g = probes[q * P + sl];
-        lbase[q * P + sl] = run;
-        run += (g >= 0 && g < G) ? nsplit[g] : 0;
-      }
-    }
-    carry += all;
+                                                          int32_t* __restrict__ qoff) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int tot = 0;
+  for (int sl = 0; sl < P; ++sl) {
+    const int g = probes[q * P + sl];
+    tot += (g >= 0 && g < G) ? nsplit[g] : 0;
   }
-  if (threadIdx.x == 0) qoff[nq] = carry;
+  qoff[q] = tot;
+}
+
+__global__ __launch_bounds__(1024) void query_scan_kernel(int64_t nq, int32_t* __restrict__ qoff) {
+  __shared__ int tmp[32];
+  const int64_t per = (nq + (int64_t)blockDim.x - 1) / (int64_t)blockDim.x;
+  const int64_t q0 = (int64_t)threadIdx.x * per;
+  const int64_t q1 = q0 + per < nq ? q0 + per : nq;
+  int sum = 0;
+  for (int64_t q = q0; q < q1; ++q) sum += qoff[q];
+  int all;
+  int run = block_exclusive_scan(sum, tmp, all);
+  for (int64_t q = q0; q < q1; ++q) {
+    const int v = qoff[q];
+    qoff[q] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) qoff[nq] = all;
+}
+
+__global__ __launch_bounds__(256) void pair_lists_kernel(const int32_t* __restrict__ probes, int64_t nq, int P,
+                                                         int G, const int32_t* __restrict__ nsplit,
+                                                         const int32_t* __restrict__ qoff,
+                                                         int32_t* __restrict__ lbase) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int run = qoff[q];
+  for (int sl = 0; sl < P; ++sl) {
+    const int g = probes[q * P + sl];
+    lbase[q * P + sl] = run;
+    run += (g >= 0 && g < G) ? nsplit[g] : 0;
+  }
 }
 
 __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
@@ -301,9 +319,76 @@ void launch_fill_multi(const FillList& L, hipStream_t s) {
   HIP_TRY(hipGetLastError());
 }
 
+namespace {
+// Largest rank with ioff[rank] <= item (ioff[G] > item).
+__device__ __forceinline__ int item_rank(const int32_t* __restrict__ ioff, int G, int item) {
+  int lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ioff[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void item_table_kernel(ItemLists lists, const int32_t* __restrict__ gorder, int G,
+                                                         int qt, int64_t max_items, ItemDesc* __restrict__ out) {
+  const int64_t it64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it64 >= max_items) return;
+  const int it = (int)it64;
+  const int nP = lists.ioff[LIST_ALL][G], n0 = lists.ioff[LIST_SLOT0][G], n1 = lists.ioff[LIST_REST][G];
+  if (it >= nP + n0 + n1) return;
+  ItemDesc d{};
+  if (it < nP) {
+    const int rank = item_rank(lists.ioff[LIST_ALL], G, it);
+    const int g = gorder ? gorder[rank] : rank;
+    const int first = (it - lists.ioff[LIST_ALL][rank]) * 16;
+    d.g = g;
+    d.off = lists.lstart[LIST_ALL][g] + first;
+    d.cnt = min(16, lists.lcount[LIST_ALL][g] - first);
+    d.c0 = d.c1 = it;
+  } else {
+    const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
+    const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
+    const int rank = item_rank(lists.ioff[L], G, li);
+    const int g = gorder ? gorder[rank] : rank;
+    const int lc = lists.lcount[L][g];
+    const int ntiles = (lc + qt - 1) / qt;
+    const int k = li - lists.ioff[L][rank];
+    const int tile = k % ntiles;  // range-major: a range's tiles run together
+    const int first = tile * qt;
+    d.g = g;
+    d.range = k / ntiles;
+    d.off = lists.lstart[L][g] + first;
+    d.cnt = min(qt, lc - first);
+    // a grain's projection list is its slot-0 pairs followed by the others, in
+    // 16-pair items: this tile's pairs lie in items c0 .. c1 (at most two)
+    const int base = (L == LIST_SLOT0 ? 0 : lists.lcount[LIST_SLOT0][g]) + first;
+    const int pi0 = lists.ioff[LIST_ALL][rank];
+    d.c0 = pi0 + base / 16;
+    d.c1 = pi0 + (base + d.cnt - 1) / 16;
+  }
+  out[it] = d;
+}
+}  // namespace
+
+void launch_item_table(const ItemLists& lists, const int32_t* gorder, int G, int qt, int64_t max_items,
+                       ItemDesc* out, hipStream_t s) {
+  if (max_items <= 0) return;
+  hipLaunchKernelGGL(item_table_kernel, dim3((unsigned)((max_items + 255) / 256)), dim3(256), 0, s, lists, gorder, G,
+                     qt, max_items, out);
+  HIP_TRY(hipGetLastError());
+}
+
 void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
                        int32_t* qoff, hipStream_t s) {
-  hipLaunchKernelGGL(pair_lists_kernel, dim3(1), dim3(1024), 0, s, probes, nq, P, G, nsplit, lbase, qoff);
+  if (nq <= 0) return;
+  const dim3 grid((unsigned)((nq + 255) / 256));
+  hipLaunchKernelGGL(query_lists_kernel, grid, dim3(256), 0, s, probes, nq, P, G, nsplit, qoff);
+  hipLaunchKernelGGL(query_scan_kernel, dim3(1), dim3(1024), 0, s, nq, qoff);
+  hipLaunchKernelGGL(pair_lists_kernel, grid, dim3(256), 0, s, probes, nq, P, G, nsplit, qoff, lbase);
   HIP_TRY(hipGetLastError());
 }
 

@@ -62,18 +62,6 @@ constexpr uint32_t NO_BOUND = 0xFFFFFFFFu;
 constexpr int NCTR = 8;          // scan-item ticket counters (classes of workgroups)
 constexpr int CTR_STRIDE = 64;   // ints between counters (256 bytes)
 
-__device__ __forceinline__ int find_rank(const int32_t* __restrict__ ioff, int G, int item) {
-  int lo = 0, hi = G;  // largest rank with ioff[rank] <= item (ioff[G] > item)
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (ldg(ioff + mid) <= item)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // A bound on the distance part only: the list keys carry grain positions,
 // which do not order like the original ids across grains, so every candidate
 // at the bound's distance is kept and the merge settles exact ties.
@@ -89,7 +77,7 @@ constexpr size_t wave_lds_bytes() {
 // One wave's part of a scan item: its cnt (<= QT) pairs of grain g against
 // block range `range` of the grain (no workgroup barrier inside).
 template <int RP, int CAP, int QT, int CT>
-__device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int L, int g, int range,
+__device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int g, int range,
                                           const int32_t* __restrict__ pairs, int cnt) {
   using List = typename ListOf<CAP>::type;
   constexpr int LK = ListOf<CAP>::lds;
@@ -105,11 +93,24 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   const int rb0 = a.R ? range * a.R : 0;
   const int rb1 = a.R ? min(nb, rb0 + a.R) : nb;
 
+  // lane t < cnt holds pair t, its query's current bound, its eps_q and its
+  // list base: one round of loads for all pairs of the tile
+  int pv = 0;
+  if (lane < cnt) pv = ldg(pairs + lane);
+  uint32_t obv = NO_BOUND;
+  float eqv = 0.f;
+  int lbv = pv;
+  if (lane < cnt) {
+    obv = __hip_atomic_load(gptr(a.qbound + pv / P), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    eqv = ldg(a.epsq + pv);
+    if (a.lbase) lbv = ldg(a.lbase + pv);
+  }
   for (int idx = lane; idx < QT * RP; idx += HNTL_WAVE) {
     const int t = idx / RP, j = idx % RP;
-    zq[t][j] = (t < cnt && j < r) ? ldg(a.T + (size_t)ldg(pairs + t) * r + j) : 0.f;
+    const int pt = __shfl(pv, t, 64);
+    zq[t][j] = (t < cnt && j < r) ? ldg(a.T + (size_t)pt * r + j) : 0.f;
   }
-  if (lane < QT) eq[lane] = lane < cnt ? ldg(a.epsq + ldg(pairs + lane)) : 0.f;
+  if (lane < QT) eq[lane] = eqv;
   wave_sync();
 
   const float sg = CT == 2 ? ldg(a.scales + g) : 1.f;
@@ -129,9 +130,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     live[t] = t < cnt;
     uint64_t bnd = KEY_NONE;
     if (live[t]) {
-      const int p = ldg(pairs + t);
-      const uint32_t ob = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(gptr(a.qbound + p / P), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      const uint32_t ob = (uint32_t)__builtin_amdgcn_readlane((int)obv, t);
       bnd = bound_key(ob);
       if (a.prune && ob != NO_BOUND) {
         const float v = lane < r ? zq[t][lane] : 0.f;
@@ -139,7 +138,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
         const float lb = wave_sum(dd * dd) + eq[t] + ldg(a.emin + g);
         if (__builtin_amdgcn_readfirstlane(lb * (1.f - PRUNE_SLACK) > ord2f(ob) ? 1 : 0)) {
           live[t] = false;
-          const int64_t slot = (a.lbase ? (int64_t)ldg(a.lbase + p) : (int64_t)p) + range;
+          const int64_t slot = (int64_t)__builtin_amdgcn_readlane(lbv, t) + range;
           if (lane == 0) stg(a.part + (size_t)slot * C, KEY_NONE);  // empty list
         }
       }
@@ -162,7 +161,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       if (live[t]) {
-        const int q = ldg(pairs + t) / P;
+        const int q = __builtin_amdgcn_readlane(pv, t) / P;
         const uint64_t own = Ls[t].cth();
         if (own != KEY_NONE && lane == 0)
           __hip_atomic_fetch_min(gptr(a.qbound + q), (uint32_t)(own >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -226,11 +225,11 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   for (int t = 0; t < QT; ++t) {
     if (live[t]) {
       Ls[t].finish();
-      const int p = ldg(pairs + t);
+      const int p = __builtin_amdgcn_readlane(pv, t);
       const uint64_t own = Ls[t].cth();
       if (own != KEY_NONE && lane == 0)
         __hip_atomic_fetch_min(gptr(a.qbound + p / P), (uint32_t)(own >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int64_t slot = (a.lbase ? (int64_t)ldg(a.lbase + p) : (int64_t)p) + range;
+      const int64_t slot = (int64_t)__builtin_amdgcn_readlane(lbv, t) + range;
       uint64_t* out = a.part + (size_t)slot * C;
 #pragma unroll
       for (int rr = 0; rr < CAP / 64; ++rr) {
@@ -256,6 +255,8 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const int n0 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_SLOT0] + G));
   const int n1 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_REST] + G));
   const int total = nP + n0 + n1;
+  using ivec4 = int __attribute__((ext_vector_type(4)));
+  const ivec4* desc = reinterpret_cast<const ivec4*>(a.items);  // two per item
 
   // Each wave is its own worker: it takes tickets until they run out, and
   // nothing in the loop synchronises waves.  All 64 lanes add 1 to a counter,
@@ -265,7 +266,8 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   // that find it exhausted cost no atomic); scan items are interleaved over
   // NCTR counters, one per class of workgroups, so tickets are not all taken
   // from one address.  A wave reaches the scan items only after every
-  // projection ticket has been handed out.
+  // projection ticket has been handed out.  Items are decoded once per run
+  // into descriptors (one 32-byte record each).
   using gptr = int32_t __attribute__((address_space(1)))*;
   if (a.phase != 2 && !a.proj_ext) {
     const gptr pctr = (gptr)a.ticket;
@@ -277,11 +279,10 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
           __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(pctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
           6;
       if (it >= nP) break;
-      const int rank = find_rank(a.ioff[LIST_ALL], G, it);
-      const int g = __builtin_amdgcn_readfirstlane(ldg(a.gorder + rank));
-      const int first = (it - ldg(a.ioff[LIST_ALL] + rank)) * 16;
-      const int cnt = __builtin_amdgcn_readfirstlane(min(16, ldg(a.lcount[LIST_ALL] + g) - first));
-      const int32_t* pairs = a.order + ldg(a.lstart[LIST_ALL] + g) + first;
+      const ivec4 d = ldg(desc + 2 * (size_t)it);
+      const int g = __builtin_amdgcn_readfirstlane(d[0]);
+      const int cnt = __builtin_amdgcn_readfirstlane(d[3]);
+      const int32_t* pairs = a.order + __builtin_amdgcn_readfirstlane(d[2]);
       if (a.proj_bf16)
         project_wave_bf16<NCT>(a.Q, a.d, a.P, a.centroids, a.basis16, a.r, g, pairs, cnt, a.T, a.epsq);
       else
@@ -294,45 +295,36 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   const gptr sctr = (gptr)(a.ticket + CTR_STRIDE * (1 + kc));
   const int slo = a.phase == 2 ? nP + n0 : nP;     // scan items of this launch
   const int shi = a.phase == 1 ? nP + n0 : total;
+  // the next ticket is taken while the current item runs, so its atomic
+  // round trip is hidden
+  int tv = __hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    const int t =
-        __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
-        6;
-    const int it = slo + t * NCTR + kc;
+    const int it = slo + (__builtin_amdgcn_readfirstlane(tv) >> 6) * NCTR + kc;
     if (it >= shi) break;
-    {  // ----------------------------------------------------------- scan
-      const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
-      const int li = it - (L == LIST_SLOT0 ? nP : nP + n0);
-      const int rank = find_rank(a.ioff[L], G, li);
-      const int g = __builtin_amdgcn_readfirstlane(ldg(a.gorder + rank));
-      const int lc = __builtin_amdgcn_readfirstlane(ldg(a.lcount[L] + g));
-      const int ntiles = (lc + QT - 1) / QT;
-      const int k = li - __builtin_amdgcn_readfirstlane(ldg(a.ioff[L] + rank));
-      const int range = k / ntiles, tile = k % ntiles;  // range-major: a range's tiles run together
-      const int first = tile * QT;
-      const int cnt = min(QT, lc - first);
-      // wait (acquire) for the projection items that hold this tile's pairs:
-      // a grain's projection list is its slot-0 pairs followed by the others,
-      // in 16-pair items, so the tile spans items c0 .. c1 (at most two)
-      if (!a.proj_ext) {
-        const int base = (L == LIST_SLOT0 ? 0 : __builtin_amdgcn_readfirstlane(ldg(a.lcount[LIST_SLOT0] + g))) + first;
-        const int pi0 = __builtin_amdgcn_readfirstlane(ldg(a.ioff[LIST_ALL] + rank));
-        for (int c = pi0 + base / 16; c <= pi0 + (base + cnt - 1) / 16; ++c) {
-          for (long long spin = 0;; ++spin) {
-            const int done = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(gptr(a.proj_done + c), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-            if (done != 0) break;
-            if (spin > SPIN_LIMIT) {
-              __hip_atomic_fetch_or(gptr(a.err), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+    const ivec4 d = ldg(desc + 2 * (size_t)it);
+    tv = __hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int g = __builtin_amdgcn_readfirstlane(d[0]);
+    const int range = __builtin_amdgcn_readfirstlane(d[1]);
+    const int32_t* pairs = a.order + __builtin_amdgcn_readfirstlane(d[2]);
+    const int cnt = __builtin_amdgcn_readfirstlane(d[3]);
+    if (!a.proj_ext) {
+      // wait (acquire) for the projection items that hold this tile's pairs
+      const ivec4 e = ldg(desc + 2 * (size_t)it + 1);
+      const int c0 = __builtin_amdgcn_readfirstlane(e[0]), c1 = __builtin_amdgcn_readfirstlane(e[1]);
+      for (int c = c0; c <= c1; ++c) {
+        for (long long spin = 0;; ++spin) {
+          const int done = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(gptr(a.proj_done + c), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+          if (done != 0) break;
+          if (spin > SPIN_LIMIT) {
+            __hip_atomic_fetch_or(gptr(a.err), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
           }
+          __builtin_amdgcn_s_sleep(2);
         }
       }
-      const int32_t* pairs = a.order + ldg(a.lstart[L] + g) + first;
-      scan_tile<RP, CAP, QT, CT>(a, my, L, g, range, pairs, cnt);
     }
+    scan_tile<RP, CAP, QT, CT>(a, my, g, range, pairs, cnt);
   }
 }
 

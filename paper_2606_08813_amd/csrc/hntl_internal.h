@@ -191,6 +191,18 @@ struct FillList {
   int n;
 };
 void launch_fill_multi(const FillList& L, hipStream_t s);
+// One work item of the fused kernel, decoded once per run: a projection item
+// (16 pairs of grain g from order[off]) or a scan item (cnt pairs of grain g
+// from order[off] against block range `range`; its pairs' tangents come from
+// projection items c0 .. c1).
+struct ItemDesc {
+  int32_t g, range, off, cnt, c0, c1, pad0, pad1;
+};
+// Items 0 .. nP-1 are the projection items (LIST_ALL, 16 pairs), then the
+// scan items of LIST_SLOT0 and LIST_REST (qt pairs x block ranges), in the
+// lists' item order; threads past the device item count write nothing.
+void launch_item_table(const ItemLists& lists, const int32_t* gorder, int G, int qt, int64_t max_items,
+                       ItemDesc* out, hipStream_t s);
 void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const int32_t* nsplit, int32_t* lbase,
                        int32_t* qoff, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -255,6 +267,7 @@ struct FusedArgs {
   unsigned long long* scored;
   int proj_bf16;
   int proj_ext;  // 1: tangents come from a separate projection launch (no projection items, no waits)
+  const ItemDesc* items;  // decoded work items, in ticket order
   int prune;
 };
 

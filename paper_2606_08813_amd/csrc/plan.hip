@@ -152,6 +152,8 @@ struct Plan {
   int32_t* ticket = nullptr;
   int32_t* proj_done = nullptr;  // one flag per projection item
   int64_t proj_items = 0;
+  ItemDesc* items = nullptr;  // decoded work items of the fused kernel
+  int64_t max_items = 0;
   uint32_t* qbound = nullptr;
   int32_t* err = nullptr;
   float* T = nullptr;
@@ -217,6 +219,8 @@ struct Plan {
     ticket = L.take<int32_t>(2 * TICKET_INTS);  // counters of each launch (phases 0/1 and 2)
     proj_items = (int64_t)((np + 15) / 16) + x.G;  // at most sum over grains of ceil(pairs / 16)
     proj_done = L.take<int32_t>(proj_items);
+    max_items = proj_items + (int64_t)list_slots;  // projection items + at most one scan item per list
+    items = L.take<ItemDesc>((size_t)max_items);
     qbound = L.take<uint32_t>(max_nq);
     err = L.take<int32_t>(1);
     T = L.take<float>((size_t)np * x.r);
@@ -277,6 +281,7 @@ struct Plan {
     a.scored = scored;
     a.proj_bf16 = (sp.flags & HNTL_FLAG_PROJECT_BF16) ? 1 : 0;
     a.proj_ext = sch.proj ? 1 : 0;
+    a.items = items;
     a.prune = (sp.flags & HNTL_FLAG_NO_PRUNE) ? 0 : 1;
     return a;
   }
@@ -310,6 +315,7 @@ struct Plan {
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
+    launch_item_table(b.lists, x.gorder, G, (int)sch.qt, max_items, items, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (sch.proj) launch_project(x, Q, P, b, T, epsq, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0, x.gorder, s);
     for (int ph = sch.passes == 2 ? 1 : 0; ph <= (sch.passes == 2 ? 2 : 0); ++ph) {
