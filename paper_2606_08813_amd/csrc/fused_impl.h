@@ -61,6 +61,7 @@ constexpr long long SPIN_LIMIT = 1ll << 26;  // wait polls before giving up
 constexpr uint32_t NO_BOUND = 0xFFFFFFFFu;
 constexpr int NCTR = 8;          // scan-item ticket counters (classes of workgroups)
 constexpr int CTR_STRIDE = 64;   // ints between counters (256 bytes)
+constexpr int RUN = 16;          // consecutive scan items per class and turn
 
 // A bound on the distance part only: the list keys carry grain positions,
 // which do not order like the original ids across grains, so every candidate
@@ -266,8 +267,11 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   // that find it exhausted cost no atomic); scan items are interleaved over
   // NCTR counters, one per class of workgroups, so tickets are not all taken
   // from one address.  A wave reaches the scan items only after every
-  // projection ticket has been handed out.  Items are decoded once per run
-  // into descriptors (one 32-byte record each).
+  // projection ticket has been handed out.  A class takes runs of RUN
+  // consecutive scan items (the tiles of one grain and block range are
+  // consecutive), and class kc = blockIdx.x % 8 is also the XCD the workgroup
+  // runs on, so the tiles that re-read a grain's blocks share one L2.  Items
+  // are decoded once per run into descriptors (one 32-byte record each).
   using gptr = int32_t __attribute__((address_space(1)))*;
   if (a.phase != 2 && !a.proj_ext) {
     const gptr pctr = (gptr)a.ticket;
@@ -299,7 +303,8 @@ __global__ __launch_bounds__(512) void fused_kernel(const FusedArgs* __restrict_
   // round trip is hidden
   int tv = __hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    const int it = slo + (__builtin_amdgcn_readfirstlane(tv) >> 6) * NCTR + kc;
+    const int tk = __builtin_amdgcn_readfirstlane(tv) >> 6;
+    const int it = slo + (tk / RUN) * (NCTR * RUN) + kc * RUN + tk % RUN;
     if (it >= shi) break;
     const ivec4 d = ldg(desc + 2 * (size_t)it);
     tv = __hip_atomic_fetch_add(sctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
