@@ -94,6 +94,8 @@ def parse():
                     help="learned: train the router first (router-train queries, brute-force kNN targets)")
     ap.add_argument("--P", type=int, default=0, help="probes per query (0 = the workload's)")
     ap.add_argument("--tau", type=float, default=0.0, help="learned routing: centroid fallback below this max prob")
+    ap.add_argument("--route-split", choices=("auto", "on", "off"), default="auto",
+                    help="centroid routing shortlist on split-BF16 MFMA (auto: with --codes bf16/fp8)")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
     ap.add_argument("--router-epochs", type=int, default=8)
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -165,6 +167,10 @@ def main():
     bf16_project = args.codes != "fp32" and not args.fp32_project
     if bf16_project:
         flags |= hntl.HNTL_FLAG_PROJECT_BF16
+    route_split = args.route == "centroid" and (args.route_split == "on" or
+                                                (args.route_split == "auto" and args.codes != "fp32"))
+    if route_split:
+        flags |= hntl.HNTL_FLAG_ROUTE_BF16X3
     rkw = dict(route=args.route, tau=args.tau)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -188,7 +194,7 @@ def main():
         stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
         scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
     else:
-        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE)
+        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3)
         t0 = time.time()
         if args.sched:
             sched = {k: int(v) for k, v in (kv.split("=") for kv in args.sched.split(","))}
@@ -219,7 +225,8 @@ def main():
 
     # work accounting from one staged run (probes -> vectors scanned per step)
     o = hntl.hntl_search_stages(ix, Q, P, W.C, W.k, codes=args.codes,
-                                flags=hntl.HNTL_FLAG_SYNC | (flags & hntl.HNTL_FLAG_PROJECT_BF16), **rkw)
+                                flags=hntl.HNTL_FLAG_SYNC | (flags & (hntl.HNTL_FLAG_PROJECT_BF16 |
+                                                                     hntl.HNTL_FLAG_ROUTE_BF16X3)), **rkw)
     probes = o["probes"].cpu().numpy()
     ex = hntl.hntl_index_export(ix)
     sizes = np.diff(ex["offsets"])
@@ -329,6 +336,7 @@ def main():
         "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
                    "P": P, "C": W.C, "k": W.k, "codes": args.codes,
                    "projection": "bf16" if bf16_project else "fp32", "form": args.form, "route": args.route,
+                   "route_shortlist": "split-bf16" if route_split else ("fp32" if args.route == "centroid" else None),
                    "schedule": sched},
         "recall_at_10": round(recall, 4),
         "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),

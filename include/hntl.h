@@ -76,6 +76,10 @@ typedef enum hntl_codes {
 #define HNTL_FLAG_PROJECT_BF16 16u /* projection on BF16 MFMA: q - mu_g (FP32) and W_g rounded to BF16 (nearest
                                       even), FP32 accumulation; eps_q stays FP32.  Needs an index with a
                                       reduced-precision code form (the BF16 bases are built with it) and d % 8 == 0 */
+#define HNTL_FLAG_ROUTE_BF16X3 32u /* centroid routing's shortlist from BF16 MFMA with each operand split into a
+                                      BF16 high and low part (q_hi c_hi + q_hi c_lo + q_lo c_hi, FP32 accumulation,
+                                      about 2^-16 relative); the P probes are still chosen on FP32 direct
+                                      differences of the shortlist.  Needs d % 8 == 0 */
 /*
  * Exact pruning.  By default the nearest probed grain of each query is scanned
  * first; its C-th best (D, id) key then bounds the other probed grains: their

@@ -424,10 +424,19 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
         const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
         float* qn = learned ? nullptr : sc.get<float>(nq);
         float* Dm = learned ? nullptr : sc.get<float>((size_t)std::min<int64_t>(chunk, nq) * ix.G);
+        const bool split = !learned && (sp->flags & HNTL_FLAG_ROUTE_BF16X3);
+        uint16_t* As = nullptr;
+        if (split) {
+          ensure_centroid_split(const_cast<Index&>(ix), s);  // derived data, made once under a lock
+          As = sc.get<uint16_t>((size_t)std::min<int64_t>(chunk, nq) * 3 * ix.d);
+        }
         if (!learned) launch_row_norms(Q, nq, (int)ix.d, qn, s);
         for (int64_t q0 = 0; q0 < nq && !learned; q0 += chunk) {
           const int64_t rows = std::min<int64_t>(chunk, nq - q0);
-          launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
+          if (split)
+            launch_dist_bf16x3(ix, Q + q0 * ix.d, qn + q0, rows, As, Dm, s);
+          else
+            launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
           launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,
                            Q + q0 * ix.d, qn + q0, ix.centroids, ix.cnorm, (int)ix.d);
         }

@@ -77,6 +77,7 @@ struct Index {
   float* bhi = nullptr;        // G x rp: per-grain maximum
   float* emin = nullptr;       // G: per-grain minimum eps_i
   int32_t* gorder = nullptr;   // G: grains by size, largest first (made by the first search plan)
+  uint16_t* cent_split = nullptr;  // G x 3d bf16: [hi | lo | hi] of the centroids (split-BF16 routing, on first use)
   std::unique_ptr<Router> router;  // learned router (trained or imported), else null
 
   std::vector<int64_t> offsets_h;
@@ -143,6 +144,12 @@ struct Scratch {
 void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream_t s);
 // With nlim (device), rows from *nlim - row_base on are skipped (batches whose
 // size lives in device memory).
+// Split-BF16 routing distances: D (rows x G) = max(an + ||mu||^2 - 2 <a, mu>, 0) with
+// <a, mu> from BF16 MFMA over [a_hi | a_hi | a_lo] . [mu_hi | mu_lo | mu_hi]; As is
+// scratch of rows x 3d bf16.  ensure_centroid_split makes the index's centroid split once.
+void ensure_centroid_split(Index& ix, hipStream_t s);
+void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
+                        hipStream_t s, const int32_t* nlim = nullptr, int64_t row_base = 0);
 void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
                         int cols, int d, float* D, hipStream_t s, const int32_t* nlim = nullptr,
                         int64_t row_base = 0);

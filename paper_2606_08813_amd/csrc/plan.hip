@@ -72,6 +72,8 @@ constexpr size_t LDS_LIMIT = 64 * 1024;
 // one projection counter and 8 scan counters per launch, 256 bytes apart
 constexpr int TICKET_INTS = 9 * 64;
 constexpr int MIN_GRID = 8;  // every class of scan counters needs a workgroup
+// search flags a plan honours (beyond HNTL_FLAG_SYNC)
+constexpr uint32_t PLAN_FLAGS = HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3;
 constexpr uint64_t MAX_LIST_BYTES = 4ull << 30;  // candidate-list storage of one plan
 
 // Bump allocation over one block (base == nullptr: sizing pass).
@@ -115,7 +117,7 @@ std::string tune_key(const Index& ix, const hntl_search_params& sp, uint32_t nq)
   std::ostringstream k;
   k << device_key(ix.device) << " N=" << ix.N << " d=" << ix.d << " G=" << ix.G << " r=" << ix.r
     << " maxgrain=" << ix.max_grain << " P=" << sp.P << " C=" << sp.C << " k=" << sp.k << " codes=" << sp.codes
-    << " flags=" << (sp.flags & (HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE)) << " route=" << sp.route
+    << " flags=" << (sp.flags & PLAN_FLAGS) << " route=" << sp.route
     << " nq=" << nq;
   return k.str();
 }
@@ -153,6 +155,7 @@ struct Plan {
   int32_t* proj_done = nullptr;  // one flag per projection item
   int64_t proj_items = 0;
   ItemDesc* items = nullptr;  // decoded work items of the fused kernel
+  uint16_t* Asplit = nullptr;  // split-BF16 query rows of one routing chunk
   int64_t max_items = 0;
   uint32_t* qbound = nullptr;
   int32_t* err = nullptr;
@@ -195,6 +198,7 @@ struct Plan {
     qn = L.take<float>(max_nq);
     chunk = std::min<int64_t>(max_nq, std::max<int64_t>(64, ((int64_t)1 << 28) / x.G));
     Dm = L.take<float>((size_t)chunk * x.G);
+    if (sp.flags & HNTL_FLAG_ROUTE_BF16X3) Asplit = L.take<uint16_t>((size_t)chunk * 3 * x.d);
     b.G = (int)x.G;
     b.gcount = L.take<int32_t>(x.G);
     b.gcount0 = L.take<int32_t>(x.G);
@@ -308,7 +312,10 @@ struct Plan {
       launch_row_norms(Q, max_nq, d, qn, s);
     for (int64_t q0 = 0; q0 < (int64_t)max_nq && sp.route != HNTL_ROUTE_LEARNED; q0 += chunk) {
       const int64_t rows = std::min<int64_t>(chunk, (int64_t)max_nq - q0);
-      launch_dist_matrix(Q + q0 * d, qn + q0, rows, x.centroids, x.cnorm, G, d, Dm, s, nq_dev, q0);
+      if (sp.flags & HNTL_FLAG_ROUTE_BF16X3)
+        launch_dist_bf16x3(x, Q + q0 * d, qn + q0, rows, Asplit, Dm, s, nq_dev, q0);
+      else
+        launch_dist_matrix(Q + q0 * d, qn + q0, rows, x.centroids, x.cnorm, G, d, Dm, s, nq_dev, q0);
       launch_topk_rows(Dm, rows, G, P, probes + q0 * P, nullptr, s, Q + q0 * d, qn + q0, x.centroids, x.cnorm, d,
                        nq_dev, q0);
     }
@@ -397,6 +404,7 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   if (lds_per_wave((int)ix.rp, (int)sp.C, (int)sch.qt) * sch.nw > LDS_LIMIT)
     throw ArgError{HNTL_EUNSUPPORTED, "schedule needs more than 64 KiB of LDS per workgroup"};
   ensure_grain_order(ix);
+  if ((sp.flags & HNTL_FLAG_ROUTE_BF16X3) && sp.route != HNTL_ROUTE_LEARNED) ensure_centroid_split(ix, s);
   std::unique_ptr<Plan> pl(new Plan());
   pl->ix = &ix;
   pl->sp = sp;
@@ -639,7 +647,7 @@ hntl_status hntl_tune(hntl_index* index, const hntl_search_params* sp, const flo
     hipStream_t s = (hipStream_t)stream;
     check_plan_shape(ix, *sp);
     hntl_search_params spp = *sp;
-    spp.flags &= (HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE);
+    spp.flags &= PLAN_FLAGS;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -720,7 +728,7 @@ hntl_status hntl_schedule_lookup(const hntl_index* index, const hntl_search_para
   if (!index || !sp || !db_path || !out) return fail(HNTL_EINVAL, "null pointer");
   return guarded_call([&] {
     hntl_search_params spp = *sp;
-    spp.flags &= (HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE);
+    spp.flags &= PLAN_FLAGS;
     const std::string key = tune_key(index->ix, spp, max_nq);
     std::ifstream in(db_path);
     std::string line;

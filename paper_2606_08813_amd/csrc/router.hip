@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -55,7 +56,7 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // ------------------------------------------------------------------ GEMM
 constexpr int GM = 128, GN = 128, GK = 64, GLD = GK + 8;  // LDS rows padded by 8 bf16
 
-enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2, EPI_BIAS_F32 = 3 };
+enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2, EPI_BIAS_F32 = 3, EPI_DIST = 4 };
 struct Epi {
   float* C;            // FP32 output (EPI_F32, EPI_BIAS_F32: the result; EPI_BIAS_GELU: pre-activation, optional)
   int ldc;
@@ -67,7 +68,30 @@ struct Epi {
   float* D;            // EPI_GELU_GRAD: FP32 acc * gelu'(z)
   int ldd;
   float scale;         // EPI_BIAS_F32: result = scale * (acc + bias)
+  const float* an;     // EPI_DIST: C = max(an[row] + bn[col] - 2 acc, 0)
+  const float* bn;
+  int64_t row_base;    // rows from *mlim - row_base on are skipped
 };
+
+// Epilogue of one output element (row < M, col < N checked by the caller).
+template <int EPI>
+__device__ __forceinline__ void epi_store(const Epi& e, int row, int col, float v) {
+  if constexpr (EPI == EPI_F32) {
+    e.C[(size_t)row * e.ldc + col] = v;
+  } else if constexpr (EPI == EPI_BIAS_F32) {
+    e.C[(size_t)row * e.ldc + col] = e.scale * (v + e.bias[col]);
+  } else if constexpr (EPI == EPI_BIAS_GELU) {
+    const float z = v + e.bias[col];
+    if (e.C) e.C[(size_t)row * e.ldc + col] = z;
+    e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
+  } else if constexpr (EPI == EPI_DIST) {
+    e.C[(size_t)row * e.ldc + col] = fmaxf(e.an[row] + e.bn[col] - 2.f * v, 0.f);
+  } else {
+    const float gz = v * gelu_grad(e.Z[(size_t)row * e.ldz + col]);
+    e.D[(size_t)row * e.ldd + col] = gz;
+    e.H[(size_t)row * e.ldh + col] = to_bf16(gz);
+  }
+}
 
 // One thread's share of a 128 x 64 tile of X(r, k) (rows r0.., depths k0..):
 // 32 bf16 in four 16-byte words.  XT = false: X(r, k) = X[r * ld + k], the
@@ -145,7 +169,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int m0 = blockIdx.y * GM, n0 = blockIdx.x * GN;
   if (mlim) {
-    const int lim = *mlim;
+    const int lim = (int)(*mlim - e.row_base);
     if (m0 >= lim) return;
     if (lim < M) M = lim;
   }
@@ -192,39 +216,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
         const int row = m0 + wm + 16 * a + 4 * kq + j;
         const int col = n0 + wn + 16 * b + i;
         if (row >= M || col >= N) continue;
-        const float v = acc[a][b][j];
-        if constexpr (EPI == EPI_F32) {
-          e.C[(size_t)row * e.ldc + col] = v;
-        } else if constexpr (EPI == EPI_BIAS_F32) {
-          e.C[(size_t)row * e.ldc + col] = e.scale * (v + e.bias[col]);
-        } else if constexpr (EPI == EPI_BIAS_GELU) {
-          const float z = v + e.bias[col];
-          if (e.C) e.C[(size_t)row * e.ldc + col] = z;
-          e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
-        } else {
-          const float gz = v * gelu_grad(e.Z[(size_t)row * e.ldz + col]);
-          e.D[(size_t)row * e.ldd + col] = gz;
-          e.H[(size_t)row * e.ldh + col] = to_bf16(gz);
-        }
+        epi_store<EPI>(e, row, col, acc[a][b][j]);
       }
-}
-
-// Epilogue of one output element (row < M, col < N checked by the caller).
-template <int EPI>
-__device__ __forceinline__ void epi_store(const Epi& e, int row, int col, float v) {
-  if constexpr (EPI == EPI_F32) {
-    e.C[(size_t)row * e.ldc + col] = v;
-  } else if constexpr (EPI == EPI_BIAS_F32) {
-    e.C[(size_t)row * e.ldc + col] = e.scale * (v + e.bias[col]);
-  } else if constexpr (EPI == EPI_BIAS_GELU) {
-    const float z = v + e.bias[col];
-    if (e.C) e.C[(size_t)row * e.ldc + col] = z;
-    e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
-  } else {
-    const float gz = v * gelu_grad(e.Z[(size_t)row * e.ldz + col]);
-    e.D[(size_t)row * e.ldd + col] = gz;
-    e.H[(size_t)row * e.ldh + col] = to_bf16(gz);
-  }
 }
 
 // ---------------------------------------------- large-tile GEMM, both k-contiguous
@@ -284,7 +277,7 @@ __global__ __launch_bounds__(512) void gemm_nn_kernel(const uint16_t* __restrict
   if (tile >= ntiles) return;
   const int m0 = (tile / tiles_n) * NM, n0 = (tile % tiles_n) * NN;
   if (mlim) {
-    const int lim = *mlim;
+    const int lim = (int)(*mlim - e.row_base);
     if (m0 >= lim) return;
     if (lim < M) M = lim;
   }
@@ -599,6 +592,60 @@ void Router::refresh_bf16(hipStream_t s) {
 // Learned routing of nq rows of Q: probes (nq x P) by descending score (ties:
 // lower grain), pdist = the negated scores; rows whose largest softmax
 // probability is below tau use centroid routing instead.
+namespace {
+// FP32 rows split into BF16 high and low parts (nearest even): an output row is
+// [hi | hi | lo] (queries) or [hi | lo | hi] (centroids, corder), so that one
+// product over 3d depths gives q_hi c_hi + q_hi c_lo + q_lo c_hi.
+__global__ void split3_kernel(const float* __restrict__ X, int64_t rows, int d, int corder,
+                              uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * d) return;
+  const int64_t r = i / d;
+  const int k = (int)(i - r * d);
+  const float x = X[i];
+  const uint16_t h = to_bf16(x);
+  const uint16_t l = to_bf16(x - __uint_as_float((uint32_t)h << 16));
+  uint16_t* o = out + r * 3 * d;
+  o[k] = h;
+  o[d + k] = corder ? l : h;
+  o[2 * d + k] = corder ? h : l;
+}
+std::mutex g_split_mu;
+}  // namespace
+
+void ensure_centroid_split(Index& ix, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  if (ix.cent_split) return;
+  if (ix.d % 8 != 0) throw ArgError{HNTL_EUNSUPPORTED, "split-BF16 routing needs d % 8 == 0"};
+  uint16_t* p = dev_alloc<uint16_t>(&ix, (size_t)ix.G * 3 * ix.d);
+  const int64_t n = (int64_t)ix.G * ix.d;
+  hipLaunchKernelGGL(split3_kernel, dim3(blocks(n)), dim3(256), 0, s, ix.centroids, (int64_t)ix.G, (int)ix.d, 1, p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  ix.cent_split = p;
+}
+
+void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
+                        hipStream_t s, const int32_t* nlim, int64_t row_base) {
+  if (rows <= 0) return;
+  if (rows <= 16) {  // a few rows: exact FP32 direct differences, one pass over the centroids
+    launch_dist_matrix(A, an, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, D, s, nlim, row_base);
+    return;
+  }
+  if (!ix.cent_split) throw ArgError{HNTL_ESTATE, "split-BF16 routing: centroid split not built"};
+  const int64_t n = rows * ix.d;
+  hipLaunchKernelGGL(split3_kernel, dim3(blocks(n)), dim3(256), 0, s, A, rows, (int)ix.d, 0, As);
+  HIP_TRY(hipGetLastError());
+  Epi e{};
+  e.C = D;
+  e.ldc = (int)ix.G;
+  e.an = an;
+  e.bn = ix.cnorm;
+  e.row_base = row_base;
+  const int K3 = 3 * (int)ix.d;
+  gemm<false, false, EPI_DIST>(As, K3, ix.cent_split, K3, (int)rows, (int)ix.G, K3, e, s, nlim);
+}
+
 void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
                           float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim) {
   const Router& rt = *ix.router;

@@ -20,6 +20,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
+HNTL_FLAG_ROUTE_BF16X3 = 32
 HNTL_ROUTE_CENTROID, HNTL_ROUTE_LEARNED = 0, 1
 HNTL_ROUTER_KEEP_WEIGHTS, HNTL_ROUTER_NO_SHUFFLE = 1, 2
 ROUTES = {"centroid": HNTL_ROUTE_CENTROID, "learned": HNTL_ROUTE_LEARNED}

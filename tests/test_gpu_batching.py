@@ -199,3 +199,20 @@ def test_plan_unequal_grains(bt):
             plan = hntl.hntl_plan_create(ix, W.P, W.C, W.k, 1000, codes=codes, flags=fl, sched=sched)
             assert_same(hntl.hntl_plan_search(plan, Q), ref, f"G=100 {codes} {sched}")
             assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
+
+
+def test_split_bf16_routing(bt):
+    """Routing's shortlist from split-BF16 MFMA products picks the same probes
+    (the P winners are decided on FP32 direct differences either way), so the
+    whole search is unchanged; plans honour the flag."""
+    W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
+    announce("split-BF16 routing vs FP32 routing (staged and plan)")
+    fl = hntl.HNTL_FLAG_ROUTE_BF16X3
+    for nb in (1000, 9):  # 9 rows take the direct-difference path
+        Q = bt["Qd"][:nb].contiguous()
+        a = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k)
+        b = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
+        assert torch.equal(a["probes"], b["probes"]), nb
+        assert torch.equal(a["ids"], b["ids"]) and torch.equal(a["dist"], b["dist"]), nb
+    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, flags=fl, sched=dict(qt=2, nw=4, range=1, proj=1))
+    assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], flags=fl), "plan, split routing")
