@@ -106,6 +106,19 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     eqv = ldg(a.epsq + pv);
     if (a.lbase) lbv = ldg(a.lbase + pv);
   }
+  // eps_q + the grain's smallest eps_i bounds eq. 6 from below without the
+  // tangent (the squared tangent distance is >= 0 and the float sums are
+  // monotone): when it already exceeds every pair's query bound, the tile is
+  // done without loading its tangents
+  if (a.prune) {
+    const float emin_g = ldg(a.emin + g);
+    const bool cut = lane < cnt && obv != NO_BOUND && (eqv + emin_g) * (1.f - PRUNE_SLACK) > ord2f(obv);
+    const uint64_t all = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+    if (__ballot(cut) == all) {
+      if (lane < cnt) stg(a.part + (size_t)((int64_t)lbv + range) * C, KEY_NONE);  // empty lists
+      return;
+    }
+  }
   for (int idx = lane; idx < QT * RP; idx += HNTL_WAVE) {
     const int t = idx / RP, j = idx % RP;
     const int pt = __shfl(pv, t, 64);
