@@ -3,26 +3,31 @@
 // over grains of very uneven size.
 //
 // One launch runs a fixed number of workgroups (as many as fit the device);
-// every wave of them is an independent worker that takes work items from one
-// device ticket counter until the items run out (no workgroup barriers).
+// every wave of them is an independent worker that takes work items from
+// device ticket counters until the items run out (no workgroup barriers).
 // The items come in three runs, each ordered largest grain first so that the
 // long items start early:
 //
 //   1. projection items: 16 (query, grain) pairs of one grain, whose tangents
 //      z_q and eps_q the wave computes on the MFMA units (the same wave
-//      routine as the grain-major projection kernel), then counts the item
-//      as done for its grain (release);
+//      routine as the grain-major projection kernel), then flags the item
+//      as done (release);
 //   2. scan items of probe slot 0 (each query's nearest grain);
 //   3. scan items of the other probe slots.
 //
+// With the schedule option proj = 1 the projection runs as its own launch
+// before this kernel, which then has no projection items and no waits.
+//
 // A scan item holds QT pairs of one grain and one block range of it (R
-// blocks, or the whole grain for R = 0).  Consecutive tickets are the tiles
-// of one range, so waves that run them together read the same blocks (L2
-// hits).  Before it reads tangents, a scan item waits until every projection
-// item of its grain is done (acquire).  The wait cannot deadlock: tickets are
-// handed out in item order, so every projection item was taken earlier by a
-// running wave that never waits itself; a spin limit still bounds it and
-// flags an error.
+// blocks, or the whole grain for R = 0).  Consecutive items are the tiles of
+// one range; a class of workgroups takes runs of them, so the waves that run
+// them read the same blocks through one L2.  Every item was decoded before
+// the launch into a descriptor (grain, range, pairs, and the projection items
+// that hold those pairs).  Before it reads tangents, a scan item waits until
+// those projection items are done (acquire).  The wait cannot deadlock:
+// tickets are handed out in item order, so every projection item was taken
+// earlier by a running wave that never waits itself; a spin limit still
+// bounds it and flags an error.
 //
 // Two passes (a schedule option): the launch with phase 1 runs only the
 // projection and slot-0 items, a second launch with phase 2 the other slots,
@@ -34,11 +39,12 @@
 // candidates.  The query's final pool (the C smallest (D, id) over all its
 // probed grains) cannot contain a candidate whose distance exceeds that
 // bound, so a list may drop such candidates, and a whole pair is skipped when
-// the exact lower bound of eq. 6 over its grain (box distance of z_q to the
-// grain's code bounding box + eps_q + the grain's smallest eps_i) exceeds it.
-// Lists publish their C-th distance (atomic min) and re-read the bound every
-// REFRESH blocks.  Which candidates a list drops depends on timing; the merged
-// pool does not, since it is the exact top C in every case.
+// a lower bound of eq. 6 over its grain exceeds it: first eps_q + the grain's
+// smallest eps_i (no tangent needed), then the box distance of z_q to the
+// grain's code bounding box added to that.  Lists publish their C-th distance
+// (atomic min) and re-read the bound every REFRESH blocks.  Which candidates
+// a list drops depends on timing; the merged pool does not, since it is the
+// exact top C in every case.
 #pragma once
 
 #include <algorithm>
