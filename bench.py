@@ -48,15 +48,15 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # scaled by its reading for a plain 1 GiB device copy; valid while the kernel
 # source is unchanged (sha1 below).  Recorded in
 # profiles/merge_rerank_patch1M_d768_G1024_r32_hbm_counters.md.
-TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "plan", "codes": "fp32", "P": 8,
+TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "plan", "codes": "fp32", "P": 8, "mode": "B",
            "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "f6e9612345c74c5b52f217f275ed940a00260033",
            "fetch_kib": 995029.1, "fetch_scale": 1048576.0 / 524307.8125, "write_kib": 1250.0, "write_scale": 1.0}
 
 
-def measured_traffic(stage, workload, form, codes, P):
+def measured_traffic(stage, workload, form, codes, P, mode):
     import hashlib
     t = TRAFFIC
-    if (stage, workload, form, codes, P) != (t["stage"], t["workload"], t["form"], t["codes"], t["P"]):
+    if (stage, workload, form, codes, P, mode) != (t["stage"], t["workload"], t["form"], t["codes"], t["P"], t["mode"]):
         return None
     src = ROOT / t["src"]
     if not src.exists() or hashlib.sha1(src.read_bytes()).hexdigest() != t["sha1"]:
@@ -94,6 +94,8 @@ def parse():
                     help="learned: train the router first (router-train queries, brute-force kNN targets)")
     ap.add_argument("--P", type=int, default=0, help="probes per query (0 = the workload's)")
     ap.add_argument("--tau", type=float, default=0.0, help="learned routing: centroid fallback below this max prob")
+    ap.add_argument("--mode", choices=("A", "B"), default="B",
+                    help="B: exact rerank against the raw vectors; A: the answer from the index alone")
     ap.add_argument("--route-split", choices=("auto", "on", "off"), default="auto",
                     help="centroid routing shortlist on split-BF16 MFMA (auto: with --codes bf16/fp8)")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
@@ -171,6 +173,8 @@ def main():
                                                 (args.route_split == "auto" and args.codes != "fp32"))
     if route_split:
         flags |= hntl.HNTL_FLAG_ROUTE_BF16X3
+    if args.mode == "A":
+        flags |= hntl.HNTL_FLAG_MODE_A
     rkw = dict(route=args.route, tau=args.tau)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -194,7 +198,8 @@ def main():
         stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
         scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
     else:
-        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3)
+        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3 |
+                          hntl.HNTL_FLAG_MODE_A)
         t0 = time.time()
         if args.sched:
             sched = {k: int(v) for k, v in (kv.split("=") for kv in args.sched.split(","))}
@@ -284,8 +289,8 @@ def main():
         "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s",
                         peak=BF16_MFMA_PEAK_TFLOPS if bf16_project else FP32_MFMA_PEAK_TFLOPS),
         "scan": dict(bound="alu", work=3.0 * W.r * (scored or scanned), unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
-        "rerank": dict(bound="hbm", work=float(W.nq) * W.C * W.d * 4 + W.nq * P * W.C * 8, unit="GB/s",
-                       peak=HBM_PEAK_GBS),
+        "rerank": dict(bound="hbm", work=(float(W.nq) * W.C * W.d * 4 if args.mode == "B" else W.nq * W.C * 4.0)
+                       + W.nq * P * W.C * 8, unit="GB/s", peak=HBM_PEAK_GBS),
     }
     roof = {}
     for name, s in per_stage.items():
@@ -311,7 +316,7 @@ def main():
             while done < nmax and el < args.cpu_seconds:
                 cs = order[done:done + 25]
                 t0 = time.time()
-                osr.search(queries.X[cs], ex, corpus.X, P, W.C, W.k)
+                osr.search(queries.X[cs], ex, corpus.X, P, W.C, W.k, mode=args.mode)
                 el += time.time() - t0
                 done += len(cs)
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
@@ -337,6 +342,7 @@ def main():
                    "P": P, "C": W.C, "k": W.k, "codes": args.codes,
                    "projection": "bf16" if bf16_project else "fp32", "form": args.form, "route": args.route,
                    "route_shortlist": "split-bf16" if route_split else ("fp32" if args.route == "centroid" else None),
+                   "mode": args.mode,
                    "schedule": sched},
         "recall_at_10": round(recall, 4),
         "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
@@ -349,7 +355,7 @@ def main():
         "build_s": round(build_s, 2),
         "captured_variance": round(info["captured_variance"], 5),
         "roofline": dict(roof.get(dominant, {}), kernel=dominant,
-                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P)) if dominant else None,
+                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode)) if dominant else None,
         "stage_rooflines": roof,
         "cpu_baseline": cpu,
         "precision": precision,

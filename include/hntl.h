@@ -76,6 +76,11 @@ typedef enum hntl_codes {
 #define HNTL_FLAG_PROJECT_BF16 16u /* projection on BF16 MFMA: q - mu_g (FP32) and W_g rounded to BF16 (nearest
                                       even), FP32 accumulation; eps_q stays FP32.  Needs an index with a
                                       reduced-precision code form (the BF16 bases are built with it) and d % 8 == 0 */
+#define HNTL_FLAG_MODE_A 64u /* the paper's Mode A (Section 2.1): the answer comes from the index alone, no raw
+                                vectors are read: the k smallest reconstruction distances
+                                ||q - (mu_g + W_g z_i)||^2 = ||z_q - z_i||^2 + eps_q over the pool (eq. 2-4 and 6;
+                                computed as the pool's eq. 6 score minus eps_i).  The returned distances are
+                                these.  Needs the merged pool (not an injected one) */
 #define HNTL_FLAG_ROUTE_BF16X3 32u /* centroid routing's shortlist from BF16 MFMA with each operand split into a
                                       BF16 high and low part (q_hi c_hi + q_hi c_lo + q_lo c_hi, FP32 accumulation,
                                       about 2^-16 relative); the P probes are still chosen on FP32 direct
@@ -132,7 +137,9 @@ hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const hntl_build_
  *   perm       N int32        grain-order position -> original row id (ascending inside a grain)
  *   codes      N x r          tangent coordinates z_i in grain order
  *   eps        N              residual energies eps_i in grain order (>= 0)
- *   X          N x d          raw vectors in original row order (copied for rerank)
+ *   X          N x d          raw vectors in original row order (copied for rerank), or NULL:
+ *                             an index without raw vectors, which answers HNTL_FLAG_MODE_A
+ *                             searches only (others fail with ESTATE)
  *   codes_mask as in hntl_build_params (derived reduced-precision codes to build)
  * Synchronous.  Errors: EINVAL (null pointer, inconsistent offsets/perm), EUNSUPPORTED, ENOMEM, EDEVICE.
  */

@@ -1,6 +1,7 @@
 """HNTL search, step by step (oracle, FP64 on the stored index values).
 
-Query lifecycle of Section 2.1 in Mode B (tiered filter), with the
+Query lifecycle of Section 2.1 in Mode B (tiered filter; Mode A, the answer
+from the index alone, replaces step 4 by ``answer_mode_a``), with the
 hierarchical routing of Section 2.3:
 
 1. ``route``   - squared Euclidean distance from q to every centroid mu_g;
@@ -153,9 +154,40 @@ def rerank(Q: np.ndarray, pool_ids: np.ndarray, X: np.ndarray, k: int):
     return ids, dist
 
 
+def answer_mode_a(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, pool_ids: np.ndarray, stored: dict, k: int,
+                  form: str = "fp32"):
+    """Mode A (Section 2.1): the answer from the index alone.  Every pool member
+    i of grain g is reconstructed in the grain's subspace, x_i' = mu_g + W_g z_i,
+    and ranked by ||q - x_i'||^2.  With q - x_i' = (q' - W_g z_q) + W_g (z_q - z_i)
+    and W_g orthonormal (eq. 2-4) this is ||z_q - z_i||^2 + eps_q, evaluated
+    here with the pair's tangent (z_q, eps_q) and the code values of the given
+    form; the k smallest (distance, id)."""
+    codes = stored["codes"] if form == "fp32" else quant.decoded_codes(stored["codes"], stored["offsets"], form)
+    off = np.asarray(stored["offsets"], dtype=np.int64)
+    perm = np.asarray(stored["perm"], dtype=np.int64)
+    pos_of = np.empty(len(perm), dtype=np.int64)
+    pos_of[perm] = np.arange(len(perm))
+    nq = probes.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    dist = np.full((nq, k), INF)
+    for i in range(nq):
+        cand = pool_ids[i][pool_ids[i] >= 0].astype(np.int64)
+        if len(cand) == 0:
+            continue
+        pos = pos_of[cand]
+        g = np.searchsorted(off, pos, side="right") - 1
+        slot = np.array([int(np.flatnonzero(probes[i] == gg)[0]) for gg in g])
+        Z = np.asarray(codes[pos], dtype=np.float64)
+        dd = ((zq[i, slot] - Z) ** 2).sum(axis=1) + epsq[i, slot]
+        ids[i], dist[i] = _lexsmallest(dd, cand, k)
+    return ids, dist
+
+
 def search(Q, stored: dict, X, P: int, C: int, k: int, probes=None, zq=None, epsq=None,
-           pool_ids=None, form: str = "fp32", bf16_project: bool = False):
-    """The whole lifecycle; any stage's input may be supplied to check later stages."""
+           pool_ids=None, form: str = "fp32", bf16_project: bool = False, mode: str = "B"):
+    """The whole lifecycle; any stage's input may be supplied to check later stages.
+    mode "B": exact rerank against the raw vectors X; mode "A": the answer from
+    the index alone (X unused)."""
     G = stored["centroids"].shape[0]
     if not (1 <= P <= G) or k < 1 or C < k:
         raise ValueError("invalid P, C or k")
@@ -171,7 +203,10 @@ def search(Q, stored: dict, X, P: int, C: int, k: int, probes=None, zq=None, eps
         pool_ids, pool_D = scan_pool(zq, epsq, probes, stored, C, form)
         out["pool_D"] = pool_D
     out["pool_ids"] = pool_ids
-    out["ids"], out["dist"] = rerank(Q, pool_ids, X, k)
+    if mode == "A":
+        out["ids"], out["dist"] = answer_mode_a(zq, epsq, probes, pool_ids, stored, k, form)
+    else:
+        out["ids"], out["dist"] = rerank(Q, pool_ids, X, k)
     return out
 
 

@@ -213,8 +213,8 @@ hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, co
   g_last_error.clear();
   if (!out) return fail(HNTL_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!centroids || !basis || !offsets || !perm || !codes || !eps || !X)
-    return fail(HNTL_EINVAL, "null array pointer");
+  if (!centroids || !basis || !offsets || !perm || !codes || !eps)
+    return fail(HNTL_EINVAL, "null array pointer");  // X may be null: an index for Mode A answers only
   if (N == 0 || d == 0 || G == 0 || r == 0) return fail(HNTL_EINVAL, "N, d, G and r must be positive");
   if (G > N) return fail(HNTL_EINVAL, "G > N");
   if (r > d) return fail(HNTL_EINVAL, "r > d");
@@ -252,7 +252,7 @@ hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, co
     ix->centroids = upload(ix, centroids, (size_t)G * d);
     ix->basis = upload(ix, basis, (size_t)G * r * d);
     ix->perm = upload(ix, pm.data(), N);
-    ix->X = upload(ix, X, (size_t)N * d);
+    if (X) ix->X = upload(ix, X, (size_t)N * d);
     finish_index(ix, off, cz.data(), ce.data());
     ix->captured.assign(G, -1.0);
     ix->codes_mask = 1u;
@@ -388,6 +388,9 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
   if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
   const bool learned = sp->route == HNTL_ROUTE_LEARNED && !probes_in && !pool_in;
   if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
+  const bool mode_a = (sp->flags & HNTL_FLAG_MODE_A) != 0;
+  if (!mode_a && !ix.X) return fail(HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches");
+  if (mode_a && pool_in) return fail(HNTL_EUNSUPPORTED, "Mode A answers need the merged pool, not an injected one");
   if (nq == 0) return HNTL_OK;
   if (!Q || !ids || !dist) return fail(HNTL_EINVAL, "Q, ids and dist are required");
   hipStream_t s = (hipStream_t)stream;
@@ -489,7 +492,9 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
     }
     // 5. pool merge + exact rerank
     clk.at(HNTL_STAGE_RERANK);
-    launch_merge_rerank(ix, Q, nq, (int)P, (int)C, (int)k, probes, part, pool_in, pool_out, pool_D_out, ids, dist, s);
+    if (mode_a) ensure_eps_by_id(const_cast<Index&>(ix), s);  // derived data, made once under a lock
+    launch_merge_rerank(ix, Q, nq, (int)P, (int)C, (int)k, probes, part, pool_in, pool_out, pool_D_out, ids, dist, s,
+                        nullptr, mode_a ? ix.eps_id : nullptr);
     clk.done();
     if (sp->flags & HNTL_FLAG_SYNC) {
       HIP_TRY(hipStreamSynchronize(s));

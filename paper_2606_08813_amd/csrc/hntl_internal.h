@@ -78,6 +78,7 @@ struct Index {
   float* emin = nullptr;       // G: per-grain minimum eps_i
   int32_t* gorder = nullptr;   // G: grains by size, largest first (made by the first search plan)
   uint16_t* cent_split = nullptr;  // G x 3d bf16: [hi | lo | hi] of the centroids (split-BF16 routing, on first use)
+  float* eps_id = nullptr;         // N: eps_i by original row id (Mode A answers, on first use)
   std::unique_ptr<Router> router;  // learned router (trained or imported), else null
 
   std::vector<int64_t> offsets_h;
@@ -226,10 +227,13 @@ void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, 
                  const Buckets& b, int list, uint64_t* part, const uint64_t* bound_lists, bool prune,
                  unsigned long long* scored, hipStream_t s);
 void launch_grain_bounds(Index& ix, hipStream_t s);
+// eps_i by original id, made once (Mode A).
+void ensure_eps_by_id(Index& ix, hipStream_t s);
+// eps_id != null: Mode A (reconstruction distances of the pool, no raw vectors).
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k,
                          const int32_t* probes, const uint64_t* part, const int32_t* pool_in, int32_t* pool_out,
                          float* pool_D_out, int32_t* ids, float* dist, hipStream_t s,
-                         const int32_t* qoff = nullptr);
+                         const int32_t* qoff = nullptr, const float* eps_id = nullptr);
 
 // Persistent fused project-scan-select kernel (the batching form).  Its
 // waves take work items from one device ticket counter, in three runs:

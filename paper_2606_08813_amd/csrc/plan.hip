@@ -73,7 +73,7 @@ constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int TICKET_INTS = 9 * 64;
 constexpr int MIN_GRID = 8;  // every class of scan counters needs a workgroup
 // search flags a plan honours (beyond HNTL_FLAG_SYNC)
-constexpr uint32_t PLAN_FLAGS = HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3;
+constexpr uint32_t PLAN_FLAGS = HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3 | HNTL_FLAG_MODE_A;
 constexpr uint64_t MAX_LIST_BYTES = 4ull << 30;  // candidate-list storage of one plan
 
 // Bump allocation over one block (base == nullptr: sizing pass).
@@ -333,7 +333,7 @@ struct Plan {
     }
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     launch_merge_rerank(x, Q, max_nq, P, (int)sp.C, (int)sp.k, probes, part, nullptr, nullptr, nullptr, ids, dist, s,
-                        sch.range ? qoff : nullptr);
+                        sch.range ? qoff : nullptr, (sp.flags & HNTL_FLAG_MODE_A) ? x.eps_id : nullptr);
     if (ev) HIP_TRY(hipEventRecord(ev[4], s));
   }
 
@@ -363,6 +363,8 @@ void check_plan_shape(const Index& ix, const hntl_search_params& sp) {
   if (sp.route == HNTL_ROUTE_LEARNED && !(ix.router && ix.router->trained))
     throw ArgError{HNTL_ESTATE, "learned routing needs a trained router"};
   if (ix.d % 8 != 0) throw ArgError{HNTL_EUNSUPPORTED, "the fused kernel needs d % 8 == 0"};
+  if (!(sp.flags & HNTL_FLAG_MODE_A) && !ix.X)
+    throw ArgError{HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches"};
   if (ix.rp != 16 && ix.rp != 32 && ix.rp != 48 && ix.rp != 64)
     throw ArgError{HNTL_EUNSUPPORTED, "the fused kernel needs a padded rank of 16, 32, 48 or 64"};
 }
@@ -405,6 +407,7 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
     throw ArgError{HNTL_EUNSUPPORTED, "schedule needs more than 64 KiB of LDS per workgroup"};
   ensure_grain_order(ix);
   if ((sp.flags & HNTL_FLAG_ROUTE_BF16X3) && sp.route != HNTL_ROUTE_LEARNED) ensure_centroid_split(ix, s);
+  if (sp.flags & HNTL_FLAG_MODE_A) ensure_eps_by_id(ix, s);
   std::unique_ptr<Plan> pl(new Plan());
   pl->ix = &ix;
   pl->sp = sp;

@@ -9,6 +9,8 @@
 //      16-byte non-temporal loads (each row is used once), two rows per wave
 //      at a time (measured faster than one or four on MI355X).
 //   3. wave 0 keeps the k smallest (distance, id).
+#include <mutex>
+
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -24,7 +26,8 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
                                                            const float* __restrict__ X, int32_t* __restrict__ pool_out,
                                                            float* __restrict__ pool_D_out, int32_t* __restrict__ ids,
                                                            float* __restrict__ dist, bool vec4,
-                                                           const int32_t* __restrict__ qoff) {
+                                                           const int32_t* __restrict__ qoff,
+                                                           const float* __restrict__ eps_id) {
   __shared__ uint64_t lst[2 * CAP];
   __shared__ int32_t pool[CAP];
   __shared__ float delta[CAP];
@@ -63,6 +66,8 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         if (lane < C) {
           const int32_t id = L.best == KEY_NONE ? -1 : (int32_t)key_id(L.best);
           pool[lane] = id;
+          // Mode A: eq. 6 minus eps_i is the reconstruction distance ||z_q - z_i||^2 + eps_q
+          if (eps_id) delta[lane] = id < 0 ? __builtin_inff() : key_dist(L.best) - eps_id[id];
           if (pool_out) pool_out[q * C + lane] = id;
           if (pool_D_out) pool_D_out[q * C + lane] = L.best == KEY_NONE ? __builtin_inff() : key_dist(L.best);
         }
@@ -106,6 +111,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         const uint64_t key = L.best[rr];
         const int32_t id = key == KEY_NONE ? -1 : (int32_t)key_id(key);
         pool[c] = id;
+        if (eps_id) delta[c] = id < 0 ? __builtin_inff() : key_dist(key) - eps_id[id];
         if (pool_out) pool_out[q * C + c] = id;
         if (pool_D_out) pool_D_out[q * C + c] = key == KEY_NONE ? __builtin_inff() : key_dist(key);
       }
@@ -118,9 +124,9 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   }
   __syncthreads();
 
-  // each wave gathers RR pool rows at a time
+  // each wave gathers RR pool rows at a time (Mode B only)
   const float* qv = Q + (size_t)q * d;
-  for (int c0 = wave * RR; c0 < C; c0 += 4 * RR) {
+  for (int c0 = wave * RR; c0 < C && !eps_id; c0 += 4 * RR) {
     int32_t id[RR];
     const float* x[RR];
     float acc[RR];
@@ -207,20 +213,41 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   }
 }
 
+// eps_id[perm[p]] = eps of grain position p (one workgroup per grain).
+__global__ __launch_bounds__(256) void eps_by_id_kernel(const float* __restrict__ eps, const int32_t* __restrict__ goff,
+                                                        const int32_t* __restrict__ boff,
+                                                        const int32_t* __restrict__ perm, float* __restrict__ out) {
+  const int g = blockIdx.x;
+  const int a = goff[g], n = goff[g + 1] - a, b0 = boff[g];
+  for (int m = threadIdx.x; m < n; m += blockDim.x) out[perm[a + m]] = eps[((size_t)b0 + m / B) * B + m % B];
+}
+std::mutex g_eps_mu;
 }  // namespace
+
+void ensure_eps_by_id(Index& ix, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_eps_mu);
+  if (ix.eps_id) return;
+  float* p = dev_alloc<float>(&ix, ix.N);
+  hipLaunchKernelGGL(eps_by_id_kernel, dim3(ix.G), dim3(256), 0, s, ix.eps, ix.goff, ix.boff, ix.perm, p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  ix.eps_id = p;
+}
 
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k, const int32_t* probes,
                          const uint64_t* part,
                          const int32_t* pool_in, int32_t* pool_out, float* pool_D_out, int32_t* ids, float* dist,
-                         hipStream_t s, const int32_t* qoff) {
+                         hipStream_t s, const int32_t* qoff, const float* eps_id) {
   if (nq <= 0) return;
+  if (eps_id && pool_in) throw ArgError{HNTL_EUNSUPPORTED, "Mode A answers need the merged pool, not an injected one"};
+  if (!eps_id && !ix.X) throw ArgError{HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches"};
   const bool vec4 = (ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0 && ((uintptr_t)ix.X % 16) == 0;
   const int cap = pow2_at_least(C < 64 ? 64 : C);
   dim3 grid((unsigned)nq);
 #define HNTL_MR(CAPV)                                                                                             \
   hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 2, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
                      (int64_t)ix.N, probes, part, pool_in, ix.X,                                                  \
-                     pool_out, pool_D_out, ids, dist, vec4, qoff)
+                     pool_out, pool_D_out, ids, dist, vec4, qoff, eps_id)
   if (cap == 64)
     HNTL_MR(64);
   else if (cap == 128)

@@ -990,6 +990,7 @@ hntl_status hntl_knn(const hntl_index* index, const float* Q, uint32_t nq, uint3
   if (!index || !Q || !ids) return fail(HNTL_EINVAL, "null pointer");
   if (nq == 0) return HNTL_OK;
   const Index& ix = index->ix;
+  if (!ix.X) return fail(HNTL_ESTATE, "this index holds no raw vectors");
   return guarded_r([&] {
     HIP_TRY(hipSetDevice(ix.device));
     launch_knn(Q, nq, ix.X, (int64_t)ix.N, (int)ix.d, (int)k, ids, dist, (hipStream_t)stream);
@@ -1032,6 +1033,7 @@ hntl_status hntl_router_train(hntl_index* index, const float* Qtrain, uint32_t n
     if (targets) {
       tg = const_cast<int32_t*>(targets);
     } else {
+      if (!ix.X) throw ArgError{HNTL_ESTATE, "kNN training targets need the raw vectors (pass targets instead)"};
       int32_t *ids = nullptr, *lab = nullptr;
       HIP_TRY(hipMalloc((void**)&tg, sizeof(int32_t) * (size_t)n * kt));
       tg_own.reset(tg);

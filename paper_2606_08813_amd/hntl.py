@@ -21,6 +21,7 @@ HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED 
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
 HNTL_FLAG_ROUTE_BF16X3 = 32
+HNTL_FLAG_MODE_A = 64
 HNTL_ROUTE_CENTROID, HNTL_ROUTE_LEARNED = 0, 1
 HNTL_ROUTER_KEEP_WEIGHTS, HNTL_ROUTER_NO_SHUFFLE = 1, 2
 ROUTES = {"centroid": HNTL_ROUTE_CENTROID, "learned": HNTL_ROUTE_LEARNED}
@@ -199,7 +200,8 @@ def hntl_build(X, G: int, r: int, *, kmeans_iters=0, train_per_grain=0, eig_iter
 
 
 def hntl_index_create(stored: dict, X, codes=("fp32",)) -> Index:
-    """Index from stored-format arrays (numpy host arrays or CUDA tensors)."""
+    """Index from stored-format arrays (numpy host arrays or CUDA tensors).  X = None
+    gives an index without raw vectors, which answers Mode A searches only."""
     def prep(a, dt):
         if isinstance(a, np.ndarray):
             return np.ascontiguousarray(a, dtype=dt)
@@ -210,7 +212,7 @@ def hntl_index_create(stored: dict, X, codes=("fp32",)) -> Index:
     per = prep(stored["perm"], np.int32)
     cod = prep(stored["codes"], np.float32)
     eps = prep(stored["eps"], np.float32)
-    Xc = prep(X, np.float32)
+    Xc = None if X is None else prep(X, np.float32)
     G, d = cen.shape
     r = bas.shape[1]
     N = per.shape[0]
@@ -219,7 +221,7 @@ def hntl_index_create(stored: dict, X, codes=("fp32",)) -> Index:
         mask |= 1 << CODES[c]
     out = C.c_void_p()
     _check(lib().hntl_index_create(N, d, G, r, _ptr(cen), _ptr(bas), _ptr(off), _ptr(per), _ptr(cod), _ptr(eps),
-                                   _ptr(Xc), mask, C.byref(out)))
+                                   None if Xc is None else _ptr(Xc), mask, C.byref(out)))
     return Index(out, N, d, G, r)
 
 

@@ -423,3 +423,57 @@ def test_router_fallback_reduces_to_its_two_routes():
     np.testing.assert_array_equal(pm[pmax < tau], cp[pmax < tau])
     np.testing.assert_array_equal(pm[pmax >= tau], lp[pmax >= tau])
     assert ((pmax > 0) & (pmax <= 1)).all()
+
+
+# ---------------------------------------------------------------- Mode A
+
+def test_mode_a_distance_is_the_explicit_reconstruction_distance(tiny_mix):
+    """Mode A ranks pool members by the distance from q to their reconstruction
+    mu_g + W_g z_i (Section 2.1); rebuild those vectors explicitly in float64 and
+    compare with the tangent-space evaluation of the oracle."""
+    X, Q = tiny_mix
+    idx = oi.build(X, 5, 4, seed=7)
+    st = dict(idx.stored(), basis=np.stack([w.T for w in idx.W]), codes=idx.codes, eps=idx.eps,
+              centroids=idx.centroids)  # the float64 index: W_g orthonormal to rounding
+    out = osr.search(Q, st, None, P=3, C=30, k=10, mode="A")
+    perm = np.asarray(st["perm"], dtype=np.int64)
+    off = np.asarray(st["offsets"], dtype=np.int64)
+    pos_of = np.empty(len(perm), dtype=np.int64)
+    pos_of[perm] = np.arange(len(perm))
+    for i in range(len(Q)):
+        for j in range(10):
+            rid = int(out["ids"][i, j])
+            p = pos_of[rid]
+            g = int(np.searchsorted(off, p, side="right") - 1)
+            W = st["basis"][g].astype(np.float64).T            # d x r
+            rec = st["centroids"][g].astype(np.float64) + W @ st["codes"][p].astype(np.float64)
+            ref = ((Q[i].astype(np.float64) - rec) ** 2).sum()
+            assert abs(out["dist"][i, j] - ref) <= 1e-9 * max(ref, 1.0), (i, j)
+        assert np.all(np.diff(out["dist"][i]) >= 0)
+
+
+def test_mode_a_at_full_rank_equals_mode_b():
+    """At r = d the reconstruction is exact (eps = 0), so Mode A's answer is the
+    exact top-k of the pool, i.e. Mode B's."""
+    X = pm.uniform_rows(300, 8, seed=8)
+    Q = pm.uniform_rows(10, 8, seed=9)
+    idx = oi.build(X, 3, 8, seed=10)
+    st64 = dict(idx.stored(), basis=np.stack([w.T for w in idx.W]), codes=idx.codes, eps=idx.eps,
+                centroids=idx.centroids)
+    a = osr.search(Q, st64, None, P=3, C=50, k=10, mode="A")
+    b = osr.search(Q, st64, X, P=3, C=50, k=10)
+    np.testing.assert_array_equal(a["ids"], b["ids"])
+    np.testing.assert_allclose(a["dist"], b["dist"], rtol=1e-9)
+
+
+def test_mode_a_distance_never_exceeds_the_scan_score(tiny_mix):
+    """Mode A's distance is eq. 6 without eps_i, so it is never above the pool score."""
+    X, Q = tiny_mix
+    idx = oi.build(X, 5, 4, seed=7)
+    st = idx.stored()
+    out = osr.search(Q, st, None, P=3, C=30, k=30, mode="A")
+    for i in range(len(Q)):
+        score = dict(zip(out["pool_ids"][i].tolist(), out["pool_D"][i].tolist()))
+        for rid, d in zip(out["ids"][i], out["dist"][i]):
+            if rid >= 0:
+                assert d <= score[int(rid)] + 1e-12
