@@ -133,3 +133,80 @@ def decoded_codes(codes: np.ndarray, offsets: np.ndarray, form: str) -> np.ndarr
                 out[a:b] = c[a:b].astype(np.float32) * sc[g]
         return out.astype(np.float64)
     raise ValueError(form)
+
+
+# ------------------------------------------------------------ int16 (eq. 5)
+# The paper's own reduced form: z_hat = round(z / Delta) as signed 16-bit and
+# r_hat = round(r / Delta_res) as unsigned 16-bit (eq. 5), with the score
+# ||z_q - z_i||^2 + r_q + r_i evaluated on the integers.  The paper gives no
+# rule for the steps; here they are per grain and make the largest member
+# value the largest code:  inv_g = fl32(32767 / amax_g) over |z_ij| (j < r),
+# rinv_g = fl32(65535 / max_i eps_i) (1 when the maximum is 0); Delta = 1 / inv,
+# Delta_res = 1 / rinv.  A value is quantised as rint(fl32(x) * inv) with the
+# product formed in float32 (ties to even), then clamped to the 16-bit range;
+# a query coordinate that needs clamping is saturated.  The query's residual
+# r_q is one number per (query, grain) and enters unquantised (with the
+# members' step it would clamp for every query far from the grain).  The score
+# is Delta^2 * S + Delta_res * r_hat_i + r_q, S = sum_j (z_hat_q,j - z_hat_i,j)^2
+# exactly (it needs more than 32 bits: up to r * 65534^2).
+I16_MAX = 32767
+U16_MAX = 65535
+ENVELOPE_FRACTION = 0.25  # a grain is pruned for a query when more than this share of its coordinates saturate
+
+
+def int16_grain_steps(codes: np.ndarray, eps: np.ndarray, offsets: np.ndarray, r: int):
+    """Per-grain float32 reciprocal steps (inv_g, rinv_g)."""
+    z = np.asarray(codes, dtype=np.float32)
+    e = np.asarray(eps, dtype=np.float32)
+    G = len(offsets) - 1
+    inv = np.ones(G, dtype=np.float32)
+    rinv = np.ones(G, dtype=np.float32)
+    for g in range(G):
+        a, b = int(offsets[g]), int(offsets[g + 1])
+        if b > a:
+            amax = float(np.abs(z[a:b, :r]).max())
+            emax = float(e[a:b].max())
+            if amax > 0:
+                inv[g] = np.float32(I16_MAX / np.float64(np.float32(amax)))
+            if emax > 0:
+                rinv[g] = np.float32(U16_MAX / np.float64(np.float32(emax)))
+    return inv, rinv
+
+
+def int16_quantize(x, inv, lim: int, signed: bool = True):
+    """rint(fl32(x) * fl32(inv)) (float32 product, ties to even) clamped to
+    [-lim, lim] (signed) or [0, lim]; returns (int64 values, saturated mask)."""
+    p = np.asarray(x, dtype=np.float32) * np.float32(inv)
+    q = np.rint(p.astype(np.float64))
+    lo = -lim if signed else 0
+    sat = (q > lim) | (q < lo)
+    return np.clip(q, lo, lim).astype(np.int64), sat
+
+
+def int16_grain_codes(codes: np.ndarray, eps: np.ndarray, offsets: np.ndarray, r: int):
+    """Integer codes (N x r) and residuals (N) in grain order, and the steps."""
+    inv, rinv = int16_grain_steps(codes, eps, offsets, r)
+    z = np.asarray(codes, dtype=np.float32)[:, :r]
+    e = np.asarray(eps, dtype=np.float32)
+    zh = np.zeros(z.shape, dtype=np.int64)
+    rh = np.zeros(len(e), dtype=np.int64)
+    for g in range(len(offsets) - 1):
+        a, b = int(offsets[g]), int(offsets[g + 1])
+        if b > a:
+            zh[a:b], _ = int16_quantize(z[a:b], inv[g], I16_MAX)
+            rh[a:b], _ = int16_quantize(e[a:b], rinv[g], U16_MAX, signed=False)
+    return zh, rh, inv, rinv
+
+
+def int16_scores(zq, epsq, zh, rh, inv, rinv):
+    """The integer-form score of members (zh, rh) of one grain for one query:
+    (scores float64, envelope-pruned flag)."""
+    r = zh.shape[1]
+    zq_h, sat = int16_quantize(np.asarray(zq)[:r], inv, I16_MAX)
+    if sat.sum() > ENVELOPE_FRACTION * r:
+        return None, True
+    S = ((zq_h[None, :] - zh) ** 2).sum(axis=1)  # exact int64
+    step = 1.0 / np.float64(inv)
+    rstep = 1.0 / np.float64(rinv)
+    eq = np.float64(np.float32(epsq))
+    return S.astype(np.float64) * step * step + rh.astype(np.float64) * rstep + eq, False

@@ -119,7 +119,12 @@ def grain_scores(zq: np.ndarray, epsq: float, g: int, stored: dict, codes=None):
 
 def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict, C: int, form: str = "fp32"):
     """Candidate pool (nq, C) ids and scores over the union of the probed grains,
-    scanning the code values of the given form (fp32, bf16, fp8)."""
+    scanning the code values of the given form (fp32, bf16, fp8, int16).  The
+    int16 form scores on the integer codes (eq. 5) and applies the
+    quantisation envelope filter (Section 2.3): a probed grain in which more
+    than a quarter of the query's coordinates saturate contributes nothing."""
+    if form == "int16":
+        return _scan_pool_int16(zq, epsq, probes, stored, C)
     codes = None if form == "fp32" else quant.decoded_codes(stored["codes"], stored["offsets"], form)
     nq, P = probes.shape
     pool_ids = np.full((nq, C), -1, dtype=np.int64)
@@ -133,6 +138,30 @@ def scan_pool(zq: np.ndarray, epsq: np.ndarray, probes: np.ndarray, stored: dict
             gi, gd = grain_scores(zq[i, s], epsq[i, s], g, stored, codes)
             ids.append(gi)
             Ds.append(gd)
+        if ids:
+            pool_ids[i], pool_D[i] = _lexsmallest(np.concatenate(Ds), np.concatenate(ids), C)
+    return pool_ids, pool_D
+
+
+def _scan_pool_int16(zq, epsq, probes, stored, C):
+    r = stored["basis"].shape[1]
+    zh, rh, inv, rinv = quant.int16_grain_codes(stored["codes"], stored["eps"], stored["offsets"], r)
+    off = stored["offsets"]
+    nq, P = probes.shape
+    pool_ids = np.full((nq, C), -1, dtype=np.int64)
+    pool_D = np.full((nq, C), INF)
+    for i in range(nq):
+        ids, Ds = [], []
+        for s in range(P):
+            g = int(probes[i, s])
+            if g < 0:
+                continue
+            a, b = int(off[g]), int(off[g + 1])
+            D, pruned = quant.int16_scores(zq[i, s], epsq[i, s], zh[a:b], rh[a:b], inv[g], rinv[g])
+            if pruned or b == a:
+                continue
+            ids.append(stored["perm"][a:b].astype(np.int64))
+            Ds.append(D)
         if ids:
             pool_ids[i], pool_D[i] = _lexsmallest(np.concatenate(Ds), np.concatenate(ids), C)
     return pool_ids, pool_D

@@ -477,3 +477,84 @@ def test_mode_a_distance_never_exceeds_the_scan_score(tiny_mix):
         for rid, d in zip(out["ids"][i], out["dist"][i]):
             if rid >= 0:
                 assert d <= score[int(rid)] + 1e-12
+
+
+# ------------------------------------------------------------- int16 (eq. 5)
+
+def test_int16_codes_round_trip_and_full_range(tiny_mix):
+    """Each code is within half a step of its value (eq. 5 with the per-grain
+    step; plus the float32 rounding of the product z * inv, at most 2^-24 of
+    32767 steps, so 0.502 steps), and every grain's largest |z| takes the
+    largest code 32767."""
+    X, _ = tiny_mix
+    idx = oi.build(X, 5, 4, seed=7)
+    st = idx.stored()
+    r = st["basis"].shape[1]
+    zh, rh, inv, rinv = quant.int16_grain_codes(st["codes"], st["eps"], st["offsets"], r)
+    off = st["offsets"]
+    for g in range(len(off) - 1):
+        a, b = int(off[g]), int(off[g + 1])
+        z = st["codes"][a:b, :r].astype(np.float64)
+        step = 1.0 / np.float64(inv[g])
+        assert np.abs(zh[a:b] * step - z).max() <= 0.502 * step
+        assert np.abs(zh[a:b]).max() == quant.I16_MAX
+        e = st["eps"][a:b].astype(np.float64)
+        rstep = 1.0 / np.float64(rinv[g])
+        assert np.abs(rh[a:b] * rstep - e).max() <= 0.502 * rstep
+        assert rh[a:b].max() == quant.U16_MAX and rh[a:b].min() >= 0
+
+
+def test_int16_score_is_exact_integer_and_within_its_quantisation_bound(tiny_mix):
+    """S = sum (z_hat_q - z_hat_i)^2 is computed exactly (compared with Python
+    integers), and the integer-form score differs from eq. 6 by no more than
+    the bound sum_j (2 h |z_q,j - z_i,j| Delta + h^2 Delta^2) + 0.502 Delta_res
+    (+ the float32 rounding of eps_q), h = 2 x 0.502 (both operands within
+    0.502 steps)."""
+    X, Q = tiny_mix
+    idx = oi.build(X, 5, 4, seed=7)
+    st = idx.stored()
+    r = st["basis"].shape[1]
+    zh, rh, inv, rinv = quant.int16_grain_codes(st["codes"], st["eps"], st["offsets"], r)
+    probes, _ = osr.route(Q, st["centroids"], 2)
+    zq, eq = osr.project(Q, probes, st)
+    off = st["offsets"]
+    checked = 0
+    for i in range(len(Q)):
+        for s in range(2):
+            g = int(probes[i, s])
+            a, b = int(off[g]), int(off[g + 1])
+            D, pruned = quant.int16_scores(zq[i, s], eq[i, s], zh[a:b], rh[a:b], inv[g], rinv[g])
+            if pruned:
+                continue
+            zq_h, _ = quant.int16_quantize(zq[i, s][:r], inv[g], quant.I16_MAX)
+            m = b - 1
+            S_big = sum((int(x) - int(y)) ** 2 for x, y in zip(zq_h, zh[m]))
+            step, rstep = 1.0 / np.float64(inv[g]), 1.0 / np.float64(rinv[g])
+            assert D[-1] == np.float64(S_big) * step * step + int(rh[m]) * rstep + np.float64(np.float32(eq[i, s]))
+            _, D6 = osr.grain_scores(zq[i, s], eq[i, s], g, st)
+            diff = np.abs(zq[i, s][None, :r] - st["codes"][a:b, :r].astype(np.float64))
+            h = 2 * 0.502
+            bound = (2 * h * diff * step + h * h * step * step).sum(axis=1) + 0.502 * rstep + 1e-6 * eq[i, s]
+            assert (np.abs(D - D6) <= bound * (1 + 1e-9) + 1e-12).all()
+            checked += 1
+    assert checked > 0
+
+
+def test_int16_envelope_filter_prunes_saturated_queries():
+    """Section 2.3: a grain is pruned when more than 25% of the query's
+    coordinates saturate the signed 16-bit range; exactly 25% is kept."""
+    r = 8
+    zh = np.array([[quant.I16_MAX, -quant.I16_MAX] + [0] * (r - 2)], dtype=np.int64)
+    rh = np.array([0], dtype=np.int64)
+    inv, rinv = np.float32(1000.0), np.float32(1.0)
+    amax = quant.I16_MAX / 1000.0
+    q = np.zeros(r)
+    q[:2] = 3 * amax   # 2 of 8 saturate: 25%, kept
+    D, pruned = quant.int16_scores(q, 0.0, zh, rh, inv, rinv)
+    assert not pruned and np.isfinite(D).all()
+    q[2] = -3 * amax   # 3 of 8: pruned
+    _, pruned = quant.int16_scores(q, 0.0, zh, rh, inv, rinv)
+    assert pruned
+    q[:] = 0.5 * amax  # none saturate
+    _, pruned = quant.int16_scores(q, 0.0, zh, rh, inv, rinv)
+    assert not pruned
