@@ -15,6 +15,8 @@ Zipf-grain batching workload, 16,384 queries per step, P = 16, C = 100):
   --route learned  the learned router, trained first on --router-train
                    generated queries with brute-force kNN targets
   --codes bf16|fp8 reduced-precision codes (BF16 MFMA projection by default)
+  --codes int16    the paper's own int16 form (eq. 5, envelope filter; staged search)
+  --mode A         the answer from the index alone (no raw-vector rerank)
 
 Prints one JSON line: queries/s (whole job), ns per vector scanned,
 Recall@10 against exact brute force on a query sample, per-stage device times
@@ -74,7 +76,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="patch1M_d768_G1024_r32")
-    ap.add_argument("--codes", default="fp32")
+    ap.add_argument("--codes", choices=("fp32", "bf16", "fp8", "int16"), default="fp32")
     ap.add_argument("--recall-sample", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="most queries timed on the CPU oracle (-1 = the whole batch, 0 = skip)")
@@ -115,6 +117,9 @@ def main():
     from workloads import WORKLOADS
     from paper_2606_08813_amd import hntl
 
+    if args.codes == "int16" and args.form == "plan":
+        print("the int16 form (eq. 5) runs in the staged search only: add --form staged", file=sys.stderr)
+        sys.exit(2)
     W = WORKLOADS[args.workload]
     if args.copy_gib > 0:  # a copy of known size: n bytes read, n bytes written
         n = int(args.copy_gib * (1 << 30)) // 4
@@ -166,11 +171,11 @@ def main():
     flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
     if args.no_prune:
         flags |= hntl.HNTL_FLAG_NO_PRUNE
-    bf16_project = args.codes != "fp32" and not args.fp32_project
+    bf16_project = args.codes in ("bf16", "fp8") and not args.fp32_project
     if bf16_project:
         flags |= hntl.HNTL_FLAG_PROJECT_BF16
     route_split = args.route == "centroid" and (args.route_split == "on" or
-                                                (args.route_split == "auto" and args.codes != "fp32"))
+                                                (args.route_split == "auto" and args.codes in ("bf16", "fp8")))
     if route_split:
         flags |= hntl.HNTL_FLAG_ROUTE_BF16X3
     if args.mode == "A":
@@ -280,7 +285,7 @@ def main():
     # rooflines per stage (algorithmic work per launch / average stage time)
     npairs = W.nq * P
     rp = (W.r + 7) // 8 * 8
-    code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1}[args.codes]
+    code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1, "int16": 2}[args.codes]
     route_work = (2.0 * W.nq * (W.d * 1024 + 1024 * 1024 + 1024 * W.G) if args.route == "learned"
                   else 2.0 * W.nq * W.G * W.d)
     per_stage = {
@@ -336,7 +341,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.codes],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "int16": "i16"}[args.codes],
         "data": "synthetic",
         "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
                    "P": P, "C": W.C, "k": W.k, "codes": args.codes,

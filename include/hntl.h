@@ -65,7 +65,13 @@ typedef enum hntl_status {
 typedef enum hntl_codes {
   HNTL_CODES_FP32 = 0,
   HNTL_CODES_BF16 = 1,      /* bf16, round-to-nearest-even of the fp32 codes */
-  HNTL_CODES_FP8_E4M3 = 2   /* OCP e4m3fn of z / s_g, per-grain fp32 scale s_g = amax / 448 */
+  HNTL_CODES_FP8_E4M3 = 2,  /* OCP e4m3fn of z / s_g, per-grain fp32 scale s_g = amax / 448 */
+  HNTL_CODES_INT16 = 3      /* the paper's eq. 5: int16 z_hat = rint(fl32(z) * inv_g) with inv_g = fl32(32767 / amax_g),
+                               uint16 r_hat_i = rint(fl32(eps_i) * rinv_g), rinv_g = fl32(65535 / max_i eps_i);
+                               score (1 / inv_g)^2 sum_j (z_hat_q,j - z_hat_i,j)^2 (exact integer sum)
+                               + r_hat_i / rinv_g + eps_q; a probed grain in which more than 25% of the
+                               query's coordinates saturate is pruned (envelope filter).  Staged search
+                               only (plans: EUNSUPPORTED), Mode B only */
 } hntl_codes;
 
 /* Search flags. */

@@ -257,7 +257,7 @@ hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, co
     ix->captured.assign(G, -1.0);
     ix->codes_mask = 1u;
     if (codes_mask & ~1u) {
-      ix->codes_mask |= codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3));
+      ix->codes_mask |= codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3) | (1u << HNTL_CODES_INT16));
       launch_derive_lowp(*ix, nullptr);
       HIP_TRY(hipDeviceSynchronize());
     }
@@ -306,16 +306,24 @@ hntl_status hntl_index_export_codes(const hntl_index* index, uint32_t codes, voi
   g_last_error.clear();
   if (!index) return fail(HNTL_EINVAL, "index is NULL");
   const Index& ix = index->ix;
-  if (codes != HNTL_CODES_BF16 && codes != HNTL_CODES_FP8_E4M3) return fail(HNTL_EINVAL, "codes must be BF16 or FP8");
+  if (codes != HNTL_CODES_BF16 && codes != HNTL_CODES_FP8_E4M3 && codes != HNTL_CODES_INT16)
+    return fail(HNTL_EINVAL, "codes must be BF16, FP8 or INT16");
   if (!(ix.codes_mask & (1u << codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
   return guarded([&] {
     const uint32_t G = ix.G, r = ix.r, rp = ix.rp;
     if (scales && codes == HNTL_CODES_FP8_E4M3)
       HIP_TRY(hipMemcpy(scales, ix.scales, sizeof(float) * G, hipMemcpyDefault));
+    if (scales && codes == HNTL_CODES_INT16) {  // inv_g
+      auto st = to_host(ix.i16_steps, (size_t)G * 4);
+      std::vector<float> inv(G);
+      for (uint32_t g = 0; g < G; ++g) inv[g] = st[(size_t)g * 4];
+      HIP_TRY(hipMemcpy(scales, inv.data(), sizeof(float) * G, hipMemcpyDefault));
+    }
     if (!out) return;
-    const int per = codes == HNTL_CODES_BF16 ? 2 : 4;  // values per 32-bit word
-    auto words = to_host(codes == HNTL_CODES_BF16 ? ix.codes_bf16 : ix.codes_fp8, (size_t)ix.nblocks * (rp / per) * B);
-    const size_t esz = codes == HNTL_CODES_BF16 ? 2 : 1;
+    const int per = codes == HNTL_CODES_FP8_E4M3 ? 4 : 2;  // values per 32-bit word
+    auto words = to_host(codes == HNTL_CODES_BF16 ? ix.codes_bf16 : codes == HNTL_CODES_INT16 ? ix.codes_i16 : ix.codes_fp8,
+                         (size_t)ix.nblocks * (rp / per) * B);
+    const size_t esz = per == 2 ? 2 : 1;
     std::vector<uint8_t> o((size_t)ix.N * r * esz);
     for (uint32_t g = 0; g < G; ++g) {
       const int64_t a = ix.offsets_h[g], n = ix.offsets_h[g + 1] - a;
@@ -382,7 +390,9 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
   if (P > HNTL_MAX_P) return fail(HNTL_EUNSUPPORTED, "P exceeds HNTL_MAX_P");
   if (k < 1 || C < k) return fail(HNTL_EINVAL, "need 1 <= k <= C");
   if (C > HNTL_MAX_C) return fail(HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C");
-  if (sp->codes > HNTL_CODES_FP8_E4M3) return fail(HNTL_EINVAL, "unknown codes form");
+  if (sp->codes > HNTL_CODES_INT16) return fail(HNTL_EINVAL, "unknown codes form");
+  if (sp->codes == HNTL_CODES_INT16 && (sp->flags & HNTL_FLAG_MODE_A))
+    return fail(HNTL_EUNSUPPORTED, "Mode A answers use the FP32 / BF16 / FP8 code forms");
   if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
   if ((tangent_in == nullptr) != (epsq_in == nullptr)) return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
   if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");

@@ -794,7 +794,8 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
     plog("covariance, eigensolve, codes");
     launch_grain_bounds(*ix, s);
     ix->codes_mask = 1u;
-    const uint32_t want = params->codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3));
+    const uint32_t want =
+        params->codes_mask & ((1u << HNTL_CODES_BF16) | (1u << HNTL_CODES_FP8_E4M3) | (1u << HNTL_CODES_INT16));
     if (want) {
       ix->codes_mask |= want;
       launch_derive_lowp(*ix, s);

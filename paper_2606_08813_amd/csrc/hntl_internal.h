@@ -71,6 +71,9 @@ struct Index {
   uint32_t* codes_bf16 = nullptr;  // nblocks x (rp / 2) x B words, 2 bf16 per word
   uint32_t* codes_fp8 = nullptr;   // nblocks x (rp / 4) x B words, 4 e4m3fn per word
   float* scales = nullptr;         // G fp8 scales
+  uint32_t* codes_i16 = nullptr;   // nblocks x (rp / 2) x B words, 2 int16 per word (eq. 5 codes)
+  float* i16_steps = nullptr;      // G x 4: inv_g, rinv_g, (1 / inv_g)^2, 1 / rinv_g
+  float* eps_i16 = nullptr;        // nblocks x B: r_hat_i / rinv_g (0 past a grain's members)
   uint16_t* basis_bf16 = nullptr;  // G x r x d (bf16 bits)
   float* X = nullptr;          // N x d, original row order
   float* blo = nullptr;        // G x rp: per-grain minimum of each code coordinate

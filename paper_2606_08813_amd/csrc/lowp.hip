@@ -11,8 +11,8 @@
 // FP8 E4M3 "fn" (OCP 8-bit float specification): bias 7, 3 mantissa bits,
 // largest finite 448, no infinities.  Code = e4m3(z / s_g) rounded to nearest
 // even with saturation to +-448, s_g = amax_{i in g, j < r} |z_ij| / 448
-// (1 for an all-zero grain).  The paper's own reduced form is int16 with a
-// per-grain step (eq. 5); these are its MI355X counterparts.
+// (1 for an all-zero grain).  INT16 (the paper's own reduced form, eq. 5):
+// two int16 codes per word as BF16, per-grain steps, decoded member residuals.
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -105,6 +105,71 @@ __global__ void fp8_pack_kernel(const float* __restrict__ codes, int rp, const i
   out[i] = w;
 }
 
+// int16 form (eq. 5), one workgroup per grain: inv_g = fl32(32767 / amax_g)
+// over |z_ij| (j < r), rinv_g = fl32(65535 / max_i eps_i) (1 when the maximum
+// is 0), computed as float64 divisions rounded once; also (1 / inv_g)^2 and
+// 1 / rinv_g for the score.
+__global__ __launch_bounds__(256) void int16_steps_kernel(const float* __restrict__ codes, const float* __restrict__ eps,
+                                                          int rp, int r, const int32_t* __restrict__ goff,
+                                                          const int32_t* __restrict__ boff, float* __restrict__ steps) {
+  __shared__ float red[2][256];
+  const int g = blockIdx.x;
+  const int b0 = boff[g], nb = boff[g + 1] - b0, ng = goff[g + 1] - goff[g];
+  float m = 0.f, em = 0.f;
+  for (int64_t e = threadIdx.x; e < (int64_t)nb * rp * B; e += 256) {
+    const int blk = (int)(e / (rp * B)), rem = (int)(e % (rp * B)), j = rem / B, lane = rem % B;
+    if (j < r && blk * B + lane < ng) m = fmaxf(m, fabsf(codes[(size_t)(b0 + blk) * rp * B + rem]));
+  }
+  for (int i = threadIdx.x; i < ng; i += 256) em = fmaxf(em, eps[((size_t)b0 + i / B) * B + i % B]);
+  red[0][threadIdx.x] = m;
+  red[1][threadIdx.x] = em;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = fmaxf(red[0][threadIdx.x], red[0][threadIdx.x + o]);
+      red[1][threadIdx.x] = fmaxf(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float inv = red[0][0] > 0.f ? (float)(32767.0 / (double)red[0][0]) : 1.f;
+    const float rinv = red[1][0] > 0.f ? (float)(65535.0 / (double)red[1][0]) : 1.f;
+    const double st = 1.0 / (double)inv;
+    steps[(size_t)g * 4] = inv;
+    steps[(size_t)g * 4 + 1] = rinv;
+    steps[(size_t)g * 4 + 2] = (float)(st * st);
+    steps[(size_t)g * 4 + 3] = (float)(1.0 / (double)rinv);
+  }
+}
+
+__device__ __forceinline__ int q16(float x, float inv, int lo, int hi) {
+  const float q = rintf(x * inv);  // float32 product, ties to even
+  return (int)fminf(fmaxf(q, (float)lo), (float)hi);
+}
+
+// codes [blk][rp][64] f32 -> words [blk][rp / 2][64] of two int16; residuals
+// decoded as r_hat / rinv (0 past the grain's members)
+__global__ void int16_pack_kernel(const float* __restrict__ codes, const float* __restrict__ eps, int rp,
+                                  const int32_t* __restrict__ block_grain, const int32_t* __restrict__ goff,
+                                  const int32_t* __restrict__ boff, const float* __restrict__ steps, int64_t nblocks,
+                                  uint32_t* __restrict__ out, float* __restrict__ eps_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)(rp / 2) * B;
+  if (i >= nblocks * per) return;
+  const int64_t blk = i / per, rem = i % per, j2 = rem / B, lane = rem % B;
+  const int g = block_grain[blk];
+  const float inv = steps[(size_t)g * 4];
+  const float* c = codes + (size_t)blk * rp * B;
+  const uint32_t lo = (uint16_t)(int16_t)q16(c[(2 * j2) * B + lane], inv, -32767, 32767);
+  const uint32_t hi = (uint16_t)(int16_t)q16(c[(2 * j2 + 1) * B + lane], inv, -32767, 32767);
+  out[i] = lo | (hi << 16);
+  if (j2 == 0) {
+    const bool valid = (blk - boff[g]) * B + lane < goff[g + 1] - goff[g];
+    const float rh = (float)q16(eps[blk * B + lane], steps[(size_t)g * 4 + 1], 0, 65535);
+    eps_out[blk * B + lane] = valid ? rh * steps[(size_t)g * 4 + 3] : 0.f;
+  }
+}
+
 }  // namespace
 
 void launch_derive_lowp(Index& ix, hipStream_t s) {
@@ -116,20 +181,35 @@ void launch_derive_lowp(Index& ix, hipStream_t s) {
                        (int64_t)ix.nblocks, ix.codes_bf16);
     HIP_TRY(hipGetLastError());
   }
-  if (ix.codes_mask & (1u << HNTL_CODES_FP8_E4M3)) {
-    if (!ix.scales) ix.scales = dev_alloc<float>(&ix, ix.G);
-    if (!ix.codes_fp8) ix.codes_fp8 = dev_alloc<uint32_t>(&ix, nw4);
-    hipLaunchKernelGGL(grain_scale_kernel, dim3(ix.G), dim3(256), 0, s, ix.codes, (int)ix.rp, (int)ix.r, ix.goff,
-                       ix.boff, ix.scales);
+  const bool fp8 = (ix.codes_mask & (1u << HNTL_CODES_FP8_E4M3)) != 0;
+  const bool i16 = (ix.codes_mask & (1u << HNTL_CODES_INT16)) != 0;
+  if (fp8 || i16) {
     std::vector<int32_t> bg(ix.nblocks);
     for (uint32_t g = 0; g < ix.G; ++g)
       for (int q = ix.boff_h[g]; q < ix.boff_h[g + 1]; ++q) bg[q] = (int32_t)g;
     int32_t* d_bg = nullptr;
     HIP_TRY(hipMalloc((void**)&d_bg, sizeof(int32_t) * std::max<size_t>(1, bg.size())));
     HIP_TRY(hipMemcpy(d_bg, bg.data(), sizeof(int32_t) * bg.size(), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(fp8_pack_kernel, dim3((unsigned)((nw4 + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp,
-                       d_bg, ix.scales, (int64_t)ix.nblocks, ix.codes_fp8);
-    HIP_TRY(hipGetLastError());
+    if (fp8) {
+      if (!ix.scales) ix.scales = dev_alloc<float>(&ix, ix.G);
+      if (!ix.codes_fp8) ix.codes_fp8 = dev_alloc<uint32_t>(&ix, nw4);
+      hipLaunchKernelGGL(grain_scale_kernel, dim3(ix.G), dim3(256), 0, s, ix.codes, (int)ix.rp, (int)ix.r, ix.goff,
+                         ix.boff, ix.scales);
+      hipLaunchKernelGGL(fp8_pack_kernel, dim3((unsigned)((nw4 + 255) / 256)), dim3(256), 0, s, ix.codes, (int)ix.rp,
+                         d_bg, ix.scales, (int64_t)ix.nblocks, ix.codes_fp8);
+      HIP_TRY(hipGetLastError());
+    }
+    if (i16) {
+      if (!ix.i16_steps) ix.i16_steps = dev_alloc<float>(&ix, (size_t)ix.G * 4);
+      if (!ix.codes_i16) ix.codes_i16 = dev_alloc<uint32_t>(&ix, nw2);
+      if (!ix.eps_i16) ix.eps_i16 = dev_alloc<float>(&ix, (size_t)ix.nblocks * B);
+      hipLaunchKernelGGL(int16_steps_kernel, dim3(ix.G), dim3(256), 0, s, ix.codes, ix.eps, (int)ix.rp, (int)ix.r,
+                         ix.goff, ix.boff, ix.i16_steps);
+      hipLaunchKernelGGL(int16_pack_kernel, dim3((unsigned)((nw2 + 255) / 256)), dim3(256), 0, s, ix.codes, ix.eps,
+                         (int)ix.rp, d_bg, ix.goff, ix.boff, ix.i16_steps, (int64_t)ix.nblocks, ix.codes_i16,
+                         ix.eps_i16);
+      HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipFree(d_bg));
   }

@@ -355,7 +355,8 @@ void check_plan_shape(const Index& ix, const hntl_search_params& sp) {
   if (sp.P > HNTL_MAX_P) throw ArgError{HNTL_EUNSUPPORTED, "P exceeds HNTL_MAX_P"};
   if (sp.k < 1 || sp.C < sp.k) throw ArgError{HNTL_EINVAL, "need 1 <= k <= C"};
   if (sp.C > HNTL_MAX_C) throw ArgError{HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C"};
-  if (sp.codes > HNTL_CODES_FP8_E4M3) throw ArgError{HNTL_EINVAL, "unknown codes form"};
+  if (sp.codes > HNTL_CODES_INT16) throw ArgError{HNTL_EINVAL, "unknown codes form"};
+  if (sp.codes == HNTL_CODES_INT16) throw ArgError{HNTL_EUNSUPPORTED, "plans run the FP32, BF16 and FP8 code forms"};
   if (!(ix.codes_mask & (1u << sp.codes))) throw ArgError{HNTL_ESTATE, "codes form not built for this index"};
   if ((sp.flags & HNTL_FLAG_PROJECT_BF16) && !ix.basis_bf16)
     throw ArgError{HNTL_ESTATE, "BF16 projection needs the BF16 basis (build a reduced-precision code form)"};

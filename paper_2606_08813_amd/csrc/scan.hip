@@ -11,6 +11,8 @@ void launch_scan_ct1(const Index&, const float*, const float*, int, int, const B
                      const uint64_t*, bool, unsigned long long*, hipStream_t);
 void launch_scan_ct2(const Index&, const float*, const float*, int, int, const Buckets&, int, uint64_t*,
                      const uint64_t*, bool, unsigned long long*, hipStream_t);
+void launch_scan_ct3(const Index&, const float*, const float*, int, int, const Buckets&, int, uint64_t*,
+                     const uint64_t*, bool, unsigned long long*, hipStream_t);
 
 namespace {
 
@@ -67,8 +69,10 @@ void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, 
     launch_scan_ct0(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
   else if (codes == HNTL_CODES_BF16)
     launch_scan_ct1(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
-  else
+  else if (codes == HNTL_CODES_FP8_E4M3)
     launch_scan_ct2(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
+  else
+    launch_scan_ct3(ix, T, epsq, P, C, b, list, part, bound_lists, prune, scored, s);
   HIP_TRY(hipGetLastError());
 }
 

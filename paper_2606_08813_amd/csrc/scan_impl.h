@@ -51,6 +51,14 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
       c[2 * j] = __uint_as_float(w << 16);
       c[2 * j + 1] = __uint_as_float(w & 0xFFFF0000u);
     }
+  } else if constexpr (CT == 3) {
+    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
+#pragma unroll
+    for (int j = 0; j < RP / 2; ++j) {
+      const uint32_t w = ldg(wb + j * B + lane);
+      c[2 * j] = (float)(int16_t)(w & 0xFFFFu);
+      c[2 * j + 1] = (float)(int16_t)(w >> 16);
+    }
   } else {
     const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 4) * B;
 #pragma unroll
@@ -105,18 +113,35 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
   }
   if (lane < QT) eq[lane] = lane < cnt ? epsq[pairs[lane]] : 0.f;
   wave_sync();
+  // int16 form: the query coordinates quantised with the grain's step (float32
+  // product, ties to even, clamped to +-32767), counting saturated ones
+  int nsat[QT];
+  float d2 = 1.f;
+  if constexpr (CT == 3) {
+    const float inv = scales[(size_t)g * 4];
+    d2 = scales[(size_t)g * 4 + 2];
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      const float q = rintf((lane < r ? zq[t][lane] : 0.f) * inv);
+      const bool sat = lane < r && fabsf(q) > 32767.f;
+      nsat[t] = __popcll(__ballot(sat));
+      if (lane < r) zq[t][lane] = fminf(fmaxf(q, -32767.f), 32767.f);
+    }
+    wave_sync();
+  }
 
   List L[QT];
   bool live[QT];
   int nlive = 0;
   const float sg = CT == 2 ? scales[g] : 1.f;
+  prune = CT == 3 ? 0 : prune;  // the box lives in float code space, not in the int16 one
   // this lane's coordinate of the grain's code bounding box (lanes >= r idle),
   // widened by the largest rounding error of the code form so that it holds
   // the decoded values the scan uses: BF16 half-ulp 2^-9 relative; FP8 E4M3
   // half-ulp 2^-4 relative plus the subnormal quantum 2^-10 s_g
   float lo = (bound_lists && prune && lane < r) ? blo[(size_t)g * RP + lane] : 0.f;
   float hi = (bound_lists && prune && lane < r) ? bhi[(size_t)g * RP + lane] : 0.f;
-  if (CT != 0) {
+  if (CT == 1 || CT == 2) {
     const float amax = fmaxf(fabsf(lo), fabsf(hi));
     const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
     lo -= 1.0001f * w;
@@ -126,6 +151,14 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
   for (int t = 0; t < QT; ++t) {
     uint64_t bnd = KEY_NONE;
     live[t] = t < cnt;
+    if constexpr (CT == 3) {
+      // quantisation envelope filter (Section 2.3): more than a quarter of the
+      // coordinates saturated -> the grain is pruned for this query
+      if (live[t] && 4 * nsat[t] > r) {
+        live[t] = false;
+        if (lane == 0) part[(size_t)pairs[t] * C] = KEY_NONE;  // empty list
+      }
+    }
     if (live[t] && bound_lists) {
       const int p = pairs[t];
       bnd = bound_lists[((size_t)(p / P) * P) * C + C - 1];  // C-th key of the query's probe-0 list
@@ -161,13 +194,24 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
 #pragma unroll
       for (int t = 0; t < QT; ++t) {
         if (live[t]) {
-          float acc = 0.f;
+          if constexpr (CT == 3) {
+            // integer differences (|d| <= 65534) squared and summed exactly in float64
+            double acc = 0.0;
 #pragma unroll
-          for (int j = 0; j < RP; ++j) {
-            const float df = zq[t][j] - c[j];
-            acc = fmaf(df, df, acc);
+            for (int j = 0; j < RP; ++j) {
+              const double df = (double)(zq[t][j] - c[j]);
+              acc = fma(df, df, acc);
+            }
+            L[t].offer(make_key(fmaf((float)acc, d2, ei + eq[t]), pos), valid);
+          } else {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < RP; ++j) {
+              const float df = zq[t][j] - c[j];
+              acc = fmaf(df, df, acc);
+            }
+            L[t].offer(make_key(acc + eq[t] + ei, pos), valid);
           }
-          L[t].offer(make_key(acc + eq[t] + ei, pos), valid);
         }
       }
     }
@@ -194,16 +238,21 @@ void launch_rp_cap(const Index& ix, const float* T, const float* epsq, int P, in
   // waves in flight; bounded lists insert rarely: 16 pairs share every code load
   constexpr int QT_WIDE = CAP <= 128 ? 16 : 8;
   const dim3 grid((unsigned)b.max_items[list]);
-  const void* codes = CT == 0 ? (const void*)ix.codes : CT == 1 ? (const void*)ix.codes_bf16 : (const void*)ix.codes_fp8;
+  const void* codes = CT == 0 ? (const void*)ix.codes
+                    : CT == 1 ? (const void*)ix.codes_bf16
+                    : CT == 2 ? (const void*)ix.codes_fp8
+                              : (const void*)ix.codes_i16;
+  const float* scales = CT == 3 ? ix.i16_steps : ix.scales;
+  const float* eps = CT == 3 ? ix.eps_i16 : ix.eps;
   const ItemLists& Ls = b.lists;
   if (bound_lists == nullptr)
-    hipLaunchKernelGGL((scan_f32_kernel<RP, CAP, 4, CT>), grid, dim3(64 * (ITEM / 4)), 0, s, codes, ix.scales, ix.eps,
+    hipLaunchKernelGGL((scan_f32_kernel<RP, CAP, 4, CT>), grid, dim3(64 * (ITEM / 4)), 0, s, codes, scales, eps,
                        ix.goff,
                        ix.boff, ix.perm, (int)ix.r, T, epsq, P, C, Ls.ioff[list], Ls.lstart[list], Ls.lcount[list],
                        (int)ix.G, b.order, part, bound_lists, prune ? 1 : 0, ix.blo, ix.bhi, ix.emin, scored);
   else
     hipLaunchKernelGGL((scan_f32_kernel<RP, CAP, QT_WIDE, CT>), grid, dim3(64 * (ITEM / QT_WIDE)), 0, s, codes,
-                       ix.scales, ix.eps, ix.goff, ix.boff, ix.perm, (int)ix.r, T, epsq, P, C, Ls.ioff[list], Ls.lstart[list],
+                       scales, eps, ix.goff, ix.boff, ix.perm, (int)ix.r, T, epsq, P, C, Ls.ioff[list], Ls.lstart[list],
                        Ls.lcount[list], (int)ix.G, b.order, part, bound_lists, prune ? 1 : 0, ix.blo, ix.bhi, ix.emin, scored);
 }
 

@@ -18,7 +18,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 
 HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
-HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3 = 0, 1, 2
+HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3, HNTL_CODES_INT16 = 0, 1, 2, 3
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
 HNTL_FLAG_ROUTE_BF16X3 = 32
 HNTL_FLAG_MODE_A = 64
@@ -27,7 +27,7 @@ HNTL_ROUTER_KEEP_WEIGHTS, HNTL_ROUTER_NO_SHUFFLE = 1, 2
 ROUTES = {"centroid": HNTL_ROUTE_CENTROID, "learned": HNTL_ROUTE_LEARNED}
 STAGES = ("route", "bucket", "project", "scan", "rerank")
 HNTL_MAX_R, HNTL_MAX_C, HNTL_MAX_P, HNTL_BLOCK = 64, 256, 48, 64
-CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3}
+CODES = {"fp32": HNTL_CODES_FP32, "bf16": HNTL_CODES_BF16, "fp8": HNTL_CODES_FP8_E4M3, "int16": HNTL_CODES_INT16}
 
 
 class hntl_build_params(C.Structure):
@@ -239,7 +239,13 @@ def hntl_index_export(index: Index, with_scales=False) -> dict:
 
 
 def hntl_index_export_codes(index: Index, codes: str):
-    """Reduced-precision codes (N x r bit patterns, grain order) and, for FP8, the per-grain scales."""
+    """Reduced-precision codes (N x r bit patterns, grain order) and, for FP8, the
+    per-grain scales; for int16, the signed codes and the per-grain inv_g."""
+    if codes == "int16":
+        out = np.empty((index.N, index.r), np.int16)
+        sc = np.empty(index.G, np.float32)
+        _check(lib().hntl_index_export_codes(index.handle, HNTL_CODES_INT16, out.ctypes.data, sc.ctypes.data))
+        return out, sc
     if codes == "bf16":
         out = np.empty((index.N, index.r), np.uint16)
         _check(lib().hntl_index_export_codes(index.handle, HNTL_CODES_BF16, out.ctypes.data, None))
