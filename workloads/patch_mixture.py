@@ -190,6 +190,19 @@ def zipf_queries(nq: int, d: int, sizes: np.ndarray, data_seed: int, query_seed:
     return Mixture(Q, labels, len(sizes), query_seed)
 
 
+BYTE_SCALE = 32.0
+BYTE_OFFSET = 24.0
+
+
+def byte_valued(m: Mixture) -> Mixture:
+    """A SIFT1M-shaped stand-in: the mixture mapped affinely to non-negative
+    byte values, x -> clip(rint(32 x + 24), 0, 255), stored as float32 (about
+    a quarter of the components clip at 0, as in gradient-histogram
+    descriptors)."""
+    X = np.clip(np.rint(m.X * BYTE_SCALE + BYTE_OFFSET), 0.0, 255.0).astype(np.float32)
+    return Mixture(X, m.labels, m.n_patches, m.seed)
+
+
 def isotropic(n: int, d: int, seed: int) -> np.ndarray:
     """Isotropic standard Gaussian rows (the isotropic data set of the paper's
     recall table)."""
