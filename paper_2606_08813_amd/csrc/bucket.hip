@@ -19,7 +19,7 @@ namespace hntl {
 namespace {
 
 constexpr int CHUNK = 4096;      // pairs per workgroup
-constexpr int LDS_MAX_G = 8192;  // grain counters kept in LDS up to this G
+constexpr int LDS_MAX_G = 8192;  // grain counters kept in LDS up to this G (scatter: 4 G ints = 128 KiB)
 
 __device__ __forceinline__ int probe_of(const int32_t* __restrict__ probes, int64_t p, int G) {
   const int g = probes[p];
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void bucket_scatter_kernel(const int32_t* __re
                                                              int32_t* __restrict__ cur0, int32_t* __restrict__ cur1,
                                                              int32_t* __restrict__ order) {
   extern __shared__ int lds_mem[];
-  const bool lds = G <= LDS_MAX_G / 2;
+  const bool lds = G <= LDS_MAX_G;
   const int64_t p0 = (int64_t)blockIdx.x * CHUNK;
   if (!lds) {
     for (int u = threadIdx.x; u < CHUNK; u += 256) {
@@ -412,8 +412,15 @@ void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, 
                      b.cur0, b.cur1, b.lists);
   HIP_TRY(hipGetLastError());
   if (npairs > 0) {
-    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), G <= LDS_MAX_G / 2 ? 4 * G * sizeof(int) : 0, s,
-                       probes, npairs, P, G, b.gstart, b.gcount0, b.cur0, b.cur1, b.order);
+    const size_t lds = G <= LDS_MAX_G ? 4 * (size_t)G * sizeof(int) : 0;
+    static bool lds_set = false;  // up to 128 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
+    if (!lds_set) {
+      HIP_TRY(hipFuncSetAttribute((const void*)bucket_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(4 * LDS_MAX_G * sizeof(int))));
+      lds_set = true;
+    }
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), lds, s, probes, npairs, P, G, b.gstart, b.gcount0,
+                       b.cur0, b.cur1, b.order);
     HIP_TRY(hipGetLastError());
   }
 }
