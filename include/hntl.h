@@ -154,6 +154,40 @@ hntl_status hntl_index_create(uint64_t N, uint32_t d, uint32_t G, uint32_t r, co
                               const float* codes, const float* eps, const float* X, uint32_t codes_mask,
                               hntl_index** out);
 
+/* Parameters of hntl_index_append (NULL = all defaults). */
+typedef struct hntl_append_params {
+  uint32_t split_max;         /* grains above this many members after the append are split (0 = never) */
+  uint32_t eig_iters;         /* subspace iterations for the split grains' bases (0 = default 40) */
+  uint64_t seed;              /* seed of the eigensolver's start vectors */
+} hntl_append_params;
+
+/*
+ * hntl_index_append - a new index holding the rows of `base` plus n new rows
+ * (Section 1 and the segment layer of Section 2 with Fig. 1: grains are
+ * self-contained, so appending touches no other grain and no existing code).
+ * `base` is not modified (an immutable segment); the result is independent of
+ * it and both are freed separately.
+ *   X       n x d float32 row-major, host or device; the new rows get ids
+ *           N .. N + n - 1.  Copied.  n = 0 gives a copy of base.
+ * Each new row joins the grain of its nearest centroid (FP32 distances, ties
+ * to the lower grain) and is encoded by eq. 1-4 with that grain's stored
+ * centroid and basis (FP64 arithmetic from the stored FP32 values); the
+ * centroids, bases and codes of existing members are kept bit for bit.  With
+ * split_max > 0, a grain holding more than split_max members is cut into
+ * m = ceil(n_g / split_max) children: members ordered by their stored FP32
+ * first code coordinate (ties by id) and cut into m runs whose sizes differ by
+ * at most one; child 0 keeps the grain's number, children 1 .. m-1 get the
+ * numbers G, G + 1, ... in ascending order of the grains split; every child
+ * gets the exact FP64 mean of its members as centroid, its own local PCA basis
+ * (as in hntl_build) and new codes.  The result holds the base's code forms
+ * (codes_mask) and no learned router (train or import one again).
+ * Synchronous.  Errors: EINVAL (null base/out, X NULL with n > 0),
+ * EUNSUPPORTED (N + n >= 2^31; split_max > 0 on an index without raw
+ * vectors), ENOMEM, EDEVICE.
+ */
+hntl_status hntl_index_append(const hntl_index* base, const float* X, uint64_t n,
+                              const hntl_append_params* params, void* stream, hntl_index** out);
+
 /*
  * hntl_index_export - copy the stored-format arrays out of an index.  Any pointer may
  * be NULL to skip that array; all are host or device, sized as in hntl_index_create.

@@ -20,8 +20,9 @@ hntl_status fail(hntl_status s, const std::string& msg) {
 }
 
 Index::~Index() {
-  void* ptrs[] = {centroids, cnorm, basis, goff, boff, perm, codes, eps, codes_bf16, codes_fp8, scales, basis_bf16, X,
-                  blo, bhi, emin, gorder};
+  void* ptrs[] = {centroids, cnorm,    basis,   goff,      boff,     perm,       codes,  eps,
+                  codes_bf16, codes_fp8, scales, basis_bf16, codes_i16, i16_steps, eps_i16, X,
+                  blo,       bhi,       emin,   gorder,     cent_split, eps_id};
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);

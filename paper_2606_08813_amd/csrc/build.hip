@@ -209,8 +209,9 @@ __global__ __launch_bounds__(64) void kpp_sample_kernel(int64_t n, const float* 
 __global__ __launch_bounds__(256) void segmented_mean_kernel(const float* __restrict__ Xs, int d,
                                                              const int32_t* __restrict__ order,
                                                              const int64_t* __restrict__ off,
+                                                             const int* __restrict__ gmap,
                                                              float* __restrict__ cent) {
-  const int g = blockIdx.x;
+  const int g = gmap ? gmap[blockIdx.x] : (int)blockIdx.x;
   const int j = blockIdx.y * 256 + threadIdx.x;
   if (j >= d) return;
   const int64_t a = off[g], b = off[g + 1];
@@ -220,17 +221,18 @@ __global__ __launch_bounds__(256) void segmented_mean_kernel(const float* __rest
   cent[(size_t)g * d + j] = (float)(s / (double)(b - a));
 }
 
-// Grouped FP64 covariance of a chunk of grains.  grid (tile pair index, grain
-// in chunk); 64x64 output tile per workgroup, 4x4 per thread; both the tile
+// Grouped FP64 covariance of a chunk of grains (grain gmap[i] for chunk
+// slot i).  grid (tile pair index, slot in chunk); 64x64 output tile per workgroup, 4x4 per thread; both the tile
 // and its transpose are written.
 constexpr int CT = 64, CK = 16;
 __global__ __launch_bounds__(256) void covariance_kernel(const float* __restrict__ X, int d,
                                                          const int32_t* __restrict__ perm,
                                                          const int64_t* __restrict__ off, const float* __restrict__ mu,
-                                                         int g0, double* __restrict__ S, const int* __restrict__ tiles) {
+                                                         const int* __restrict__ gmap, double* __restrict__ S,
+                                                         const int* __restrict__ tiles) {
   __shared__ double Xi[CK][CT + 1];
   __shared__ double Xj[CK][CT + 1];
-  const int gl = blockIdx.y, g = g0 + gl;
+  const int gl = blockIdx.y, g = gmap[gl];
   const int ti = tiles[2 * blockIdx.x], tj = tiles[2 * blockIdx.x + 1];
   const int i0 = ti * CT, j0 = tj * CT;
   const int64_t a = off[g], n = off[g + 1] - off[g];
@@ -307,10 +309,11 @@ __global__ void randn_kernel(double* __restrict__ V, int64_t n, uint64_t seed, u
 }
 
 // Top-r Ritz vectors (columns b-1, b-2, ... of Wf, column-major d x b) ->
-// sign-fixed FP64 rows Wd[g][j][:] and FP32 basis rows.  grid (r, chunk).
+// sign-fixed FP64 rows Wd[slot][j][:] and FP32 basis rows of grain gmap[slot].
+// grid (r, chunk).
 __global__ __launch_bounds__(256) void extract_basis_kernel(const double* __restrict__ Wf, int d, int b, int r,
                                                             double* __restrict__ Wd, float* __restrict__ basis,
-                                                            int g0) {
+                                                            const int* __restrict__ gmap) {
   __shared__ double bv[256];
   __shared__ int bi[256];
   const int j = blockIdx.x, gl = blockIdx.y;
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(256) void extract_basis_kernel(const double* __rest
   }
   const double sgn = col[bi[0]] < 0.0 ? -1.0 : 1.0;
   double* wd = Wd + ((size_t)gl * r + j) * d;
-  float* bs = basis + ((size_t)(g0 + gl) * r + j) * d;
+  float* bs = basis + ((size_t)gmap[gl] * r + j) * d;
   for (int i = threadIdx.x; i < d; i += 256) {
     const double v = sgn * col[i];
     wd[i] = v;
@@ -350,25 +353,26 @@ __global__ __launch_bounds__(256) void extract_basis_kernel(const double* __rest
 
 // Codes of one Block-SoA block: z = W_g^T (x - mu_g) and eps = ||x'||^2 - ||z||^2
 // in FP64.  256 threads: member m = t & 63, coordinates j = (t >> 6) + 4u.
+// blk_desc holds (grain, chunk slot of its FP64 basis, block of the grain)
+// per workgroup; the block is written at boff[grain] + block.
 constexpr int EK = 32;
 __global__ __launch_bounds__(256) void encode_kernel(const float* __restrict__ X, int d, int r, int rp,
                                                      const int32_t* __restrict__ perm,
                                                      const int64_t* __restrict__ off, const float* __restrict__ mu,
-                                                     const double* __restrict__ Wd, const int* __restrict__ blk_grain,
-                                                     const int* __restrict__ blk_index, int g0, int blk0,
+                                                     const double* __restrict__ Wd, const int* __restrict__ blk_desc,
                                                      const int32_t* __restrict__ boff, float* __restrict__ codes,
                                                      float* __restrict__ eps) {
   __shared__ double xs[HNTL_WAVE][EK + 1];
   __shared__ double ws[HNTL_MAX_R][EK + 1];
-  const int blk = blk0 + blockIdx.x;
-  const int g = blk_grain[blockIdx.x];
-  const int bi = blk_index[blockIdx.x];
+  const int g = blk_desc[3 * blockIdx.x], slot = blk_desc[3 * blockIdx.x + 1];
+  const int bi = blk_desc[3 * blockIdx.x + 2];
+  const int blk = boff[g] + bi;
   const int t = threadIdx.x, m = t & 63, jq = t >> 6;
   const int64_t a = off[g], n = off[g + 1] - off[g];
   const int64_t mem = (int64_t)bi * B + m;
   const bool valid = mem < n;
   const float* mug = mu + (size_t)g * d;
-  const double* W = Wd + (size_t)(g - g0) * r * d;
+  const double* W = Wd + (size_t)slot * r * d;
   double z[HNTL_MAX_R / 4];
 #pragma unroll
   for (int u = 0; u < HNTL_MAX_R / 4; ++u) z[u] = 0.0;
@@ -413,7 +417,6 @@ __global__ __launch_bounds__(256) void encode_kernel(const float* __restrict__ X
     const double tot = zpart[0][m] + zpart[1][m] + zpart[2][m] + zpart[3][m];
     eps[(size_t)blk * B + m] = valid ? (float)fmax(sq - tot, 0.0) : __builtin_inff();
   }
-  (void)boff;
 }
 
 // ---------------------------------------------------------------- host side
@@ -455,6 +458,161 @@ std::vector<int64_t> counting_sort(const std::vector<int32_t>& lab, int G, std::
 }
 
 }  // namespace
+
+// Local PCA of the grains in glist (FP64 covariance, subspace iteration on
+// S_g + delta_g I with Cholesky-QR2, Rayleigh-Ritz), their FP32 basis rows,
+// captured-variance fractions and the codes of every block they own.  Needs
+// ix->X, perm, centroids, boff / boff_h, basis, codes, eps and captured (G
+// entries) in place; d_off holds the G + 1 grain-order offsets on the device.
+// The start vectors of the chunk from list position p0 come from counter
+// stream stream_base + p0.
+void pca_encode_grains(Index* ix, const int64_t* d_off, const std::vector<int32_t>& glist, uint32_t eig_iters,
+                       uint64_t seed, uint64_t stream_base, hipStream_t s) {
+  const uint32_t d = ix->d, r = ix->r;
+  const int ng = (int)glist.size();
+  if (ng == 0) return;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } tmp;
+  Blas blas(s);
+  const int bsz = (int)std::min<uint32_t>(d, std::max<uint32_t>(r + 16, 2 * r));
+  const int GC = (int)std::max<int64_t>(1, std::min<int64_t>(ng, ((int64_t)1 << 30) / ((int64_t)d * d * 8)));
+  double* S = dev_alloc<double>(nullptr, (size_t)GC * d * d);
+  tmp.p.push_back(S);
+  double* V = dev_alloc<double>(nullptr, (size_t)GC * d * bsz);
+  tmp.p.push_back(V);
+  double* Y = dev_alloc<double>(nullptr, (size_t)GC * d * bsz);
+  tmp.p.push_back(Y);
+  double* M = dev_alloc<double>(nullptr, (size_t)GC * bsz * bsz);
+  tmp.p.push_back(M);
+  double* Wev = dev_alloc<double>(nullptr, (size_t)GC * bsz);
+  tmp.p.push_back(Wev);
+  double* res = dev_alloc<double>(nullptr, GC);
+  tmp.p.push_back(res);
+  int* nsw = dev_alloc<int>(nullptr, GC);
+  tmp.p.push_back(nsw);
+  int* info = dev_alloc<int>(nullptr, GC);
+  tmp.p.push_back(info);
+  double* trace = dev_alloc<double>(nullptr, GC);
+  tmp.p.push_back(trace);
+  double* delta = dev_alloc<double>(nullptr, GC);
+  tmp.p.push_back(delta);
+  double* Wd = dev_alloc<double>(nullptr, (size_t)GC * r * d);
+  tmp.p.push_back(Wd);
+  int* d_glist = dev_alloc<int>(nullptr, ng);
+  tmp.p.push_back(d_glist);
+  HIP_TRY(hipMemcpyAsync(d_glist, glist.data(), sizeof(int) * ng, hipMemcpyHostToDevice, s));
+  // upper-triangle tile list
+  const int nt = (int)((d + CT - 1) / CT);
+  std::vector<int> tiles;
+  for (int i = 0; i < nt; ++i)
+    for (int j = i; j < nt; ++j) {
+      tiles.push_back(i);
+      tiles.push_back(j);
+    }
+  int* d_tiles = dev_alloc<int>(nullptr, tiles.size());
+  tmp.p.push_back(d_tiles);
+  HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice, s));
+  // per-block work descriptors (grain, chunk slot, block of the grain), all chunks
+  int64_t nblk_all = 0;
+  for (int32_t g : glist) nblk_all += ix->boff_h[g + 1] - ix->boff_h[g];
+  int* d_desc = dev_alloc<int>(nullptr, (size_t)std::max<int64_t>(1, 3 * nblk_all));
+  tmp.p.push_back(d_desc);
+  std::vector<double> ev_h((size_t)GC * bsz), tr_h(GC), dl_h(GC);
+  std::vector<int> desc;
+  const double one = 1.0, zero = 0.0;
+  int64_t desc_pos = 0;
+  for (int p0 = 0; p0 < ng; p0 += GC) {
+    const int gc = std::min(GC, ng - p0);
+    const int* gmap = d_glist + p0;
+    hipLaunchKernelGGL(covariance_kernel, dim3((unsigned)(tiles.size() / 2), gc), dim3(256), 0, s, ix->X, (int)d,
+                       ix->perm, d_off, ix->centroids, gmap, S, d_tiles);
+    hipLaunchKernelGGL(shift_kernel, dim3(gc), dim3(256), 0, s, S, (int)d, trace, delta);
+    const int64_t nv = (int64_t)gc * d * bsz;
+    hipLaunchKernelGGL(randn_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, V, nv, seed,
+                       stream_base + (uint64_t)p0);
+    HIP_TRY(hipGetLastError());
+    const rocblas_stride sS = (rocblas_stride)d * d, sV = (rocblas_stride)d * bsz, sM = (rocblas_stride)bsz * bsz;
+    auto cholqr = [&](double* Yp) {
+      for (int rep = 0; rep < 2; ++rep) {
+        rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_transpose, rocblas_operation_none, bsz, bsz, (int)d,
+                                         &one, Yp, (int)d, sV, Yp, (int)d, sV, &zero, M, bsz, sM, gc),
+           "dgemm Y^T*Y");
+        rb(rocsolver_dpotrf_strided_batched(blas.h, rocblas_fill_upper, bsz, M, bsz, sM, info, gc), "dpotrf");
+        rb(rocblas_dtrsm_strided_batched(blas.h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                         rocblas_diagonal_non_unit, (int)d, bsz, &one, M, bsz, sM, Yp, (int)d, sV, gc),
+           "dtrsm");
+      }
+    };
+    cholqr(V);
+    for (uint32_t itx = 0; itx < eig_iters; ++itx) {
+      rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, (int)d,
+                                       &one, S, (int)d, sS, V, (int)d, sV, &zero, Y, (int)d, sV, gc),
+         "dgemm S*V");
+      cholqr(Y);
+      std::swap(V, Y);
+    }
+    // Rayleigh-Ritz: H = V^T S V, eigen-decomposed; W = V * U
+    rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, (int)d, &one,
+                                     S, (int)d, sS, V, (int)d, sV, &zero, Y, (int)d, sV, gc),
+       "dgemm S*V");
+    rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_transpose, rocblas_operation_none, bsz, bsz, (int)d,
+                                     &one, V, (int)d, sV, Y, (int)d, sV, &zero, M, bsz, sM, gc),
+       "dgemm V^T*Y");
+    rb(rocsolver_dsyevj_strided_batched(blas.h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
+                                        bsz, M, bsz, sM, 0.0, res, 100, nsw, Wev, bsz, info, gc),
+       "dsyevj");
+    rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, bsz, &one, V,
+                                     (int)d, sV, M, bsz, sM, &zero, Y, (int)d, sV, gc),
+       "dgemm V*U");
+    hipLaunchKernelGGL(extract_basis_kernel, dim3(r, gc), dim3(256), 0, s, Y, (int)d, bsz, (int)r, Wd, ix->basis,
+                       gmap);
+    HIP_TRY(hipGetLastError());
+    // codes of every block of the chunk's grains
+    desc.clear();
+    for (int gl = 0; gl < gc; ++gl) {
+      const int g = glist[p0 + gl];
+      for (int q = 0; q < ix->boff_h[g + 1] - ix->boff_h[g]; ++q) {
+        desc.push_back(g);
+        desc.push_back(gl);
+        desc.push_back(q);
+      }
+    }
+    const int nb = (int)(desc.size() / 3);
+    if (nb > 0) {
+      int* dd = d_desc + desc_pos;  // each chunk has its own range: no reuse while a copy is in flight
+      desc_pos += (int64_t)desc.size();
+      HIP_TRY(hipMemcpyAsync(dd, desc.data(), sizeof(int) * desc.size(), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(encode_kernel, dim3((unsigned)nb), dim3(256), 0, s, ix->X, (int)d, (int)r, (int)ix->rp,
+                         ix->perm, d_off, ix->centroids, Wd, dd, ix->boff, ix->codes, ix->eps);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(ev_h.data(), Wev, sizeof(double) * gc * bsz, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(tr_h.data(), trace, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(dl_h.data(), delta, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int gl = 0; gl < gc; ++gl)
+      for (int j = 0; j < bsz; ++j)
+        if (!std::isfinite(ev_h[(size_t)gl * bsz + j]))
+          throw HipError(hipErrorUnknown,
+                         "eigensolver produced a non-finite value for grain " + std::to_string(glist[p0 + gl]));
+    for (int gl = 0; gl < gc; ++gl) {
+      double top = 0.0;
+      for (uint32_t j = 0; j < r; ++j) top += ev_h[(size_t)gl * bsz + bsz - 1 - j] - dl_h[gl];
+      ix->captured[glist[p0 + gl]] = tr_h[gl] > 0 ? top / tr_h[gl] : 1.0;
+    }
+  }
+}
+
+void launch_segmented_mean(const float* X, int d, const int32_t* order, const int64_t* off, const int* gmap, int ng,
+                           float* cent, hipStream_t s) {
+  if (ng <= 0) return;
+  hipLaunchKernelGGL(segmented_mean_kernel, dim3(ng, (d + 255) / 256), dim3(256), 0, s, X, d, order, off, gmap, cent);
+  HIP_TRY(hipGetLastError());
+}
 
 }  // namespace hntl
 
@@ -597,7 +755,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       HIP_TRY(hipMemcpyAsync(d_order, order_h.data(), sizeof(int32_t) * n_train, hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(segmented_mean_kernel, dim3(G, (d + 255) / 256), dim3(256), 0, s, Xt, (int)d, d_order, d_off,
-                         ix->centroids);
+                         nullptr, ix->centroids);
       HIP_TRY(hipGetLastError());
       // re-seed empty grains with the farthest training rows
       std::vector<char> taken;
@@ -640,7 +798,7 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
       HIP_TRY(hipMemcpyAsync(ix->perm, perm_h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(d_off, ix->offsets_h.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(segmented_mean_kernel, dim3(G, (d + 255) / 256), dim3(256), 0, s, ix->X, (int)d, ix->perm,
-                         d_off, ix->centroids);
+                         d_off, nullptr, ix->centroids);
       HIP_TRY(hipGetLastError());
       launch_row_norms(ix->centroids, G, (int)d, ix->cnorm, s);
     }
@@ -670,126 +828,10 @@ extern "C" hntl_status hntl_build(const float* X, uint64_t N, uint32_t d, const 
 
     // ---------------- local PCA per grain chunk + codes
     {
-      Blas blas(s);
-      const int bsz = (int)std::min<uint32_t>(d, std::max<uint32_t>(r + 16, 2 * r));
-      const int GC = (int)std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 30) / ((int64_t)d * d * 8)));
-      double* S = dev_alloc<double>(nullptr, (size_t)GC * d * d);
-      double* V = dev_alloc<double>(nullptr, (size_t)GC * d * bsz);
-      double* Y = dev_alloc<double>(nullptr, (size_t)GC * d * bsz);
-      double* M = dev_alloc<double>(nullptr, (size_t)GC * bsz * bsz);
-      double* Wev = dev_alloc<double>(nullptr, (size_t)GC * bsz);
-      double* res = dev_alloc<double>(nullptr, GC);
-      int* nsw = dev_alloc<int>(nullptr, GC);
-      int* info = dev_alloc<int>(nullptr, GC);
-      double* trace = dev_alloc<double>(nullptr, GC);
-      double* delta = dev_alloc<double>(nullptr, GC);
-      double* Wd = dev_alloc<double>(nullptr, (size_t)GC * r * d);
-      tmp.p.insert(tmp.p.end(), {S, V, Y, M, Wev, res, nsw, info, trace, delta, Wd});
-      // upper-triangle tile list
-      const int nt = (int)((d + CT - 1) / CT);
-      std::vector<int> tiles;
-      for (int i = 0; i < nt; ++i)
-        for (int j = i; j < nt; ++j) {
-          tiles.push_back(i);
-          tiles.push_back(j);
-        }
-      int* d_tiles = dev_alloc<int>(nullptr, tiles.size());
-      tmp.p.push_back(d_tiles);
-      HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice, s));
+      std::vector<int32_t> all(G);
+      std::iota(all.begin(), all.end(), 0);
       ix->captured.assign(G, -1.0);
-      std::vector<double> ev_h((size_t)GC * bsz), tr_h(GC), dl_h(GC);
-      std::vector<int> info_h(GC);
-      const double one = 1.0, zero = 0.0;
-      for (uint32_t g0 = 0; g0 < G; g0 += GC) {
-        const int gc = (int)std::min<uint32_t>(GC, G - g0);
-        hipLaunchKernelGGL(covariance_kernel, dim3((unsigned)(tiles.size() / 2), gc), dim3(256), 0, s, ix->X, (int)d,
-                           ix->perm, d_off, ix->centroids, (int)g0, S, d_tiles);
-        hipLaunchKernelGGL(shift_kernel, dim3(gc), dim3(256), 0, s, S, (int)d, trace, delta);
-        const int64_t nv = (int64_t)gc * d * bsz;
-        hipLaunchKernelGGL(randn_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, V, nv, seed,
-                           (uint64_t)3 + g0);
-        HIP_TRY(hipGetLastError());
-        const rocblas_stride sS = (rocblas_stride)d * d, sV = (rocblas_stride)d * bsz, sM = (rocblas_stride)bsz * bsz;
-        auto cholqr = [&](double* Yp) {
-          for (int rep = 0; rep < 2; ++rep) {
-            rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_transpose, rocblas_operation_none, bsz, bsz,
-                                             (int)d, &one, Yp, (int)d, sV, Yp, (int)d, sV, &zero, M, bsz, sM, gc),
-               "dgemm Y^T*Y");
-            rb(rocsolver_dpotrf_strided_batched(blas.h, rocblas_fill_upper, bsz, M, bsz, sM, info, gc), "dpotrf");
-            rb(rocblas_dtrsm_strided_batched(blas.h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                             rocblas_diagonal_non_unit, (int)d, bsz, &one, M, bsz, sM, Yp, (int)d, sV,
-                                             gc),
-               "dtrsm");
-          }
-        };
-        cholqr(V);
-        for (uint32_t itx = 0; itx < eig_iters; ++itx) {
-          rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, (int)d,
-                                           &one, S, (int)d, sS, V, (int)d, sV, &zero, Y, (int)d, sV, gc),
-             "dgemm S*V");
-          cholqr(Y);
-          std::swap(V, Y);
-        }
-        // Rayleigh-Ritz: H = V^T S V, eigen-decomposed; W = V * U
-        rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, (int)d,
-                                         &one, S, (int)d, sS, V, (int)d, sV, &zero, Y, (int)d, sV, gc),
-           "dgemm S*V");
-        rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_transpose, rocblas_operation_none, bsz, bsz, (int)d,
-                                         &one, V, (int)d, sV, Y, (int)d, sV, &zero, M, bsz, sM, gc),
-           "dgemm V^T*Y");
-        rb(rocsolver_dsyevj_strided_batched(blas.h, rocblas_esort_ascending, rocblas_evect_original,
-                                            rocblas_fill_upper, bsz, M, bsz, sM, 0.0, res, 100, nsw, Wev, bsz, info,
-                                            gc),
-           "dsyevj");
-        rb(rocblas_dgemm_strided_batched(blas.h, rocblas_operation_none, rocblas_operation_none, (int)d, bsz, bsz,
-                                         &one, V, (int)d, sV, M, bsz, sM, &zero, Y, (int)d, sV, gc),
-           "dgemm V*U");
-        hipLaunchKernelGGL(extract_basis_kernel, dim3(r, gc), dim3(256), 0, s, Y, (int)d, bsz, (int)r, Wd, ix->basis,
-                           (int)g0);
-        HIP_TRY(hipGetLastError());
-        // codes of every block of the chunk's grains
-        const int blk_a = ix->boff_h[g0], blk_b = ix->boff_h[g0 + gc];
-        if (blk_b > blk_a) {
-          std::vector<int> bg(blk_b - blk_a), bidx(blk_b - blk_a);
-          for (int g = (int)g0; g < (int)g0 + gc; ++g)
-            for (int q = ix->boff_h[g]; q < ix->boff_h[g + 1]; ++q) {
-              bg[q - blk_a] = g;
-              bidx[q - blk_a] = q - ix->boff_h[g];
-            }
-          int* d_bg = nullptr;
-          int* d_bi = nullptr;
-          HIP_TRY(hipMallocAsync((void**)&d_bg, sizeof(int) * bg.size(), s));
-          HIP_TRY(hipMallocAsync((void**)&d_bi, sizeof(int) * bidx.size(), s));
-          HIP_TRY(hipMemcpyAsync(d_bg, bg.data(), sizeof(int) * bg.size(), hipMemcpyHostToDevice, s));
-          HIP_TRY(hipMemcpyAsync(d_bi, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice, s));
-          hipLaunchKernelGGL(encode_kernel, dim3((unsigned)bg.size()), dim3(256), 0, s, ix->X, (int)d, (int)r,
-                             (int)ix->rp, ix->perm, d_off, ix->centroids, Wd, d_bg, d_bi, (int)g0, blk_a, ix->boff,
-                             ix->codes, ix->eps);
-          HIP_TRY(hipGetLastError());
-          HIP_TRY(hipMemcpyAsync(ev_h.data(), Wev, sizeof(double) * gc * bsz, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipMemcpyAsync(tr_h.data(), trace, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipMemcpyAsync(dl_h.data(), delta, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipMemcpyAsync(info_h.data(), info, sizeof(int) * gc, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipStreamSynchronize(s));
-          (void)hipFree(d_bg);
-          (void)hipFree(d_bi);
-        } else {
-          HIP_TRY(hipMemcpyAsync(ev_h.data(), Wev, sizeof(double) * gc * bsz, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipMemcpyAsync(tr_h.data(), trace, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipMemcpyAsync(dl_h.data(), delta, sizeof(double) * gc, hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipStreamSynchronize(s));
-        }
-        for (int gl = 0; gl < gc; ++gl)
-          for (int j = 0; j < bsz; ++j)
-            if (!std::isfinite(ev_h[(size_t)gl * bsz + j]))
-              throw HipError(hipErrorUnknown, "eigensolver produced a non-finite value for grain " +
-                                                  std::to_string(g0 + gl));
-        for (int gl = 0; gl < gc; ++gl) {
-          double top = 0.0;
-          for (uint32_t j = 0; j < r; ++j) top += ev_h[(size_t)gl * bsz + bsz - 1 - j] - dl_h[gl];
-          ix->captured[g0 + gl] = tr_h[gl] > 0 ? top / tr_h[gl] : 1.0;
-        }
-      }
+      pca_encode_grains(ix, d_off, all, eig_iters, seed, 3, s);
     }
     plog("covariance, eigensolve, codes");
     launch_grain_bounds(*ix, s);

@@ -230,6 +230,13 @@ void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, 
                  const Buckets& b, int list, uint64_t* part, const uint64_t* bound_lists, bool prune,
                  unsigned long long* scored, hipStream_t s);
 void launch_grain_bounds(Index& ix, hipStream_t s);
+// Build-side steps shared by the build and the append (build.hip).
+void pca_encode_grains(Index* ix, const int64_t* d_off, const std::vector<int32_t>& glist, uint32_t eig_iters,
+                       uint64_t seed, uint64_t stream_base, hipStream_t s);
+// Exact member means (FP64 sums in member order) of grains gmap[0 .. ng-1]
+// (gmap null: grains 0 .. ng-1).
+void launch_segmented_mean(const float* X, int d, const int32_t* order, const int64_t* off, const int* gmap, int ng,
+                           float* cent, hipStream_t s);
 // eps_i by original id, made once (Mode A).
 void ensure_eps_by_id(Index& ix, hipStream_t s);
 // eps_id != null: Mode A (reconstruction distances of the pool, no raw vectors).

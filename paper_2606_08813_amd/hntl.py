@@ -36,6 +36,10 @@ class hntl_build_params(C.Structure):
                 ("seed", C.c_uint64), ("init_centroids", C.c_void_p)]
 
 
+class hntl_append_params(C.Structure):
+    _fields_ = [("split_max", C.c_uint32), ("eig_iters", C.c_uint32), ("seed", C.c_uint64)]
+
+
 class hntl_search_params(C.Structure):
     _fields_ = [("P", C.c_uint32), ("C", C.c_uint32), ("k", C.c_uint32), ("codes", C.c_uint32),
                 ("flags", C.c_uint32), ("route", C.c_uint32), ("tau", C.c_float)]
@@ -80,6 +84,8 @@ EXPORTS = {
     "hntl_index_create": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32] + [C.c_void_p] * 7
                           + [C.c_uint32, C.POINTER(C.c_void_p)]),
     "hntl_index_export": (C.c_int, [C.c_void_p] * 8),
+    "hntl_index_append": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(hntl_append_params), C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
     "hntl_index_export_codes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "hntl_index_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_index_info)]),
     "hntl_index_captured": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -223,6 +229,29 @@ def hntl_index_create(stored: dict, X, codes=("fp32",)) -> Index:
     _check(lib().hntl_index_create(N, d, G, r, _ptr(cen), _ptr(bas), _ptr(off), _ptr(per), _ptr(cod), _ptr(eps),
                                    None if Xc is None else _ptr(Xc), mask, C.byref(out)))
     return Index(out, N, d, G, r)
+
+
+def hntl_index_append(base: Index, X, *, split_max=0, eig_iters=0, seed=0, stream=None) -> Index:
+    """A new index holding base's rows plus the rows of X (n x d float32, numpy
+    or CUDA tensor; ids N .. N + n - 1).  base is left as it was."""
+    if isinstance(X, np.ndarray):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        n = X.shape[0]
+    else:
+        import torch
+        if X.dtype != torch.float32:
+            raise TypeError("X must be float32")
+        X = X.contiguous()
+        n = X.shape[0]
+    if X.ndim != 2 or X.shape[1] != base.d:
+        raise ValueError(f"X must be n x {base.d}")
+    p = hntl_append_params(split_max, eig_iters, seed)
+    out = C.c_void_p()
+    _check(lib().hntl_index_append(base.handle, _ptr(X) if n else None, n, C.byref(p), _stream(stream),
+                                   C.byref(out)))
+    info = hntl_index_info()
+    _check(lib().hntl_index_info_get(out, C.byref(info)))
+    return Index(out, info.N, info.d, info.G, info.r)
 
 
 def hntl_index_export(index: Index, with_scales=False) -> dict:
