@@ -102,6 +102,9 @@ def parse():
                     help="centroid routing shortlist on split-BF16 MFMA (auto: with --codes bf16/fp8)")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
     ap.add_argument("--router-epochs", type=int, default=8)
+    ap.add_argument("--append-rows", type=int, default=0,
+                    help="after the search timing, time hntl_index_append of this many new rows of the workload")
+    ap.add_argument("--split-max", type=int, default=0, help="split_max of the timed append (0 = no splits)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="run one plain device copy of this many GiB first (calibrates HBM counters)")
     return ap.parse_args()
@@ -330,6 +333,26 @@ def main():
                "ns_per_vector_scanned": round(el / done / (scanned / W.nq) * 1e9, 2)}
         log(f"[bench] CPU oracle: {cpu['value']} queries/s on 1 core")
 
+    # incremental segment: a new index = this one plus appended rows (build side, timed separately)
+    append = None
+    if args.append_rows > 0:
+        Xa = torch.from_numpy(W.queries(nq=args.append_rows, query_seed=4242).X).to(dev)
+        times = []
+        for _ in range(2):  # the first call also loads the append's code objects
+            torch.cuda.synchronize()
+            t0 = time.time()
+            ix2 = hntl.hntl_index_append(ix, Xa, split_max=args.split_max, seed=1)
+            torch.cuda.synchronize()
+            times.append(time.time() - t0)
+            G2 = ix2.G
+            del ix2
+            torch.cuda.empty_cache()
+        t = min(times)
+        append = {"rows": args.append_rows, "base_rows": W.N, "split_max": args.split_max, "grains_after": G2,
+                  "seconds": round(t, 4), "rows_per_s": round(args.append_rows / t, 1)}
+        log(f"[bench] append of {args.append_rows} rows: {t * 1e3:.1f} ms, {G2 - W.G} new grains")
+        del Xa
+
     out = {
         "metric": METRIC,
         "value": round(qps, 1),
@@ -366,6 +389,8 @@ def main():
         "precision": precision,
         "router": router,
     }
+    if append is not None:
+        out["append"] = append
     print(json.dumps(out), flush=True)
 
 

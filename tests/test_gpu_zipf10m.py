@@ -90,3 +90,76 @@ def test_learned_routing_full_size(z):
     f = hntl.hntl_search(z["ix"], Q, 4, W.C, W.k, codes="bf16", flags=fl | hntl.HNTL_FLAG_SYNC, route="learned",
                          tau=1.01)
     assert torch.equal(c[0], f[0]) and torch.equal(c[1], f[1])
+
+
+def test_append_full_size(z):
+    """100,000 rows of the same mixture appended to the 10M index with grains
+    capped at 16,384 members (the largest Zipf grains hold up to 20,000):
+    the result is a permutation of all ids with every grain at or below the
+    cap; grains that were not split keep their members, codes, centroid and
+    basis bit for bit with the new rows after them; sampled new rows sit in
+    their nearest base centroid's grain (or in a child of a split grain) with
+    codes and eps equal to the FP64 encoding by the stored centroid and basis;
+    children have orthonormal bases and member-mean centroids; an appended
+    row searched through the result is its own nearest neighbour."""
+    from oracle import index as oi
+    W, hntl, torch = z["W"], z["hntl"], z["torch"]
+    cap, n = 16384, 100_000
+    Xn = W.queries(nq=n, query_seed=4242).X
+    announce(f"10M: append {n} rows with split_max {cap}")
+    base = hntl.hntl_index_export(z["ix"])
+    ix2 = hntl.hntl_index_append(z["ix"], to_dev(Xn), split_max=cap, seed=1)
+    ex = hntl.hntl_index_export(ix2)
+    N, G = W.N, W.G
+    assert ix2.N == N + n and ix2.G > G
+    assert np.all(np.bincount(ex["perm"], minlength=N + n) == 1)
+    off0, off2 = base["offsets"], ex["offsets"]
+    assert np.diff(off2).max() <= cap
+    grain = np.empty(N + n, np.int64)
+    for g in range(ix2.G):
+        grain[ex["perm"][off2[g]:off2[g + 1]]] = g
+    unsplit = np.zeros(ix2.G, bool)
+    for g in range(G):
+        a0, b0, a2, b2 = off0[g], off0[g + 1], off2[g], off2[g + 1]
+        if b2 - a2 >= b0 - a0 and np.array_equal(ex["perm"][a2:a2 + (b0 - a0)], base["perm"][a0:b0]):
+            unsplit[g] = True
+            np.testing.assert_array_equal(ex["codes"][a2:a2 + (b0 - a0)], base["codes"][a0:b0])
+            np.testing.assert_array_equal(ex["eps"][a2:a2 + (b0 - a0)], base["eps"][a0:b0])
+            np.testing.assert_array_equal(ex["centroids"][g], base["centroids"][g])
+            np.testing.assert_array_equal(ex["basis"][g], base["basis"][g])
+            tail = ex["perm"][a2 + (b0 - a0):b2]
+            assert np.all(tail >= N) and np.all(np.diff(tail) > 0)
+    n_split = int(G - unsplit[:G].sum())
+    announce(f"10M append: {n_split} grains split into {ix2.G - G + n_split} children")
+    assert n_split >= 1
+    # sampled new rows: nearest base centroid, codes by the stored centroid and basis
+    rs = np.random.default_rng(9).choice(n, 2000, replace=False)
+    C0 = base["centroids"].astype(np.float64)
+    xs = Xn[rs].astype(np.float64)
+    D = (xs ** 2).sum(1)[:, None] + (C0 ** 2).sum(1)[None, :] - 2.0 * xs @ C0.T
+    near = np.argmin(D, axis=1)
+    gs = grain[N + rs]
+    ok_unsplit = unsplit[gs]
+    D_sorted = np.sort(D, axis=1)
+    clear = (D_sorted[:, 1] - D_sorted[:, 0]) > 1e-4 * np.abs(D_sorted[:, 0])
+    np.testing.assert_array_equal(gs[ok_unsplit & clear], near[ok_unsplit & clear])
+    assert not np.any(unsplit[near[~ok_unsplit & clear]])  # rows in children came from a split grain
+    pos = np.empty(N + n, np.int64)
+    pos[ex["perm"]] = np.arange(N + n)
+    for g in np.unique(gs):
+        rows = rs[gs == g]
+        zc, ec = oi.encode(Xn[rows], ex["centroids"][g], ex["basis"][g].astype(np.float64).T)
+        p = pos[N + rows]
+        np.testing.assert_allclose(ex["codes"][p], zc, rtol=0, atol=2e-5 * np.sqrt(np.abs(zc).max() + 1))
+        np.testing.assert_allclose(ex["eps"][p], ec, rtol=1e-4, atol=1e-4)
+    for g in np.nonzero(~unsplit)[0][:8]:
+        Bg = ex["basis"][g].astype(np.float64)
+        assert np.abs(Bg @ Bg.T - np.eye(W.r)).max() < 2e-6
+        ids = ex["perm"][off2[g]:off2[g + 1]]
+        Xm = np.concatenate([z["X"][ids[ids < N]], Xn[ids[ids >= N] - N]]).astype(np.float64)
+        np.testing.assert_allclose(ex["centroids"][g], Xm.mean(0), rtol=0, atol=2e-6 * max(1.0, np.abs(Xm).max()))
+    del base, ex
+    q = to_dev(Xn[rs[:1000]])
+    ids, dist = hntl.hntl_search(ix2, q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC)
+    np.testing.assert_array_equal(ids.cpu().numpy()[:, 0], N + rs[:1000])
+    assert float(dist[:, 0].abs().max()) < 1e-3
