@@ -124,7 +124,10 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   }
   __syncthreads();
 
-  // each wave gathers RR pool rows at a time (Mode B only)
+  // each wave gathers RR pool rows at a time (Mode B only); a lane issues the
+  // loads of JU float4 column groups of all RR rows before using any of them,
+  // so every wave keeps RR x JU x 1 KB of row data in flight
+  constexpr int JU = 3;
   const float* qv = Q + (size_t)q * d;
   for (int c0 = wave * RR; c0 < C && !eps_id; c0 += 4 * RR) {
     int32_t id[RR];
@@ -137,29 +140,41 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
       acc[u] = 0.f;
     }
     if (vec4) {
-      for (int j = lane * 4; j < d; j += 4 * HNTL_WAVE) {
-        const float4 b = *reinterpret_cast<const float4*>(qv + j);
-        float4 a[RR];
+      for (int j0 = lane * 4; j0 < d; j0 += 4 * HNTL_WAVE * JU) {
+        float4 b[JU];
+        float4 a[RR][JU];
 #pragma unroll
-        for (int u = 0; u < RR; ++u) {
-          if (id[u] < 0) {
-            a[u] = b;
-          } else if (NT) {
-            const float4* src = reinterpret_cast<const float4*>(x[u] + j);
-            a[u] = make_float4(__builtin_nontemporal_load(&src->x), __builtin_nontemporal_load(&src->y),
-                               __builtin_nontemporal_load(&src->z), __builtin_nontemporal_load(&src->w));
-          } else {
-            a[u] = *reinterpret_cast<const float4*>(x[u] + j);
+        for (int v = 0; v < JU; ++v) {
+          const int j = j0 + v * 4 * HNTL_WAVE;
+          b[v] = j < d ? *reinterpret_cast<const float4*>(qv + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < RR; ++u)
+#pragma unroll
+          for (int v = 0; v < JU; ++v) {
+            const int j = j0 + v * 4 * HNTL_WAVE;
+            if (id[u] < 0 || j >= d) {
+              a[u][v] = make_float4(0.f, 0.f, 0.f, 0.f);  // masked below; no wait on the query loads
+            } else if (NT) {
+              const float4* src = reinterpret_cast<const float4*>(x[u] + j);
+              a[u][v] = make_float4(__builtin_nontemporal_load(&src->x), __builtin_nontemporal_load(&src->y),
+                                    __builtin_nontemporal_load(&src->z), __builtin_nontemporal_load(&src->w));
+            } else {
+              a[u][v] = *reinterpret_cast<const float4*>(x[u] + j);
+            }
           }
-        }
 #pragma unroll
-        for (int u = 0; u < RR; ++u) {
-          const float d0 = a[u].x - b.x, d1 = a[u].y - b.y, d2 = a[u].z - b.z, d3 = a[u].w - b.w;
-          acc[u] = fmaf(d0, d0, acc[u]);
-          acc[u] = fmaf(d1, d1, acc[u]);
-          acc[u] = fmaf(d2, d2, acc[u]);
-          acc[u] = fmaf(d3, d3, acc[u]);
-        }
+        for (int u = 0; u < RR; ++u)
+#pragma unroll
+          for (int v = 0; v < JU; ++v) {
+            const bool ok = id[u] >= 0 && j0 + v * 4 * HNTL_WAVE < d;
+            const float d0 = ok ? a[u][v].x - b[v].x : 0.f, d1 = ok ? a[u][v].y - b[v].y : 0.f;
+            const float d2 = ok ? a[u][v].z - b[v].z : 0.f, d3 = ok ? a[u][v].w - b[v].w : 0.f;
+            acc[u] = fmaf(d0, d0, acc[u]);
+            acc[u] = fmaf(d1, d1, acc[u]);
+            acc[u] = fmaf(d2, d2, acc[u]);
+            acc[u] = fmaf(d3, d3, acc[u]);
+          }
       }
     } else {
       for (int j = lane; j < d; j += HNTL_WAVE) {
@@ -245,7 +260,7 @@ void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int
   const int cap = pow2_at_least(C < 64 ? 64 : C);
   dim3 grid((unsigned)nq);
 #define HNTL_MR(CAPV)                                                                                             \
-  hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 2, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
+  hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 4, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
                      (int64_t)ix.N, probes, part, pool_in, ix.X,                                                  \
                      pool_out, pool_D_out, ids, dist, vec4, qoff, eps_id)
   if (cap == 64)
