@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--mode", choices=("A", "B"), default="B",
                     help="B: exact rerank against the raw vectors; A: the answer from the index alone")
     ap.add_argument("--route-split", choices=("auto", "on", "off"), default="auto",
-                    help="centroid routing shortlist on split-BF16 MFMA (auto: with --codes bf16/fp8)")
+                    help="centroid routing shortlist from the split-BF16 library GEMM (auto: on when d % 8 == 0); "
+                         "the probes are picked by FP32 direct differences either way")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
     ap.add_argument("--router-epochs", type=int, default=8)
     ap.add_argument("--append-rows", type=int, default=0,
@@ -178,7 +179,7 @@ def main():
     if bf16_project:
         flags |= hntl.HNTL_FLAG_PROJECT_BF16
     route_split = args.route == "centroid" and (args.route_split == "on" or
-                                                (args.route_split == "auto" and args.codes in ("bf16", "fp8")))
+                                                (args.route_split == "auto" and W.d % 8 == 0))
     if route_split:
         flags |= hntl.HNTL_FLAG_ROUTE_BF16X3
     if args.mode == "A":

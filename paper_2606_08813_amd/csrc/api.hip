@@ -447,12 +447,14 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
         if (!learned) launch_row_norms(Q, nq, (int)ix.d, qn, s);
         for (int64_t q0 = 0; q0 < nq && !learned; q0 += chunk) {
           const int64_t rows = std::min<int64_t>(chunk, nq - q0);
-          if (split)
+          // dot products on the library GEMM (enough rows), else the distance kernels
+          const bool dots = launch_route_dots(ix, Q + q0 * ix.d, rows, split, As, Dm, s);
+          if (!dots && split)
             launch_dist_bf16x3(ix, Q + q0 * ix.d, qn + q0, rows, As, Dm, s);
-          else
+          else if (!dots)
             launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
           launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,
-                           Q + q0 * ix.d, qn + q0, ix.centroids, ix.cnorm, (int)ix.d);
+                           Q + q0 * ix.d, qn + q0, ix.centroids, ix.cnorm, (int)ix.d, nullptr, 0, dots);
         }
         probes = pr;
       }

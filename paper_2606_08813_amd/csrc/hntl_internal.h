@@ -161,9 +161,28 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
                         int cols, int d, int32_t* label, float* dmin, hipStream_t s);
 // top-P per row of D; with A and Bm given, the winners are re-scored by exact
 // direct differences (routing).  Rows beyond *nlim - row_base get probes -1.
+// With dot, D holds dot products a . b and the expansion distance is formed as
+// max(||a||^2 + ||b||^2 - 2 D, 0) (needs an and bn).
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
-                      const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0);
+                      const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0,
+                      bool dot = false);
+// Library GEMMs (blaslt.hip): D (rows x cols, FP32) = A (rows x k) . B (cols x k)^T,
+// operands row-major BF16 or FP32.  prepare (outside graph capture) makes the
+// shape's descriptors; abt enqueues.  Both return false when the library has no
+// algorithm for the shape.
+constexpr int LT_F32 = 0, LT_BF16 = 1;
+constexpr int64_t LT_MIN_ROWS = 64;  // fewer routing rows stay on the library-free kernels
+bool lt_gemm_prepare(int dt, int64_t rows, int64_t cols, int64_t k);
+bool lt_gemm_abt(int dt, const void* A, const void* B, float* D, int64_t rows, int64_t cols, int64_t k,
+                 hipStream_t s);
+// Routing dot products Q . mu^T of rows queries on the library GEMM: FP32, or
+// (split) BF16 over the split operands [q_hi | q_hi | q_lo] . [mu_hi | mu_lo | mu_hi]
+// with As as rows x 3d scratch.  Returns false (nothing enqueued) below
+// LT_MIN_ROWS rows or without a library algorithm; prepare_only makes the
+// descriptors without enqueueing.
+bool launch_route_dots(const Index& ix, const float* Q, int64_t rows, bool split, uint16_t* As, float* D,
+                       hipStream_t s, bool prepare_only = false);
 
 // exact k nearest rows of B (cols x d) for every row of A (rows x d), k <= 16:
 // MFMA expansion shortlist of 32 per row, re-scored by direct differences

@@ -7,15 +7,18 @@
 //
 //   reset (fill kernels: ticket, per-grain projection counters, per-query
 //          bounds; graphs hold kernel nodes only)
-//   routing          row norms, centroid distances (MFMA), top-P + exact re-score
+//   routing          row norms, centroid dot products (library GEMM) or distances
+//                    (MFMA kernels), top-P + exact re-score
 //   bucketing        pairs grouped by grain, items numbered largest grain first
 //   pair lists       per-pair list slots when grains are split into ranges
 //   fused kernel     projection + scan + per-list top-C (persistent)
 //   merge + rerank   pool = exact top C over the query's lists, FP32 rerank
 //
 // The batch size lives in device memory (written by a one-thread kernel
-// before each run) and the routing kernels skip rows past it, so one captured
-// graph serves every batch size up to max_nq.
+// before each run) and the kernels skip rows past it.  The library GEMM of
+// centroid routing cannot, so a plan captures one graph per routing row
+// bucket (64, 128, ... up to max_nq rows); a run replays the smallest bucket
+// that holds its batch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -168,8 +171,11 @@ struct Plan {
   RouterScratch rs;
   // graph
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<uint32_t> bucket_nq;     // routing rows of each captured graph, ascending
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
+  int64_t route_rows = 0;              // rows the library routing GEMM computes (enqueue)
+  bool lib_route = false;              // centroid routing on the library GEMM
   hipStream_t last_stream = nullptr;
   uint32_t wait_errors = 0;
 
@@ -177,8 +183,8 @@ struct Plan {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(device);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : execs) (void)hipGraphExecDestroy(e);
+    for (auto g : graphs) (void)hipGraphDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (arena) (void)hipFree(arena);
     (void)hipSetDevice(prev);
@@ -312,12 +318,21 @@ struct Plan {
       launch_row_norms(Q, max_nq, d, qn, s);
     for (int64_t q0 = 0; q0 < (int64_t)max_nq && sp.route != HNTL_ROUTE_LEARNED; q0 += chunk) {
       const int64_t rows = std::min<int64_t>(chunk, (int64_t)max_nq - q0);
-      if (sp.flags & HNTL_FLAG_ROUTE_BF16X3)
+      const bool split = (sp.flags & HNTL_FLAG_ROUTE_BF16X3) != 0;
+      // library dot products for the first route_rows rows (rows past the batch
+      // are never read); the distance kernels read the batch size themselves
+      const int64_t lr = std::min<int64_t>(rows, route_rows - q0);
+      bool dots = false;
+      if (lib_route && lr > 0) {
+        dots = launch_route_dots(x, Q + q0 * d, lr, split, Asplit, Dm, s);
+        if (!dots) throw ArgError{HNTL_EDEVICE, "library routing GEMM unavailable for a prepared shape"};
+      }
+      if (!lib_route && split)
         launch_dist_bf16x3(x, Q + q0 * d, qn + q0, rows, Asplit, Dm, s, nq_dev, q0);
-      else
+      else if (!lib_route)
         launch_dist_matrix(Q + q0 * d, qn + q0, rows, x.centroids, x.cnorm, G, d, Dm, s, nq_dev, q0);
       launch_topk_rows(Dm, rows, G, P, probes + q0 * P, nullptr, s, Q + q0 * d, qn + q0, x.centroids, x.cnorm, d,
-                       nq_dev, q0);
+                       nq_dev, q0, lib_route);
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
@@ -337,13 +352,23 @@ struct Plan {
     if (ev) HIP_TRY(hipEventRecord(ev[4], s));
   }
 
+  // Smallest routing bucket holding nq rows.
+  int bucket_of(uint32_t nq) const {
+    for (size_t i = 0; i < bucket_nq.size(); ++i)
+      if (nq <= bucket_nq[i]) return (int)i;
+    return (int)bucket_nq.size() - 1;
+  }
+
   void run(uint32_t nq, hipStream_t s) {
     hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, nq_dev, (int32_t)nq);
     HIP_TRY(hipGetLastError());
-    if (exec)
-      HIP_TRY(hipGraphLaunch(exec, s));
-    else
+    const int bi = bucket_of(nq);
+    if (!execs.empty()) {
+      HIP_TRY(hipGraphLaunch(execs[bi], s));
+    } else {
+      route_rows = bucket_nq[bi];
       enqueue(s);
+    }
     last_stream = s;
   }
 };
@@ -454,19 +479,49 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   }
   HIP_TRY(hipMemcpyAsync(pl->args_dev, a, sizeof(a), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  // routing row buckets; centroid routing uses the library GEMM when every
+  // bucket's shape has an algorithm (descriptors made and kernels loaded here,
+  // outside capture, by one eager call per shape on the zeroed query buffer)
+  if (sp.route != HNTL_ROUTE_LEARNED) {
+    for (uint32_t b = (uint32_t)LT_MIN_ROWS; b < max_nq; b *= 2) pl->bucket_nq.push_back(b);
+  }
+  pl->bucket_nq.push_back(max_nq);
+  pl->lib_route = false;
+  if (sp.route != HNTL_ROUTE_LEARNED && pl->bucket_nq.front() >= (uint32_t)LT_MIN_ROWS) {
+    const bool split = (sp.flags & HNTL_FLAG_ROUTE_BF16X3) != 0;
+    bool ok = true;
+    for (uint32_t b : pl->bucket_nq)
+      ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s, true);
+    if (ok) {
+      for (uint32_t b : pl->bucket_nq)
+        ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s);
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    pl->lib_route = ok;
+  }
+  if (!pl->lib_route) pl->bucket_nq.assign(1, max_nq);  // one graph serves every batch size
+  pl->route_rows = max_nq;
   if (plan_flags & HNTL_PLAN_GRAPH) {
     HIP_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-    try {
-      pl->enqueue(pl->cap_stream);
-    } catch (...) {
+    for (uint32_t b : pl->bucket_nq) {
+      pl->route_rows = b;
+      HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        pl->enqueue(pl->cap_stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(pl->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
       hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(pl->cap_stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
+      HIP_TRY(hipStreamEndCapture(pl->cap_stream, &g));
+      pl->graphs.push_back(g);
+      hipGraphExec_t e = nullptr;
+      HIP_TRY(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+      pl->execs.push_back(e);
     }
-    HIP_TRY(hipStreamEndCapture(pl->cap_stream, &pl->graph));
-    HIP_TRY(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    pl->route_rows = max_nq;
   }
   return pl.release();
 }
@@ -590,7 +645,7 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out) {
     std::memset(out, 0, sizeof(*out));
     out->max_nq = pl.max_nq;
     out->sched = pl.sch;
-    out->graph = pl.exec ? 1u : 0u;
+    out->graph = pl.execs.empty() ? 0u : 1u;
     out->device_bytes = pl.arena_bytes;
     out->list_slots = pl.list_slots;
     out->wait_errors = read_wait_errors(pl);
@@ -614,6 +669,7 @@ hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, doubl
     try {
       for (uint32_t rep = 0; rep < reps; ++rep) {
         hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl.nq_dev, (int32_t)nq);
+        pl.route_rows = pl.bucket_nq[pl.bucket_of(nq)];
         pl.enqueue(s, ev);
         HIP_TRY(hipEventSynchronize(ev[4]));
         for (int i = 0; i < 4; ++i) {

@@ -625,6 +625,23 @@ void ensure_centroid_split(Index& ix, hipStream_t s) {
   ix.cent_split = p;
 }
 
+bool launch_route_dots(const Index& ix, const float* Q, int64_t rows, bool split, uint16_t* As, float* D,
+                       hipStream_t s, bool prepare_only) {
+  if (rows < LT_MIN_ROWS) return false;
+  const int64_t G = ix.G, d = ix.d;
+  if (split) {
+    if (!ix.cent_split) throw ArgError{HNTL_ESTATE, "split-BF16 routing: centroid split not built"};
+    if (prepare_only) return lt_gemm_prepare(LT_BF16, rows, G, 3 * d);
+    if (!lt_gemm_prepare(LT_BF16, rows, G, 3 * d)) return false;
+    const int64_t n = rows * d;
+    hipLaunchKernelGGL(split3_kernel, dim3(blocks(n)), dim3(256), 0, s, Q, rows, (int)d, 0, As);
+    HIP_TRY(hipGetLastError());
+    return lt_gemm_abt(LT_BF16, As, ix.cent_split, D, rows, G, 3 * d, s);
+  }
+  if (prepare_only) return lt_gemm_prepare(LT_F32, rows, G, d);
+  return lt_gemm_abt(LT_F32, Q, ix.centroids, D, rows, G, d, s);
+}
+
 void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
                         hipStream_t s, const int32_t* nlim, int64_t row_base) {
   if (rows <= 0) return;
