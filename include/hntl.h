@@ -369,6 +369,7 @@ typedef struct hntl_plan_info {
   uint64_t device_bytes;   /* the plan's device buffers */
   uint64_t list_slots;     /* capacity of per-(pair, range) candidate lists */
   uint32_t wait_errors;    /* waits that gave up since creation (0 in a healthy run) */
+  uint32_t lib_route;      /* 1 if routing's products run on the library GEMM (one graph per row bucket) */
 } hntl_plan_info;
 
 /* hntl_plan_info_get - plan facts; synchronises the plan's last stream to read wait_errors. */

@@ -433,7 +433,7 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
           RouterScratch w;
           char* base = sc.get<char>(w.layout(nullptr, ix, nq, (int)P));
           w.layout(base, ix, nq, (int)P);
-          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s);
+          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s, nullptr, nq);
         }
         const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
         float* qn = learned ? nullptr : sc.get<float>(nq);

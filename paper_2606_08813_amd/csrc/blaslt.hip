@@ -1,14 +1,18 @@
 // Plain library GEMMs (hipBLASLt) for the dot products of centroid routing
-// (§2.1 step 1, §2.3): D = A . B^T with A (rows x k) and B (cols x k) both
-// row-major, BF16 or FP32 operands, FP32 accumulation and FP32 output
-// (HIPBLAS_COMPUTE_32F: no reduced-precision FP32 path), D row-major
-// (rows x cols).  In the library's column-major terms D^T (cols x rows) =
+// (§2.1 step 1, §2.3) and the learned router's layers: D = alpha A . B^T
+// with A (rows x k) and B (cols x k) both row-major, BF16 or
+// FP32 operands, FP32 accumulation and FP32 output (HIPBLAS_COMPUTE_32F: no
+// reduced-precision FP32 path), D row-major (rows x cols).  In the library's column-major terms D^T (cols x rows) =
 // B (k x cols, transposed) . A (k x rows): the TN layout.
 //
-// Descriptors and the heuristic's algorithm are made once per (device, type,
-// shape) by lt_gemm_prepare, which must run outside graph capture; lt_gemm_abt
-// then only enqueues the library kernel (capturable).  No workspace is given
-// to the library.
+// Descriptors are made once per (device, type, shape) by lt_gemm_prepare,
+// which must run outside graph capture; lt_gemm_abt then only enqueues the
+// library kernel (capturable).  No workspace is given to the library.  The
+// algorithm is the heuristic's pick for a fixed reference row count, used for
+// every row count it supports: one kernel, and so one summation order per
+// output element, whatever the batch size, so that a row's result does not
+// depend on the rows searched with it.
+#include <hipblaslt/hipblaslt-ext.hpp>
 #include <hipblaslt/hipblaslt.h>
 
 #include <map>
@@ -34,6 +38,7 @@ struct LtDevice {
 
 std::mutex g_lt_mu;
 LtDevice g_lt[64];
+constexpr int64_t LT_REF_ROWS = 16384;
 
 void lt_check(hipblasStatus_t st, const char* what) {
   if (st != HIPBLAS_STATUS_SUCCESS) throw HipError(hipErrorUnknown, std::string("hipBLASLt ") + what + " failed");
@@ -62,14 +67,26 @@ LtShape* shape_locked(int dev, int dt, int64_t rows, int64_t cols, int64_t k) {
   const uint64_t ws = 0;
   lt_check(hipblasLtMatmulPreferenceSetAttribute(pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &ws, sizeof(ws)),
            "workspace");
+  // the heuristic's algorithm for the reference row count, checked for this shape
+  hipblasLtMatrixLayout_t lb_ref = nullptr, ld_ref = nullptr;
+  lt_check(hipblasLtMatrixLayoutCreate(&lb_ref, in, (uint64_t)k, (uint64_t)LT_REF_ROWS, k), "layout b");
+  lt_check(hipblasLtMatrixLayoutCreate(&ld_ref, HIP_R_32F, (uint64_t)cols, (uint64_t)LT_REF_ROWS, cols), "layout d");
   hipblasLtMatmulHeuristicResult_t res[1];
   int got = 0;
   const hipblasStatus_t st =
-      hipblasLtMatmulAlgoGetHeuristic(D.h, sh.desc, sh.la, sh.lb, sh.ld, sh.ld, pref, 1, res, &got);
+      hipblasLtMatmulAlgoGetHeuristic(D.h, sh.desc, sh.la, lb_ref, ld_ref, ld_ref, pref, 1, res, &got);
   (void)hipblasLtMatmulPreferenceDestroy(pref);
+  (void)hipblasLtMatrixLayoutDestroy(lb_ref);
+  (void)hipblasLtMatrixLayoutDestroy(ld_ref);
   if (st == HIPBLAS_STATUS_SUCCESS && got > 0 && res[0].state == HIPBLAS_STATUS_SUCCESS && res[0].workspaceSize == 0) {
-    sh.algo = res[0].algo;
-    sh.ok = true;
+    const float one = 1.f, zero = 0.f;
+    size_t need = 0;
+    if (hipblaslt_ext::matmulIsAlgoSupported(D.h, sh.desc, &one, sh.la, sh.lb, &zero, sh.ld, sh.ld, res[0].algo,
+                                             need) == HIPBLAS_STATUS_SUCCESS &&
+        need == 0) {
+      sh.algo = res[0].algo;
+      sh.ok = true;
+    }
   }
   auto& slot = D.shapes[key];
   slot = sh;
@@ -88,21 +105,16 @@ bool lt_gemm_prepare(int dt, int64_t rows, int64_t cols, int64_t k) {
 }
 
 bool lt_gemm_abt(int dt, const void* A, const void* B, float* D, int64_t rows, int64_t cols, int64_t k,
-                 hipStream_t s) {
+                 hipStream_t s, float alpha) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return false;
-  LtShape* sh = nullptr;
-  hipblasLtHandle_t h = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_lt_mu);
-    sh = shape_locked(dev, dt, rows, cols, k);
-    h = g_lt[dev].h;
-  }
+  std::lock_guard<std::mutex> lk(g_lt_mu);
+  LtShape* sh = shape_locked(dev, dt, rows, cols, k);
   if (!sh) return false;
-  const float one = 1.f, zero = 0.f;
-  lt_check(hipblasLtMatmul(h, sh->desc, &one, B, sh->la, A, sh->lb, &zero, D, sh->ld, D, sh->ld, &sh->algo, nullptr, 0,
-                           s),
+  const float zero = 0.f;
+  lt_check(hipblasLtMatmul(g_lt[dev].h, sh->desc, &alpha, B, sh->la, A, sh->lb, &zero, D, sh->ld, D, sh->ld,
+                           &sh->algo, nullptr, 0, s),
            "matmul");
   return true;
 }

@@ -46,6 +46,8 @@ struct Index;
 struct RouterScratch {
   uint16_t *xh = nullptr, *h1 = nullptr, *h2 = nullptr;
   float* negS = nullptr;
+  float* z = nullptr;    // FP32 pre-activations of a hidden layer (library path)
+  float* nb2 = nullptr;  // negated output bias (library path)
   int32_t *fb_rows = nullptr, *fb_count = nullptr, *fb_probes = nullptr;
   float *fb_Q = nullptr, *fb_qn = nullptr, *fb_pdist = nullptr;
   size_t layout(char* base, const Index& ix, int64_t nq, int P);
@@ -162,20 +164,22 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 // top-P per row of D; with A and Bm given, the winners are re-scored by exact
 // direct differences (routing).  Rows beyond *nlim - row_base get probes -1.
 // With dot, D holds dot products a . b and the expansion distance is formed as
-// max(||a||^2 + ||b||^2 - 2 D, 0) (needs an and bn).
+// max(||a||^2 + ||b||^2 - 2 D, 0) (needs an and bn).  Without A (plain top-P),
+// colbias adds a per-column term: the P smallest of D[row][c] + colbias[c].
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
                       const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0,
-                      bool dot = false);
+                      bool dot = false, const float* colbias = nullptr);
 // Library GEMMs (blaslt.hip): D (rows x cols, FP32) = A (rows x k) . B (cols x k)^T,
 // operands row-major BF16 or FP32.  prepare (outside graph capture) makes the
 // shape's descriptors; abt enqueues.  Both return false when the library has no
 // algorithm for the shape.
 constexpr int LT_F32 = 0, LT_BF16 = 1;
 constexpr int64_t LT_MIN_ROWS = 64;  // fewer routing rows stay on the library-free kernels
+// abt computes D = alpha A . B^T.
 bool lt_gemm_prepare(int dt, int64_t rows, int64_t cols, int64_t k);
 bool lt_gemm_abt(int dt, const void* A, const void* B, float* D, int64_t rows, int64_t cols, int64_t k,
-                 hipStream_t s);
+                 hipStream_t s, float alpha = 1.f);
 // Routing dot products Q . mu^T of rows queries on the library GEMM: FP32, or
 // (split) BF16 over the split operands [q_hi | q_hi | q_lo] . [mu_hi | mu_lo | mu_hi]
 // with As as rows x 3d scratch.  Returns false (nothing enqueued) below
@@ -312,9 +316,13 @@ struct FusedArgs {
 };
 
 // learned routing: probes by descending router score; rows whose largest
-// softmax probability is below tau fall back to centroid routing
-void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr);
+// softmax probability is below tau fall back to centroid routing.  With
+// lib_rows >= LT_MIN_ROWS the three layer products of the first lib_rows rows
+// run on the library GEMM (when it has algorithms for them); prepare_only
+// makes those descriptors and reports whether they exist, enqueueing nothing.
+bool launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr,
+                          int64_t lib_rows = 0, bool prepare_only = false);
 
 // build helpers
 void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);

@@ -313,7 +313,7 @@ struct Plan {
     f.n = 6;
     launch_fill_multi(f, s);
     if (sp.route == HNTL_ROUTE_LEARNED)
-      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev);
+      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev, lib_route ? route_rows : 0);
     else
       launch_row_norms(Q, max_nq, d, qn, s);
     for (int64_t q0 = 0; q0 < (int64_t)max_nq && sp.route != HNTL_ROUTE_LEARNED; q0 += chunk) {
@@ -479,22 +479,29 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   }
   HIP_TRY(hipMemcpyAsync(pl->args_dev, a, sizeof(a), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // routing row buckets; centroid routing uses the library GEMM when every
-  // bucket's shape has an algorithm (descriptors made and kernels loaded here,
-  // outside capture, by one eager call per shape on the zeroed query buffer)
-  if (sp.route != HNTL_ROUTE_LEARNED) {
-    for (uint32_t b = (uint32_t)LT_MIN_ROWS; b < max_nq; b *= 2) pl->bucket_nq.push_back(b);
-  }
+  // routing row buckets; routing uses the library GEMM when every bucket's
+  // shapes have an algorithm (descriptors made and kernels loaded here,
+  // outside capture, by one eager call per bucket on the zeroed query buffer)
+  for (uint32_t b = (uint32_t)LT_MIN_ROWS; b < max_nq; b *= 2) pl->bucket_nq.push_back(b);
   pl->bucket_nq.push_back(max_nq);
   pl->lib_route = false;
-  if (sp.route != HNTL_ROUTE_LEARNED && pl->bucket_nq.front() >= (uint32_t)LT_MIN_ROWS) {
+  if (pl->bucket_nq.front() >= (uint32_t)LT_MIN_ROWS) {
+    const bool learned = sp.route == HNTL_ROUTE_LEARNED;
     const bool split = (sp.flags & HNTL_FLAG_ROUTE_BF16X3) != 0;
     bool ok = true;
     for (uint32_t b : pl->bucket_nq)
-      ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s, true);
+      ok = ok && (learned ? launch_route_learned(ix, pl->Q, max_nq, (int)sp.P, 0.f, pl->probes, nullptr, pl->rs, s,
+                                                 pl->nq_dev, b, true)
+                          : launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm,
+                                              s, true));
     if (ok) {
-      for (uint32_t b : pl->bucket_nq)
-        ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s);
+      hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl->nq_dev, 0);
+      for (uint32_t b : pl->bucket_nq) {
+        if (learned)
+          launch_route_learned(ix, pl->Q, max_nq, (int)sp.P, 0.f, pl->probes, nullptr, pl->rs, s, pl->nq_dev, b);
+        else
+          ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s);
+      }
       HIP_TRY(hipStreamSynchronize(s));
     }
     pl->lib_route = ok;
@@ -649,6 +656,7 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out) {
     out->device_bytes = pl.arena_bytes;
     out->list_slots = pl.list_slots;
     out->wait_errors = read_wait_errors(pl);
+    out->lib_route = pl.lib_route ? 1u : 0u;
   });
 }
 

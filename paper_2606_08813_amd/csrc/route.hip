@@ -281,6 +281,9 @@ constexpr float ERR = 5e-5f;
 // shortlist entries that can still reach the top P are re-scored by direct
 // differences ||a - b||^2 in FP32 and the P smallest exact distances are kept,
 // so probe order and reported distances carry direct-difference accuracy.
+// MODE 0: D holds distances (or, without A, the values to rank); 1: dot
+// products, ranked as max(||a||^2 + ||b||^2 - 2 D, 0); 2: D + colbias[c].
+template <int MODE>
 __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
                                                         int M, const float* __restrict__ A,
                                                         const float* __restrict__ an,
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
                                                         const float* __restrict__ bn, int d,
                                                         int32_t* __restrict__ idx, float* __restrict__ val,
                                                         const int32_t* __restrict__ nlim, int64_t row_base,
-                                                        bool dot) {
+                                                        const float* __restrict__ colbias) {
   __shared__ uint64_t stage[4][64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
   WaveTop64 L;
   L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
-  const float an_row = dot ? an[row] : 0.f;
+  const float an_row = MODE == 1 ? an[row] : 0.f;
   constexpr int U = 8;  // chunks of 64 loaded together (memory-level parallelism for one row)
   for (int c0 = 0; c0 < cols; c0 += U * HNTL_WAVE) {
     float v[U];
@@ -312,7 +315,19 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * HNTL_WAVE + lane;
       v[u] = c < cols ? drow[c] : 0.f;
-      if (dot) v[u] = c < cols ? fmaxf(fmaf(-2.f, v[u], an_row + bn[c]), 0.f) : 0.f;
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * HNTL_WAVE + lane;
+        v[u] = c < cols ? fmaxf(fmaf(-2.f, v[u], an_row + bn[c]), 0.f) : 0.f;
+      }
+    } else if constexpr (MODE == 2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * HNTL_WAVE + lane;
+        v[u] = c < cols ? v[u] + colbias[c] : 0.f;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -506,14 +521,21 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A, const float* an, const float* Bm, const float* bn, int d,
-                      const int32_t* nlim, int64_t row_base, bool dot) {
+                      const int32_t* nlim, int64_t row_base, bool dot, const float* colbias) {
   if (dot && (!an || !bn)) throw ArgError{HNTL_EINVAL, "dot-product routing needs both norm vectors"};
   if (rows <= 0) return;
   if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + 3) / 4));
   const int M = A ? std::min(cols, P + 16) : P;
-  hipLaunchKernelGGL(topk_rows_kernel, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val, nlim,
-                     row_base, dot);
+  if (dot)
+    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+                       nlim, row_base, colbias);
+  else if (colbias)
+    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+                       nlim, row_base, colbias);
+  else
+    hipLaunchKernelGGL(topk_rows_kernel<0>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+                       nlim, row_base, colbias);
   HIP_TRY(hipGetLastError());
 }
 

@@ -370,6 +370,18 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t*
 }
 
 // xh[r][j] = bf16((X[rows[r]][j] - mean[j]) / std[j]) (rows == null: r itself)
+// h = bf16(gelu(z + bias[col])) over a rows x cols block of FP32 dot products
+__global__ void gelu_bias_bf16_kernel(const float* __restrict__ z, int64_t rows, int cols,
+                                      const float* __restrict__ bias, uint16_t* __restrict__ h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows * cols) h[i] = to_bf16(gelu(z[i] + bias[i % cols]));
+}
+
+__global__ void negate_kernel(const float* __restrict__ a, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -a[i];
+}
+
 __global__ void standardize_kernel(const float* __restrict__ X, const int32_t* __restrict__ rows, int64_t n, int d,
                                    const float* __restrict__ mean, const float* __restrict__ stdv,
                                    uint16_t* __restrict__ xh, const int32_t* __restrict__ nlim) {
@@ -477,20 +489,22 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 
 // Max softmax probability of each row of negated scores (1 / sum exp(s - max));
 // rows below tau are appended to the fallback list.
+// (negS + colbias when the bias is not in negS yet)
 __global__ __launch_bounds__(256) void fallback_select_kernel(const float* __restrict__ negS, int64_t rows, int G,
                                                               float tau, int32_t* __restrict__ fb_rows,
                                                               int32_t* __restrict__ fb_count,
-                                                              const int32_t* __restrict__ nlim) {
+                                                              const int32_t* __restrict__ nlim,
+                                                              const float* __restrict__ colbias) {
   const int lane = lane_id();
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows || (nlim && r >= *nlim)) return;
   const float* s = negS + r * G;
   float mn = __builtin_inff();
-  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
+  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g] + (colbias ? colbias[g] : 0.f));
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
   float z = 0.f;
-  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
+  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - (s[g] + (colbias ? colbias[g] : 0.f)));
   z = wave_sum(z);
   if (lane == 0 && 1.f / z < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
 }
@@ -663,31 +677,56 @@ void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_
   gemm<false, false, EPI_DIST>(As, K3, ix.cent_split, K3, (int)rows, (int)ix.G, K3, e, s, nlim);
 }
 
-void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim) {
+bool launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim, int64_t lib_rows,
+                          bool prepare_only) {
   const Router& rt = *ix.router;
+  const int64_t lr = std::min<int64_t>(lib_rows, nq);
+  const bool lib = lr >= LT_MIN_ROWS && lt_gemm_prepare(LT_BF16, lr, rt.h1, rt.d) &&
+                   lt_gemm_prepare(LT_BF16, lr, rt.h2, rt.h1) && lt_gemm_prepare(LT_BF16, lr, rt.G, rt.h2);
+  if (prepare_only) return lib;
   hipLaunchKernelGGL(standardize_kernel, dim3(blocks(nq * rt.d)), dim3(256), 0, s, Q, nullptr, nq, rt.d, rt.mean,
                      rt.stdv, w.xh, nlim);
-  Epi e{};
-  e.bias = rt.b[0];
-  e.H = w.h1;
-  e.ldh = rt.h1;
-  gemm<false, false, EPI_BIAS_GELU>(w.xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s, nlim);
-  e.bias = rt.b[1];
-  e.H = w.h2;
-  e.ldh = rt.h2;
-  gemm<false, false, EPI_BIAS_GELU>(w.h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s, nlim);
-  Epi o{};
-  o.C = w.negS;
-  o.ldc = rt.G;
-  o.bias = rt.b[2];
-  o.scale = -1.f;
-  gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
-  launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, nlim, 0);
+  if (lib) {
+    // library products; bias, GELU (erf form) and the BF16 rounding of the
+    // activations in one pass over the FP32 dot products
+    if (!lt_gemm_abt(LT_BF16, w.xh, rt.Wb[0], w.z, lr, rt.h1, rt.d, s))
+      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
+    hipLaunchKernelGGL(gelu_bias_bf16_kernel, dim3(blocks(lr * rt.h1)), dim3(256), 0, s, w.z, lr, rt.h1, rt.b[0],
+                       w.h1);
+    if (!lt_gemm_abt(LT_BF16, w.h1, rt.Wb[1], w.z, lr, rt.h2, rt.h1, s))
+      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
+    hipLaunchKernelGGL(gelu_bias_bf16_kernel, dim3(blocks(lr * rt.h2)), dim3(256), 0, s, w.z, lr, rt.h2, rt.b[1],
+                       w.h2);
+    // negS = -(h2 . W3^T) here; the output bias enters where negS is read, as -b3
+    hipLaunchKernelGGL(negate_kernel, dim3(blocks(rt.G)), dim3(256), 0, s, rt.b[2], (int64_t)rt.G, w.nb2);
+    if (!lt_gemm_abt(LT_BF16, w.h2, rt.Wb[2], w.negS, lr, rt.G, rt.h2, s, -1.f))
+      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
+    HIP_TRY(hipGetLastError());
+  } else {
+    Epi e{};
+    e.bias = rt.b[0];
+    e.H = w.h1;
+    e.ldh = rt.h1;
+    gemm<false, false, EPI_BIAS_GELU>(w.xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s, nlim);
+    e.bias = rt.b[1];
+    e.H = w.h2;
+    e.ldh = rt.h2;
+    gemm<false, false, EPI_BIAS_GELU>(w.h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s, nlim);
+    Epi o{};
+    o.C = w.negS;
+    o.ldc = rt.G;
+    o.bias = rt.b[2];
+    o.scale = -1.f;
+    gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
+  }
+  const float* colbias = lib ? w.nb2 : nullptr;
+  launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, nlim, 0, false,
+                   colbias);
   if (tau > 0.f) {
     launch_fill_i32(w.fb_count, 1, 0, s);
     hipLaunchKernelGGL(fallback_select_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, tau, w.fb_rows,
-                       w.fb_count, nlim);
+                       w.fb_count, nlim, colbias);
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)nq), dim3(256), 0, s, Q, (int)ix.d, w.fb_rows, w.fb_count,
                        w.fb_Q);
     launch_row_norms(w.fb_Q, nq, (int)ix.d, w.fb_qn, s);
@@ -703,6 +742,7 @@ void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, fl
                        w.fb_probes, w.fb_pdist, probes, pdist);
     HIP_TRY(hipGetLastError());
   }
+  return lib;
 }
 
 // Buffers of launch_route_learned carved from one block (base == nullptr:
@@ -721,6 +761,8 @@ size_t RouterScratch::layout(char* base, const Index& ix, int64_t nq, int P) {
   h2 = (uint16_t*)take(2 * (size_t)nq * rt.h2);
   const int64_t chunk = std::min<int64_t>(nq, std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G));
   negS = (float*)take(4 * (size_t)std::max<int64_t>(nq * rt.G, chunk * ix.G));
+  z = (float*)take(4 * (size_t)nq * std::max(rt.h1, rt.h2));
+  nb2 = (float*)take(4 * (size_t)rt.G);
   fb_rows = (int32_t*)take(4 * (size_t)nq);
   fb_count = (int32_t*)take(4);
   fb_Q = (float*)take(4 * (size_t)nq * ix.d);

@@ -64,7 +64,8 @@ class hntl_schedule(C.Structure):
 
 class hntl_plan_info(C.Structure):
     _fields_ = [("max_nq", C.c_uint32), ("sched", hntl_schedule), ("graph", C.c_uint32),
-                ("device_bytes", C.c_uint64), ("list_slots", C.c_uint64), ("wait_errors", C.c_uint32)]
+                ("device_bytes", C.c_uint64), ("list_slots", C.c_uint64), ("wait_errors", C.c_uint32),
+                ("lib_route", C.c_uint32)]
 
 
 HNTL_PLAN_GRAPH = 1
@@ -435,7 +436,8 @@ def hntl_plan_info_get(plan: Plan) -> dict:
     info = hntl_plan_info()
     _check(lib().hntl_plan_info_get(plan.handle, C.byref(info)))
     return {"max_nq": info.max_nq, "sched": sched_dict(info.sched), "graph": bool(info.graph),
-            "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors}
+            "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors,
+            "lib_route": bool(info.lib_route)}
 
 
 PLAN_STAGES = ("route", "bucket", "fused", "rerank")
