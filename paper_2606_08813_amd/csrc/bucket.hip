@@ -138,13 +138,46 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
   const int per = (G + (int)blockDim.x - 1) / (int)blockDim.x;
   const int r0 = (int)threadIdx.x * per;
   const int t0 = lists.tile[LIST_SLOT0], t1 = lists.tile[LIST_REST], t2 = lists.tile[LIST_ALL];
+  // up to SCAN_REG ranks per thread (G <= 8,192): every load of a thread's ranks
+  // is issued before any is used, and the values stay in registers for the
+  // second pass (no chains of dependent loads)
+  constexpr int SCAN_REG = 8;
+  const bool reg = per <= SCAN_REG;
+  int gg[SCAN_REG], cc[SCAN_REG], c0s[SCAN_REG], sp[SCAN_REG];
+  if (reg) {
+#pragma unroll
+    for (int i = 0; i < SCAN_REG; ++i) {
+      const int rank = r0 + i;
+      gg[i] = (i < per && rank < G) ? (gorder ? gorder[rank] : rank) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < SCAN_REG; ++i) {
+      const int g = gg[i];
+      cc[i] = g >= 0 ? gcount[g] : 0;
+      c0s[i] = g >= 0 ? gcount0[g] : 0;
+      sp[i] = g >= 0 ? (nsplit ? nsplit[g] : 1) : 0;
+    }
+  }
+  auto fetch = [&](int i, int& g, int& c, int& c0, int& split) -> bool {
+    const int rank = r0 + i;
+    if (i >= per || rank >= G) return false;
+    if (reg && i < SCAN_REG) {
+      g = gg[i];
+      c = cc[i];
+      c0 = c0s[i];
+      split = sp[i];
+    } else {
+      g = gorder ? gorder[rank] : rank;
+      c = gcount[g];
+      c0 = gcount0[g];
+      split = nsplit ? nsplit[g] : 1;
+    }
+    return true;
+  };
   int loc[4] = {0, 0, 0, 0};  // pairs, items of slot 0, of the rest, of all
   for (int i = 0; i < per; ++i) {
-    const int rank = r0 + i;
-    if (rank >= G) break;
-    const int g = gorder ? gorder[rank] : rank;
-    const int c = gcount[g], c0 = gcount0[g];
-    const int split = nsplit ? nsplit[g] : 1;
+    int g, c, c0, split;
+    if (!fetch(i, g, c, c0, split)) break;
     loc[0] += c;
     loc[1] += (c0 + t0 - 1) / t0 * split;
     loc[2] += (c - c0 + t1 - 1) / t1 * split;
@@ -153,11 +186,9 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
   int run[4], tot[4];
   block_exclusive_scan4(loc, run, tot, tmp);
   for (int i = 0; i < per; ++i) {
+    int g, c, c0, split;
+    if (!fetch(i, g, c, c0, split)) break;
     const int rank = r0 + i;
-    if (rank >= G) break;
-    const int g = gorder ? gorder[rank] : rank;
-    const int c = gcount[g], c0 = gcount0[g];
-    const int split = nsplit ? nsplit[g] : 1;
     const int st = run[0];
     gstart[g] = st;
     cur0[g] = 0;
@@ -264,7 +295,27 @@ __global__ __launch_bounds__(1024) void query_scan_kernel(int64_t nq, int32_t* _
   const int64_t per = (nq + (int64_t)blockDim.x - 1) / (int64_t)blockDim.x;
   const int64_t q0 = (int64_t)threadIdx.x * per;
   const int64_t q1 = q0 + per < nq ? q0 + per : nq;
+  // up to QREG queries per thread (nq <= 16,384): all loads issued at once and
+  // kept in registers for the second pass
+  constexpr int QREG = 16;
   int sum = 0;
+  if (per <= QREG) {
+    int v[QREG];
+#pragma unroll
+    for (int i = 0; i < QREG; ++i) v[i] = q0 + i < q1 ? qoff[q0 + i] : 0;
+#pragma unroll
+    for (int i = 0; i < QREG; ++i) sum += v[i];
+    int all;
+    int run = block_exclusive_scan(sum, tmp, all);
+#pragma unroll
+    for (int i = 0; i < QREG; ++i)
+      if (q0 + i < q1) {
+        qoff[q0 + i] = run;
+        run += v[i];
+      }
+    if (threadIdx.x == 0) qoff[nq] = all;
+    return;
+  }
   for (int64_t q = q0; q < q1; ++q) sum += qoff[q];
   int all;
   int run = block_exclusive_scan(sum, tmp, all);

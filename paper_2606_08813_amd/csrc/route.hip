@@ -281,6 +281,8 @@ constexpr float ERR = 5e-5f;
 // shortlist entries that can still reach the top P are re-scored by direct
 // differences ||a - b||^2 in FP32 and the P smallest exact distances are kept,
 // so probe order and reported distances carry direct-difference accuracy.
+constexpr int TOPK_LDS_COLS = 8192;  // per-column terms staged in LDS up to this many columns
+
 // MODE 0: D holds distances (or, without A, the values to rank); 1: dot
 // products, ranked as max(||a||^2 + ||b||^2 - 2 D, 0); 2: D + colbias[c].
 template <int MODE>
@@ -293,8 +295,19 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
                                                         const int32_t* __restrict__ nlim, int64_t row_base,
                                                         const float* __restrict__ colbias) {
   __shared__ uint64_t stage[4][64];
+  extern __shared__ float colv[];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  // the per-column term (||b||^2 or colbias) read once per workgroup into LDS
+  // when it fits, instead of once per row
+  const float* colterm = MODE == 1 ? bn : colbias;
+  if constexpr (MODE != 0) {
+    if (cols <= TOPK_LDS_COLS) {
+      for (int c = threadIdx.x; c < cols; c += blockDim.x) colv[c] = colterm[c];
+      __syncthreads();
+      colterm = colv;
+    }
+  }
   if (row >= rows) return;
   if (nlim && row >= (int64_t)*nlim - row_base) {  // not part of this batch: no probes
     if (lane < P) {
@@ -320,13 +333,13 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = c0 + u * HNTL_WAVE + lane;
-        v[u] = c < cols ? fmaxf(fmaf(-2.f, v[u], an_row + bn[c]), 0.f) : 0.f;
+        v[u] = c < cols ? fmaxf(fmaf(-2.f, v[u], an_row + colterm[c]), 0.f) : 0.f;
       }
     } else if constexpr (MODE == 2) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = c0 + u * HNTL_WAVE + lane;
-        v[u] = c < cols ? v[u] + colbias[c] : 0.f;
+        v[u] = c < cols ? v[u] + colterm[c] : 0.f;
       }
     }
 #pragma unroll
@@ -527,11 +540,12 @@ void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* id
   if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + 3) / 4));
   const int M = A ? std::min(cols, P + 16) : P;
+  const size_t lds = ((dot || colbias) && cols <= TOPK_LDS_COLS) ? sizeof(float) * cols : 0;
   if (dot)
-    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, dim3(256), lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
                        nlim, row_base, colbias);
   else if (colbias)
-    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, dim3(256), lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
                        nlim, row_base, colbias);
   else
     hipLaunchKernelGGL(topk_rows_kernel<0>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
