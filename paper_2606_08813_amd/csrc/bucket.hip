@@ -11,6 +11,8 @@
 // a kernel finds the grain of item i by binary search in ioff.
 #include <algorithm>
 
+#include <atomic>
+
 #include "hntl_device.h"
 #include "hntl_internal.h"
 
@@ -464,11 +466,14 @@ void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, 
   HIP_TRY(hipGetLastError());
   if (npairs > 0) {
     const size_t lds = G <= LDS_MAX_G ? 4 * (size_t)G * sizeof(int) : 0;
-    static bool lds_set = false;  // up to 128 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
-    if (!lds_set) {
+    // up to 128 KiB of dynamic LDS (gfx950 has 160 KiB per CU), allowed once per device
+    static std::atomic<bool> lds_set[64];
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || !lds_set[dev].load()) {
       HIP_TRY(hipFuncSetAttribute((const void*)bucket_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(4 * LDS_MAX_G * sizeof(int))));
-      lds_set = true;
+      if (dev >= 0 && dev < 64) lds_set[dev].store(true);
     }
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nb), dim3(256), lds, s, probes, npairs, P, G, b.gstart, b.gcount0,
                        b.cur0, b.cur1, b.order);
