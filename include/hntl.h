@@ -52,6 +52,7 @@ typedef enum hntl_status {
   HNTL_ENOMEM = -2,      /* device or host allocation failed */
   HNTL_EDEVICE = -3,     /* no usable GPU, or a HIP runtime error */
   HNTL_ESTATE = -4,      /* the index lacks what the call needs (e.g. codes form not built) */
+  HNTL_EIO = -5,         /* a file could not be written or read, or failed its checks */
   HNTL_EUNSUPPORTED = -6 /* a size outside the compiled limits (see HNTL_MAX_*) */
 } hntl_status;
 
@@ -187,6 +188,25 @@ typedef struct hntl_append_params {
  */
 hntl_status hntl_index_append(const hntl_index* base, const float* X, uint64_t n,
                               const hntl_append_params* params, void* stream, hntl_index** out);
+
+/*
+ * hntl_index_save / hntl_index_load - an index as a directory of files (the
+ * immutable segment of Section 2, Fig. 1, on disk): one NumPy .npy file per
+ * stored-format array (centroids f4 G x d, basis f4 G x r x d, offsets i8 G+1,
+ * perm i4 N, codes f4 N x r in grain order, eps f4 N), X.npy (f4 N x d) when
+ * the index holds raw vectors, captured.npy (f8 G) when the build recorded it,
+ * the learned router's arrays (router_W1.npy .. router_std.npy) when it has one,
+ * and meta.json with the sizes, the code forms and a 64-bit FNV-1a checksum of
+ * every file's data bytes.  save creates `dir` if needed and overwrites the
+ * files; load reads what save wrote, verifies every checksum and shape, and
+ * builds the index as hntl_index_create does (same checks), with the router and
+ * captured record restored.  Host-side files; synchronous.
+ * Errors: EINVAL (null pointers), EIO (unwritable or missing directory or file,
+ * malformed header, shape or checksum mismatch), ENOMEM, EDEVICE, and the
+ * errors of hntl_index_create for inconsistent arrays.
+ */
+hntl_status hntl_index_save(const hntl_index* index, const char* dir);
+hntl_status hntl_index_load(const char* dir, hntl_index** out);
 
 /*
  * hntl_index_export - copy the stored-format arrays out of an index.  Any pointer may

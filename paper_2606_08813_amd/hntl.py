@@ -17,7 +17,7 @@ import numpy as np
 
 LIB_PATH = Path(__file__).resolve().parent / "libhntl.so"
 
-HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EIO, HNTL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3, HNTL_CODES_INT16 = 0, 1, 2, 3
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
 HNTL_FLAG_ROUTE_BF16X3 = 32
@@ -87,6 +87,8 @@ EXPORTS = {
     "hntl_index_export": (C.c_int, [C.c_void_p] * 8),
     "hntl_index_append": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(hntl_append_params), C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
+    "hntl_index_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "hntl_index_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_void_p)]),
     "hntl_index_export_codes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
     "hntl_index_info_get": (C.c_int, [C.c_void_p, C.POINTER(hntl_index_info)]),
     "hntl_index_captured": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -250,6 +252,20 @@ def hntl_index_append(base: Index, X, *, split_max=0, eig_iters=0, seed=0, strea
     out = C.c_void_p()
     _check(lib().hntl_index_append(base.handle, _ptr(X) if n else None, n, C.byref(p), _stream(stream),
                                    C.byref(out)))
+    info = hntl_index_info()
+    _check(lib().hntl_index_info_get(out, C.byref(info)))
+    return Index(out, info.N, info.d, info.G, info.r)
+
+
+def hntl_index_save(index: Index, path) -> None:
+    """Write the index to the directory `path` (.npy arrays + meta.json)."""
+    _check(lib().hntl_index_save(index.handle, str(path).encode()))
+
+
+def hntl_index_load(path) -> Index:
+    """Read an index written by hntl_index_save."""
+    out = C.c_void_p()
+    _check(lib().hntl_index_load(str(path).encode(), C.byref(out)))
     info = hntl_index_info()
     _check(lib().hntl_index_info_get(out, C.byref(info)))
     return Index(out, info.N, info.d, info.G, info.r)
