@@ -70,6 +70,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Measurement helpers (FP64 host arithmetic; the timed path never uses them).
+def exact_knn(X, Qs, k, chunk=1 << 16, extra=32):
+    """Exact k nearest rows of X (squared L2) for each row of Qs: a float64
+    expansion over row chunks keeps k + extra candidates per query, which are
+    re-scored by direct differences."""
+    Qd = np.asarray(Qs, dtype=np.float64)
+    qn = (Qd ** 2).sum(1)
+    m = k + extra
+    cand_i = np.zeros((len(Qd), 0), np.int64)
+    cand_d = np.zeros((len(Qd), 0))
+    for a in range(0, len(X), chunk):
+        Xc = np.asarray(X[a:a + chunk], dtype=np.float64)
+        D = qn[:, None] + (Xc ** 2).sum(1)[None, :] - 2.0 * (Qd @ Xc.T)
+        ci = np.concatenate([cand_i, np.broadcast_to(np.arange(a, a + len(Xc)), D.shape)], 1)
+        cd = np.concatenate([cand_d, D], 1)
+        keep = np.argpartition(cd, min(m, cd.shape[1] - 1), axis=1)[:, :m]
+        cand_i = np.take_along_axis(ci, keep, 1)
+        cand_d = np.take_along_axis(cd, keep, 1)
+    ids = np.empty((len(Qd), k), np.int64)
+    for i in range(len(Qd)):
+        dd = ((np.asarray(X[cand_i[i]], dtype=np.float64) - Qd[i]) ** 2).sum(1)
+        o = np.lexsort((cand_i[i], dd))[:k]
+        ids[i] = cand_i[i][o]
+    return ids
+
+
+def recall_at_k(ids, gt, k):
+    return float(np.mean([len(set(a[:k].tolist()) & set(b[:k].tolist())) / k for a, b in zip(ids, gt)]))
+
+
+def fp64_grain_scores(q, g, ex):
+    """eq. 6 scores ||z_q - z_i||^2 + eps_q + eps_i of every member of grain g,
+    from the stored centroid, basis, codes and eps in float64 (eq. 1-4 for q)."""
+    mu = ex["centroids"][g].astype(np.float64)
+    W = ex["basis"][g].astype(np.float64)
+    qp = np.asarray(q, dtype=np.float64) - mu
+    z = W @ qp
+    e = qp - W.T @ z
+    a, b = int(ex["offsets"][g]), int(ex["offsets"][g + 1])
+    Z = ex["codes"][a:b].astype(np.float64)
+    return ex["perm"][a:b], ((Z - z) ** 2).sum(1) + float(e @ e) + ex["eps"][a:b].astype(np.float64)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +130,7 @@ def parse():
     ap.add_argument("--fp32-project", action="store_true",
                     help="with --codes bf16/fp8, keep the FP32 projection (default: BF16 MFMA projection)")
     ap.add_argument("--error-sample", type=int, default=100,
-                    help="queries for the reduced-precision error report against the FP64 oracle")
+                    help="queries for the reduced-precision error report against FP64 scores of the stored index")
     ap.add_argument("--form", choices=("staged", "plan"), default="plan",
                     help="staged: hntl_search; plan: the persistent fused kernel in an autotuned, graph-replayed plan")
     ap.add_argument("--sched", default="",
@@ -103,6 +146,9 @@ def parse():
                          "the probes are picked by FP32 direct differences either way")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
     ap.add_argument("--router-epochs", type=int, default=8)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time every (P, C) of {1,2,4,8,16,32} x {k, 2k, 20, 64, 100, 200} as a tuned plan and "
+                         "report the fastest with Recall@10 >= 0.95 on the recall sample (operating point)")
     ap.add_argument("--append-rows", type=int, default=0,
                     help="after the search timing, time hntl_index_append of this many new rows of the workload")
     ap.add_argument("--split-max", type=int, default=0, help="split_max of the timed append (0 = no splits)")
@@ -248,28 +294,27 @@ def main():
     ids_h = ids.cpu().numpy()
 
     # Recall@10 against exact brute force on a query sample
-    from oracle import brute, search as osr
     rs = np.random.default_rng(7).choice(W.nq, size=min(args.recall_sample, W.nq), replace=False)
     t0 = time.time()
-    gt, _ = brute.knn(corpus.X, queries.X[rs], W.k)
-    recall = osr.recall(ids_h[rs], gt, W.k)
+    gt = exact_knn(corpus.X, queries.X[rs], W.k)
+    recall = recall_at_k(ids_h[rs], gt, W.k)
     log(f"[bench] Recall@10 on {len(rs)} sampled queries: {recall:.4f} (brute force {time.time() - t0:.1f}s)")
 
-    # reduced-precision error report against the FP64 oracle (eq. 6 scores of
-    # the GPU's pool entries and final distances, on a query sample)
+    # reduced-precision error report against FP64 (eq. 6 scores of the GPU's pool
+    # entries from the stored FP32 index in float64, and final distances)
     precision = None
     if args.codes != "fp32" and args.error_sample > 0:
         es = np.random.default_rng(13).choice(W.nq, size=min(args.error_sample, W.nq), replace=False)
         probes_s = probes[es]
-        zq64, eq64 = osr.project(queries.X[es], probes_s, ex)
         pool_ids = o["pool_ids"].cpu().numpy()[es]
         pool_D = o["pool_D"].cpu().numpy()[es].astype(np.float64)
         rel = []
         for i in range(len(es)):
             m = {}
             for sl in range(P):
-                gi, gd = osr.grain_scores(zq64[i, sl], eq64[i, sl], int(probes_s[i, sl]), ex)
-                m.update(zip(gi.tolist(), gd.tolist()))
+                if probes_s[i, sl] >= 0:
+                    gi, gd = fp64_grain_scores(queries.X[es[i]], int(probes_s[i, sl]), ex)
+                    m.update(zip(gi.tolist(), gd.tolist()))
             for pid, pd in zip(pool_ids[i], pool_D[i]):
                 if pid >= 0:
                     ref = m[int(pid)]
@@ -317,6 +362,7 @@ def main():
     # CPU oracle on a bounded query sample against the same index (timing only)
     cpu = None
     if args.cpu_sample != 0:
+        from oracle import search as osr
         from threadpoolctl import threadpool_limits
         nmax = W.nq if args.cpu_sample < 0 else min(args.cpu_sample, W.nq)
         order = np.random.default_rng(11).permutation(W.nq)[:nmax]
@@ -333,6 +379,37 @@ def main():
                          f"lifecycle in float64 (numpy, 1 thread), same index, {el:.1f}s",
                "ns_per_vector_scanned": round(el / done / (scanned / W.nq) * 1e9, 2)}
         log(f"[bench] CPU oracle: {cpu['value']} queries/s on 1 core")
+
+    # operating point: the fastest (P, C) of the grid at Recall@10 >= 0.95 (plans, tuned per point)
+    sweep = None
+    if args.sweep and args.form == "plan":
+        pts = []
+        for Ps in (1, 2, 4, 8, 16, 32):
+            if Ps > W.G:
+                continue
+            for Cs in sorted({W.k, 2 * W.k, 20, 64, 100, 200}):
+                if Cs < W.k:
+                    continue
+                sc, _ = hntl.hntl_tune(ix, Q, Ps, Cs, W.k, codes=args.codes, flags=pflags, **rkw)
+                pl = hntl.hntl_plan_create(ix, Ps, Cs, W.k, W.nq, codes=args.codes, flags=pflags, sched=sc, **rkw)
+                for _ in range(2):
+                    hntl.hntl_plan_search(pl, Q, out=(ids, dist))
+                torch.cuda.synchronize()
+                ev0.record(stream)
+                reps = max(3, args.steps // 2)
+                for _ in range(reps):
+                    hntl.hntl_plan_search(pl, Q, out=(ids, dist))
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1) / reps
+                rec = recall_at_k(ids.cpu().numpy()[rs], gt, W.k)
+                pts.append({"P": Ps, "C": Cs, "queries_per_s": round(W.nq / (ms / 1e3), 1), "recall_at_10": round(rec, 4)})
+                log(f"[bench] sweep P={Ps} C={Cs}: {pts[-1]['queries_per_s']:,.0f} q/s, Recall@10 {rec:.4f}")
+                del pl
+        ok = [p for p in pts if p["recall_at_10"] >= 0.95]
+        best = max(ok, key=lambda p: p["queries_per_s"]) if ok else None
+        sweep = {"grid": pts, "operating_point": best, "recall_sample": int(len(rs))}
+        log(f"[bench] operating point {best}")
 
     # incremental segment: a new index = this one plus appended rows (build side, timed separately)
     append = None
@@ -392,6 +469,8 @@ def main():
     }
     if append is not None:
         out["append"] = append
+    if sweep is not None:
+        out["sweep"] = sweep
     print(json.dumps(out), flush=True)
 
 
