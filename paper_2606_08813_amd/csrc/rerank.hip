@@ -18,7 +18,7 @@ namespace hntl {
 
 namespace {
 
-template <int CAP, int RR, bool NT>
+template <int CAP, int RR, int JU, bool NT>
 __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restrict__ Q, int d, int P, int C, int k,
                                                            int G, int64_t N, const int32_t* __restrict__ probes,
                                                            const uint64_t* __restrict__ part,
@@ -127,7 +127,6 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
   // each wave gathers RR pool rows at a time (Mode B only); a lane issues the
   // loads of JU float4 column groups of all RR rows before using any of them,
   // so every wave keeps RR x JU x 1 KB of row data in flight
-  constexpr int JU = 3;
   const float* qv = Q + (size_t)q * d;
   for (int c0 = wave * RR; c0 < C && !eps_id; c0 += 4 * RR) {
     int32_t id[RR];
@@ -259,16 +258,29 @@ void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int
   const bool vec4 = (ix.d % 4) == 0 && ((uintptr_t)Q % 16) == 0 && ((uintptr_t)ix.X % 16) == 0;
   const int cap = pow2_at_least(C < 64 ? 64 : C);
   dim3 grid((unsigned)nq);
-#define HNTL_MR(CAPV)                                                                                             \
-  hipLaunchKernelGGL((merge_rerank_kernel<CAPV, 4, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k, (int)ix.G,    \
-                     (int64_t)ix.N, probes, part, pool_in, ix.X,                                                  \
-                     pool_out, pool_D_out, ids, dist, vec4, qoff, eps_id)
-  if (cap == 64)
-    HNTL_MR(64);
-  else if (cap == 128)
-    HNTL_MR(128);
-  else
-    HNTL_MR(256);
+  // rows of up to 256 floats: one column group per lane and 8 rows per wave (few
+  // registers, many waves); longer rows: 3 column groups x 4 rows
+#define HNTL_MR(CAPV, RRV, JUV)                                                                                  \
+  hipLaunchKernelGGL((merge_rerank_kernel<CAPV, RRV, JUV, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k,      \
+                     (int)ix.G, (int64_t)ix.N, probes, part, pool_in, ix.X, pool_out, pool_D_out, ids, dist, vec4,   \
+                     qoff, eps_id)
+  const bool narrow = ix.d <= 4 * HNTL_WAVE;
+  if (cap == 64) {
+    if (narrow)
+      HNTL_MR(64, 8, 1);
+    else
+      HNTL_MR(64, 4, 3);
+  } else if (cap == 128) {
+    if (narrow)
+      HNTL_MR(128, 8, 1);
+    else
+      HNTL_MR(128, 4, 3);
+  } else {
+    if (narrow)
+      HNTL_MR(256, 8, 1);
+    else
+      HNTL_MR(256, 4, 3);
+  }
 #undef HNTL_MR
   HIP_TRY(hipGetLastError());
 }
