@@ -51,8 +51,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # source is unchanged (sha1 below).  Recorded in
 # profiles/merge_rerank_patch1M_d768_G1024_r32_hbm_counters.md.
 TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "plan", "codes": "fp32", "P": 8, "mode": "B",
-           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "e1b157fecdccadf2c859a7d5df9b3057340ec5b1",
-           "fetch_kib": 994984.8, "fetch_scale": 1048576.0 / 524307.8125, "write_kib": 1250.0, "write_scale": 1.0}
+           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "4616a1568044311e49c3d3680623e71d312b47f8",
+           "fetch_kib": 994974.9, "fetch_scale": 1048576.0 / 524307.8125, "write_kib": 1250.0, "write_scale": 1.0}
 
 
 def measured_traffic(stage, workload, form, codes, P, mode):
