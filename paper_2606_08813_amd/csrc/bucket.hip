@@ -122,10 +122,11 @@ __device__ void block_exclusive_scan4(const int (&v)[4], int (&ex)[4], int (&tot
   __syncthreads();
 }
 
-// Single workgroup: grain ranges, the three lists' ranges and item offsets.
+// Single workgroup: grain starts (gstart) and the three lists' item offsets.
 // Grains are visited in the order `gorder` (rank -> grain; identity if null)
-// and ioff is indexed by that rank, so items come out in that order; lstart and
-// lcount stay indexed by grain.  With `nsplit`, a grain's slot-0 and rest
+// and ioff is indexed by that rank, so items come out in that order; the
+// per-grain list ranges (lstart, lcount, indexed by grain) follow from gstart
+// in bucket_lists_kernel.  With `nsplit`, a grain's slot-0 and rest
 // tiles each become nsplit[g] items (one per block range of the grain).
 // Thread t owns the consecutive ranks t * per .. t * per + per - 1: a local
 // pass sums its pairs and items, one workgroup scan turns the sums into
@@ -134,8 +135,7 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
                                                            const int32_t* __restrict__ gcount0, int G,
                                                            const int32_t* __restrict__ gorder,
                                                            const int32_t* __restrict__ nsplit,
-                                                           int32_t* __restrict__ gstart, int32_t* __restrict__ cur0,
-                                                           int32_t* __restrict__ cur1, ItemLists lists) {
+                                                           int32_t* __restrict__ gstart, ItemLists lists) {
   __shared__ int tmp[16][4];
   const int per = (G + (int)blockDim.x - 1) / (int)blockDim.x;
   const int r0 = (int)threadIdx.x * per;
@@ -191,19 +191,10 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
     int g, c, c0, split;
     if (!fetch(i, g, c, c0, split)) break;
     const int rank = r0 + i;
-    const int st = run[0];
-    gstart[g] = st;
-    cur0[g] = 0;
-    cur1[g] = 0;
+    gstart[g] = run[0];  // the other per-grain fields: bucket_lists_kernel, many workgroups
     lists.ioff[LIST_SLOT0][rank] = run[1];
     lists.ioff[LIST_REST][rank] = run[2];
     lists.ioff[LIST_ALL][rank] = run[3];
-    lists.lstart[LIST_SLOT0][g] = st;
-    lists.lcount[LIST_SLOT0][g] = c0;
-    lists.lstart[LIST_REST][g] = st + c0;
-    lists.lcount[LIST_REST][g] = c - c0;
-    lists.lstart[LIST_ALL][g] = st;
-    lists.lcount[LIST_ALL][g] = c;
     run[0] += c;
     run[1] += (c0 + t0 - 1) / t0 * split;
     run[2] += (c - c0 + t1 - 1) / t1 * split;
@@ -214,6 +205,26 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __rest
     lists.ioff[LIST_REST][G] = tot[2];
     lists.ioff[LIST_ALL][G] = tot[3];
   }
+}
+
+// Per-grain list ranges from the grain starts (one thread per grain): these
+// scattered writes are spread over many workgroups instead of the scan's one.
+__global__ __launch_bounds__(256) void bucket_lists_kernel(const int32_t* __restrict__ gcount,
+                                                           const int32_t* __restrict__ gcount0, int G,
+                                                           const int32_t* __restrict__ gstart,
+                                                           int32_t* __restrict__ cur0, int32_t* __restrict__ cur1,
+                                                           ItemLists lists) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int c = gcount[g], c0 = gcount0[g], st = gstart[g];
+  cur0[g] = 0;
+  cur1[g] = 0;
+  lists.lstart[LIST_SLOT0][g] = st;
+  lists.lcount[LIST_SLOT0][g] = c0;
+  lists.lstart[LIST_REST][g] = st + c0;
+  lists.lcount[LIST_REST][g] = c - c0;
+  lists.lstart[LIST_ALL][g] = st;
+  lists.lcount[LIST_ALL][g] = c;
 }
 
 // Scatter pair ids into their grain's range (slot 0 first): each workgroup
@@ -462,7 +473,9 @@ void launch_bucket(const int32_t* probes, int64_t nq, int P, int G, Buckets& b, 
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, b.gcount, b.gcount0, G, gorder, nsplit, b.gstart,
-                     b.cur0, b.cur1, b.lists);
+                     b.lists);
+  hipLaunchKernelGGL(bucket_lists_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, b.gcount, b.gcount0, G,
+                     b.gstart, b.cur0, b.cur1, b.lists);
   HIP_TRY(hipGetLastError());
   if (npairs > 0) {
     const size_t lds = G <= LDS_MAX_G ? 4 * (size_t)G * sizeof(int) : 0;
