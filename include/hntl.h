@@ -398,9 +398,9 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out);
 /*
  * hntl_plan_profile - run the plan reps times without its graph, with HIP events
  * between its stages on `stream`, and return the mean device milliseconds per stage
- * in stage_ms[0..4): routing, bucketing (with the resets), the fused
- * project-scan-select kernel (with schedule proj = 1, the projection launch and the
- * fused kernel), merge + rerank.  *scored (may be NULL) receives the
+ * in stage_ms[0..5): routing, bucketing (with the resets), the separate projection
+ * launch (schedule proj = 1; 0 otherwise), the fused project-scan-select kernel,
+ * merge + rerank.  *scored (may be NULL) receives the
  * eq. 6 scores the last run computed.  The queries are the first nq rows of the
  * plan's Q buffer.  Synchronous.
  */

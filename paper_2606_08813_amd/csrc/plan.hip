@@ -76,6 +76,7 @@ constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int TICKET_INTS = 9 * 64;
 constexpr int MIN_GRID = 8;  // every class of scan counters needs a workgroup
 // search flags a plan honours (beyond HNTL_FLAG_SYNC)
+constexpr int PLAN_STAGES = 5;  // route, bucket, projection launch, fused kernel, merge + rerank
 constexpr uint32_t PLAN_FLAGS = HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3 | HNTL_FLAG_MODE_A;
 constexpr uint64_t MAX_LIST_BYTES = 4ull << 30;  // candidate-list storage of one plan
 
@@ -297,8 +298,9 @@ struct Plan {
   }
 
   // The launch sequence of one run (batch size already in nq_dev).  With
-  // `ev` (5 events) the stage boundaries are recorded: route, bucketing,
-  // fused kernel, merge + rerank.
+  // `ev` (6 events) the stage boundaries are recorded: route, bucketing,
+  // separate projection launch (empty with proj = 0), fused kernel, merge +
+  // rerank.
   void enqueue(hipStream_t s, hipEvent_t* ev = nullptr) {
     const Index& x = *ix;
     const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
@@ -340,16 +342,17 @@ struct Plan {
     launch_item_table(b.lists, x.gorder, G, (int)sch.qt, max_items, items, s);
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (sch.proj) launch_project(x, Q, P, b, T, epsq, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0, x.gorder, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     for (int ph = sch.passes == 2 ? 1 : 0; ph <= (sch.passes == 2 ? 2 : 0); ++ph) {
       if (!fused_launch((int)sp.codes, args_dev + ph, (int)x.rp, (int)sp.C, (int)sch.qt, (int)sch.nw, (int)sch.grid,
                         s))
         throw ArgError{HNTL_EUNSUPPORTED, "no fused kernel for this rank / pool / schedule"};
       HIP_TRY(hipGetLastError());
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
     launch_merge_rerank(x, Q, max_nq, P, (int)sp.C, (int)sp.k, probes, part, nullptr, nullptr, nullptr, ids, dist, s,
                         sch.range ? qoff : nullptr, (sp.flags & HNTL_FLAG_MODE_A) ? x.eps_id : nullptr);
-    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[5], s));
   }
 
   // Smallest routing bucket holding nq rows.
@@ -670,17 +673,17 @@ hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, doubl
   return guarded_call([&] {
     HIP_TRY(hipSetDevice(pl.device));
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t ev[5];
+    hipEvent_t ev[PLAN_STAGES + 1];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    std::vector<double> acc(4, 0.0);
+    std::vector<double> acc(PLAN_STAGES, 0.0);
     unsigned long long sc = 0;
     try {
       for (uint32_t rep = 0; rep < reps; ++rep) {
         hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl.nq_dev, (int32_t)nq);
         pl.route_rows = pl.bucket_nq[pl.bucket_of(nq)];
         pl.enqueue(s, ev);
-        HIP_TRY(hipEventSynchronize(ev[4]));
-        for (int i = 0; i < 4; ++i) {
+        HIP_TRY(hipEventSynchronize(ev[PLAN_STAGES]));
+        for (int i = 0; i < PLAN_STAGES; ++i) {
           float t = 0.f;
           HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
           acc[i] += t;
@@ -692,7 +695,7 @@ hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, doubl
       throw;
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i] / reps;
+    for (int i = 0; i < PLAN_STAGES; ++i) stage_ms[i] = acc[i] / reps;
     if (scored) *scored = sc;
     pl.last_stream = s;
   });

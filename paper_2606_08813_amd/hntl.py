@@ -456,13 +456,13 @@ def hntl_plan_info_get(plan: Plan) -> dict:
             "lib_route": bool(info.lib_route)}
 
 
-PLAN_STAGES = ("route", "bucket", "fused", "rerank")
+PLAN_STAGES = ("route", "bucket", "project", "fused", "rerank")
 
 
 def hntl_plan_profile(plan: Plan, nq: int, reps=3, stream=None):
     """Mean device ms per plan stage over reps eager runs of the queries already in
     the plan's buffer, and the eq. 6 scores of the last run."""
-    ms = np.zeros(4, np.float64)
+    ms = np.zeros(len(PLAN_STAGES), np.float64)
     sc = C.c_uint64(0)
     _check(lib().hntl_plan_profile(plan.handle, nq, reps, ms.ctypes.data, C.byref(sc), _stream(stream)))
     return dict(zip(PLAN_STAGES, ms.tolist())), sc.value
