@@ -216,3 +216,36 @@ def test_split_bf16_routing(bt):
         assert torch.equal(a["ids"], b["ids"]) and torch.equal(a["dist"], b["dist"]), nb
     plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, flags=fl, sched=dict(qt=2, nw=4, range=1, proj=1))
     assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], flags=fl), "plan, split routing")
+
+
+def test_results_do_not_depend_on_the_batch(bt):
+    """Routing's library products use one kernel for every row count, so a query's
+    probes and results are the same whatever batch it is searched in: rows of
+    batches of 1000, 300, 100 and 64 queries (library GEMM) and of 9 (distance
+    kernels) agree bit for bit, FP32 and split-BF16 shortlists."""
+    W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
+    announce("batch independence of routing and results: 1000 / 300 / 100 / 64 / 9 queries")
+    for fl in (0, hntl.HNTL_FLAG_ROUTE_BF16X3):
+        full = hntl.hntl_search_stages(bt["ix"], bt["Qd"], W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
+        for nb in (300, 100, 64, 9):
+            part = hntl.hntl_search_stages(bt["ix"], bt["Qd"][:nb].contiguous(), W.P, W.C, W.k,
+                                           flags=hntl.HNTL_FLAG_SYNC | fl)
+            for k in ("probes", "ids", "dist"):
+                assert torch.equal(part[k], full[k][:nb]), (fl, nb, k)
+
+
+def test_plan_profile_stages(bt):
+    """hntl_plan_profile reports five stages; the projection launch has time only
+    with a separate projection launch (schedule proj = 1)."""
+    W, hntl = bt["W"], bt["hntl"]
+    announce("plan profile stages with and without a separate projection launch")
+    for proj in (0, 1):
+        plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, sched=dict(qt=2, nw=4, range=0, proj=proj))
+        hntl.hntl_plan_search(plan, bt["Qd"])
+        st, scored = hntl.hntl_plan_profile(plan, 1000, reps=2)
+        assert list(st) == ["route", "bucket", "project", "fused", "rerank"]
+        assert all(v >= 0 for v in st.values()) and st["fused"] > 0 and st["rerank"] > 0 and scored > 0
+        if proj:
+            assert st["project"] > 0.005
+        else:
+            assert st["project"] < 0.05
