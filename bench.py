@@ -337,11 +337,13 @@ def main():
     npairs = W.nq * P
     rp = (W.r + 7) // 8 * 8
     code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1, "int16": 2}[args.codes]
+    # the split-BF16 shortlist runs three BF16 products per FP32 product, on the BF16 units
     route_work = (2.0 * W.nq * (W.d * 1024 + 1024 * 1024 + 1024 * W.G) if args.route == "learned"
-                  else 2.0 * W.nq * W.G * W.d)
+                  else 2.0 * W.nq * W.G * W.d * (3 if route_split else 1))
+    route_bf16 = args.route == "learned" or route_split
     per_stage = {
         "route": dict(bound="mfma", work=route_work, unit="TFLOP/s",
-                      peak=BF16_MFMA_PEAK_TFLOPS if args.route == "learned" else FP32_MFMA_PEAK_TFLOPS),
+                      peak=BF16_MFMA_PEAK_TFLOPS if route_bf16 else FP32_MFMA_PEAK_TFLOPS),
         "project": dict(bound="mfma", work=2.0 * npairs * W.r * W.d, unit="TFLOP/s",
                         peak=BF16_MFMA_PEAK_TFLOPS if bf16_project else FP32_MFMA_PEAK_TFLOPS),
         "scan": dict(bound="alu", work=3.0 * W.r * (scored or scanned), unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS),
