@@ -67,3 +67,19 @@ def test_info_and_export_reject_null():
     assert L.hntl_index_info_get(None, C.byref(info)) == hntl.HNTL_EINVAL
     assert L.hntl_index_export(None, *([None] * 7)) == hntl.HNTL_EINVAL
     L.hntl_index_free(None)
+
+
+def test_append_save_load_argument_validation_needs_no_device(tmp_path):
+    L = hntl.lib()
+    out = C.c_void_p()
+    p = hntl.hntl_append_params(0, 0, 0)
+    assert L.hntl_index_append(None, None, 0, C.byref(p), None, C.byref(out)) == hntl.HNTL_EINVAL   # no base
+    assert L.hntl_index_append(C.c_void_p(1), None, 0, C.byref(p), None, None) == hntl.HNTL_EINVAL  # no out
+    assert L.hntl_index_save(None, str(tmp_path).encode()) == hntl.HNTL_EINVAL
+    assert L.hntl_index_load(None, C.byref(out)) == hntl.HNTL_EINVAL
+    # a directory without index files: an I/O error, found before any device call
+    assert L.hntl_index_load(str(tmp_path / "none").encode(), C.byref(out)) == hntl.HNTL_EIO
+    assert "meta.json" in hntl.hntl_last_error()
+    (tmp_path / "meta.json").write_text('{"format": "something-else"}')
+    assert L.hntl_index_load(str(tmp_path).encode(), C.byref(out)) == hntl.HNTL_EIO
+    assert out.value is None
