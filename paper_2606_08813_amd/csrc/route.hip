@@ -282,11 +282,14 @@ constexpr float ERR = 5e-5f;
 // differences ||a - b||^2 in FP32 and the P smallest exact distances are kept,
 // so probe order and reported distances carry direct-difference accuracy.
 constexpr int TOPK_LDS_COLS = 8192;  // per-column terms staged in LDS up to this many columns
+// Rows per workgroup, one per wave: eight rows share one LDS copy of the
+// per-column term (32 KiB at 8,192 columns) and keep the CU at full wave occupancy.
+constexpr int TOPK_ROWS = 8;
 
 // MODE 0: D holds distances (or, without A, the values to rank); 1: dot
 // products, ranked as max(||a||^2 + ||b||^2 - 2 D, 0); 2: D + colbias[c].
 template <int MODE>
-__global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
+__global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
                                                         int M, const float* __restrict__ A,
                                                         const float* __restrict__ an,
                                                         const float* __restrict__ Bm,
@@ -294,16 +297,29 @@ __global__ __launch_bounds__(256) void topk_rows_kernel(const float* __restrict_
                                                         int32_t* __restrict__ idx, float* __restrict__ val,
                                                         const int32_t* __restrict__ nlim, int64_t row_base,
                                                         const float* __restrict__ colbias) {
-  __shared__ uint64_t stage[4][64];
+  __shared__ uint64_t stage[TOPK_ROWS][64];
   extern __shared__ float colv[];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t row = (int64_t)blockIdx.x * TOPK_ROWS + wave;
   // the per-column term (||b||^2 or colbias) read once per workgroup into LDS
   // when it fits, instead of once per row
   const float* colterm = MODE == 1 ? bn : colbias;
   if constexpr (MODE != 0) {
     if (cols <= TOPK_LDS_COLS) {
-      for (int c = threadIdx.x; c < cols; c += blockDim.x) colv[c] = colterm[c];
+      constexpr int NT = TOPK_ROWS * 64, PU = 16;  // PU loads in flight per thread
+      for (int c0 = 0; c0 < cols; c0 += PU * NT) {
+        float t[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          const int c = c0 + u * NT + (int)threadIdx.x;
+          t[u] = c < cols ? colterm[c] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+          const int c = c0 + u * NT + (int)threadIdx.x;
+          if (c < cols) colv[c] = t[u];
+        }
+      }
       __syncthreads();
       colterm = colv;
     }
@@ -538,17 +554,17 @@ void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* id
   if (dot && (!an || !bn)) throw ArgError{HNTL_EINVAL, "dot-product routing needs both norm vectors"};
   if (rows <= 0) return;
   if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
-  dim3 grid((unsigned)((rows + 3) / 4));
+  dim3 grid((unsigned)((rows + TOPK_ROWS - 1) / TOPK_ROWS)), block(TOPK_ROWS * 64);
   const int M = A ? std::min(cols, P + 16) : P;
   const size_t lds = ((dot || colbias) && cols <= TOPK_LDS_COLS) ? sizeof(float) * cols : 0;
   if (dot)
-    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, dim3(256), lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, block, lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
                        nlim, row_base, colbias);
   else if (colbias)
-    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, dim3(256), lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, block, lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
                        nlim, row_base, colbias);
   else
-    hipLaunchKernelGGL(topk_rows_kernel<0>, grid, dim3(256), 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
+    hipLaunchKernelGGL(topk_rows_kernel<0>, grid, block, 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
                        nlim, row_base, colbias);
   HIP_TRY(hipGetLastError());
 }
