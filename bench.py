@@ -161,7 +161,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(each GPU box has a single MI355X; multi-GPU sharding is design-only).", file=sys.stderr)
+              "(the search path runs on a single MI355X; sharding across GPUs is described, not built).", file=sys.stderr)
         sys.exit(2)
     import torch
     from workloads import WORKLOADS

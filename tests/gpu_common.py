@@ -13,7 +13,7 @@ def require_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2606_08813_amd import hntl
-    hntl.lib()  # raises when the HIP library is missing on a GPU machine
+    hntl.lib()  # raises when a GPU is present but the HIP library is missing
     return torch
 
 
