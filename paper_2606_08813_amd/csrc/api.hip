@@ -495,6 +495,7 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
       uint64_t* pt = sc.get<uint64_t>((size_t)npairs * C);
       clk.at(HNTL_STAGE_SCAN);
       unsigned long long* scored = (sp->flags & HNTL_FLAG_PROFILE) ? g_prof.counter(ix.device) : nullptr;
+      if (P > 1) launch_reset_slot0_tail(pt, nq, (int)P, (int)C, s);
       launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, LIST_SLOT0, pt, nullptr, false, scored, s);
       if (P > 1) {
         const bool bounded = !(sp->flags & HNTL_FLAG_NO_PRUNE);

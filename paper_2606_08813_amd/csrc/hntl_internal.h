@@ -253,6 +253,9 @@ void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, 
                  const Buckets& b, int list, uint64_t* part, const uint64_t* bound_lists, bool prune,
                  unsigned long long* scored, hipStream_t s);
 void launch_grain_bounds(Index& ix, hipStream_t s);
+// Before the slot-0 pass of the staged scan: entry C - 1 of each query's
+// slot-0 list := KEY_NONE (part is nq x P x C keys).
+void launch_reset_slot0_tail(uint64_t* part, int64_t nq, int P, int C, hipStream_t s);
 // Build-side steps shared by the build and the append (build.hip).
 void pca_encode_grains(Index* ix, const int64_t* d_off, const std::vector<int32_t>& glist, uint32_t eig_iters,
                        uint64_t seed, uint64_t stream_base, hipStream_t s);

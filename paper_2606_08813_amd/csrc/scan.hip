@@ -59,7 +59,20 @@ __global__ __launch_bounds__(256) void grain_bounds_kernel(const float* __restri
   if (threadIdx.x == 0) emin[g] = red[0];
 }
 
+// Entry C - 1 of every query's probe-slot-0 list set to KEY_NONE: a list that
+// no scan item writes (its probe is outside 0 .. G-1) then bounds nothing.
+__global__ void reset_slot0_tail_kernel(uint64_t* __restrict__ part, int64_t nq, int P, int C) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) part[(size_t)q * P * C + C - 1] = KEY_NONE;
+}
+
 }  // namespace
+
+void launch_reset_slot0_tail(uint64_t* part, int64_t nq, int P, int C, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(reset_slot0_tail_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, part, nq, P, C);
+  HIP_TRY(hipGetLastError());
+}
 
 void launch_scan(const Index& ix, int codes, const float* T, const float* epsq, int P, int C, const Buckets& b,
                  int list, uint64_t* part, const uint64_t* bound_lists, bool prune, unsigned long long* scored,

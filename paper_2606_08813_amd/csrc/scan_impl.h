@@ -156,12 +156,17 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
       // coordinates saturated -> the grain is pruned for this query
       if (live[t] && 4 * nsat[t] > r) {
         live[t] = false;
-        if (lane == 0) part[(size_t)pairs[t] * C] = KEY_NONE;  // empty list
+        // empty list: every entry, so that a bound read from entry C - 1 of a
+        // slot-0 list never sees a key left by an earlier search
+        for (int i = lane; i < C; i += HNTL_WAVE) part[(size_t)pairs[t] * C + i] = KEY_NONE;
       }
     }
     if (live[t] && bound_lists) {
       const int p = pairs[t];
-      bnd = bound_lists[((size_t)(p / P) * P) * C + C - 1];  // C-th key of the query's probe-0 list
+      // C-th key of the query's probe-0 list: KEY_NONE when that list holds
+      // fewer than C candidates, was pruned, or was never written (an invalid
+      // probe; the caller resets that entry before the slot-0 pass)
+      bnd = bound_lists[((size_t)(p / P) * P) * C + C - 1];
       // that key holds an original id while this scan keys by grain position:
       // keep every candidate whose distance does not exceed the bound's, so an
       // exact distance tie is settled by the merge, in (distance, id) order
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
         const float lb = wave_sum(dd * dd) + eq[t] + emin[g];
         if (lb * (1.f - PRUNE_SLACK) > key_dist(bnd)) {
           live[t] = false;
-          if (lane == 0) part[(size_t)p * C] = KEY_NONE;  // empty list
+          for (int i = lane; i < C; i += HNTL_WAVE) part[(size_t)p * C + i] = KEY_NONE;  // empty list
         }
       }
     }

@@ -558,3 +558,134 @@ def test_int16_envelope_filter_prunes_saturated_queries():
     q[:] = 0.5 * amax  # none saturate
     _, pruned = quant.int16_scores(q, 0.0, zh, rh, inv, rinv)
     assert not pruned
+
+
+# ------------------------------------------------- router: Adam and top-P pins
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient g at every step, both moment estimates are
+    unbiased after the bias correction: m_t / (1 - b1^t) = g and
+    v_t / (1 - b2^t) = g^2 for every t, so each step moves a weight by exactly
+    -lr g / (|g| + eps).  A wrong correction exponent, a missing correction or a
+    second moment without the square changes steps 2 and 3 (g = 0.25, -3)."""
+    lr, eps = 1e-3, 1e-8
+    for g in (0.25, -3.0):
+        p = {"w": np.array([1.0])}
+        st = {}
+        for t in (1, 2, 3):
+            router.adam_step(p, {"w": np.array([g])}, st, t, lr=lr, eps=eps)
+            expect = 1.0 - t * lr * g / (abs(g) + eps)
+            assert abs(p["w"][0] - expect) <= 1e-15, (g, t, p["w"][0], expect)
+
+
+def test_adam_two_steps_hand_derived():
+    """Gradient 1 then 0.  Step 1 moves by -lr / (1 + eps).  After step 2,
+    m = b1 (1 - b1) and v = b2 (1 - b2), so the corrected moments are
+    b1 (1 - b1) / (1 - b1^2) = b1 / (1 + b1) and b2 / (1 + b2): step 2 moves by
+    -lr (b1 / (1 + b1)) / (sqrt(b2 / (1 + b2)) + eps).  With b1 = 0.9,
+    b2 = 0.999: 0.9 / 1.9 = 0.473684..., sqrt(0.999 / 1.999) = 0.706929...,
+    a second step of -0.670058... lr."""
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    p = {"w": np.array([0.0])}
+    st = {}
+    router.adam_step(p, {"w": np.array([1.0])}, st, 1, lr=lr, b1=b1, b2=b2, eps=eps)
+    assert abs(p["w"][0] + lr / (1 + eps)) <= 1e-18
+    router.adam_step(p, {"w": np.array([0.0])}, st, 2, lr=lr, b1=b1, b2=b2, eps=eps)
+    step2 = (b1 / (1 + b1)) / (math.sqrt(b2 / (1 + b2)) + eps)
+    assert abs(step2 - 0.6700585) < 1e-6
+    assert abs(p["w"][0] - (-lr / (1 + eps) - lr * step2)) <= 1e-17
+
+
+def _loop_top_p_desc(s, P):
+    """Plain selection: P times, the largest remaining score; ties to the lower index."""
+    out = []
+    taken = set()
+    for _ in range(P):
+        best = None
+        for g in range(len(s)):
+            if g in taken:
+                continue
+            if best is None or s[g] > s[best]:
+                best = g
+        taken.add(best)
+        out.append(best)
+    return out
+
+
+def test_route_learned_is_plain_top_p_of_scores_with_ties():
+    """route_learned returns the P largest router scores, ties to the lower
+    grain: checked against a plain selection loop, with planted exact ties
+    (two grains given identical output rows and biases)."""
+    rng = np.random.default_rng(11)
+    d, G, P = 10, 13, 5
+    params = router.init_params((d, 12, 12, G), seed=5)
+    for a, b in ((3, 9), (4, 11), (0, 7)):
+        params["W3"][b] = params["W3"][a]
+        params["b3"][b] = params["b3"][a]
+    x = rng.normal(size=(30, d))
+    mean, std = x.mean(0), x.std(0)
+    s, _ = router.forward(params, x, mean, std, bf16=True)
+    assert (s[:, 3] == s[:, 9]).all() and (s[:, 0] == s[:, 7]).all()
+    probes, sc = router.route_learned(params, x, mean, std, P)
+    for i in range(len(x)):
+        ref = _loop_top_p_desc(s[i], P)
+        assert probes[i].tolist() == ref
+        np.testing.assert_array_equal(sc[i], s[i, ref])
+    # every tie that reaches the top P lists the lower grain first
+    for i in range(len(x)):
+        li = probes[i].tolist()
+        for a, b in ((3, 9), (4, 11), (0, 7)):
+            if a in li and b in li:
+                assert li.index(a) < li.index(b)
+
+
+def _stored_for_projection(centroids, basis):
+    return {"centroids": np.asarray(centroids, np.float32), "basis": np.asarray(basis, np.float32)}
+
+
+def test_bf16_projection_exact_when_operands_are_representable():
+    """With q, mu and W whose values are BF16-representable and whose
+    differences q - mu are exact in float32 and in BF16, the BF16 projection
+    rounds nothing: z equals the plain projection bit for bit and eps_q equals
+    it to rounding (Pythagoras against the explicit residual)."""
+    rng = np.random.default_rng(17)
+    d, r, G = 16, 4, 2
+    # orthonormal W with BF16-representable entries: signed unit vectors and
+    # (+-1/2) Hadamard-like rows on disjoint supports
+    basis = np.zeros((G, r, d))
+    for g in range(G):
+        cols = rng.permutation(d)
+        for j in range(r):
+            basis[g, j, cols[4 * j:4 * j + 4]] = 0.5 * rng.choice([-1.0, 1.0], size=4)
+    # small integers: exact in float32 and in BF16 (|v| < 256), and so are their differences
+    centroids = rng.integers(-20, 21, size=(G, d)).astype(np.float64)
+    Q = rng.integers(-20, 21, size=(6, d)).astype(np.float64)
+    st = _stored_for_projection(centroids, basis)
+    probes = np.array([[0, 1]] * len(Q))
+    z, e = osr.project(Q, probes, st)
+    zb, eb = osr.project(Q, probes, st, bf16=True)
+    np.testing.assert_array_equal(zb, z)
+    np.testing.assert_allclose(eb, e, rtol=1e-12, atol=1e-12)
+    # hand check of one coordinate: z_j = W_j . (q - mu)
+    assert zb[0, 1, 2] == float(basis[1, 2] @ (Q[0] - centroids[1]))
+
+
+def test_bf16_projection_rounds_the_centred_query():
+    """Only q' is off the BF16 grid (W is the identity on two coordinates), so
+    the BF16 projection returns exactly bf16(q'): 1 + 2^-10 -> 1 (nearest),
+    1 + 3 * 2^-8 -> 1 + 2^-6 (a tie between 1 + 2^-7 and 1 + 2^-6, to the even
+    mantissa), 3 -> 3.  An emulation that forgot to round q' returns q'."""
+    d = 4
+    basis = np.zeros((1, 3, d))
+    basis[0, 0, 0] = basis[0, 1, 1] = basis[0, 2, 2] = 1.0
+    centroids = np.zeros((1, d))
+    Q = np.array([[1 + 2.0 ** -10, 1 + 3 * 2.0 ** -8, 3.0, 0.75]])
+    st = _stored_for_projection(centroids, basis)
+    probes = np.array([[0]])
+    zb, eb = osr.project(Q, probes, st, bf16=True)
+    np.testing.assert_array_equal(zb[0, 0], [1.0, 1 + 2.0 ** -6, 3.0])
+    z, e = osr.project(Q, probes, st)
+    np.testing.assert_array_equal(z[0, 0], np.float32(Q[0, :3]).astype(np.float64))
+    # eps_q by Pythagoras from the unrounded q': ||q'||^2 - ||z_bf16||^2
+    qn = float((np.float32(Q[0]).astype(np.float64) ** 2).sum())
+    assert eb[0, 0] == max(0.0, qn - float(zb[0, 0] @ zb[0, 0]))
