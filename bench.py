@@ -1,28 +1,37 @@
 """Benchmark of the HNTL search path on one MI355X.
 
-Workload (default): 1,000,000 patch-mixture vectors, d = 768, 1,024 patches;
-index G = 1,024 k-means grains, r = 32; one batch of 10,000 queries; P = 8,
-C = 64, k = 10; FP32.  A step is one full search of the batch (route, bucket,
-project, scan + select, merge + rerank), inputs resident in HBM, run by an
-autotuned search plan (the persistent fused project-scan-select kernel, launch
-sequence replayed as a HIP graph; stage times come from an eager profiled run).
+Workload (default): the batching workload, 10,000,000 patch-mixture vectors,
+d = 768, Zipf(1.1)-sized patches (16..20,000 members) over 8,192 patches;
+index G = 8,192 k-means grains, r = 48; batches of 16,384 queries; P = 16,
+C = 100, k = 10; FP32 codes.  A step is one full search of the batch (route,
+bucket, project, scan + select, merge + rerank), inputs resident in HBM, run
+by an autotuned search plan (the persistent fused project-scan-select kernel,
+launch sequence replayed as a HIP graph; stage times come from eager profiled
+runs with HIP events on the plan's stream).
 
-Other forms (same JSON line; --workload zipf10M_d768_G8192_r48 is the 10M-vector
-Zipf-grain batching workload, 16,384 queries per step, P = 16, C = 100):
-  --form staged    hntl_search: one launch per stage, stage times from the
-                   library's HIP events during the timed steps
+Beside the headline (plain FP32 plan) the same JSON line carries, by default on
+the batching workload:
+  learned_bf16   the learned router (768-1024-1024-8192, trained first on
+                 200,000 generated queries with brute-force kNN targets) with
+                 BF16 codes and BF16 projection, same P and C, its Recall@10 on
+                 the same query sample and its speed-up over the plain form
+  scan_hbm       the scan in its HBM-bound regime: a 256-query batch, the fused
+                 scan kernel's time against the unique code bytes of the
+                 probed grains
+  uneven_batches a seeded sequence of uneven batch sizes (1 .. 16,384,
+                 65,536 queries in total) through one plan
+  cpu_baseline   the CPU oracle (FP64 numpy) on a bounded query sample, over a
+                 process pool on the host cores
+
+Other forms are flags of the same script:
+  --workload patch1M_d768_G1024_r32   the 1M-vector plain workload
+  --form staged    hntl_search: one launch per stage
   --sched ...      a fixed plan schedule instead of the autotuner's
-  --route learned  the learned router, trained first on --router-train
-                   generated queries with brute-force kNN targets
+  --route learned  the learned router as the headline form
   --codes bf16|fp8 reduced-precision codes (BF16 MFMA projection by default)
-  --codes int16    the paper's own int16 form (eq. 5, envelope filter; staged search)
+  --codes int16    the paper's own int16 form (eq. 5, envelope filter)
   --mode A         the answer from the index alone (no raw-vector rerank)
-
-Prints one JSON line: queries/s (whole job), ns per vector scanned,
-Recall@10 against exact brute force on a query sample, per-stage device times
-from HIP events recorded by the library on its stream during the timed steps,
-the roofline of the dominant kernel, and the CPU oracle timed on a bounded
-query sample on the host.
+  --route-form     centroid routing's shortlist products (fp32, bf16, bf16x3)
 """
 from __future__ import annotations
 
@@ -41,29 +50,31 @@ sys.path.insert(0, str(ROOT))
 METRIC = "queries/sec and ns/vector scanned at Recall@10≥0.95; scan HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-FP32_VALU_PEAK_TFLOPS = 157.3
+# FP32 VALU without packed math (every HIP source is built with packed FP32
+# off): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-
-# HBM traffic of the default workload's dominant kernel (merge + rerank) from
-# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
-# scaled by its reading for a plain 1 GiB device copy; valid while the kernel
-# source is unchanged (sha1 below).  Recorded in
-# profiles/merge_rerank_patch1M_d768_G1024_r32_hbm_counters.md.
-TRAFFIC = {"stage": "rerank", "workload": "patch1M_d768_G1024_r32", "form": "plan", "codes": "fp32", "P": 8, "mode": "B",
-           "src": "paper_2606_08813_amd/csrc/rerank.hip", "sha1": "4616a1568044311e49c3d3680623e71d312b47f8",
-           "fetch_kib": 994974.9, "fetch_scale": 1048576.0 / 524307.8125, "write_kib": 1250.0, "write_scale": 1.0}
+# Measured DRAM traffic (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, each scaled by its reading for a plain 1 GiB device copy) of
+# kernels on given workloads; valid while the kernel's sources are unchanged
+# (sha1 of the listed files).  Each entry names the profile summary it comes
+# from.
+TRAFFIC = []
 
 
-def measured_traffic(stage, workload, form, codes, P, mode):
+def measured_traffic(kernel, workload, form, codes, P, mode, batch):
     import hashlib
-    t = TRAFFIC
-    if (stage, workload, form, codes, P, mode) != (t["stage"], t["workload"], t["form"], t["codes"], t["P"], t["mode"]):
-        return None
-    src = ROOT / t["src"]
-    if not src.exists() or hashlib.sha1(src.read_bytes()).hexdigest() != t["sha1"]:
-        return None  # the kernel changed since the counters were taken
-    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
+    for t in TRAFFIC:
+        if (kernel, workload, form, codes, P, mode, batch) != (t["kernel"], t["workload"], t["form"], t["codes"],
+                                                               t["P"], t["mode"], t["batch"]):
+            continue
+        for src, sha in t["sources"].items():
+            p = ROOT / src
+            if not p.exists() or hashlib.sha1(p.read_bytes()).hexdigest() != sha:
+                return None  # the kernel changed since the counters were taken
+        return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
+    return None
 
 
 def log(*a):
@@ -113,18 +124,109 @@ def fp64_grain_scores(q, g, ex):
     return ex["perm"][a:b], ((Z - z) ** 2).sum(1) + float(e @ e) + ex["eps"][a:b].astype(np.float64)
 
 
+def uneven_batch_sizes(total=65536, seed=104):
+    """Seeded uneven batch sizes: 1, 2, 7, 64, 500, 1000, 4096, 8192, 16384,
+    then log-uniform draws in [1, 16384] until the sizes sum to `total` (the last
+    one cut to fit)."""
+    sizes = [1, 2, 7, 64, 500, 1000, 4096, 8192, 16384]
+    rng = np.random.default_rng(seed)
+    while sum(sizes) < total:
+        sizes.append(int(np.exp(rng.uniform(0.0, np.log(16384.0)))))
+    sizes[-1] -= sum(sizes) - total
+    return [s for s in sizes if s > 0]
+
+
+# ------------------------------------------------------- CPU oracle over a pool
+# The pool is forked before anything touches the GPU; the workers read the
+# corpus and queries inherited from the parent and the index from files the
+# parent writes after the GPU build.  They run the oracle only.
+_CPU = {}
+
+
+def _cpu_worker_init():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        _CPU["limit"] = threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _cpu_worker_run(job):
+    from oracle import search as osr
+    path, idx, P, C, k, mode = job
+    if _CPU.get("path") != path:
+        _CPU["ex"] = {f[:-4]: np.load(os.path.join(path, f), mmap_mode="r") for f in os.listdir(path)
+                      if f.endswith(".npy")}
+        _CPU["path"] = path
+    t0 = time.time()
+    osr.search(_CPU["queries"][idx], _CPU["ex"], _CPU["corpus"], P, C, k, mode=mode)
+    return len(idx), time.time() - t0
+
+
+def start_cpu_pool(corpus_X, queries_X):
+    import multiprocessing as mp
+    n = max(1, min(len(os.sched_getaffinity(0)), 16))
+    _CPU["corpus"] = corpus_X
+    _CPU["queries"] = queries_X
+    ctx = mp.get_context("fork")
+    return ctx.Pool(n, initializer=_cpu_worker_init), n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(pool, ncores, ex, nq, P, C, k, mode, seconds, scanned_per_query):
+    """Wall time of the oracle over the pool on chunks of 8 sampled queries,
+    stopping once `seconds` have passed; queries/s = completed / wall."""
+    import shutil
+    import tempfile
+    d = tempfile.mkdtemp(prefix="hntl_oracle_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    try:
+        for key in ("centroids", "basis", "offsets", "perm", "codes", "eps"):
+            np.save(os.path.join(d, key + ".npy"), np.ascontiguousarray(ex[key]))
+        order = np.random.default_rng(11).permutation(nq)
+        jobs = [(d, order[i:i + 8], P, C, k, mode) for i in range(0, nq, 8)]
+        done = 0
+        t0 = time.time()
+        for cnt, _ in pool.imap_unordered(_cpu_worker_run, jobs):
+            done += cnt
+            if time.time() - t0 > seconds:
+                break
+        wall = time.time() - t0
+        pool.terminate()
+        pool.join()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    qps = done / wall
+    return {"value": round(qps, 2), "unit": "queries/s", "cores": ncores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{done} of the {nq} queries in seeded random order (chunks of 8 over {ncores} worker "
+                      f"processes, one thread each, until {seconds:g} s of wall time), the full lifecycle in float64 "
+                      f"(numpy), same index and corpus; {wall:.1f} s",
+            "ns_per_vector_scanned_per_core": round(wall * ncores / done / scanned_per_query * 1e9, 2)}
+
+
+# ------------------------------------------------------------------- the GPU side
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="patch1M_d768_G1024_r32")
+    ap.add_argument("--workload", default="zipf10M_d768_G8192_r48")
     ap.add_argument("--codes", choices=("fp32", "bf16", "fp8", "int16"), default="fp32")
     ap.add_argument("--recall-sample", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=-1,
-                    help="most queries timed on the CPU oracle (-1 = the whole batch, 0 = skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="the CPU oracle runs on chunks of 25 sampled queries until this much time has passed")
+                    help="0 skips the CPU oracle baseline; otherwise it runs for --cpu-seconds")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="wall seconds of the CPU oracle over the process pool")
     ap.add_argument("--no-profile", action="store_true", help="skip per-stage HIP event records")
     ap.add_argument("--no-prune", action="store_true", help="scan every member of every probed grain")
     ap.add_argument("--fp32-project", action="store_true",
@@ -141,11 +243,20 @@ def parse():
     ap.add_argument("--tau", type=float, default=0.0, help="learned routing: centroid fallback below this max prob")
     ap.add_argument("--mode", choices=("A", "B"), default="B",
                     help="B: exact rerank against the raw vectors; A: the answer from the index alone")
-    ap.add_argument("--route-split", choices=("auto", "on", "off"), default="auto",
-                    help="centroid routing shortlist from the split-BF16 library GEMM (auto: on when d % 8 == 0); "
-                         "the probes are picked by FP32 direct differences either way")
+    ap.add_argument("--route-form", choices=("auto", "fp32", "bf16", "bf16x3"), default="auto",
+                    help="centroid routing shortlist products: FP32 MFMA, one BF16 MFMA product, or three over "
+                         "split BF16 operands (auto: bf16 when d % 8 == 0); the probes are picked by FP32 direct "
+                         "differences either way")
     ap.add_argument("--router-train", type=int, default=200000, help="router training queries")
     ap.add_argument("--router-epochs", type=int, default=8)
+    ap.add_argument("--compare", choices=("auto", "on", "off"), default="auto",
+                    help="also time the learned router + BF16 codes + BF16 projection plan at the same P and C "
+                         "(auto: on for the batching workload's default plain FP32 plan)")
+    ap.add_argument("--hbm-batch", type=int, default=-1,
+                    help="queries of the scan's HBM-regime measurement (-1: 256 on the batching workload, 0: off)")
+    ap.add_argument("--uneven", choices=("auto", "on", "off"), default="auto",
+                    help="time the seeded uneven batch sequence through one plan (auto: on for the batching "
+                         "workload's default plan)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time every (P, C) of {1,2,4,8,16,32} x {k, 2k, 20, 64, 100, 200} as a tuned plan and "
                          "report the fastest with Recall@10 >= 0.95 on the recall sample (operating point)")
@@ -157,20 +268,69 @@ def parse():
     return ap.parse_args()
 
 
+def time_plan(hntl, torch, ix, Q, P, C, k, nq, codes, flags, rkw, steps, warmup, sched_arg=""):
+    """Autotune (or take) a schedule, build a graph plan for nq queries and time
+    `steps` replays; returns the plan, its ids / dist outputs and the timings."""
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    if sched_arg:
+        sched = {kk: int(v) for kk, v in (kv.split("=") for kv in sched_arg.split(","))}
+        sched = hntl.sched_dict(hntl._sched(dict({"grid": 0, "passes": 1, "proj": 0}, **sched)))
+    else:
+        sched, _ = hntl.hntl_tune(ix, Q, P, C, k, codes=codes, flags=flags, **rkw)
+    tune_s = time.time() - t0
+    plan = hntl.hntl_plan_create(ix, P, C, k, nq, codes=codes, flags=flags, sched=sched, graph=True, **rkw)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    for _ in range(warmup):
+        hntl.hntl_plan_search(plan, Q, out=(ids, dist))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        hntl.hntl_plan_search(plan, Q, out=(ids, dist))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    stage, scored = hntl.hntl_plan_profile(plan, nq, reps=3)
+    stage = {("scan" if kk == "fused" else kk): v for kk, v in stage.items()}
+    if not sched["proj"]:  # the projection runs inside the fused kernel: no stage of its own
+        stage.pop("project")
+    assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
+    return dict(plan=plan, ids=ids, dist=dist, ms=ms, stage=stage, scored=scored, sched=sched, tune_s=tune_s)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the search path runs on a single MI355X; sharding across GPUs is described, not built).", file=sys.stderr)
+              "(the search path runs on a single MI355X; sharding across GPUs is described, not built).",
+              file=sys.stderr)
         sys.exit(2)
-    import torch
     from workloads import WORKLOADS
-    from paper_2606_08813_amd import hntl
-
     if args.codes == "int16" and args.form == "plan":
         print("the int16 form (eq. 5) runs in the staged search only: add --form staged", file=sys.stderr)
         sys.exit(2)
     W = WORKLOADS[args.workload]
+    batching = W.name == "zipf10M_d768_G8192_r48"
+    headline_plain = args.form == "plan" and args.route == "centroid" and args.codes == "fp32" and args.mode == "B"
+    compare = args.compare == "on" or (args.compare == "auto" and batching and headline_plain)
+    uneven = args.uneven == "on" or (args.uneven == "auto" and batching and headline_plain)
+    hbm_batch = (256 if batching and args.form == "plan" else 0) if args.hbm_batch < 0 else args.hbm_batch
+
+    t0 = time.time()
+    corpus = W.corpus()
+    queries = W.queries()
+    log(f"[bench] generated {W.N}x{W.d} corpus + {W.nq} queries in {time.time() - t0:.1f}s")
+    pool = None
+    if args.cpu_sample != 0:  # forked now, before the GPU is touched
+        pool, ncores = start_cpu_pool(corpus.X, queries.X)
+        log(f"[bench] CPU oracle pool: {ncores} worker processes ({cpu_model()})")
+
+    import torch
+    from paper_2606_08813_amd import hntl
+
     if args.copy_gib > 0:  # a copy of known size: n bytes read, n bytes written
         n = int(args.copy_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -181,18 +341,15 @@ def main():
         log(f"[bench] calibration copy of {n * 4} bytes")
         del src, dst
         torch.cuda.empty_cache()
-    t0 = time.time()
-    corpus = W.corpus()
-    queries = W.queries()
-    log(f"[bench] generated {W.N}x{W.d} corpus + {W.nq} queries in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     X = torch.from_numpy(corpus.X).to(dev)
     Q = torch.from_numpy(queries.X).to(dev)
     torch.cuda.synchronize()
 
     t0 = time.time()
-    codes_list = ("fp32",) if args.codes == "fp32" else ("fp32", args.codes)
-    ix = hntl.hntl_build(X, W.G, W.r, seed=W.kmeans_seed, codes=codes_list)
+    codes_list = ["fp32"] + ([args.codes] if args.codes != "fp32" else []) + (["bf16"] if compare else [])
+    codes_list = list(dict.fromkeys(codes_list))
+    ix = hntl.hntl_build(X, W.G, W.r, seed=W.kmeans_seed, codes=tuple(codes_list))
     torch.cuda.synchronize()
     build_s = time.time() - t0
     info = hntl.hntl_index_info_get(ix)
@@ -204,7 +361,7 @@ def main():
     stream = torch.cuda.current_stream()
     P = args.P or W.P
     router = None
-    if args.route == "learned":
+    if args.route == "learned" or compare:
         from workloads.configs import ROUTER_TRAIN_SEED
         t0 = time.time()
         Qtr = torch.from_numpy(W.queries(nq=args.router_train, query_seed=ROUTER_TRAIN_SEED).X).to(dev)
@@ -216,79 +373,55 @@ def main():
                   "tau": args.tau}
         log(f"[bench] router trained in {router['train_s']}s, losses {router['epoch_loss']}")
         del Qtr
-    ids = torch.empty((W.nq, W.k), dtype=torch.int32, device=dev)
-    dist = torch.empty((W.nq, W.k), dtype=torch.float32, device=dev)
     flags = 0 if args.no_profile else hntl.HNTL_FLAG_PROFILE
     if args.no_prune:
         flags |= hntl.HNTL_FLAG_NO_PRUNE
     bf16_project = args.codes in ("bf16", "fp8") and not args.fp32_project
     if bf16_project:
         flags |= hntl.HNTL_FLAG_PROJECT_BF16
-    route_split = args.route == "centroid" and (args.route_split == "on" or
-                                                (args.route_split == "auto" and W.d % 8 == 0))
-    if route_split:
-        flags |= hntl.HNTL_FLAG_ROUTE_BF16X3
+    route_form = None
+    if args.route == "centroid":
+        route_form = args.route_form if args.route_form != "auto" else ("bf16" if W.d % 8 == 0 else "fp32")
+        flags |= {"fp32": 0, "bf16": hntl.HNTL_FLAG_ROUTE_BF16, "bf16x3": hntl.HNTL_FLAG_ROUTE_BF16X3}[route_form]
     if args.mode == "A":
         flags |= hntl.HNTL_FLAG_MODE_A
     rkw = dict(route=args.route, tau=args.tau)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    plan_mask = (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3 |
+                 hntl.HNTL_FLAG_ROUTE_BF16 | hntl.HNTL_FLAG_MODE_A)
+    pflags = flags & plan_mask
     sched = None
     if args.form == "staged":
+        ids = torch.empty((W.nq, W.k), dtype=torch.int32, device=dev)
+        dist = torch.empty((W.nq, W.k), dtype=torch.float32, device=dev)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         for _ in range(args.warmup):
             hntl.hntl_search(ix, Q, P, W.C, W.k, codes=args.codes, flags=flags & ~hntl.HNTL_FLAG_PROFILE,
                              out=(ids, dist), **rkw)
         torch.cuda.synchronize()
         hntl.hntl_profile_read()  # drop warm-up records
         torch.cuda.synchronize()
-        wall0 = time.perf_counter()
         ev0.record(stream)
         for _ in range(args.steps):
             hntl.hntl_search(ix, Q, P, W.C, W.k, codes=args.codes, flags=flags, out=(ids, dist), **rkw)
         ev1.record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
         ms_per_step = ev0.elapsed_time(ev1) / args.steps
         stage_ms, calls, scored_total = hntl.hntl_profile_read()
-        stage_avg = {k: v / max(1, calls) for k, v in stage_ms.items()}
+        stage_avg = {kk: v / max(1, calls) for kk, v in stage_ms.items()}
         scored = scored_total // max(1, calls)  # eq. 6 scores actually computed per step
     else:
-        pflags = flags & (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3 |
-                          hntl.HNTL_FLAG_MODE_A)
-        t0 = time.time()
-        if args.sched:
-            sched = {k: int(v) for k, v in (kv.split("=") for kv in args.sched.split(","))}
-            sched = hntl.sched_dict(hntl._sched(dict({"grid": 0, "passes": 1, "proj": 0}, **sched)))
-            log(f"[bench] given schedule {sched}")
-        else:
-            sched, tuned_ms = hntl.hntl_tune(ix, Q, P, W.C, W.k, codes=args.codes, flags=pflags, **rkw)
-            log(f"[bench] autotuned schedule {sched} ({tuned_ms:.3f} ms) in {time.time() - t0:.1f}s")
-        plan = hntl.hntl_plan_create(ix, P, W.C, W.k, W.nq, codes=args.codes, flags=pflags, sched=sched,
-                                     graph=True, **rkw)
-        for _ in range(args.warmup):
-            hntl.hntl_plan_search(plan, Q, out=(ids, dist))
-        torch.cuda.synchronize()
-        wall0 = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            hntl.hntl_plan_search(plan, Q, out=(ids, dist))
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
-        ms_per_step = ev0.elapsed_time(ev1) / args.steps
-        stage_avg, scored = hntl.hntl_plan_profile(plan, W.nq, reps=3)
-        stage_avg = {("scan" if k == "fused" else k): v for k, v in stage_avg.items()}
-        if not sched["proj"]:  # the projection runs inside the fused kernel: no stage of its own
-            stage_avg.pop("project")
-        assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
+        r = time_plan(hntl, torch, ix, Q, P, W.C, W.k, W.nq, args.codes, pflags, rkw, args.steps, args.warmup,
+                      args.sched)
+        ids, dist, ms_per_step, stage_avg, scored, sched = r["ids"], r["dist"], r["ms"], r["stage"], r["scored"], r["sched"]
+        log(f"[bench] schedule {sched} (tuning {r['tune_s']:.1f}s)")
+        del r
     qps = W.nq / (ms_per_step / 1e3)
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
-        f"{qps:,.0f} queries/s; stages {stage_avg}")
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, {qps:,.0f} queries/s; stages {stage_avg}")
 
-    # work accounting from one staged run (probes -> vectors scanned per step)
+    # work accounting from one staged run (probes -> vectors in the probed grains per step)
     o = hntl.hntl_search_stages(ix, Q, P, W.C, W.k, codes=args.codes,
-                                flags=hntl.HNTL_FLAG_SYNC | (flags & (hntl.HNTL_FLAG_PROJECT_BF16 |
-                                                                     hntl.HNTL_FLAG_ROUTE_BF16X3)), **rkw)
+                                flags=hntl.HNTL_FLAG_SYNC | (flags & plan_mask & ~hntl.HNTL_FLAG_NO_PRUNE), **rkw)
     probes = o["probes"].cpu().numpy()
     ex = hntl.hntl_index_export(ix)
     sizes = np.diff(ex["offsets"])
@@ -337,10 +470,9 @@ def main():
     npairs = W.nq * P
     rp = (W.r + 7) // 8 * 8
     code_bytes = {"fp32": 4, "bf16": 2, "fp8": 1, "int16": 2}[args.codes]
-    # the split-BF16 shortlist runs three BF16 products per FP32 product, on the BF16 units
     route_work = (2.0 * W.nq * (W.d * 1024 + 1024 * 1024 + 1024 * W.G) if args.route == "learned"
-                  else 2.0 * W.nq * W.G * W.d * (3 if route_split else 1))
-    route_bf16 = args.route == "learned" or route_split
+                  else 2.0 * W.nq * W.G * W.d * (3 if route_form == "bf16x3" else 1))
+    route_bf16 = args.route == "learned" or route_form in ("bf16", "bf16x3")
     per_stage = {
         "route": dict(bound="mfma", work=route_work, unit="TFLOP/s",
                       peak=BF16_MFMA_PEAK_TFLOPS if route_bf16 else FP32_MFMA_PEAK_TFLOPS),
@@ -359,30 +491,80 @@ def main():
         roof[name] = {"bound": s["bound"], "achieved": round(achieved, 3), "peak": s["peak"], "unit": s["unit"],
                       "frac": round(achieved / s["peak"], 4), "ms": round(stage_avg[name], 4)}
     dominant = max(roof, key=lambda n: roof[n]["ms"]) if roof else None
-    scan_bytes = (scored or scanned) * (rp * code_bytes + 4)
     scan_ms = stage_avg.get("scan", 0.0)
-    scan_stream_gbs = scan_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None
 
-    # CPU oracle on a bounded query sample against the same index (timing only)
+    # the scan in its HBM-bound regime: a small batch whose probed grains' codes
+    # exceed the MALL, each probed grain's code blocks read once per pair tile
+    scan_hbm = None
+    if hbm_batch > 0 and args.form == "plan":
+        nb = min(hbm_batch, W.nq)
+        Qh = Q[:nb].contiguous()
+        rh = time_plan(hntl, torch, ix, Qh, P, W.C, W.k, nb, args.codes, pflags, rkw, args.steps, 2)
+        ph = hntl.hntl_search_stages(ix, Qh, P, W.C, W.k, codes=args.codes,
+                                     flags=hntl.HNTL_FLAG_SYNC | (pflags & ~hntl.HNTL_FLAG_NO_PRUNE), **rkw)["probes"]
+        pg = np.unique(ph.cpu().numpy())
+        pg = pg[pg >= 0]
+        nblk = (sizes[pg] + 63) // 64
+        unique_bytes = int(nblk.sum()) * 64 * (rp * code_bytes + 4)
+        t_scan = rh["stage"]["scan"]
+        traffic = measured_traffic("fused_scan", W.name, "plan", args.codes, P, args.mode, nb)
+        scan_hbm = {"batch": nb, "schedule": rh["sched"], "scan_ms": round(t_scan, 4),
+                    "probed_grains": int(len(pg)), "unique_code_bytes": unique_bytes,
+                    "scored": int(rh["scored"]),
+                    "achieved_GBps": round(unique_bytes / (t_scan / 1e3) / 1e9, 1),
+                    "peak_GBps": HBM_PEAK_GBS,
+                    "frac": round(unique_bytes / (t_scan / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "dram_traffic": traffic,
+                    "dram_GBps": round(traffic / (t_scan / 1e3) / 1e9, 1) if traffic else None,
+                    "ms_per_batch": round(rh["ms"], 4)}
+        log(f"[bench] scan HBM regime ({nb} queries): {scan_hbm}")
+        del rh
+
+    # the seeded uneven batch sequence through one plan (graph replays)
+    uneven_out = None
+    if uneven and args.form == "plan":
+        seq = uneven_batch_sizes(65536, seed=W.seed)
+        Qu = torch.from_numpy(W.queries(nq=W.nq, query_seed=W.seed + 5000).X).to(dev)
+        ru = time_plan(hntl, torch, ix, Qu, P, W.C, W.k, W.nq, args.codes, pflags, rkw, 1, 1, args.sched)
+        plan_u = ru["plan"]
+        views = [Qu[:nbq].contiguous() for nbq in seq]
+        for v in views[:3]:
+            hntl.hntl_plan_search(plan_u, v)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for v in views:
+            hntl.hntl_plan_search(plan_u, v)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_u = ev0.elapsed_time(ev1)
+        uneven_out = {"batches": len(seq), "queries": int(sum(seq)), "min_batch": int(min(seq)),
+                      "max_batch": int(max(seq)), "seed": W.seed, "ms": round(ms_u, 3),
+                      "queries_per_s": round(sum(seq) / (ms_u / 1e3), 1), "schedule": ru["sched"]}
+        log(f"[bench] uneven batches: {uneven_out}")
+        del ru, plan_u, Qu, views
+
+    # the learned router + BF16 codes + BF16 projection at the same P and C
+    learned = None
+    if compare:
+        fl_l = hntl.HNTL_FLAG_PROJECT_BF16
+        rl = time_plan(hntl, torch, ix, Q, P, W.C, W.k, W.nq, "bf16", fl_l, dict(route="learned", tau=args.tau),
+                       args.steps, args.warmup)
+        rec_l = recall_at_k(rl["ids"].cpu().numpy()[rs], gt, W.k)
+        learned = {"form": "plan", "route": "learned", "codes": "bf16", "projection": "bf16", "P": P, "C": W.C,
+                   "value": round(W.nq / (rl["ms"] / 1e3), 1), "ms_per_step": round(rl["ms"], 4),
+                   "recall_at_10": round(rec_l, 4), "stage_ms": {kk: round(v, 4) for kk, v in rl["stage"].items()},
+                   "schedule": rl["sched"], "speedup_vs_plain_fp32": round(ms_per_step / rl["ms"], 4),
+                   "vectors_scored_per_step": int(rl["scored"])}
+        log(f"[bench] learned + BF16: {learned}")
+        del rl
+
+    # CPU oracle over the process pool, on the same index (timing only)
     cpu = None
-    if args.cpu_sample != 0:
-        from oracle import search as osr
-        from threadpoolctl import threadpool_limits
-        nmax = W.nq if args.cpu_sample < 0 else min(args.cpu_sample, W.nq)
-        order = np.random.default_rng(11).permutation(W.nq)[:nmax]
-        done, el = 0, 0.0
-        with threadpool_limits(1):
-            while done < nmax and el < args.cpu_seconds:
-                cs = order[done:done + 25]
-                t0 = time.time()
-                osr.search(queries.X[cs], ex, corpus.X, P, W.C, W.k, mode=args.mode)
-                el += time.time() - t0
-                done += len(cs)
-        cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} of the {W.nq} queries (chunks of 25 until {args.cpu_seconds:g} s), full "
-                         f"lifecycle in float64 (numpy, 1 thread), same index, {el:.1f}s",
-               "ns_per_vector_scanned": round(el / done / (scanned / W.nq) * 1e9, 2)}
-        log(f"[bench] CPU oracle: {cpu['value']} queries/s on 1 core")
+    if pool is not None:
+        cpu = run_cpu_baseline(pool, ncores, ex, W.nq, P, W.C, W.k, args.mode, args.cpu_seconds, scanned / W.nq)
+        log(f"[bench] CPU oracle: {cpu['value']} queries/s on {cpu['cores']} processes")
 
     # operating point: the fastest (P, C) of the grid at Recall@10 >= 0.95 (plans, tuned per point)
     sweep = None
@@ -394,22 +576,13 @@ def main():
             for Cs in sorted({W.k, 2 * W.k, 20, 64, 100, 200}):
                 if Cs < W.k:
                     continue
-                sc, _ = hntl.hntl_tune(ix, Q, Ps, Cs, W.k, codes=args.codes, flags=pflags, **rkw)
-                pl = hntl.hntl_plan_create(ix, Ps, Cs, W.k, W.nq, codes=args.codes, flags=pflags, sched=sc, **rkw)
-                for _ in range(2):
-                    hntl.hntl_plan_search(pl, Q, out=(ids, dist))
-                torch.cuda.synchronize()
-                ev0.record(stream)
-                reps = max(3, args.steps // 2)
-                for _ in range(reps):
-                    hntl.hntl_plan_search(pl, Q, out=(ids, dist))
-                ev1.record(stream)
-                torch.cuda.synchronize()
-                ms = ev0.elapsed_time(ev1) / reps
-                rec = recall_at_k(ids.cpu().numpy()[rs], gt, W.k)
-                pts.append({"P": Ps, "C": Cs, "queries_per_s": round(W.nq / (ms / 1e3), 1), "recall_at_10": round(rec, 4)})
+                rr = time_plan(hntl, torch, ix, Q, Ps, Cs, W.k, W.nq, args.codes, pflags, rkw,
+                               max(3, args.steps // 2), 2)
+                rec = recall_at_k(rr["ids"].cpu().numpy()[rs], gt, W.k)
+                pts.append({"P": Ps, "C": Cs, "queries_per_s": round(W.nq / (rr["ms"] / 1e3), 1),
+                            "recall_at_10": round(rec, 4)})
                 log(f"[bench] sweep P={Ps} C={Cs}: {pts[-1]['queries_per_s']:,.0f} q/s, Recall@10 {rec:.4f}")
-                del pl
+                del rr
         ok = [p for p in pts if p["recall_at_10"] >= 0.95]
         best = max(ok, key=lambda p: p["queries_per_s"]) if ok else None
         sweep = {"grid": pts, "operating_point": best, "recall_sample": int(len(rs))}
@@ -451,24 +624,25 @@ def main():
         "config": {"workload": W.name, "N": W.N, "d": W.d, "G": W.G, "r": W.r, "queries_per_step": W.nq,
                    "P": P, "C": W.C, "k": W.k, "codes": args.codes,
                    "projection": "bf16" if bf16_project else "fp32", "form": args.form, "route": args.route,
-                   "route_shortlist": "split-bf16" if route_split else ("fp32" if args.route == "centroid" else None),
-                   "mode": args.mode,
-                   "schedule": sched},
+                   "route_shortlist": route_form, "mode": args.mode, "schedule": sched},
         "recall_at_10": round(recall, 4),
-        "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 5),
-        "scan_ns_per_vector_scored": round(scan_ms * 1e6 / scored, 5) if (scan_ms and scored) else None,
-        "vectors_in_probed_grains_per_step": scanned,
+        # per vector actually scored (exact pruning skips most members of non-nearest grains)
+        "scan_ns_per_vector_scored": round(scan_ms * 1e6 / scored, 6) if (scan_ms and scored) else None,
+        "ns_per_vector_scored": round(ms_per_step * 1e6 / scored, 6) if scored else None,
+        "ns_per_vector_scanned": round(ms_per_step * 1e6 / scanned, 6),
         "vectors_scored_per_step": scored,
+        "vectors_in_probed_grains_per_step": scanned,
         "prune": not args.no_prune,
-        # code bytes of the scored vectors per scan second: served from L2 / MALL as much as
-        # from HBM (the measured DRAM rate of the scan is lower), so not an HBM figure
-        "scan_code_GBps_cache_assisted": round(scan_stream_gbs, 1) if scan_stream_gbs else None,
-        "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "stage_ms": {kk: round(v, 4) for kk, v in stage_avg.items()},
         "build_s": round(build_s, 2),
         "captured_variance": round(info["captured_variance"], 5),
         "roofline": dict(roof.get(dominant, {}), kernel=dominant,
-                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode)) if dominant else None,
+                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode, W.nq))
+        if dominant else None,
         "stage_rooflines": roof,
+        "scan_hbm": scan_hbm,
+        "learned_bf16": learned,
+        "uneven_batches": uneven_out,
         "cpu_baseline": cpu,
         "precision": precision,
         "router": router,

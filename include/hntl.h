@@ -88,10 +88,22 @@ typedef enum hntl_codes {
                                 ||q - (mu_g + W_g z_i)||^2 = ||z_q - z_i||^2 + eps_q over the pool (eq. 2-4 and 6;
                                 computed as the pool's eq. 6 score minus eps_i).  The returned distances are
                                 these.  Needs the merged pool (not an injected one) */
-#define HNTL_FLAG_ROUTE_BF16X3 32u /* centroid routing's shortlist from BF16 MFMA with each operand split into a
-                                      BF16 high and low part (q_hi c_hi + q_hi c_lo + q_lo c_hi, FP32 accumulation,
-                                      about 2^-16 relative); the P probes are still chosen on FP32 direct
-                                      differences of the shortlist.  Needs d % 8 == 0 */
+/*
+ * Centroid routing (Section 2.1 step 1).  The P probes are always the P
+ * nearest centroids by FP32 direct differences ||q - mu_g||^2 (ties: lower g).
+ * They are found from a shortlist of expansion distances
+ * ||q||^2 + ||mu_g||^2 - 2 <q, mu_g> whose products run on MFMA in one of three
+ * forms; every shortlist entry that the form's error bound leaves in reach of
+ * the P-th is re-scored by direct differences (a row whose window passes the
+ * shortlist's end is re-read whole), so the form changes speed, not probes.
+ * Without either flag the products are FP32 MFMA.  Setting both is EINVAL.
+ */
+#define HNTL_FLAG_ROUTE_BF16X3 32u /* products on BF16 MFMA with each operand split into a BF16 high and low part
+                                      (q_hi c_hi + q_hi c_lo + q_lo c_hi, FP32 accumulation, about 2^-16
+                                      relative): three BF16 products.  Needs d % 8 == 0 */
+#define HNTL_FLAG_ROUTE_BF16 128u  /* products on BF16 MFMA of bf16(q) . bf16(mu_g) (nearest even, FP32
+                                      accumulation; error at most about 2^-8 (||q||^2 + ||mu||^2) / 2 per entry,
+                                      a wider re-scored window): one BF16 product.  Needs d % 8 == 0 */
 /*
  * Exact pruning.  By default the nearest probed grain of each query is scanned
  * first; its C-th best (D, id) key then bounds the other probed grains: their
@@ -389,7 +401,6 @@ typedef struct hntl_plan_info {
   uint64_t device_bytes;   /* the plan's device buffers */
   uint64_t list_slots;     /* capacity of per-(pair, range) candidate lists */
   uint32_t wait_errors;    /* waits that gave up since creation (0 in a healthy run) */
-  uint32_t lib_route;      /* 1 if routing's products run on the library GEMM (one graph per row bucket) */
 } hntl_plan_info;
 
 /* hntl_plan_info_get - plan facts; synchronises the plan's last stream to read wait_errors. */

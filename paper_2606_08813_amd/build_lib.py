@@ -26,7 +26,7 @@ CFLAGS = [
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-LIBS = ["-lrocblas", "-lrocsolver", "-lhipblaslt"]
+LIBS = ["-lrocblas", "-lrocsolver"]
 
 
 def sources():

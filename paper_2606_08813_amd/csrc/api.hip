@@ -397,6 +397,8 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
   if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
   if ((tangent_in == nullptr) != (epsq_in == nullptr)) return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
   if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
+  if ((sp->flags & HNTL_FLAG_ROUTE_BF16X3) && (sp->flags & HNTL_FLAG_ROUTE_BF16))
+    return fail(HNTL_EINVAL, "choose one centroid routing form");
   const bool learned = sp->route == HNTL_ROUTE_LEARNED && !probes_in && !pool_in;
   if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
   const bool mode_a = (sp->flags & HNTL_FLAG_MODE_A) != 0;
@@ -433,28 +435,14 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
           RouterScratch w;
           char* base = sc.get<char>(w.layout(nullptr, ix, nq, (int)P));
           w.layout(base, ix, nq, (int)P);
-          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s, nullptr, nq);
-        }
-        const int64_t chunk = std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G);
-        float* qn = learned ? nullptr : sc.get<float>(nq);
-        float* Dm = learned ? nullptr : sc.get<float>((size_t)std::min<int64_t>(chunk, nq) * ix.G);
-        const bool split = !learned && (sp->flags & HNTL_FLAG_ROUTE_BF16X3);
-        uint16_t* As = nullptr;
-        if (split) {
-          ensure_centroid_split(const_cast<Index&>(ix), s);  // derived data, made once under a lock
-          As = sc.get<uint16_t>((size_t)std::min<int64_t>(chunk, nq) * 3 * ix.d);
-        }
-        if (!learned) launch_row_norms(Q, nq, (int)ix.d, qn, s);
-        for (int64_t q0 = 0; q0 < nq && !learned; q0 += chunk) {
-          const int64_t rows = std::min<int64_t>(chunk, nq - q0);
-          // dot products on the library GEMM (enough rows), else the distance kernels
-          const bool dots = launch_route_dots(ix, Q + q0 * ix.d, rows, split, As, Dm, s);
-          if (!dots && split)
-            launch_dist_bf16x3(ix, Q + q0 * ix.d, qn + q0, rows, As, Dm, s);
-          else if (!dots)
-            launch_dist_matrix(Q + q0 * ix.d, qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, Dm, s);
-          launch_topk_rows(Dm, rows, (int)ix.G, (int)P, pr + q0 * P, pdist_out ? pdist_out + q0 * P : nullptr, s,
-                           Q + q0 * ix.d, qn + q0, ix.centroids, ix.cnorm, (int)ix.d, nullptr, 0, dots);
+          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s);
+        } else {
+          const int form = route_form(sp->flags);
+          if (form != ROUTE_F32) ensure_centroid_split(const_cast<Index&>(ix), s);  // derived data, made once under a lock
+          RouteScratch w;
+          char* base = sc.get<char>(w.layout(nullptr, ix, nq, form));
+          w.layout(base, ix, nq, form);
+          launch_route_centroid(ix, Q, nq, (int)P, w, pr, pdist_out, s);
         }
         probes = pr;
       }

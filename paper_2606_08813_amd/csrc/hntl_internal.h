@@ -46,8 +46,6 @@ struct Index;
 struct RouterScratch {
   uint16_t *xh = nullptr, *h1 = nullptr, *h2 = nullptr;
   float* negS = nullptr;
-  float* z = nullptr;    // FP32 pre-activations of a hidden layer (library path)
-  float* nb2 = nullptr;  // negated output bias (library path)
   int32_t *fb_rows = nullptr, *fb_count = nullptr, *fb_probes = nullptr;
   float *fb_Q = nullptr, *fb_qn = nullptr, *fb_pdist = nullptr;
   size_t layout(char* base, const Index& ix, int64_t nq, int P);
@@ -153,40 +151,46 @@ void launch_row_norms(const float* A, int64_t rows, int d, float* out, hipStream
 // Split-BF16 routing distances: D (rows x G) = max(an + ||mu||^2 - 2 <a, mu>, 0) with
 // <a, mu> from BF16 MFMA over [a_hi | a_hi | a_lo] . [mu_hi | mu_lo | mu_hi]; As is
 // scratch of rows x 3d bf16.  ensure_centroid_split makes the index's centroid split once.
+// launch_dist_bf16: the same with <a, mu> = bf16(a) . bf16(mu) (As: rows x d bf16).
 void ensure_centroid_split(Index& ix, hipStream_t s);
 void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
                         hipStream_t s, const int32_t* nlim = nullptr, int64_t row_base = 0);
+void launch_dist_bf16(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
+                      hipStream_t s, const int32_t* nlim = nullptr, int64_t row_base = 0);
 void launch_dist_matrix(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
                         int cols, int d, float* D, hipStream_t s, const int32_t* nlim = nullptr,
                         int64_t row_base = 0);
 void launch_argmin_rows(const float* A, const float* an, int64_t rows, const float* Bm, const float* bn,
                         int cols, int d, int32_t* label, float* dmin, hipStream_t s);
-// top-P per row of D; with A and Bm given, the winners are re-scored by exact
-// direct differences (routing).  Rows beyond *nlim - row_base get probes -1.
-// With dot, D holds dot products a . b and the expansion distance is formed as
-// max(||a||^2 + ||b||^2 - 2 D, 0) (needs an and bn).  Without A (plain top-P),
-// colbias adds a per-column term: the P smallest of D[row][c] + colbias[c].
+// top-P per row of D; with A and Bm given, D holds expansion distances whose
+// error is at most err (an[row] + bn[col]) and the winners are re-scored by
+// exact direct differences (routing).  Rows beyond *nlim - row_base get probes
+// -1.  overflow (optional, device) counts rows whose error window reached the
+// end of the shortlist and were re-read whole.
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
-                      const float* bn = nullptr, int d = 0, const int32_t* nlim = nullptr, int64_t row_base = 0,
-                      bool dot = false, const float* colbias = nullptr);
-// Library GEMMs (blaslt.hip): D (rows x cols, FP32) = A (rows x k) . B (cols x k)^T,
-// operands row-major BF16 or FP32.  prepare (outside graph capture) makes the
-// shape's descriptors; abt enqueues.  Both return false when the library has no
-// algorithm for the shape.
-constexpr int LT_F32 = 0, LT_BF16 = 1;
-constexpr int64_t LT_MIN_ROWS = 64;  // fewer routing rows stay on the library-free kernels
-// abt computes D = alpha A . B^T.
-bool lt_gemm_prepare(int dt, int64_t rows, int64_t cols, int64_t k);
-bool lt_gemm_abt(int dt, const void* A, const void* B, float* D, int64_t rows, int64_t cols, int64_t k,
-                 hipStream_t s, float alpha = 1.f);
-// Routing dot products Q . mu^T of rows queries on the library GEMM: FP32, or
-// (split) BF16 over the split operands [q_hi | q_hi | q_lo] . [mu_hi | mu_lo | mu_hi]
-// with As as rows x 3d scratch.  Returns false (nothing enqueued) below
-// LT_MIN_ROWS rows or without a library algorithm; prepare_only makes the
-// descriptors without enqueueing.
-bool launch_route_dots(const Index& ix, const float* Q, int64_t rows, bool split, uint16_t* As, float* D,
-                       hipStream_t s, bool prepare_only = false);
+                      const float* bn = nullptr, int d = 0, float err = 0.f, const int32_t* nlim = nullptr,
+                      int64_t row_base = 0, unsigned int* overflow = nullptr);
+
+// Centroid routing (Section 2.1 step 1): the P nearest centroids of every row
+// of Q by FP32 direct differences, from a shortlist of expansion distances
+// whose products run on MFMA in one of three forms.
+enum { ROUTE_F32 = 0, ROUTE_BF16 = 1, ROUTE_BF16X3 = 2 };
+struct RouteScratch {
+  int form = ROUTE_F32;
+  int64_t chunk = 0;        // rows per distance block
+  float* qn = nullptr;      // nq query norms
+  float* D = nullptr;       // chunk x G expansion distances
+  uint16_t* As = nullptr;   // chunk x d (BF16) or chunk x 3d (split BF16) query operands
+  size_t layout(char* base, const Index& ix, int64_t nq, int form);
+};
+float route_err(int form);
+inline int route_form(uint32_t flags) {
+  return (flags & HNTL_FLAG_ROUTE_BF16X3) ? ROUTE_BF16X3 : (flags & HNTL_FLAG_ROUTE_BF16) ? ROUTE_BF16 : ROUTE_F32;
+}
+void launch_route_centroid(const Index& ix, const float* Q, int64_t nq, int P, const RouteScratch& w,
+                           int32_t* probes, float* pdist, hipStream_t s, const int32_t* nlim = nullptr,
+                           unsigned int* overflow = nullptr);
 
 // exact k nearest rows of B (cols x d) for every row of A (rows x d), k <= 16:
 // MFMA expansion shortlist of 32 per row, re-scored by direct differences
@@ -318,14 +322,12 @@ struct FusedArgs {
   int prune;
 };
 
-// learned routing: probes by descending router score; rows whose largest
-// softmax probability is below tau fall back to centroid routing.  With
-// lib_rows >= LT_MIN_ROWS the three layer products of the first lib_rows rows
-// run on the library GEMM (when it has algorithms for them); prepare_only
-// makes those descriptors and reports whether they exist, enqueueing nothing.
-bool launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr,
-                          int64_t lib_rows = 0, bool prepare_only = false);
+// learned routing: probes by descending router score (three BF16 MFMA layer
+// products with fused bias / GELU epilogues, then a top-P over the scores);
+// rows whose largest softmax probability is below tau fall back to centroid
+// routing.  Rows from *nlim on are skipped.
+void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr);
 
 // build helpers
 void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);

@@ -77,7 +77,8 @@ constexpr int TICKET_INTS = 9 * 64;
 constexpr int MIN_GRID = 8;  // every class of scan counters needs a workgroup
 // search flags a plan honours (beyond HNTL_FLAG_SYNC)
 constexpr int PLAN_STAGES = 5;  // route, bucket, projection launch, fused kernel, merge + rerank
-constexpr uint32_t PLAN_FLAGS = HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3 | HNTL_FLAG_MODE_A;
+constexpr uint32_t PLAN_FLAGS =
+    HNTL_FLAG_PROJECT_BF16 | HNTL_FLAG_NO_PRUNE | HNTL_FLAG_ROUTE_BF16X3 | HNTL_FLAG_ROUTE_BF16 | HNTL_FLAG_MODE_A;
 constexpr uint64_t MAX_LIST_BYTES = 4ull << 30;  // candidate-list storage of one plan
 
 // Bump allocation over one block (base == nullptr: sizing pass).
@@ -145,9 +146,7 @@ struct Plan {
   int32_t* nq_dev = nullptr;
   // routing
   int32_t* probes = nullptr;
-  float* qn = nullptr;
-  float* Dm = nullptr;
-  int64_t chunk = 0;
+  RouteScratch route;
   // bucketing
   Buckets b{};
   int32_t* nsplit = nullptr;
@@ -159,7 +158,6 @@ struct Plan {
   int32_t* proj_done = nullptr;  // one flag per projection item
   int64_t proj_items = 0;
   ItemDesc* items = nullptr;  // decoded work items of the fused kernel
-  uint16_t* Asplit = nullptr;  // split-BF16 query rows of one routing chunk
   int64_t max_items = 0;
   uint32_t* qbound = nullptr;
   int32_t* err = nullptr;
@@ -172,11 +170,8 @@ struct Plan {
   RouterScratch rs;
   // graph
   hipStream_t cap_stream = nullptr;
-  std::vector<uint32_t> bucket_nq;     // routing rows of each captured graph, ascending
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> execs;
-  int64_t route_rows = 0;              // rows the library routing GEMM computes (enqueue)
-  bool lib_route = false;              // centroid routing on the library GEMM
   hipStream_t last_stream = nullptr;
   uint32_t wait_errors = 0;
 
@@ -202,10 +197,12 @@ struct Plan {
     dist = L.take<float>((size_t)max_nq * sp.k);
     nq_dev = L.take<int32_t>(1);
     probes = L.take<int32_t>(np);
-    qn = L.take<float>(max_nq);
-    chunk = std::min<int64_t>(max_nq, std::max<int64_t>(64, ((int64_t)1 << 28) / x.G));
-    Dm = L.take<float>((size_t)chunk * x.G);
-    if (sp.flags & HNTL_FLAG_ROUTE_BF16X3) Asplit = L.take<uint16_t>((size_t)chunk * 3 * x.d);
+    if (sp.route != HNTL_ROUTE_LEARNED) {
+      const int form = route_form(sp.flags);
+      const size_t n = route.layout(nullptr, x, max_nq, form);
+      char* rb = L.take<char>(n);
+      route.layout(rb, x, max_nq, form);
+    }
     b.G = (int)x.G;
     b.gcount = L.take<int32_t>(x.G);
     b.gcount0 = L.take<int32_t>(x.G);
@@ -303,7 +300,7 @@ struct Plan {
   // rerank.
   void enqueue(hipStream_t s, hipEvent_t* ev = nullptr) {
     const Index& x = *ix;
-    const int P = (int)sp.P, G = (int)x.G, d = (int)x.d;
+    const int P = (int)sp.P, G = (int)x.G;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     FillList f{};
     f.seg[0] = FillSeg{ticket, 2 * TICKET_INTS, 0};
@@ -314,28 +311,11 @@ struct Plan {
     f.seg[5] = FillSeg{b.gcount0, G, 0};
     f.n = 6;
     launch_fill_multi(f, s);
+    // routing reads the batch size from nq_dev: rows past it get probes -1
     if (sp.route == HNTL_ROUTE_LEARNED)
-      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev, lib_route ? route_rows : 0);
+      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev);
     else
-      launch_row_norms(Q, max_nq, d, qn, s);
-    for (int64_t q0 = 0; q0 < (int64_t)max_nq && sp.route != HNTL_ROUTE_LEARNED; q0 += chunk) {
-      const int64_t rows = std::min<int64_t>(chunk, (int64_t)max_nq - q0);
-      const bool split = (sp.flags & HNTL_FLAG_ROUTE_BF16X3) != 0;
-      // library dot products for the first route_rows rows (rows past the batch
-      // are never read); the distance kernels read the batch size themselves
-      const int64_t lr = std::min<int64_t>(rows, route_rows - q0);
-      bool dots = false;
-      if (lib_route && lr > 0) {
-        dots = launch_route_dots(x, Q + q0 * d, lr, split, Asplit, Dm, s);
-        if (!dots) throw ArgError{HNTL_EDEVICE, "library routing GEMM unavailable for a prepared shape"};
-      }
-      if (!lib_route && split)
-        launch_dist_bf16x3(x, Q + q0 * d, qn + q0, rows, Asplit, Dm, s, nq_dev, q0);
-      else if (!lib_route)
-        launch_dist_matrix(Q + q0 * d, qn + q0, rows, x.centroids, x.cnorm, G, d, Dm, s, nq_dev, q0);
-      launch_topk_rows(Dm, rows, G, P, probes + q0 * P, nullptr, s, Q + q0 * d, qn + q0, x.centroids, x.cnorm, d,
-                       nq_dev, q0, lib_route);
-    }
+      launch_route_centroid(x, Q, max_nq, P, route, probes, nullptr, s, nq_dev);
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     launch_bucket(probes, max_nq, P, G, b, s, x.gorder, nsplit, true);
     if (sch.range) launch_pair_lists(probes, max_nq, P, G, nsplit, lbase, qoff, s);
@@ -355,23 +335,13 @@ struct Plan {
     if (ev) HIP_TRY(hipEventRecord(ev[5], s));
   }
 
-  // Smallest routing bucket holding nq rows.
-  int bucket_of(uint32_t nq) const {
-    for (size_t i = 0; i < bucket_nq.size(); ++i)
-      if (nq <= bucket_nq[i]) return (int)i;
-    return (int)bucket_nq.size() - 1;
-  }
-
   void run(uint32_t nq, hipStream_t s) {
     hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, nq_dev, (int32_t)nq);
     HIP_TRY(hipGetLastError());
-    const int bi = bucket_of(nq);
-    if (!execs.empty()) {
-      HIP_TRY(hipGraphLaunch(execs[bi], s));
-    } else {
-      route_rows = bucket_nq[bi];
+    if (!execs.empty())
+      HIP_TRY(hipGraphLaunch(execs[0], s));
+    else
       enqueue(s);
-    }
     last_stream = s;
   }
 };
@@ -435,7 +405,7 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   if (lds_per_wave((int)ix.rp, (int)sp.C, (int)sch.qt) * sch.nw > LDS_LIMIT)
     throw ArgError{HNTL_EUNSUPPORTED, "schedule needs more than 64 KiB of LDS per workgroup"};
   ensure_grain_order(ix);
-  if ((sp.flags & HNTL_FLAG_ROUTE_BF16X3) && sp.route != HNTL_ROUTE_LEARNED) ensure_centroid_split(ix, s);
+  if (route_form(sp.flags) != ROUTE_F32 && sp.route != HNTL_ROUTE_LEARNED) ensure_centroid_split(ix, s);
   if (sp.flags & HNTL_FLAG_MODE_A) ensure_eps_by_id(ix, s);
   std::unique_ptr<Plan> pl(new Plan());
   pl->ix = &ix;
@@ -482,56 +452,25 @@ Plan* make_plan(Index& ix, const hntl_search_params& sp, uint32_t max_nq, const 
   }
   HIP_TRY(hipMemcpyAsync(pl->args_dev, a, sizeof(a), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // routing row buckets; routing uses the library GEMM when every bucket's
-  // shapes have an algorithm (descriptors made and kernels loaded here,
-  // outside capture, by one eager call per bucket on the zeroed query buffer)
-  for (uint32_t b = (uint32_t)LT_MIN_ROWS; b < max_nq; b *= 2) pl->bucket_nq.push_back(b);
-  pl->bucket_nq.push_back(max_nq);
-  pl->lib_route = false;
-  if (pl->bucket_nq.front() >= (uint32_t)LT_MIN_ROWS) {
-    const bool learned = sp.route == HNTL_ROUTE_LEARNED;
-    const bool split = (sp.flags & HNTL_FLAG_ROUTE_BF16X3) != 0;
-    bool ok = true;
-    for (uint32_t b : pl->bucket_nq)
-      ok = ok && (learned ? launch_route_learned(ix, pl->Q, max_nq, (int)sp.P, 0.f, pl->probes, nullptr, pl->rs, s,
-                                                 pl->nq_dev, b, true)
-                          : launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm,
-                                              s, true));
-    if (ok) {
-      hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl->nq_dev, 0);
-      for (uint32_t b : pl->bucket_nq) {
-        if (learned)
-          launch_route_learned(ix, pl->Q, max_nq, (int)sp.P, 0.f, pl->probes, nullptr, pl->rs, s, pl->nq_dev, b);
-        else
-          ok = ok && launch_route_dots(ix, pl->Q, std::min<int64_t>(b, pl->chunk), split, pl->Asplit, pl->Dm, s);
-      }
-      HIP_TRY(hipStreamSynchronize(s));
-    }
-    pl->lib_route = ok;
-  }
-  if (!pl->lib_route) pl->bucket_nq.assign(1, max_nq);  // one graph serves every batch size
-  pl->route_rows = max_nq;
   if (plan_flags & HNTL_PLAN_GRAPH) {
+    // one graph serves every batch size up to max_nq (the size is read from
+    // device memory by every kernel that depends on it)
     HIP_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    for (uint32_t b : pl->bucket_nq) {
-      pl->route_rows = b;
-      HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-      try {
-        pl->enqueue(pl->cap_stream);
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(pl->cap_stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
+    HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      pl->enqueue(pl->cap_stream);
+    } catch (...) {
       hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamEndCapture(pl->cap_stream, &g));
-      pl->graphs.push_back(g);
-      hipGraphExec_t e = nullptr;
-      HIP_TRY(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
-      pl->execs.push_back(e);
+      (void)hipStreamEndCapture(pl->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
     }
-    pl->route_rows = max_nq;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(pl->cap_stream, &g));
+    pl->graphs.push_back(g);
+    hipGraphExec_t e = nullptr;
+    HIP_TRY(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    pl->execs.push_back(e);
   }
   return pl.release();
 }
@@ -659,7 +598,6 @@ hntl_status hntl_plan_info_get(hntl_plan* plan, hntl_plan_info* out) {
     out->device_bytes = pl.arena_bytes;
     out->list_slots = pl.list_slots;
     out->wait_errors = read_wait_errors(pl);
-    out->lib_route = pl.lib_route ? 1u : 0u;
   });
 }
 
@@ -680,7 +618,6 @@ hntl_status hntl_plan_profile(hntl_plan* plan, uint32_t nq, uint32_t reps, doubl
     try {
       for (uint32_t rep = 0; rep < reps; ++rep) {
         hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, pl.nq_dev, (int32_t)nq);
-        pl.route_rows = pl.bucket_nq[pl.bucket_of(nq)];
         pl.enqueue(s, ev);
         HIP_TRY(hipEventSynchronize(ev[PLAN_STAGES]));
         for (int i = 0; i < PLAN_STAGES; ++i) {

@@ -4,10 +4,11 @@
 // assignment of the build (nearest centroid per row).
 //
 // Distances use the expansion ||a||^2 + ||b||^2 - 2 a.b with the a.b term on
-// FP32 MFMA (v_mfma_f32_16x16x4_f32).  Its rounding error (about 1e-4
-// relative when ||q|| and ||mu|| are large against ||q - mu||) is harmless for
-// the k-means assignment; routing re-scores a short list of the nearest
-// centroids by direct differences before it picks the P probes.
+// MFMA: FP32 (v_mfma_f32_16x16x4_f32) here, BF16 (plain or split operands) in
+// router.hip.  The expansion's rounding error is harmless for the k-means
+// assignment; routing bounds it per entry and re-scores every shortlist entry
+// that the bound leaves in reach of the P-th by direct differences before it
+// picks the P probes.
 #include <algorithm>
 
 #include "hntl_device.h"
@@ -264,66 +265,42 @@ __global__ __launch_bounds__(256) void argmin_rows_kernel(const float* __restric
   }
 }
 
-// Top-P per row.  Without A/Bm: the P smallest entries of D.  With them
-// (routing): a shortlist of the M = min(cols, P + 16) smallest expansion
-// distances is re-scored by direct differences ||a - b||^2 in FP32 and the P
-// smallest exact distances are kept, so the probe order and the reported
-// distances carry direct-difference accuracy; the FP32 expansion error (about
-// 1e-4 relative at these magnitudes) is far below the gap that 16 extra ranks
-// open between the P-th and M-th centroid.
-// Expansion error bound used to decide which shortlist entries can still
-// reach the top P: ERR * (||a||^2 + ||b||^2) is several times the FP32
-// rounding error of a 768-term dot product at these magnitudes.
-constexpr float ERR = 5e-5f;
-
-// Top-P per row, shortlist of M <= 64 held in registers (lane j = j-th entry).
-// Without A/Bm: the P smallest entries of D.  With them (routing): the
-// shortlist entries that can still reach the top P are re-scored by direct
-// differences ||a - b||^2 in FP32 and the P smallest exact distances are kept,
-// so probe order and reported distances carry direct-difference accuracy.
-constexpr int TOPK_LDS_COLS = 8192;  // per-column terms staged in LDS up to this many columns
-// Rows per workgroup, one per wave: eight rows share one LDS copy of the
-// per-column term (32 KiB at 8,192 columns) and keep the CU at full wave occupancy.
+// Top-P per row of D.  Without A/Bm: the P smallest entries of D.  With them
+// (routing), D holds expansion distances ||a||^2 + ||b||^2 - 2 <a, b> whose
+// error against the exact distance is at most err (||a||^2 + ||b||^2) per
+// entry (the caller's bound for its product form).  A shortlist of the M
+// smallest expansion values is kept; every entry j whose interval
+// [D_j - bound_j, D_j + bound_j] reaches the P-th entry's upper end can still
+// be among the P nearest, so exactly those are re-scored by direct
+// differences ||a - b||^2 in FP32 and the P smallest exact distances are kept
+// (ties: lower column).  Probe order and reported distances then carry
+// direct-difference accuracy.  If the window reaches the end of the
+// shortlist (entry M - 1 qualifies while columns remain beyond it), entries
+// past M may qualify as well: the row is then re-read whole, and every column
+// inside the window is re-scored.
+//
+// Rows per workgroup, one per wave.
 constexpr int TOPK_ROWS = 8;
 
-// MODE 0: D holds distances (or, without A, the values to rank); 1: dot
-// products, ranked as max(||a||^2 + ||b||^2 - 2 D, 0); 2: D + colbias[c].
-template <int MODE>
-__global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(const float* __restrict__ D, int64_t rows, int cols, int P,
-                                                        int M, const float* __restrict__ A,
-                                                        const float* __restrict__ an,
-                                                        const float* __restrict__ Bm,
-                                                        const float* __restrict__ bn, int d,
-                                                        int32_t* __restrict__ idx, float* __restrict__ val,
-                                                        const int32_t* __restrict__ nlim, int64_t row_base,
-                                                        const float* __restrict__ colbias) {
+// Direct FP32 squared distance of row a and column row b (both d long), one
+// wave, every lane ends with the total.
+__device__ __forceinline__ float wave_dist(const float* __restrict__ a, const float* __restrict__ b, int d) {
+  float acc = 0.f;
+  for (int t = lane_id(); t < d; t += HNTL_WAVE) {
+    const float df = a[t] - b[t];
+    acc = fmaf(df, df, acc);
+  }
+  return wave_sum(acc);
+}
+
+__global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
+    const float* __restrict__ D, int64_t rows, int cols, int P, int M, const float* __restrict__ A,
+    const float* __restrict__ an, const float* __restrict__ Bm, const float* __restrict__ bn, int d, float err,
+    int32_t* __restrict__ idx, float* __restrict__ val, const int32_t* __restrict__ nlim, int64_t row_base,
+    unsigned int* __restrict__ overflow) {
   __shared__ uint64_t stage[TOPK_ROWS][64];
-  extern __shared__ float colv[];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * TOPK_ROWS + wave;
-  // the per-column term (||b||^2 or colbias) read once per workgroup into LDS
-  // when it fits, instead of once per row
-  const float* colterm = MODE == 1 ? bn : colbias;
-  if constexpr (MODE != 0) {
-    if (cols <= TOPK_LDS_COLS) {
-      constexpr int NT = TOPK_ROWS * 64, PU = 16;  // PU loads in flight per thread
-      for (int c0 = 0; c0 < cols; c0 += PU * NT) {
-        float t[PU];
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          const int c = c0 + u * NT + (int)threadIdx.x;
-          t[u] = c < cols ? colterm[c] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-          const int c = c0 + u * NT + (int)threadIdx.x;
-          if (c < cols) colv[c] = t[u];
-        }
-      }
-      __syncthreads();
-      colterm = colv;
-    }
-  }
   if (row >= rows) return;
   if (nlim && row >= (int64_t)*nlim - row_base) {  // not part of this batch: no probes
     if (lane < P) {
@@ -336,7 +313,6 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(const float* 
   WaveTop64 L;
   L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
-  const float an_row = MODE == 1 ? an[row] : 0.f;
   constexpr int U = 8;  // chunks of 64 loaded together (memory-level parallelism for one row)
   for (int c0 = 0; c0 < cols; c0 += U * HNTL_WAVE) {
     float v[U];
@@ -344,19 +320,6 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(const float* 
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * HNTL_WAVE + lane;
       v[u] = c < cols ? drow[c] : 0.f;
-    }
-    if constexpr (MODE == 1) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + u * HNTL_WAVE + lane;
-        v[u] = c < cols ? fmaxf(fmaf(-2.f, v[u], an_row + colterm[c]), 0.f) : 0.f;
-      }
-    } else if constexpr (MODE == 2) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + u * HNTL_WAVE + lane;
-        v[u] = c < cols ? v[u] + colterm[c] : 0.f;
-      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -372,43 +335,68 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(const float* 
     }
     return;
   }
-  // entries j >= P qualify while expansion(j) - bound(j) <= expansion(P-1) + bound(P-1)
+  // entries j >= P qualify while D_j - bound_j <= D_{P-1} + bound_{P-1}
   const float arow = an[row];
   const uint64_t mine = L.best;
   const uint64_t kp = shfl_u64(mine, P - 1);
-  const float hiP = key_dist(kp) + ERR * (arow + bn[key_id(kp)]);
-  const bool in = lane >= P && lane < M && key_dist(mine) - ERR * (arow + bn[key_id(mine)]) <= hiP;
+  const float hiP = key_dist(kp) + err * (arow + bn[key_id(kp)]);
+  const bool in = lane >= P && lane < M && mine != KEY_NONE &&
+                  key_dist(mine) - err * (arow + bn[key_id(mine)]) <= hiP;
   const uint64_t qual = __ballot(in);
   const int Mr = qual ? 64 - __clzll(qual) : P;  // re-score the prefix [0, Mr)
   const float* a = A + row * d;
-  constexpr int RB = 8;  // shortlist entries re-scored together
   uint64_t ex = KEY_NONE;
-  for (int j0 = 0; j0 < Mr; j0 += RB) {
-    int cs[RB];
-    const float* bp[RB];
-    float acc[RB];
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int j = j0 + u < Mr ? j0 + u : j0;
-      cs[u] = (int)key_id(shfl_u64(mine, j));
-      bp[u] = Bm + (size_t)cs[u] * d;
-      acc[u] = 0.f;
+  if (Mr == M && M < cols) {
+    // the window may extend past the shortlist: every column of the row whose
+    // interval reaches hiP is re-scored, into a fresh top-P list
+    if (overflow && lane == 0) atomicAdd(overflow, 1u);
+    WaveTop64 X;
+    wave_sync();
+    X.init(stage[wave], P);
+    for (int c0 = 0; c0 < cols; c0 += HNTL_WAVE) {
+      const int c = c0 + lane;
+      const bool w = c < cols && drow[c] - err * (arow + bn[c]) <= hiP;
+      uint64_t m = __ballot(w);
+      uint64_t keyc = KEY_NONE;
+      while (m) {  // wave-uniform loop over the window columns of this chunk
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        const float dd = wave_dist(a, Bm + (size_t)(c0 + j) * d, d);
+        if (lane == j) keyc = make_key(dd, (uint32_t)(c0 + j));
+      }
+      X.offer(keyc, w);
     }
-    for (int t = lane; t < d; t += HNTL_WAVE) {
-      const float av = a[t];
+    X.finish();
+    ex = X.best;
+  } else {
+    constexpr int RB = 8;  // shortlist entries re-scored together
+    for (int j0 = 0; j0 < Mr; j0 += RB) {
+      int cs[RB];
+      const float* bp[RB];
+      float acc[RB];
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        const float df = av - bp[u][t];
-        acc[u] = fmaf(df, df, acc[u]);
+        const int j = j0 + u < Mr ? j0 + u : j0;
+        cs[u] = (int)key_id(shfl_u64(mine, j));
+        bp[u] = Bm + (size_t)cs[u] * d;
+        acc[u] = 0.f;
+      }
+      for (int t = lane; t < d; t += HNTL_WAVE) {
+        const float av = a[t];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const float df = av - bp[u][t];
+          acc[u] = fmaf(df, df, acc[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const float tot = wave_sum(acc[u]);
+        if (lane == j0 + u && lane < Mr) ex = make_key(tot, (uint32_t)cs[u]);
       }
     }
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const float tot = wave_sum(acc[u]);
-      if (lane == j0 + u && lane < Mr) ex = make_key(tot, (uint32_t)cs[u]);
-    }
+    ex = wave_sort64(ex);
   }
-  ex = wave_sort64(ex);
   if (lane < P) {
     idx[row * P + lane] = (int32_t)key_id(ex);
     if (val) val[row * P + lane] = key_dist(ex);
@@ -549,23 +537,16 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 }
 
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
-                      const float* A, const float* an, const float* Bm, const float* bn, int d,
-                      const int32_t* nlim, int64_t row_base, bool dot, const float* colbias) {
-  if (dot && (!an || !bn)) throw ArgError{HNTL_EINVAL, "dot-product routing needs both norm vectors"};
+                      const float* A, const float* an, const float* Bm, const float* bn, int d, float err,
+                      const int32_t* nlim, int64_t row_base, unsigned int* overflow) {
+  if (A && (!an || !bn || !Bm)) throw ArgError{HNTL_EINVAL, "routing re-score needs both norm vectors and the centroids"};
   if (rows <= 0) return;
-  if (P > 48) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
+  if (P > HNTL_MAX_P) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + TOPK_ROWS - 1) / TOPK_ROWS)), block(TOPK_ROWS * 64);
-  const int M = A ? std::min(cols, P + 16) : P;
-  const size_t lds = ((dot || colbias) && cols <= TOPK_LDS_COLS) ? sizeof(float) * cols : 0;
-  if (dot)
-    hipLaunchKernelGGL(topk_rows_kernel<1>, grid, block, lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
-                       nlim, row_base, colbias);
-  else if (colbias)
-    hipLaunchKernelGGL(topk_rows_kernel<2>, grid, block, lds, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
-                       nlim, row_base, colbias);
-  else
-    hipLaunchKernelGGL(topk_rows_kernel<0>, grid, block, 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, idx, val,
-                       nlim, row_base, colbias);
+  // shortlist: the window of the P-th entry plus 48 more (one key per lane)
+  const int M = A ? std::min(cols, std::min(64, P + 48)) : P;
+  hipLaunchKernelGGL(topk_rows_kernel, grid, block, 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, err, idx, val, nlim,
+                     row_base, overflow);
   HIP_TRY(hipGetLastError());
 }
 

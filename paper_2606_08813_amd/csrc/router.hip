@@ -493,18 +493,17 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 __global__ __launch_bounds__(256) void fallback_select_kernel(const float* __restrict__ negS, int64_t rows, int G,
                                                               float tau, int32_t* __restrict__ fb_rows,
                                                               int32_t* __restrict__ fb_count,
-                                                              const int32_t* __restrict__ nlim,
-                                                              const float* __restrict__ colbias) {
+                                                              const int32_t* __restrict__ nlim) {
   const int lane = lane_id();
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows || (nlim && r >= *nlim)) return;
   const float* s = negS + r * G;
   float mn = __builtin_inff();
-  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g] + (colbias ? colbias[g] : 0.f));
+  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
   float z = 0.f;
-  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - (s[g] + (colbias ? colbias[g] : 0.f)));
+  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
   z = wave_sum(z);
   if (lane == 0 && 1.f / z < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
 }
@@ -639,30 +638,9 @@ void ensure_centroid_split(Index& ix, hipStream_t s) {
   ix.cent_split = p;
 }
 
-bool launch_route_dots(const Index& ix, const float* Q, int64_t rows, bool split, uint16_t* As, float* D,
-                       hipStream_t s, bool prepare_only) {
-  if (rows < LT_MIN_ROWS) return false;
-  const int64_t G = ix.G, d = ix.d;
-  if (split) {
-    if (!ix.cent_split) throw ArgError{HNTL_ESTATE, "split-BF16 routing: centroid split not built"};
-    if (prepare_only) return lt_gemm_prepare(LT_BF16, rows, G, 3 * d);
-    if (!lt_gemm_prepare(LT_BF16, rows, G, 3 * d)) return false;
-    const int64_t n = rows * d;
-    hipLaunchKernelGGL(split3_kernel, dim3(blocks(n)), dim3(256), 0, s, Q, rows, (int)d, 0, As);
-    HIP_TRY(hipGetLastError());
-    return lt_gemm_abt(LT_BF16, As, ix.cent_split, D, rows, G, 3 * d, s);
-  }
-  if (prepare_only) return lt_gemm_prepare(LT_F32, rows, G, d);
-  return lt_gemm_abt(LT_F32, Q, ix.centroids, D, rows, G, d, s);
-}
-
 void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
                         hipStream_t s, const int32_t* nlim, int64_t row_base) {
   if (rows <= 0) return;
-  if (rows <= 16) {  // a few rows: exact FP32 direct differences, one pass over the centroids
-    launch_dist_matrix(A, an, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d, D, s, nlim, row_base);
-    return;
-  }
   if (!ix.cent_split) throw ArgError{HNTL_ESTATE, "split-BF16 routing: centroid split not built"};
   const int64_t n = rows * ix.d;
   hipLaunchKernelGGL(split3_kernel, dim3(blocks(n)), dim3(256), 0, s, A, rows, (int)ix.d, 0, As);
@@ -677,56 +655,103 @@ void launch_dist_bf16x3(const Index& ix, const float* A, const float* an, int64_
   gemm<false, false, EPI_DIST>(As, K3, ix.cent_split, K3, (int)rows, (int)ix.G, K3, e, s, nlim);
 }
 
-bool launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim, int64_t lib_rows,
-                          bool prepare_only) {
+// Plain BF16 expansion distances: <a, mu> from bf16(a) . bf16(mu) (the high
+// parts of the split centroid rows, row stride 3d), FP32 accumulation.
+void launch_dist_bf16(const Index& ix, const float* A, const float* an, int64_t rows, uint16_t* As, float* D,
+                      hipStream_t s, const int32_t* nlim, int64_t row_base) {
+  if (rows <= 0) return;
+  if (!ix.cent_split) throw ArgError{HNTL_ESTATE, "BF16 routing: centroid split not built"};
+  const int64_t n = rows * ix.d;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(n)), dim3(256), 0, s, A, n, As);
+  HIP_TRY(hipGetLastError());
+  Epi e{};
+  e.C = D;
+  e.ldc = (int)ix.G;
+  e.an = an;
+  e.bn = ix.cnorm;
+  e.row_base = row_base;
+  const int d = (int)ix.d;
+  gemm<false, false, EPI_DIST>(As, d, ix.cent_split, 3 * d, (int)rows, (int)ix.G, d, e, s, nlim);
+}
+
+size_t RouteScratch::layout(char* base, const Index& ix, int64_t nq, int form_) {
+  form = form_;
+  chunk = std::min<int64_t>(std::max<int64_t>(nq, 1), std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G));
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) / 256 * 256;
+    char* p = base ? base + off : nullptr;
+    off += std::max<size_t>(bytes, 1);
+    return p;
+  };
+  qn = (float*)take(4 * (size_t)std::max<int64_t>(nq, 1));
+  D = (float*)take(4 * (size_t)chunk * ix.G);
+  const int w = form == ROUTE_BF16X3 ? 3 : form == ROUTE_BF16 ? 1 : 0;
+  As = w ? (uint16_t*)take(2 * (size_t)chunk * w * ix.d) : nullptr;
+  return off;
+}
+
+float route_err(int form) {
+  // Bound on |expansion - exact| per entry, as a multiple of ||q||^2 + ||mu||^2
+  // (|<q, mu>| <= (||q||^2 + ||mu||^2) / 2):
+  //  - FP32 MFMA: products and sums in FP32 over d <= 1024 terms, about 1e-5;
+  //  - split BF16: the dropped lo x lo term and the parts' own rounding (about
+  //    3 x 2^-18) plus FP32 accumulation over 3d terms;
+  //  - plain BF16: each operand rounded to nearest even (2^-9 relative each),
+  //    2^-8 + 2^-18 of sum |q_j mu_j|, plus the FP32 accumulation.
+  // Each factor also covers the FP32 norms and the final combination.
+  return form == ROUTE_BF16 ? 4.0e-3f : 5.0e-5f;
+}
+
+void launch_route_centroid(const Index& ix, const float* Q, int64_t nq, int P, const RouteScratch& w,
+                           int32_t* probes, float* pdist, hipStream_t s, const int32_t* nlim,
+                           unsigned int* overflow) {
+  if (nq <= 0) return;
+  if (w.form != ROUTE_F32 && !ix.cent_split) throw ArgError{HNTL_ESTATE, "BF16 routing: centroid split not built"};
+  const int G = (int)ix.G, d = (int)ix.d;
+  launch_row_norms(Q, nq, d, w.qn, s);
+  for (int64_t q0 = 0; q0 < nq; q0 += w.chunk) {
+    const int64_t rows = std::min<int64_t>(w.chunk, nq - q0);
+    const float* Qc = Q + q0 * d;
+    if (rows <= 16 || w.form == ROUTE_F32)  // a few rows: exact direct differences (FP32 MFMA expansion otherwise)
+      launch_dist_matrix(Qc, w.qn + q0, rows, ix.centroids, ix.cnorm, G, d, w.D, s, nlim, q0);
+    else if (w.form == ROUTE_BF16X3)
+      launch_dist_bf16x3(ix, Qc, w.qn + q0, rows, w.As, w.D, s, nlim, q0);
+    else
+      launch_dist_bf16(ix, Qc, w.qn + q0, rows, w.As, w.D, s, nlim, q0);
+    launch_topk_rows(w.D, rows, G, P, probes + q0 * P, pdist ? pdist + q0 * P : nullptr, s, Qc, w.qn + q0,
+                     ix.centroids, ix.cnorm, d, route_err(w.form), nlim, q0, overflow);
+  }
+}
+
+void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim) {
   const Router& rt = *ix.router;
-  const int64_t lr = std::min<int64_t>(lib_rows, nq);
-  const bool lib = lr >= LT_MIN_ROWS && lt_gemm_prepare(LT_BF16, lr, rt.h1, rt.d) &&
-                   lt_gemm_prepare(LT_BF16, lr, rt.h2, rt.h1) && lt_gemm_prepare(LT_BF16, lr, rt.G, rt.h2);
-  if (prepare_only) return lib;
   hipLaunchKernelGGL(standardize_kernel, dim3(blocks(nq * rt.d)), dim3(256), 0, s, Q, nullptr, nq, rt.d, rt.mean,
                      rt.stdv, w.xh, nlim);
-  if (lib) {
-    // library products; bias, GELU (erf form) and the BF16 rounding of the
-    // activations in one pass over the FP32 dot products
-    if (!lt_gemm_abt(LT_BF16, w.xh, rt.Wb[0], w.z, lr, rt.h1, rt.d, s))
-      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
-    hipLaunchKernelGGL(gelu_bias_bf16_kernel, dim3(blocks(lr * rt.h1)), dim3(256), 0, s, w.z, lr, rt.h1, rt.b[0],
-                       w.h1);
-    if (!lt_gemm_abt(LT_BF16, w.h1, rt.Wb[1], w.z, lr, rt.h2, rt.h1, s))
-      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
-    hipLaunchKernelGGL(gelu_bias_bf16_kernel, dim3(blocks(lr * rt.h2)), dim3(256), 0, s, w.z, lr, rt.h2, rt.b[1],
-                       w.h2);
-    // negS = -(h2 . W3^T) here; the output bias enters where negS is read, as -b3
-    hipLaunchKernelGGL(negate_kernel, dim3(blocks(rt.G)), dim3(256), 0, s, rt.b[2], (int64_t)rt.G, w.nb2);
-    if (!lt_gemm_abt(LT_BF16, w.h2, rt.Wb[2], w.negS, lr, rt.G, rt.h2, s, -1.f))
-      throw ArgError{HNTL_EDEVICE, "library GEMM unavailable for a prepared shape"};
-    HIP_TRY(hipGetLastError());
-  } else {
-    Epi e{};
-    e.bias = rt.b[0];
-    e.H = w.h1;
-    e.ldh = rt.h1;
-    gemm<false, false, EPI_BIAS_GELU>(w.xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s, nlim);
-    e.bias = rt.b[1];
-    e.H = w.h2;
-    e.ldh = rt.h2;
-    gemm<false, false, EPI_BIAS_GELU>(w.h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s, nlim);
-    Epi o{};
-    o.C = w.negS;
-    o.ldc = rt.G;
-    o.bias = rt.b[2];
-    o.scale = -1.f;
-    gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
-  }
-  const float* colbias = lib ? w.nb2 : nullptr;
-  launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, nlim, 0, false,
-                   colbias);
+  HIP_TRY(hipGetLastError());
+  Epi e{};
+  e.bias = rt.b[0];
+  e.H = w.h1;
+  e.ldh = rt.h1;
+  gemm<false, false, EPI_BIAS_GELU>(w.xh, rt.d, rt.Wb[0], rt.d, (int)nq, rt.h1, rt.d, e, s, nlim);
+  e.bias = rt.b[1];
+  e.H = w.h2;
+  e.ldh = rt.h2;
+  gemm<false, false, EPI_BIAS_GELU>(w.h1, rt.h1, rt.Wb[1], rt.h1, (int)nq, rt.h2, rt.h1, e, s, nlim);
+  // negS = -(h2 W3^T + b3): the P smallest are the P largest scores
+  Epi o{};
+  o.C = w.negS;
+  o.ldc = rt.G;
+  o.bias = rt.b[2];
+  o.scale = -1.f;
+  gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
+  launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, 0.f, nlim, 0,
+                   nullptr);
   if (tau > 0.f) {
     launch_fill_i32(w.fb_count, 1, 0, s);
     hipLaunchKernelGGL(fallback_select_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, tau, w.fb_rows,
-                       w.fb_count, nlim, colbias);
+                       w.fb_count, nlim);
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)nq), dim3(256), 0, s, Q, (int)ix.d, w.fb_rows, w.fb_count,
                        w.fb_Q);
     launch_row_norms(w.fb_Q, nq, (int)ix.d, w.fb_qn, s);
@@ -736,13 +761,13 @@ bool launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, fl
       launch_dist_matrix(w.fb_Q + q0 * ix.d, w.fb_qn + q0, rows, ix.centroids, ix.cnorm, (int)ix.G, (int)ix.d,
                          w.negS, s, w.fb_count, q0);  // the scores are no longer needed: reuse as scratch
       launch_topk_rows(w.negS, rows, (int)ix.G, P, w.fb_probes + q0 * P, w.fb_pdist + q0 * P, s,
-                       w.fb_Q + q0 * ix.d, w.fb_qn + q0, ix.centroids, ix.cnorm, (int)ix.d, w.fb_count, q0);
+                       w.fb_Q + q0 * ix.d, w.fb_qn + q0, ix.centroids, ix.cnorm, (int)ix.d, route_err(ROUTE_F32),
+                       w.fb_count, q0, nullptr);
     }
     hipLaunchKernelGGL(scatter_probes_kernel, dim3((unsigned)nq), dim3(64), 0, s, w.fb_rows, w.fb_count, P,
                        w.fb_probes, w.fb_pdist, probes, pdist);
     HIP_TRY(hipGetLastError());
   }
-  return lib;
 }
 
 // Buffers of launch_route_learned carved from one block (base == nullptr:
@@ -761,8 +786,6 @@ size_t RouterScratch::layout(char* base, const Index& ix, int64_t nq, int P) {
   h2 = (uint16_t*)take(2 * (size_t)nq * rt.h2);
   const int64_t chunk = std::min<int64_t>(nq, std::max<int64_t>(64, ((int64_t)1 << 28) / ix.G));
   negS = (float*)take(4 * (size_t)std::max<int64_t>(nq * rt.G, chunk * ix.G));
-  z = (float*)take(4 * (size_t)nq * std::max(rt.h1, rt.h2));
-  nb2 = (float*)take(4 * (size_t)rt.G);
   fb_rows = (int32_t*)take(4 * (size_t)nq);
   fb_count = (int32_t*)take(4);
   fb_Q = (float*)take(4 * (size_t)nq * ix.d);

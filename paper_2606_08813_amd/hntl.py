@@ -21,6 +21,7 @@ HNTL_OK, HNTL_EINVAL, HNTL_ENOMEM, HNTL_EDEVICE, HNTL_ESTATE, HNTL_EIO, HNTL_EUN
 HNTL_CODES_FP32, HNTL_CODES_BF16, HNTL_CODES_FP8_E4M3, HNTL_CODES_INT16 = 0, 1, 2, 3
 HNTL_FLAG_SYNC, HNTL_FLAG_CHECK_Q, HNTL_FLAG_PROFILE, HNTL_FLAG_NO_PRUNE, HNTL_FLAG_PROJECT_BF16 = 1, 2, 4, 8, 16
 HNTL_FLAG_ROUTE_BF16X3 = 32
+HNTL_FLAG_ROUTE_BF16 = 128
 HNTL_FLAG_MODE_A = 64
 HNTL_ROUTE_CENTROID, HNTL_ROUTE_LEARNED = 0, 1
 HNTL_ROUTER_KEEP_WEIGHTS, HNTL_ROUTER_NO_SHUFFLE = 1, 2
@@ -64,8 +65,7 @@ class hntl_schedule(C.Structure):
 
 class hntl_plan_info(C.Structure):
     _fields_ = [("max_nq", C.c_uint32), ("sched", hntl_schedule), ("graph", C.c_uint32),
-                ("device_bytes", C.c_uint64), ("list_slots", C.c_uint64), ("wait_errors", C.c_uint32),
-                ("lib_route", C.c_uint32)]
+                ("device_bytes", C.c_uint64), ("list_slots", C.c_uint64), ("wait_errors", C.c_uint32)]
 
 
 HNTL_PLAN_GRAPH = 1
@@ -452,8 +452,7 @@ def hntl_plan_info_get(plan: Plan) -> dict:
     info = hntl_plan_info()
     _check(lib().hntl_plan_info_get(plan.handle, C.byref(info)))
     return {"max_nq": info.max_nq, "sched": sched_dict(info.sched), "graph": bool(info.graph),
-            "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors,
-            "lib_route": bool(info.lib_route)}
+            "device_bytes": info.device_bytes, "list_slots": info.list_slots, "wait_errors": info.wait_errors}
 
 
 PLAN_STAGES = ("route", "bucket", "project", "fused", "rerank")

@@ -201,31 +201,42 @@ def test_plan_unequal_grains(bt):
             assert hntl.hntl_plan_info_get(plan)["wait_errors"] == 0
 
 
-def test_split_bf16_routing(bt):
-    """Routing's shortlist from split-BF16 MFMA products picks the same probes
-    (the P winners are decided on FP32 direct differences either way), so the
-    whole search is unchanged; plans honour the flag."""
+def test_bf16_routing_forms(bt):
+    """Routing's shortlist from plain BF16 or split-BF16 MFMA products (own
+    kernels) picks the same probes as FP32 MFMA products: the P winners are
+    decided on FP32 direct differences in every form, inside each form's error
+    window, so the whole search is unchanged; plans honour the flags."""
     W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
-    announce("split-BF16 routing vs FP32 routing (staged and plan)")
-    fl = hntl.HNTL_FLAG_ROUTE_BF16X3
-    for nb in (1000, 9):  # 9 rows take the direct-difference path
-        Q = bt["Qd"][:nb].contiguous()
-        a = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k)
-        b = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
-        assert torch.equal(a["probes"], b["probes"]), nb
-        assert torch.equal(a["ids"], b["ids"]) and torch.equal(a["dist"], b["dist"]), nb
-    plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, flags=fl, sched=dict(qt=2, nw=4, range=1, proj=1))
-    assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], flags=fl), "plan, split routing")
+    announce("BF16 and split-BF16 routing vs FP32 routing (staged and plan)")
+    for fl in (hntl.HNTL_FLAG_ROUTE_BF16X3, hntl.HNTL_FLAG_ROUTE_BF16):
+        for nb in (1000, 9):  # 9 rows take the direct-difference path
+            Q = bt["Qd"][:nb].contiguous()
+            a = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k)
+            b = hntl.hntl_search_stages(bt["ix"], Q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
+            assert torch.equal(a["probes"], b["probes"]), (fl, nb)
+            assert torch.equal(a["ids"], b["ids"]) and torch.equal(a["dist"], b["dist"]), (fl, nb)
+        plan = hntl.hntl_plan_create(bt["ix"], W.P, W.C, W.k, 1000, flags=fl, sched=dict(qt=2, nw=4, range=1, proj=1))
+        assert_same(hntl.hntl_plan_search(plan, bt["Qd"]), staged(bt, bt["Qd"], flags=fl), f"plan, routing {fl}")
+
+
+def test_routing_forms_reject_both_flags(bt):
+    """The two BF16 routing forms are exclusive: asking for both is EINVAL."""
+    W, hntl = bt["W"], bt["hntl"]
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_search_stages(bt["ix"], bt["Qd"][:8].contiguous(), W.P, W.C, W.k,
+                                flags=hntl.HNTL_FLAG_ROUTE_BF16X3 | hntl.HNTL_FLAG_ROUTE_BF16)
+    assert e.value.status == hntl.HNTL_EINVAL
 
 
 def test_results_do_not_depend_on_the_batch(bt):
-    """Routing's library products use one kernel for every row count, so a query's
-    probes and results are the same whatever batch it is searched in: rows of
-    batches of 1000, 300, 100 and 64 queries (library GEMM) and of 9 (distance
-    kernels) agree bit for bit, FP32 and split-BF16 shortlists."""
+    """Every routing product is computed by one kernel whatever the row count
+    (a row's output tile and depth order do not depend on the batch), so a
+    query's probes and results are the same whatever batch it is searched in:
+    rows of batches of 1000, 300, 100 and 64 queries (MFMA products) and of 9
+    (direct differences) agree bit for bit, in all three routing forms."""
     W, hntl, torch = bt["W"], bt["hntl"], bt["torch"]
     announce("batch independence of routing and results: 1000 / 300 / 100 / 64 / 9 queries")
-    for fl in (0, hntl.HNTL_FLAG_ROUTE_BF16X3):
+    for fl in (0, hntl.HNTL_FLAG_ROUTE_BF16X3, hntl.HNTL_FLAG_ROUTE_BF16):
         full = hntl.hntl_search_stages(bt["ix"], bt["Qd"], W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
         for nb in (300, 100, 64, 9):
             part = hntl.hntl_search_stages(bt["ix"], bt["Qd"][:nb].contiguous(), W.P, W.C, W.k,

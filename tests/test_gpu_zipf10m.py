@@ -12,7 +12,11 @@ at any size plus sampled outputs the oracle computes one by one:
   FP64 from the corpus (1e-4 relative);
 * Recall@10 against the oracle's brute force on a query sample is >= 0.95;
 * learned routing (router trained briefly here) through a plan equals the
-  staged learned search, and tau above 1 equals centroid routing.
+  staged learned search, and tau above 1 equals centroid routing;
+* oracle parity on a 48-query sample of the exported index: routing probes,
+  the pool and final ids from the oracle's probes, and the plan's final ids;
+* the router at full width (8,192 outputs) against the oracle: forward scores,
+  every gradient tensor, and the search path's learned probes.
 """
 import numpy as np
 import pytest
@@ -163,3 +167,108 @@ def test_append_full_size(z):
     ids, dist = hntl.hntl_search(ix2, q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC)
     np.testing.assert_array_equal(ids.cpu().numpy()[:, 0], N + rs[:1000])
     assert float(dist[:, 0].abs().max()) < 1e-3
+
+
+def test_full_size_oracle_parity(z):
+    """Oracle parity at the full Zipf size on a 48-query sample: the index's
+    stored arrays are exported and the oracle searches them (FP64, eq. 1-6) at
+    the P = 16, C = 100, k = 10 the plan runs at.  The GPU's own routing probes,
+    its pool and final ids from the oracle's probes (stage input injected), and
+    the plan's final ids must all meet the parity rule (ids exact except
+    near-ties within 1e-5 relative; distances within 1e-4 relative)."""
+    from oracle import search as osr
+    from tests import parity
+    from tests.gpu_common import centroid_dist_fn, exact_dist_fn, scan_dist_fn
+    W, hntl, torch = z["W"], z["hntl"], z["torch"]
+    rs = np.random.default_rng(21).choice(W.nq, 48, replace=False)
+    Qs = z["Q"][rs]
+    announce("10M: oracle search of 48 sampled queries on the exported index, P=16 C=100 k=10")
+    ex = hntl.hntl_index_export(z["ix"])
+    orc = osr.search(Qs, ex, z["X"], W.P, W.C, W.k)
+    Qd = to_dev(Qs)
+    announce("10M: GPU routing, pool (oracle probes injected) and plan ids vs the oracle")
+    own = hntl.hntl_search_stages(z["ix"], Qd, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | hntl.HNTL_FLAG_ROUTE_BF16)
+    parity.check_lists(own["probes"].cpu().numpy(), own["pdist"].cpu().numpy(), orc["probes"], orc["pdist"],
+                       centroid_dist_fn(ex["centroids"], Qs), what="10M probes")
+    inj = hntl.hntl_search_stages(z["ix"], Qd, W.P, W.C, W.k, probes_in=to_dev(orc["probes"].astype(np.int32)))
+    parity.check_lists(inj["pool_ids"].cpu().numpy(), inj["pool_D"].cpu().numpy(), orc["pool_ids"], orc["pool_D"],
+                       scan_dist_fn(ex, orc["zq"], orc["epsq"], orc["probes"]), what="10M pool")
+    parity.check_lists(inj["ids"].cpu().numpy(), inj["dist"].cpu().numpy(), orc["ids"], orc["dist"],
+                       exact_dist_fn(z["X"], Qs), what="10M ids (oracle probes)")
+    plan = hntl.hntl_plan_create(z["ix"], W.P, W.C, W.k, 48, flags=hntl.HNTL_FLAG_ROUTE_BF16)
+    ids, dist = hntl.hntl_plan_search(plan, Qd)
+    torch.cuda.synchronize()
+    parity.check_lists(ids.cpu().numpy(), dist.cpu().numpy(), orc["ids"], orc["dist"], exact_dist_fn(z["X"], Qs),
+                       what="10M plan ids")
+
+
+def _check_top_scores(gpu_probes, s, P, what, rel=2e-3):
+    """gpu_probes (rows x P) against full oracle scores s (rows x G): the P
+    largest scores, ties to the lower grain, up to near-ties within
+    rel * max |s| of the row.  The window covers the GPU's score error against
+    the oracle's BF16 emulation: FP32 and FP64 accumulation can round a hidden
+    activation to neighbouring BF16 values (2^-8 relative), which moves scores
+    by about 1e-4 of their scale (the forward test bounds the whole error at
+    1e-3 relative)."""
+    for i in range(len(s)):
+        order = np.lexsort((np.arange(s.shape[1]), -s[i]))[:P]
+        thr = s[i, order[-1]]
+        tol = rel * float(np.abs(s[i]).max())
+        g = gpu_probes[i]
+        assert len(set(g.tolist())) == P, (what, i)
+        assert (s[i, g] >= thr - tol).all(), (what, i, g, order)
+        missing = set(order.tolist()) - set(g.tolist())
+        assert all(s[i, m] <= thr + tol for m in missing), (what, i)
+        assert (np.diff(s[i, g]) <= tol).all(), (what, i)  # descending within the tie window
+
+
+def test_router_parity_full_width(z):
+    """The router at its full width, 768-1024-1024-8192 (the logits layer spans
+    64 column tiles of 128): forward scores and every gradient tensor of a
+    256-query batch against the oracle's BF16 emulation (1e-3 relative
+    Frobenius), and the search path's learned probes (256 rows through the
+    staged search, and the plan's results) against the oracle's
+    route_learned on the same weights."""
+    from oracle import router as orr
+    W, hntl, torch = z["W"], z["hntl"], z["torch"]
+    announce("10M: router 768-1024-1024-8192 with oracle weights: forward, gradients, search probes")
+    dims = (W.d, 1024, 1024, W.G)
+    params = orr.init_params(dims, seed=8)
+    mean = z["Qtr"].astype(np.float64).mean(0)
+    std = z["Qtr"].astype(np.float64).std(0)
+    hntl.hntl_router_set(z["ix"], {k: v.astype(np.float32) for k, v in params.items()}, mean.astype(np.float32),
+                         std.astype(np.float32))
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
+    m, sd = mean.astype(np.float32).astype(np.float64), std.astype(np.float32).astype(np.float64)
+    Q = z["Q"][:256]
+    s_gpu = hntl.hntl_router_forward(z["ix"], to_dev(Q)).cpu().numpy().astype(np.float64)
+    s_orc, cache = orr.forward(p, Q, m, sd, bf16=True)
+    err = np.linalg.norm(s_gpu - s_orc) / np.linalg.norm(s_orc)
+    announce(f"forward rel Frobenius error {err:.2e}")
+    assert err < 1e-3
+    # gradients against seeded targets (10 grain ids per row)
+    tg = np.random.default_rng(3).integers(0, W.G, size=(256, 10)).astype(np.int32)
+    loss_gpu, g_gpu = hntl.hntl_router_grad(z["ix"], to_dev(z["Qtr"][:256]), to_dev(tg))
+    s2, c2 = orr.forward(p, z["Qtr"][:256], m, sd, bf16=True)
+    y = orr.grain_targets(tg, np.arange(W.G), W.G)
+    loss_orc, ds = orr.loss_and_dlogits(s2, y)
+    g_orc = orr.backward(p, c2, ds, bf16=True)
+    assert abs(loss_gpu - loss_orc) <= 1e-4 * abs(loss_orc), (loss_gpu, loss_orc)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        e = np.linalg.norm(np.asarray(g_gpu[k], np.float64) - g_orc[k]) / np.linalg.norm(g_orc[k])
+        assert e < 1e-3, (k, e)
+    # the search path's probes (learned routing, 256 rows) against route_learned
+    Qd = to_dev(Q)
+    o = hntl.hntl_search_stages(z["ix"], Qd, W.P, W.C, W.k, route="learned")
+    gp = o["probes"].cpu().numpy()
+    # exactly the P largest of the GPU's own forward scores (ties: lower grain)
+    own = np.lexsort((np.broadcast_to(np.arange(W.G), s_gpu.shape), -s_gpu), axis=1)[:, :W.P]
+    np.testing.assert_array_equal(gp, own)
+    lp, _ = orr.route_learned(p, Q, m, sd, W.P)
+    _check_top_scores(gp, s_orc, W.P, "learned probes")
+    announce(f"learned probes equal to route_learned in {(gp == lp).all(1).mean():.4f} of rows")
+    # and the plan's results equal the staged learned search on those rows
+    plan = hntl.hntl_plan_create(z["ix"], W.P, W.C, W.k, 256, route="learned")
+    ids, dist = hntl.hntl_plan_search(plan, Qd)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, o["ids"]) and torch.equal(dist, o["dist"])
