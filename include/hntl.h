@@ -286,6 +286,31 @@ hntl_status hntl_search(const hntl_index* index, const float* Q, uint32_t nq, co
                         int32_t* ids, float* dist, void* stream);
 
 /*
+ * hntl_search_noalloc - hntl_search for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, arithmetic and results as hntl_search
+ * (the same kernels); the call's scratch (routing distances, bucketing
+ * arrays, tangents, candidate lists) comes from one static device array of
+ * HNTL_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the process
+ * ends, instead of the stream-ordered pool.  The call makes no hipMalloc or
+ * hipFree; the caller still owns Q, ids and dist.
+ *   - A call whose scratch would exceed HNTL_NOALLOC_SCRATCH_BYTES fails with
+ *     EINVAL (the message states the bytes it needs): the scratch grows with
+ *     nq x (G + P x (r + C x 2)) x 4 bytes plus a few G-sized arrays.
+ *   - Derived index data is not made here: the BF16 routing forms need the
+ *     index's split centroids and Mode A its eps by id, which the first
+ *     hntl_search with the same flags makes; without them: ESTATE.
+ *   - HNTL_FLAG_PROFILE is refused (EINVAL); HNTL_FLAG_CHECK_Q and
+ *     HNTL_FLAG_SYNC synchronise the stream as in hntl_search.
+ *   - Every call on one GPU uses that GPU's one array and leaves its contents
+ *     behind; each call clears what it needs cleared.  Calls that overlap on
+ *     one GPU (other streams or host threads) race on it: serialise them.
+ */
+#define HNTL_NOALLOC_SCRATCH_BYTES (64u << 20) /* 64 MiB per GPU */
+hntl_status hntl_search_noalloc(const hntl_index* index, const float* Q, uint32_t nq, const hntl_search_params* sp,
+                                int32_t* ids, float* dist, void* stream);
+
+/*
  * hntl_search_stages - the same lifecycle with every stage's output observable and
  * every stage's input injectable, for stage-by-stage checking.  All pointers device;
  * any may be NULL.

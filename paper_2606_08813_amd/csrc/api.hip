@@ -156,6 +156,218 @@ __global__ void nonfinite_kernel(const float* __restrict__ A, int64_t n, int* __
   if (i < n && !isfinite(A[i])) atomicOr(flag, 1);
 }
 
+// Caller buffers of one staged search (any stage input may be injected, any
+// stage output observed; see hntl_search_stages).
+struct StagedIO {
+  const int32_t* probes_in;
+  int32_t* probes_out;
+  float* pdist_out;
+  const float* tangent_in;
+  const float* epsq_in;
+  float* tangent_out;
+  float* epsq_out;
+  const int32_t* pool_in;
+  int32_t* pool_out;
+  float* pool_D_out;
+  int32_t* ids;
+  float* dist;
+};
+
+hntl_status check_search(const hntl_index* index, const float* Q, uint32_t nq, const hntl_search_params* sp,
+                         const StagedIO& io) {
+  if (!index || !sp) return fail(HNTL_EINVAL, "null index or params");
+  const Index& ix = index->ix;
+  const uint32_t P = sp->P, C = sp->C, k = sp->k;
+  if (P < 1 || P > ix.G) return fail(HNTL_EINVAL, "need 1 <= P <= G");
+  if (P > HNTL_MAX_P) return fail(HNTL_EUNSUPPORTED, "P exceeds HNTL_MAX_P");
+  if (k < 1 || C < k) return fail(HNTL_EINVAL, "need 1 <= k <= C");
+  if (C > HNTL_MAX_C) return fail(HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C");
+  if (sp->codes > HNTL_CODES_INT16) return fail(HNTL_EINVAL, "unknown codes form");
+  if (sp->codes == HNTL_CODES_INT16 && (sp->flags & HNTL_FLAG_MODE_A))
+    return fail(HNTL_EUNSUPPORTED, "Mode A answers use the FP32 / BF16 / FP8 code forms");
+  if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
+  if ((io.tangent_in == nullptr) != (io.epsq_in == nullptr))
+    return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
+  if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
+  if ((sp->flags & HNTL_FLAG_ROUTE_BF16X3) && (sp->flags & HNTL_FLAG_ROUTE_BF16))
+    return fail(HNTL_EINVAL, "choose one centroid routing form");
+  const bool learned = sp->route == HNTL_ROUTE_LEARNED && !io.probes_in && !io.pool_in;
+  if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
+  const bool mode_a = (sp->flags & HNTL_FLAG_MODE_A) != 0;
+  if (!mode_a && !ix.X) return fail(HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches");
+  if (mode_a && io.pool_in) return fail(HNTL_EUNSUPPORTED, "Mode A answers need the merged pool, not an injected one");
+  if (nq == 0) return HNTL_OK;
+  if (!Q || !io.ids || !io.dist) return fail(HNTL_EINVAL, "Q, ids and dist are required");
+  return HNTL_OK;
+}
+
+bool routes_by_centroid(const hntl_search_params& sp, const StagedIO& io) {
+  return !io.pool_in && !io.probes_in && sp.route != HNTL_ROUTE_LEARNED;
+}
+
+// Index data a search derives on first use: the split centroid operands of
+// the BF16 routing forms and eps by row id for Mode A.
+void derive_search_data(Index& ix, const hntl_search_params& sp, const StagedIO& io, hipStream_t s) {
+  if (routes_by_centroid(sp, io) && route_form(sp.flags) != ROUTE_F32) ensure_centroid_split(ix, s);
+  if (sp.flags & HNTL_FLAG_MODE_A) ensure_eps_by_id(ix, s);
+}
+
+bool search_data_ready(const Index& ix, const hntl_search_params& sp, const StagedIO& io) {
+  if (routes_by_centroid(sp, io) && route_form(sp.flags) != ROUTE_F32 && !ix.cent_split) return false;
+  if ((sp.flags & HNTL_FLAG_MODE_A) && !ix.eps_id) return false;
+  return true;
+}
+
+// Scratch of one staged search, carved from one block (base == nullptr: the
+// sizing pass, which returns the bytes needed).
+struct StagedScratch {
+  int* qflag = nullptr;      // non-finite query flag (HNTL_FLAG_CHECK_Q)
+  int32_t* probes = nullptr;  // probes when the caller observes none
+  RouterScratch rw;
+  RouteScratch cw;
+  Buckets b{};
+  float* T = nullptr;
+  float* eq = nullptr;
+  uint64_t* part = nullptr;
+
+  size_t layout(char* base, const Index& ix, uint32_t nq, const hntl_search_params& sp, const StagedIO& io) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+      off = (off + 255) / 256 * 256;
+      char* p = base ? base + off : nullptr;
+      off += std::max<size_t>(bytes, 1);
+      return p;
+    };
+    const int64_t P = sp.P, npairs = (int64_t)nq * P;
+    if (sp.flags & HNTL_FLAG_CHECK_Q) qflag = (int*)take(sizeof(int));
+    if (io.pool_in) return off;
+    if (!io.probes_in) {
+      if (!io.probes_out) probes = (int32_t*)take(sizeof(int32_t) * npairs);
+      if (sp.route == HNTL_ROUTE_LEARNED) {
+        char* rb = take(rw.layout(nullptr, ix, nq, (int)P));
+        rw.layout(rb, ix, nq, (int)P);
+      } else {
+        const int form = route_form(sp.flags);
+        char* rb = take(cw.layout(nullptr, ix, nq, form));
+        cw.layout(rb, ix, nq, form);
+      }
+    }
+    b.G = (int)ix.G;
+    b.gcount = (int32_t*)take(4 * (size_t)ix.G);
+    b.gcount0 = (int32_t*)take(4 * (size_t)ix.G);
+    b.gstart = (int32_t*)take(4 * (size_t)ix.G);
+    b.cur0 = (int32_t*)take(4 * (size_t)ix.G);
+    b.cur1 = (int32_t*)take(4 * (size_t)ix.G);
+    b.order = (int32_t*)take(4 * (size_t)npairs);
+    const int tiles[3] = {16, 16, PROJECT_TILE};
+    const int64_t np[3] = {(int64_t)nq, (int64_t)nq * (P - 1), npairs};
+    for (int L = 0; L < 3; ++L) {
+      b.lists.tile[L] = tiles[L];
+      b.lists.ioff[L] = (int32_t*)take(4 * ((size_t)ix.G + 1));
+      b.lists.lstart[L] = (int32_t*)take(4 * (size_t)ix.G);
+      b.lists.lcount[L] = (int32_t*)take(4 * (size_t)ix.G);
+      b.max_items[L] = (int)(np[L] / tiles[L] + std::min<int64_t>(ix.G, np[L]) + 1);
+    }
+    if (!io.tangent_in) {
+      if (!io.tangent_out) T = (float*)take(4 * (size_t)npairs * ix.r);
+      if (!io.epsq_out) eq = (float*)take(4 * (size_t)npairs);
+    }
+    part = (uint64_t*)take(8 * (size_t)npairs * sp.C);
+    return off;
+  }
+};
+
+// The staged search's launch sequence on scratch w (laid out for this call).
+void run_staged(const Index& ix, const float* Q, uint32_t nq, const hntl_search_params& sp, const StagedIO& io,
+                StagedScratch& w, hipStream_t s) {
+  const uint32_t P = sp.P, C = sp.C, k = sp.k;
+  if (sp.flags & HNTL_FLAG_CHECK_Q) {
+    launch_fill_i32(w.qflag, 1, 0, s);
+    const int64_t n = (int64_t)nq * ix.d;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, n, w.qflag);
+    HIP_TRY(hipGetLastError());
+    int hflag = 0;
+    HIP_TRY(hipMemcpyAsync(&hflag, w.qflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    require(hflag == 0, "queries contain NaN or Inf");
+  }
+  const bool mode_a = (sp.flags & HNTL_FLAG_MODE_A) != 0;
+  StageClock clk((sp.flags & HNTL_FLAG_PROFILE) != 0, s);
+  const uint64_t* part = nullptr;
+  const int32_t* probes = io.probes_in;
+  if (!io.pool_in) {
+    // 1. routing
+    if (!probes) {
+      clk.at(HNTL_STAGE_ROUTE);
+      int32_t* pr = io.probes_out ? io.probes_out : w.probes;
+      if (sp.route == HNTL_ROUTE_LEARNED)
+        launch_route_learned(ix, Q, nq, (int)P, sp.tau, pr, io.pdist_out, w.rw, s);
+      else
+        launch_route_centroid(ix, Q, nq, (int)P, w.cw, pr, io.pdist_out, s);
+      probes = pr;
+    }
+    // 2. bucketing by grain (each grain's probe-slot-0 pairs first, so that
+    //    slot 0 is scanned first and its C-th key bounds the other slots)
+    clk.at(HNTL_STAGE_BUCKET);
+    launch_bucket(probes, nq, (int)P, (int)ix.G, w.b, s);
+    // 3. projection
+    const float* T = io.tangent_in;
+    const float* eq = io.epsq_in;
+    if (!T) {
+      clk.at(HNTL_STAGE_PROJECT);
+      float* To = io.tangent_out ? io.tangent_out : w.T;
+      float* eo = io.epsq_out ? io.epsq_out : w.eq;
+      launch_project(ix, Q, (int)P, w.b, To, eo, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0, nullptr, s);
+      T = To;
+      eq = eo;
+    }
+    // 4. scan + per-pair top-C: slot 0 unbounded, then the other slots
+    //    bounded by it (and pruned by the exact lower bound unless disabled)
+    uint64_t* pt = w.part;
+    clk.at(HNTL_STAGE_SCAN);
+    unsigned long long* scored = (sp.flags & HNTL_FLAG_PROFILE) ? g_prof.counter(ix.device) : nullptr;
+    if (P > 1) launch_reset_slot0_tail(pt, nq, (int)P, (int)C, s);
+    launch_scan(ix, (int)sp.codes, T, eq, (int)P, (int)C, w.b, LIST_SLOT0, pt, nullptr, false, scored, s);
+    if (P > 1) {
+      const bool bounded = !(sp.flags & HNTL_FLAG_NO_PRUNE);
+      launch_scan(ix, (int)sp.codes, T, eq, (int)P, (int)C, w.b, LIST_REST, pt, bounded ? pt : nullptr, bounded,
+                  scored, s);
+    }
+    part = pt;
+  }
+  // 5. pool merge + exact rerank
+  clk.at(HNTL_STAGE_RERANK);
+  launch_merge_rerank(ix, Q, nq, (int)P, (int)C, (int)k, probes, part, io.pool_in, io.pool_out, io.pool_D_out, io.ids,
+                      io.dist, s, nullptr, mode_a ? ix.eps_id : nullptr);
+  clk.done();
+  if (sp.flags & HNTL_FLAG_SYNC) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+  }
+}
+
+// Scratch of hntl_search_noalloc: one static device array per GPU, held until
+// the process ends.  Its address on a device comes from hipGetSymbolAddress,
+// taken once per device with that device current; host code never passes
+// the array's own name to a kernel or a copy (on the host it is only a
+// stand-in, not a device address).
+__device__ __align__(256) unsigned char scratch[HNTL_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of this device's scratch array (the current device).
+char* noalloc_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= 64) throw ArgError{HNTL_EUNSUPPORTED, "device ordinal above 63"};
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw ArgError{HNTL_EDEVICE, "no device address for the static scratch array"};
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
 }  // namespace
 
 // Finish an index whose host-side grain offsets, codes and eps (grain order) are
@@ -384,124 +596,49 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
                                const int32_t* pool_in, int32_t* pool_out, float* pool_D_out, int32_t* ids,
                                float* dist, void* stream) {
   g_last_error.clear();
-  if (!index || !sp) return fail(HNTL_EINVAL, "null index or params");
+  const StagedIO io{probes_in, probes_out, pdist_out, tangent_in, epsq_in, tangent_out, epsq_out,
+                    pool_in,   pool_out,   pool_D_out, ids,       dist};
+  const hntl_status st = check_search(index, Q, nq, sp, io);
+  if (st != HNTL_OK || nq == 0) return st;
   const Index& ix = index->ix;
-  const uint32_t P = sp->P, C = sp->C, k = sp->k;
-  if (P < 1 || P > ix.G) return fail(HNTL_EINVAL, "need 1 <= P <= G");
-  if (P > HNTL_MAX_P) return fail(HNTL_EUNSUPPORTED, "P exceeds HNTL_MAX_P");
-  if (k < 1 || C < k) return fail(HNTL_EINVAL, "need 1 <= k <= C");
-  if (C > HNTL_MAX_C) return fail(HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C");
-  if (sp->codes > HNTL_CODES_INT16) return fail(HNTL_EINVAL, "unknown codes form");
-  if (sp->codes == HNTL_CODES_INT16 && (sp->flags & HNTL_FLAG_MODE_A))
-    return fail(HNTL_EUNSUPPORTED, "Mode A answers use the FP32 / BF16 / FP8 code forms");
-  if (!(ix.codes_mask & (1u << sp->codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
-  if ((tangent_in == nullptr) != (epsq_in == nullptr)) return fail(HNTL_EINVAL, "tangent_in and epsq_in go together");
-  if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
-  if ((sp->flags & HNTL_FLAG_ROUTE_BF16X3) && (sp->flags & HNTL_FLAG_ROUTE_BF16))
-    return fail(HNTL_EINVAL, "choose one centroid routing form");
-  const bool learned = sp->route == HNTL_ROUTE_LEARNED && !probes_in && !pool_in;
-  if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
-  const bool mode_a = (sp->flags & HNTL_FLAG_MODE_A) != 0;
-  if (!mode_a && !ix.X) return fail(HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches");
-  if (mode_a && pool_in) return fail(HNTL_EUNSUPPORTED, "Mode A answers need the merged pool, not an injected one");
-  if (nq == 0) return HNTL_OK;
-  if (!Q || !ids || !dist) return fail(HNTL_EINVAL, "Q, ids and dist are required");
   hipStream_t s = (hipStream_t)stream;
   return guarded([&] {
     HIP_TRY(hipSetDevice(ix.device));
     ensure_pool(ix.device);
+    derive_search_data(const_cast<Index&>(ix), *sp, io, s);  // derived index data, made once under a lock
     Scratch sc(s);
-    if (sp->flags & HNTL_FLAG_CHECK_Q) {
-      int* flag = sc.get<int>(1);
-      HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
-      const int64_t n = (int64_t)nq * ix.d;
-      hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, n, flag);
-      HIP_TRY(hipGetLastError());
-      int hflag = 0;
-      HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      require(hflag == 0, "queries contain NaN or Inf");
-    }
-    const int64_t npairs = (int64_t)nq * P;
-    StageClock clk((sp->flags & HNTL_FLAG_PROFILE) != 0, s);
-    const uint64_t* part = nullptr;
-    const int32_t* probes = probes_in;
-    if (!pool_in) {
-      // 1. routing
-      if (!probes) {
-        clk.at(HNTL_STAGE_ROUTE);
-        int32_t* pr = probes_out ? probes_out : sc.get<int32_t>(npairs);
-        if (learned) {
-          RouterScratch w;
-          char* base = sc.get<char>(w.layout(nullptr, ix, nq, (int)P));
-          w.layout(base, ix, nq, (int)P);
-          launch_route_learned(ix, Q, nq, (int)P, sp->tau, pr, pdist_out, w, s);
-        } else {
-          const int form = route_form(sp->flags);
-          if (form != ROUTE_F32) ensure_centroid_split(const_cast<Index&>(ix), s);  // derived data, made once under a lock
-          RouteScratch w;
-          char* base = sc.get<char>(w.layout(nullptr, ix, nq, form));
-          w.layout(base, ix, nq, form);
-          launch_route_centroid(ix, Q, nq, (int)P, w, pr, pdist_out, s);
-        }
-        probes = pr;
-      }
-      // 2. bucketing by grain (each grain's probe-slot-0 pairs first, so that
-      //    slot 0 is scanned first and its C-th key bounds the other slots)
-      clk.at(HNTL_STAGE_BUCKET);
-      Buckets b;
-      b.G = (int)ix.G;
-      b.gcount = sc.get<int32_t>(ix.G);
-      b.gcount0 = sc.get<int32_t>(ix.G);
-      b.gstart = sc.get<int32_t>(ix.G);
-      b.cur0 = sc.get<int32_t>(ix.G);
-      b.cur1 = sc.get<int32_t>(ix.G);
-      b.order = sc.get<int32_t>(npairs);
-      const int tiles[3] = {16, 16, PROJECT_TILE};
-      const int64_t np[3] = {(int64_t)nq, (int64_t)nq * (P - 1), npairs};
-      for (int L = 0; L < 3; ++L) {
-        b.lists.tile[L] = tiles[L];
-        b.lists.ioff[L] = sc.get<int32_t>(ix.G + 1);
-        b.lists.lstart[L] = sc.get<int32_t>(ix.G);
-        b.lists.lcount[L] = sc.get<int32_t>(ix.G);
-        b.max_items[L] = (int)(np[L] / tiles[L] + std::min<int64_t>(ix.G, np[L]) + 1);
-      }
-      launch_bucket(probes, nq, (int)P, (int)ix.G, b, s);
-      // 3. projection
-      const float* T = tangent_in;
-      const float* eq = epsq_in;
-      if (!T) {
-        clk.at(HNTL_STAGE_PROJECT);
-        float* To = tangent_out ? tangent_out : sc.get<float>((size_t)npairs * ix.r);
-        float* eo = epsq_out ? epsq_out : sc.get<float>(npairs);
-        launch_project(ix, Q, (int)P, b, To, eo, (sp->flags & HNTL_FLAG_PROJECT_BF16) != 0, nullptr, s);
-        T = To;
-        eq = eo;
-      }
-      // 4. scan + per-pair top-C: slot 0 unbounded, then the other slots
-      //    bounded by it (and pruned by the exact lower bound unless disabled)
-      uint64_t* pt = sc.get<uint64_t>((size_t)npairs * C);
-      clk.at(HNTL_STAGE_SCAN);
-      unsigned long long* scored = (sp->flags & HNTL_FLAG_PROFILE) ? g_prof.counter(ix.device) : nullptr;
-      if (P > 1) launch_reset_slot0_tail(pt, nq, (int)P, (int)C, s);
-      launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, LIST_SLOT0, pt, nullptr, false, scored, s);
-      if (P > 1) {
-        const bool bounded = !(sp->flags & HNTL_FLAG_NO_PRUNE);
-        launch_scan(ix, (int)sp->codes, T, eq, (int)P, (int)C, b, LIST_REST, pt, bounded ? pt : nullptr, bounded,
-                    scored, s);
-      }
-      part = pt;
-    }
-    // 5. pool merge + exact rerank
-    clk.at(HNTL_STAGE_RERANK);
-    if (mode_a) ensure_eps_by_id(const_cast<Index&>(ix), s);  // derived data, made once under a lock
-    launch_merge_rerank(ix, Q, nq, (int)P, (int)C, (int)k, probes, part, pool_in, pool_out, pool_D_out, ids, dist, s,
-                        nullptr, mode_a ? ix.eps_id : nullptr);
-    clk.done();
-    if (sp->flags & HNTL_FLAG_SYNC) {
-      HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipGetLastError());
-    }
+    StagedScratch w;
+    char* base = sc.get<char>(w.layout(nullptr, ix, nq, *sp, io));
+    w.layout(base, ix, nq, *sp, io);
+    run_staged(ix, Q, nq, *sp, io, w, s);
+  });
+}
+
+hntl_status hntl_search_noalloc(const hntl_index* index, const float* Q, uint32_t nq,
+                                const hntl_search_params* sp, int32_t* ids, float* dist, void* stream) {
+  g_last_error.clear();
+  const StagedIO io{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                    nullptr, nullptr, nullptr, ids,     dist};
+  const hntl_status st = check_search(index, Q, nq, sp, io);
+  if (st != HNTL_OK || nq == 0) return st;
+  if (sp->flags & HNTL_FLAG_PROFILE)
+    return fail(HNTL_EINVAL, "hntl_search_noalloc records no stage events (HNTL_FLAG_PROFILE)");
+  const Index& ix = index->ix;
+  if (!search_data_ready(ix, *sp, io))
+    return fail(HNTL_ESTATE, "derived index data missing (split centroids of a BF16 routing form, or eps by id of "
+                             "Mode A): run one hntl_search with the same flags first");
+  StagedScratch w;
+  const size_t need = w.layout(nullptr, ix, nq, *sp, io);
+  if (need > (size_t)HNTL_NOALLOC_SCRATCH_BYTES)
+    return fail(HNTL_EINVAL, "hntl_search_noalloc needs " + std::to_string(need) + " bytes of scratch for this call, "
+                             "more than HNTL_NOALLOC_SCRATCH_BYTES (" + std::to_string(HNTL_NOALLOC_SCRATCH_BYTES) +
+                             "): use a smaller batch or hntl_search");
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&] {
+    HIP_TRY(hipSetDevice(ix.device));
+    char* base = noalloc_scratch(ix.device);
+    w.layout(base, ix, nq, *sp, io);
+    run_staged(ix, Q, nq, *sp, io, w, s);
   });
 }
 

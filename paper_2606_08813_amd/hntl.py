@@ -95,6 +95,8 @@ EXPORTS = {
     "hntl_index_free": (None, [C.c_void_p]),
     "hntl_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params), C.c_void_p,
                               C.c_void_p, C.c_void_p]),
+    "hntl_search_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params), C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
     "hntl_search_stages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(hntl_search_params)]
                            + [C.c_void_p] * 13),
     "hntl_profile_read": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -340,6 +342,27 @@ def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0,
     _check(lib().hntl_search(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
                              _stream(stream)))
     return ids, dist
+
+
+def hntl_search_noalloc(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None,
+                        route="centroid", tau=0.0):
+    """hntl_search with its scratch in the library's static per-GPU array (no device
+    allocation by the library); out = (ids, dist) CUDA tensors, else new ones."""
+    import torch
+    _cuda_f32(Q, "Q")
+    nq = Q.shape[0]
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    else:
+        ids, dist = out
+    sp = _params(P, C_, k, codes, flags, route, tau)
+    _check(lib().hntl_search_noalloc(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
+                                     _stream(stream)))
+    return ids, dist
+
+
+HNTL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def hntl_profile_read():
