@@ -29,7 +29,7 @@ Other forms are flags of the same script:
   --sched ...      a fixed plan schedule instead of the autotuner's
   --route learned  the learned router as the headline form
   --codes bf16|fp8 reduced-precision codes (BF16 MFMA projection by default)
-  --codes int16    the paper's own int16 form (eq. 5, envelope filter)
+  --codes int16    the paper's own int16 form (eq. 5, envelope filter, integer distances)
   --mode A         the answer from the index alone (no raw-vector rerank)
   --route-form     centroid routing's shortlist products (fp32, bf16, bf16x3)
 """
@@ -309,9 +309,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     from workloads import WORKLOADS
-    if args.codes == "int16" and args.form == "plan":
-        print("the int16 form (eq. 5) runs in the staged search only: add --form staged", file=sys.stderr)
-        sys.exit(2)
     W = WORKLOADS[args.workload]
     batching = W.name == "zipf10M_d768_G8192_r48"
     headline_plain = args.form == "plan" and args.route == "centroid" and args.codes == "fp32" and args.mode == "B"

@@ -71,8 +71,9 @@ typedef enum hntl_codes {
                                uint16 r_hat_i = rint(fl32(eps_i) * rinv_g), rinv_g = fl32(65535 / max_i eps_i);
                                score (1 / inv_g)^2 sum_j (z_hat_q,j - z_hat_i,j)^2 (exact integer sum)
                                + r_hat_i / rinv_g + eps_q; a probed grain in which more than 25% of the
-                               query's coordinates saturate is pruned (envelope filter).  Staged search
-                               only (plans: EUNSUPPORTED), Mode B only */
+                               query's coordinates saturate is pruned (envelope filter).  The integer sum
+                               is exact (64-bit); exact pruning uses the grain's code box in code space.
+                               Mode B only */
 } hntl_codes;
 
 /* Search flags. */
@@ -231,11 +232,16 @@ hntl_status hntl_index_export(const hntl_index* index, float* centroids, float* 
 
 /*
  * hntl_index_export_codes - the reduced-precision codes of an index, unpacked to
- * N x r in grain order: uint16 BF16 bit patterns (codes = HNTL_CODES_BF16) or
- * uint8 E4M3fn bit patterns (codes = HNTL_CODES_FP8_E4M3, value = code * scales[g]).
- * out and scales (G floats, FP8 only) are host or device and may be NULL.
- * Errors: EINVAL (FP32 requested), ESTATE (form not built).  Synchronous.
+ * N x r in grain order: uint16 BF16 bit patterns (codes = HNTL_CODES_BF16),
+ * uint8 E4M3fn bit patterns (codes = HNTL_CODES_FP8_E4M3, value = code * scales[g],
+ * scales: the G FP8 scales) or int16 codes z_hat (codes = HNTL_CODES_INT16,
+ * scales: the G inv_g).  With codes = HNTL_CODES_INT16 | HNTL_EXPORT_RESIDUALS,
+ * out receives the N uint16 residual codes r_hat_i (eq. 5, grain order) and
+ * scales the G rinv_g.  out and scales are host or device and may be NULL.
+ * Errors: EINVAL (FP32 requested, residuals of another form), ESTATE (form not
+ * built).  Synchronous.
  */
+#define HNTL_EXPORT_RESIDUALS 0x100u
 hntl_status hntl_index_export_codes(const hntl_index* index, uint32_t codes, void* out, float* scales);
 
 typedef struct hntl_index_info {

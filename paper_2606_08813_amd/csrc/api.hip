@@ -519,9 +519,36 @@ hntl_status hntl_index_export_codes(const hntl_index* index, uint32_t codes, voi
   g_last_error.clear();
   if (!index) return fail(HNTL_EINVAL, "index is NULL");
   const Index& ix = index->ix;
+  const bool resid = (codes & HNTL_EXPORT_RESIDUALS) != 0;
+  codes &= ~HNTL_EXPORT_RESIDUALS;
   if (codes != HNTL_CODES_BF16 && codes != HNTL_CODES_FP8_E4M3 && codes != HNTL_CODES_INT16)
     return fail(HNTL_EINVAL, "codes must be BF16, FP8 or INT16");
+  if (resid && codes != HNTL_CODES_INT16) return fail(HNTL_EINVAL, "residual codes exist for INT16 only");
   if (!(ix.codes_mask & (1u << codes))) return fail(HNTL_ESTATE, "codes form not built for this index");
+  if (resid)
+    return guarded([&] {
+      // r_hat_i from the stored decoded residual fl32(r_hat_i * fl32(1 / rinv_g)):
+      // its relative error is below 2^-23, so r_hat_i <= 65535 is the nearest integer
+      // of decoded * rinv_g
+      const uint32_t G = ix.G;
+      auto st = to_host(ix.i16_steps, (size_t)G * 4);
+      auto dec = to_host(ix.eps_i16, (size_t)ix.nblocks * B);
+      if (scales) {
+        std::vector<float> rinv(G);
+        for (uint32_t g = 0; g < G; ++g) rinv[g] = st[(size_t)g * 4 + 1];
+        HIP_TRY(hipMemcpy(scales, rinv.data(), sizeof(float) * G, hipMemcpyDefault));
+      }
+      if (!out) return;
+      std::vector<uint16_t> o(ix.N);
+      for (uint32_t g = 0; g < G; ++g) {
+        const int64_t a = ix.offsets_h[g], n = ix.offsets_h[g + 1] - a;
+        for (int64_t i = 0; i < n; ++i) {
+          const double v = (double)dec[((size_t)ix.boff_h[g] + i / B) * B + i % B] * (double)st[(size_t)g * 4 + 1];
+          o[a + i] = (uint16_t)std::llround(v);
+        }
+      }
+      HIP_TRY(hipMemcpy(out, o.data(), o.size() * sizeof(uint16_t), hipMemcpyDefault));
+    });
   return guarded([&] {
     const uint32_t G = ix.G, r = ix.r, rp = ix.rp;
     if (scales && codes == HNTL_CODES_FP8_E4M3)

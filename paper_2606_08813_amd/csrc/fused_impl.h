@@ -57,9 +57,11 @@ namespace fused_detail {
 
 using proj_detail::project_wave;
 using proj_detail::project_wave_bf16;
+using scan_detail::int_sq_dist;
 using scan_detail::ListOf;
 using scan_detail::load_block;
 using scan_detail::PRUNE_SLACK;
+using scan_detail::q16f;
 
 constexpr int REFRESH = 16;                 // blocks between bound exchanges
 constexpr long long SPIN_LIMIT = 1ll << 26;  // wait polls before giving up
@@ -112,12 +114,20 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     eqv = ldg(a.epsq + pv);
     if (a.lbase) lbv = ldg(a.lbase + pv);
   }
+  // the grain's smallest eps_i; for the int16 form the smallest decoded
+  // residual (monotone in eps_i, so the decoded value of the grain's smallest
+  // eps_i), with the index's own arithmetic
+  float emin_g = 0.f;
+  if (a.prune) {
+    emin_g = ldg(a.emin + g);
+    if constexpr (CT == 3)
+      emin_g = q16f(emin_g, ldg(a.scales + (size_t)g * 4 + 1), 0.f, 65535.f) * ldg(a.scales + (size_t)g * 4 + 3);
+  }
   // eps_q + the grain's smallest eps_i bounds eq. 6 from below without the
   // tangent (the squared tangent distance is >= 0 and the float sums are
   // monotone): when it already exceeds every pair's query bound, the tile is
   // done without loading its tangents
   if (a.prune) {
-    const float emin_g = ldg(a.emin + g);
     const bool cut = lane < cnt && obv != NO_BOUND && (eqv + emin_g) * (1.f - PRUNE_SLACK) > ord2f(obv);
     const uint64_t all = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
     if (__ballot(cut) == all) {
@@ -132,15 +142,35 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   }
   if (lane < QT) eq[lane] = eqv;
   wave_sync();
+  // int16 form: the pairs' tangents quantised with the grain's step (float32
+  // product, ties to even, clamped to +-32767, kept as exact float integers),
+  // counting saturated coordinates for the envelope filter
+  int nsat[QT];
+  float d2 = 1.f;
+  if constexpr (CT == 3) {
+    const float inv = ldg(a.scales + (size_t)g * 4);
+    d2 = ldg(a.scales + (size_t)g * 4 + 2);
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      const float qv = rintf((lane < r ? zq[t][lane] : 0.f) * inv);
+      nsat[t] = __popcll(__ballot(lane < r && fabsf(qv) > 32767.f));
+      if (lane < r) zq[t][lane] = fminf(fmaxf(qv, -32767.f), 32767.f);
+    }
+    wave_sync();
+  }
 
   const float sg = CT == 2 ? ldg(a.scales + g) : 1.f;
   float lo = (a.prune && lane < r) ? ldg(a.blo + (size_t)g * RP + lane) : 0.f;
   float hi = (a.prune && lane < r) ? ldg(a.bhi + (size_t)g * RP + lane) : 0.f;
-  if (CT != 0) {  // the box must hold the decoded values the scan uses
+  if (CT == 1 || CT == 2) {  // the box must hold the decoded values the scan uses
     const float amax = fmaxf(fabsf(lo), fabsf(hi));
     const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
     lo -= 1.0001f * w;
     hi += 1.0001f * w;
+  } else if (CT == 3) {  // the box in code space (the code rounding is monotone)
+    const float inv = ldg(a.scales + (size_t)g * 4);
+    lo = lane < r ? q16f(lo, inv, -32767.f, 32767.f) : 0.f;
+    hi = lane < r ? q16f(hi, inv, -32767.f, 32767.f) : 0.f;
   }
   List Ls[QT];
   bool live[QT];
@@ -149,13 +179,30 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   for (int t = 0; t < QT; ++t) {
     live[t] = t < cnt;
     uint64_t bnd = KEY_NONE;
+    if constexpr (CT == 3) {
+      // quantisation envelope filter (Section 2.3): more than a quarter of the
+      // coordinates saturated -> the grain is pruned for this query
+      if (live[t] && 4 * nsat[t] > r) {
+        live[t] = false;
+        const int64_t slot = (int64_t)__builtin_amdgcn_readlane(lbv, t) + range;
+        if (lane == 0) stg(a.part + (size_t)slot * C, KEY_NONE);  // empty list
+      }
+    }
     if (live[t]) {
       const uint32_t ob = (uint32_t)__builtin_amdgcn_readlane((int)obv, t);
       bnd = bound_key(ob);
       if (a.prune && ob != NO_BOUND) {
-        const float v = lane < r ? zq[t][lane] : 0.f;
-        const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
-        const float lb = wave_sum(dd * dd) + eq[t] + ldg(a.emin + g);
+        float lb;
+        if constexpr (CT == 3) {
+          // exact integer distance to the code box, then the score's arithmetic
+          const float v = lane < r ? zq[t][lane] : 0.f;
+          const double dd = (double)fmaxf(fmaxf(lo - v, v - hi), 0.f);
+          lb = fmaf((float)wave_sum_d(dd * dd), d2, emin_g + eq[t]);
+        } else {
+          const float v = lane < r ? zq[t][lane] : 0.f;
+          const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
+          lb = wave_sum(dd * dd) + eq[t] + emin_g;
+        }
         if (__builtin_amdgcn_readfirstlane(lb * (1.f - PRUNE_SLACK) > ord2f(ob) ? 1 : 0)) {
           live[t] = false;
           const int64_t slot = (int64_t)__builtin_amdgcn_readlane(lbv, t) + range;
@@ -197,13 +244,18 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       if (live[t]) {
-        float acc = 0.f;
+        if constexpr (CT == 3) {
+          const uint64_t S = int_sq_dist<RP>(zq[t], c);
+          Ls[t].offer(make_key(fmaf((float)S, d2, e + eq[t]), pos), valid);
+        } else {
+          float acc = 0.f;
 #pragma unroll
-        for (int j = 0; j < RP; ++j) {
-          const float df = zq[t][j] - c[j];
-          acc = fmaf(df, df, acc);
+          for (int j = 0; j < RP; ++j) {
+            const float df = zq[t][j] - c[j];
+            acc = fmaf(df, df, acc);
+          }
+          Ls[t].offer(make_key(acc + eq[t] + e, pos), valid);
         }
-        Ls[t].offer(make_key(acc + eq[t] + e, pos), valid);
       }
     }
   };

@@ -38,9 +38,11 @@ namespace hntl {
 bool launch_fused_ct0(const FusedArgs*, int, int, int, int, int, hipStream_t);
 bool launch_fused_ct1(const FusedArgs*, int, int, int, int, int, hipStream_t);
 bool launch_fused_ct2(const FusedArgs*, int, int, int, int, int, hipStream_t);
+bool launch_fused_ct3(const FusedArgs*, int, int, int, int, int, hipStream_t);
 int fused_resident_ct0(int, int, int, int);
 int fused_resident_ct1(int, int, int, int);
 int fused_resident_ct2(int, int, int, int);
+int fused_resident_ct3(int, int, int, int);
 
 namespace {
 
@@ -52,7 +54,8 @@ bool fused_launch(int codes, const FusedArgs* a, int rp, int C, int qt, int nw, 
   switch (codes) {
     case HNTL_CODES_FP32: return launch_fused_ct0(a, rp, C, qt, nw, grid, s);
     case HNTL_CODES_BF16: return launch_fused_ct1(a, rp, C, qt, nw, grid, s);
-    default: return launch_fused_ct2(a, rp, C, qt, nw, grid, s);
+    case HNTL_CODES_FP8_E4M3: return launch_fused_ct2(a, rp, C, qt, nw, grid, s);
+    default: return launch_fused_ct3(a, rp, C, qt, nw, grid, s);
   }
 }
 
@@ -60,7 +63,8 @@ int fused_resident(int codes, int rp, int C, int qt, int nw) {
   switch (codes) {
     case HNTL_CODES_FP32: return fused_resident_ct0(rp, C, qt, nw);
     case HNTL_CODES_BF16: return fused_resident_ct1(rp, C, qt, nw);
-    default: return fused_resident_ct2(rp, C, qt, nw);
+    case HNTL_CODES_FP8_E4M3: return fused_resident_ct2(rp, C, qt, nw);
+    default: return fused_resident_ct3(rp, C, qt, nw);
   }
 }
 
@@ -244,17 +248,22 @@ struct Plan {
   }
 
   const void* codes_ptr() const {
-    return sp.codes == HNTL_CODES_FP32 ? (const void*)ix->codes
-                                       : sp.codes == HNTL_CODES_BF16 ? (const void*)ix->codes_bf16
-                                                                     : (const void*)ix->codes_fp8;
+    switch (sp.codes) {
+      case HNTL_CODES_FP32: return ix->codes;
+      case HNTL_CODES_BF16: return ix->codes_bf16;
+      case HNTL_CODES_FP8_E4M3: return ix->codes_fp8;
+      default: return ix->codes_i16;
+    }
   }
 
   FusedArgs make_args() const {
     const Index& x = *ix;
     FusedArgs a{};
     a.codes = codes_ptr();
-    a.scales = x.scales;
-    a.eps = x.eps;
+    // int16 form: the per-grain steps in place of the FP8 scales, the decoded
+    // residuals r_hat_i / rinv_g in place of eps_i
+    a.scales = sp.codes == HNTL_CODES_INT16 ? x.i16_steps : x.scales;
+    a.eps = sp.codes == HNTL_CODES_INT16 ? x.eps_i16 : x.eps;
     a.goff = x.goff;
     a.boff = x.boff;
     a.perm = x.perm;
@@ -354,7 +363,8 @@ void check_plan_shape(const Index& ix, const hntl_search_params& sp) {
   if (sp.k < 1 || sp.C < sp.k) throw ArgError{HNTL_EINVAL, "need 1 <= k <= C"};
   if (sp.C > HNTL_MAX_C) throw ArgError{HNTL_EUNSUPPORTED, "C exceeds HNTL_MAX_C"};
   if (sp.codes > HNTL_CODES_INT16) throw ArgError{HNTL_EINVAL, "unknown codes form"};
-  if (sp.codes == HNTL_CODES_INT16) throw ArgError{HNTL_EUNSUPPORTED, "plans run the FP32, BF16 and FP8 code forms"};
+  if (sp.codes == HNTL_CODES_INT16 && (sp.flags & HNTL_FLAG_MODE_A))
+    throw ArgError{HNTL_EUNSUPPORTED, "Mode A answers use the FP32 / BF16 / FP8 code forms"};
   if (!(ix.codes_mask & (1u << sp.codes))) throw ArgError{HNTL_ESTATE, "codes form not built for this index"};
   if ((sp.flags & HNTL_FLAG_PROJECT_BF16) && !ix.basis_bf16)
     throw ArgError{HNTL_ESTATE, "BF16 projection needs the BF16 basis (build a reduced-precision code form)"};

@@ -52,6 +52,7 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
       c[2 * j + 1] = __uint_as_float(w & 0xFFFF0000u);
     }
   } else if constexpr (CT == 3) {
+    // int16 codes as exact float integers
     const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
 #pragma unroll
     for (int j = 0; j < RP / 2; ++j) {
@@ -72,6 +73,28 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
       c[4 * j + 3] = hi[1] * s;
     }
   }
+}
+
+// int16 form: sum_j (zq_j - c_j)^2 over integers.  Query coordinates and codes
+// are integers in [-32767, 32767] held as floats, so the float difference is
+// exact, |d| <= 65534 < 2^16, and the unsigned 24-bit product |d| |d|
+// (v_mul_u32_u24) is d^2 exactly in 32 bits (< 2^32); the sum runs in 64-bit
+// integers.  No step is signed: a square above 2^31 stays an unsigned value.
+template <int RP>
+__device__ __forceinline__ uint64_t int_sq_dist(const float* __restrict__ zq, const float (&c)[RP]) {
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    const uint32_t ad = (uint32_t)fabsf(zq[j] - c[j]);
+    acc += (uint64_t)(uint32_t)__umul24(ad, ad);
+  }
+  return acc;
+}
+
+// int16 code of a float code value (float32 product, ties to even, clamped),
+// as the index's packing computes it.
+__device__ __forceinline__ float q16f(float x, float inv, float lo, float hi) {
+  return fminf(fmaxf(rintf(x * inv), lo), hi);
 }
 
 template <int RP, int CAP, int QT, int CT>
@@ -134,7 +157,6 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
   bool live[QT];
   int nlive = 0;
   const float sg = CT == 2 ? scales[g] : 1.f;
-  prune = CT == 3 ? 0 : prune;  // the box lives in float code space, not in the int16 one
   // this lane's coordinate of the grain's code bounding box (lanes >= r idle),
   // widened by the largest rounding error of the code form so that it holds
   // the decoded values the scan uses: BF16 half-ulp 2^-9 relative; FP8 E4M3
@@ -146,6 +168,18 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
     const float w = CT == 1 ? amax * 0.001953125f : amax * 0.0625f + sg * 0.0009765625f;
     lo -= 1.0001f * w;
     hi += 1.0001f * w;
+  }
+  // int16 form: the box in code space (the code rounding is monotone, so the
+  // codes of the box ends bound every member's codes), and the smallest
+  // decoded residual (the decoded residual is monotone in eps_i)
+  float emin_g = 0.f;
+  if (CT == 3 && bound_lists && prune) {
+    const float inv = scales[(size_t)g * 4];
+    lo = lane < r ? q16f(lo, inv, -32767.f, 32767.f) : 0.f;
+    hi = lane < r ? q16f(hi, inv, -32767.f, 32767.f) : 0.f;
+    emin_g = q16f(emin[g], scales[(size_t)g * 4 + 1], 0.f, 65535.f) * scales[(size_t)g * 4 + 3];
+  } else if (bound_lists && prune) {
+    emin_g = emin[g];
   }
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
@@ -174,9 +208,20 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
       if (prune && bnd != KEY_NONE) {
         // eq. 6 lower bound over the grain: squared distance from z_q to the
         // code bounding box, plus eps_q, plus the grain's smallest eps_i
-        const float v = lane < r ? zq[t][lane] : 0.f;
-        const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
-        const float lb = wave_sum(dd * dd) + eq[t] + emin[g];
+        float lb;
+        if constexpr (CT == 3) {
+          // integer distance from the query's codes to the code box, exact in
+          // float64, then the score's own arithmetic: a lower bound of every
+          // member's score
+          const float v = lane < r ? zq[t][lane] : 0.f;
+          const double dd = (double)fmaxf(fmaxf(lo - v, v - hi), 0.f);
+          const double S = wave_sum_d(dd * dd);
+          lb = fmaf((float)S, d2, emin_g + eq[t]);
+        } else {
+          const float v = lane < r ? zq[t][lane] : 0.f;
+          const float dd = fmaxf(fmaxf(lo - v, v - hi), 0.f);
+          lb = wave_sum(dd * dd) + eq[t] + emin_g;
+        }
         if (lb * (1.f - PRUNE_SLACK) > key_dist(bnd)) {
           live[t] = false;
           for (int i = lane; i < C; i += HNTL_WAVE) part[(size_t)p * C + i] = KEY_NONE;  // empty list
@@ -200,14 +245,9 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
       for (int t = 0; t < QT; ++t) {
         if (live[t]) {
           if constexpr (CT == 3) {
-            // integer differences (|d| <= 65534) squared and summed exactly in float64
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < RP; ++j) {
-              const double df = (double)(zq[t][j] - c[j]);
-              acc = fma(df, df, acc);
-            }
-            L[t].offer(make_key(fmaf((float)acc, d2, ei + eq[t]), pos), valid);
+            // the integer distance, exact; then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
+            const uint64_t S = int_sq_dist<RP>(zq[t], c);
+            L[t].offer(make_key(fmaf((float)S, d2, ei + eq[t]), pos), valid);
           } else {
             float acc = 0.f;
 #pragma unroll

@@ -286,9 +286,19 @@ def hntl_index_export(index: Index, with_scales=False) -> dict:
     return o
 
 
+HNTL_EXPORT_RESIDUALS = 0x100
+
+
 def hntl_index_export_codes(index: Index, codes: str):
     """Reduced-precision codes (N x r bit patterns, grain order) and, for FP8, the
-    per-grain scales; for int16, the signed codes and the per-grain inv_g."""
+    per-grain scales; for int16, the signed codes and the per-grain inv_g; for
+    "int16_residuals", the N uint16 residual codes r_hat and the per-grain rinv_g."""
+    if codes == "int16_residuals":
+        out = np.empty(index.N, np.uint16)
+        sc = np.empty(index.G, np.float32)
+        _check(lib().hntl_index_export_codes(index.handle, HNTL_CODES_INT16 | HNTL_EXPORT_RESIDUALS,
+                                             out.ctypes.data, sc.ctypes.data))
+        return out, sc
     if codes == "int16":
         out = np.empty((index.N, index.r), np.int16)
         sc = np.empty(index.G, np.float32)
