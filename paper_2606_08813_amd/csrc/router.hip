@@ -337,11 +337,137 @@ __global__ __launch_bounds__(512) void gemm_nn_kernel(const uint16_t* __restrict
 }
 constexpr size_t NN_LDS = (size_t)2 * (NM + NN) * NLD * sizeof(uint16_t);
 
+// ------------------------------- 256 x 256 tiles, LDS filled by direct loads
+// The same product as gemm_nn_kernel (both operands k-contiguous) for large
+// shapes with K % 64 == 0.  One workgroup of 8 waves (two per SIMD) per
+// 256 x 256 tile of C; wave w owns rows 128 (w / 4) .. + 127 and columns
+// 64 (w % 4) .. + 63 as 8 x 4 MFMA 16x16x32 tiles.  Depth tiles of 64 go from
+// global memory straight into the LDS (global_load_lds_dwordx4: lane l of a
+// wave instruction writes 16 bytes at the instruction's LDS base + 16 l), into
+// two buffers: tile k + 1 is requested before tile k is multiplied, so its
+// latency hides behind a whole tile of MFMAs, with no registers holding it.
+// A row of a depth tile is 8 chunks of 16 bytes; chunk c of row r sits at
+// position c ^ (r % 8) of the row (an XOR swizzle), so the 16 rows read by
+// one ds_read_b128 of an MFMA fragment spread over the LDS banks.  Rows past M
+// or N load a valid clamped row (their results are never stored).  Every
+// output element is accumulated in the same order as in gemm_nn_kernel (depth
+// tiles of 64, MFMA steps of 32), so the kernels give identical results.
+constexpr int BM = 256, BN = 256;
+constexpr size_t DL_STAGE = (size_t)(BM + BN) * NK * sizeof(uint16_t);  // 64 KiB
+constexpr size_t BIG_LDS = 2 * DL_STAGE;
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Requests one operand's 256 x 64 depth tile (rows r0.., depths k0..) into
+// the LDS at `dst`: 2048 chunks, 4 wave instructions of 64 chunks per wave.
+__device__ __forceinline__ void dl_fetch(uint16_t* dst, const uint16_t* __restrict__ X, int ld, int R, int r0,
+                                         int k0) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int u = h * 8 + wave;         // instruction index: LDS bytes 1024 u .. + 1023
+    const int c = u * 64 + lane;        // chunk of the tile in LDS order
+    const int row = c >> 3, pos = c & 7;
+    const int kc = pos ^ (row & 7);     // the depth chunk stored at that position
+    const int gr = min(r0 + row, R - 1);
+    __builtin_amdgcn_global_load_lds((const void*)(X + (size_t)gr * ld + k0 + kc * 8),
+                                     (lds_ptr_t)(dst + (size_t)u * 512), 16, 0, 0);
+  }
+}
+
+// 8 bf16 of row r, depths 8 kc .. 8 kc + 7, of a swizzled depth tile.
+__device__ __forceinline__ bf16x8 dl_frag(const uint16_t* S, int r, int kc) {
+  return *reinterpret_cast<const bf16x8*>(S + ((size_t)r * 8 + (kc ^ (r & 7))) * 8);
+}
+
+template <int EPI>
+__global__ __launch_bounds__(512) void gemm_big_kernel(const uint16_t* __restrict__ A, int lda,
+                                                       const uint16_t* __restrict__ B, int ldb, int M, int N, int K,
+                                                       Epi e, const int32_t* __restrict__ mlim, int tiles_n,
+                                                       int ntiles) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t dsm[];
+  // XCD-contiguous tile order: workgroup b runs on XCD b % 8
+  const int nb = (int)gridDim.x, per = nb / 8;
+  const int bid = (int)blockIdx.x;
+  const int tile = (nb % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
+  if (tile >= ntiles) return;
+  const int m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+  if (mlim) {
+    const int lim = (int)(*mlim - e.row_base);
+    if (m0 >= lim) return;
+    if (lim < M) M = lim;
+  }
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int i = lane & 15, kq = lane >> 4;
+  floatx4 acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nk = K / NK;
+  uint16_t* const st0 = dsm;
+  uint16_t* const st1 = dsm + DL_STAGE / sizeof(uint16_t);
+  dl_fetch(st0, A, lda, M, m0, 0);
+  dl_fetch(st0 + BM * NK, B, ldb, N, n0, 0);
+  for (int k = 0; k < nk; ++k) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's requests for tile k have landed
+    __syncthreads();                // every wave's have, and every wave is done with tile k - 1
+    if (k + 1 < nk) {               // the other buffer (last read for tile k - 1) takes tile k + 1
+      uint16_t* nx = (k & 1) ? st0 : st1;
+      dl_fetch(nx, A, lda, M, m0, (k + 1) * NK);
+      dl_fetch(nx + BM * NK, B, ldb, N, n0, (k + 1) * NK);
+    }
+    const uint16_t* As = (k & 1) ? st1 : st0;
+    const uint16_t* Bs = As + BM * NK;
+#pragma unroll
+    for (int ks = 0; ks < NK; ks += 32) {
+      const int kc = (ks >> 3) + kq;
+      bf16x8 bfv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bfv[t] = dl_frag(Bs, wn + 16 * t + i, kc);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const bf16x8 af = dl_frag(As, wm + 16 * a + i, kc);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wm + 16 * a + 4 * kq + j;
+        const int col = n0 + wn + 16 * b + i;
+        if (row < M && col < N) epi_store<EPI>(e, row, col, acc[a][b][j]);
+      }
+}
+constexpr int BIG_MIN_ROWS = 512;  // fewer rows: the 256 x 128 tiles keep more workgroups busy
+
 template <bool AT, bool BT, int EPI>
 void gemm(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K, const Epi& e, hipStream_t s,
           const int32_t* mlim = nullptr) {
   if (M <= 0 || N <= 0) return;
   if constexpr (!AT && !BT) {
+    if ((K % 8) == 0 && (lda % 8) == 0 && (ldb % 8) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 &&
+        M >= BIG_MIN_ROWS && N >= BN && (K % NK) == 0) {
+      const int tn = (N + BN - 1) / BN, tm = (M + BM - 1) / BM;
+      const int nt = tn * tm;
+      const int grid = (nt + 7) / 8 * 8;  // a multiple of 8 for the XCD-contiguous order
+      static bool lds_set = false;        // more than 64 KiB of dynamic LDS
+      if (!lds_set) {
+        HIP_TRY(hipFuncSetAttribute((const void*)gemm_big_kernel<EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)BIG_LDS));
+        lds_set = true;
+      }
+      hipLaunchKernelGGL((gemm_big_kernel<EPI>), dim3((unsigned)grid), dim3(512), BIG_LDS, s, A, lda, B, ldb, M, N, K,
+                         e, mlim, tn, nt);
+      HIP_TRY(hipGetLastError());
+      return;
+    }
     if ((K % 8) == 0 && (lda % 8) == 0 && (ldb % 8) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0) {
       const int tn = (N + NN - 1) / NN, tm = (M + NM - 1) / NM;
       const int nt = tn * tm;
@@ -506,6 +632,41 @@ __global__ __launch_bounds__(256) void fallback_select_kernel(const float* __res
   for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
   z = wave_sum(z);
   if (lane == 0 && 1.f / z < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
+}
+
+// Probability-mass probe budget of one learned row (one wave): with
+// m = max score and z = sum_g exp(s_g - m) over all G scores, slots are kept
+// up to and including the first j at which sum_{i <= j} exp(s_{p_i} - m) / z
+// reaches mass; later slots become probe -1 (pdist +inf).
+__global__ __launch_bounds__(256) void mass_cut_kernel(const float* __restrict__ negS, int64_t rows, int G, int P,
+                                                       float mass, int32_t* __restrict__ probes,
+                                                       float* __restrict__ pdist, const int32_t* __restrict__ nlim) {
+  const int lane = lane_id();
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows || (nlim && r >= *nlim)) return;
+  const float* s = negS + r * G;  // negated scores
+  float mn = __builtin_inff();
+  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
+  float z = 0.f;
+  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
+  z = wave_sum(z);
+  // lane j < P: probability of slot j; an inclusive prefix sum over the lanes
+  const int32_t pj = lane < P ? probes[r * P + lane] : -1;
+  float p = pj >= 0 ? expf(mn - s[pj]) / z : 0.f;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float t = __shfl_up(p, o, 64);
+    if (lane >= o) p += t;
+  }
+  const uint64_t reached = __ballot(lane < P && p >= mass);
+  if (!reached) return;
+  const int cut = __builtin_ctzll(reached);  // the first slot that reaches the mass: kept
+  if (lane > cut && lane < P) {
+    probes[r * P + lane] = -1;
+    if (pdist) pdist[r * P + lane] = __builtin_inff();
+  }
 }
 
 // Copies the query rows of the fallback list into a compact block.
@@ -725,7 +886,7 @@ void launch_route_centroid(const Index& ix, const float* Q, int64_t nq, int P, c
 }
 
 void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim) {
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim, float mass) {
   const Router& rt = *ix.router;
   hipLaunchKernelGGL(standardize_kernel, dim3(blocks(nq * rt.d)), dim3(256), 0, s, Q, nullptr, nq, rt.d, rt.mean,
                      rt.stdv, w.xh, nlim);
@@ -748,6 +909,11 @@ void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, fl
   gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
   launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, 0.f, nlim, 0,
                    nullptr);
+  if (mass > 0.f && mass < 1.f && P > 1) {
+    hipLaunchKernelGGL(mass_cut_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, P, mass, probes, pdist,
+                       nlim);
+    HIP_TRY(hipGetLastError());
+  }
   if (tau > 0.f) {
     launch_fill_i32(w.fb_count, 1, 0, s);
     hipLaunchKernelGGL(fallback_select_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, tau, w.fb_rows,

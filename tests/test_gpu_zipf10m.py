@@ -224,11 +224,11 @@ def _check_top_scores(gpu_probes, s, P, what, rel=2e-3):
 
 def test_router_parity_full_width(z):
     """The router at its full width, 768-1024-1024-8192 (the logits layer spans
-    64 column tiles of 128): forward scores and every gradient tensor of a
-    256-query batch against the oracle's BF16 emulation (1e-3 relative
-    Frobenius), and the search path's learned probes (256 rows through the
-    staged search, and the plan's results) against the oracle's
-    route_learned on the same weights."""
+    32 column tiles of 256): forward scores of 1,024 queries and every
+    gradient tensor of a 256-query batch against the oracle's BF16 emulation
+    (1e-3 relative Frobenius), and the search path's learned probes (1,024
+    rows through the staged search, and the plan's results) against the
+    oracle's route_learned on the same weights."""
     from oracle import router as orr
     W, hntl, torch = z["W"], z["hntl"], z["torch"]
     announce("10M: router 768-1024-1024-8192 with oracle weights: forward, gradients, search probes")
@@ -240,7 +240,7 @@ def test_router_parity_full_width(z):
                          std.astype(np.float32))
     p = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
     m, sd = mean.astype(np.float32).astype(np.float64), std.astype(np.float32).astype(np.float64)
-    Q = z["Q"][:256]
+    Q = z["Q"][:1024]  # 1,024 rows: the large-tile GEMM (from 512 rows on)
     s_gpu = hntl.hntl_router_forward(z["ix"], to_dev(Q)).cpu().numpy().astype(np.float64)
     s_orc, cache = orr.forward(p, Q, m, sd, bf16=True)
     err = np.linalg.norm(s_gpu - s_orc) / np.linalg.norm(s_orc)
@@ -257,7 +257,7 @@ def test_router_parity_full_width(z):
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
         e = np.linalg.norm(np.asarray(g_gpu[k], np.float64) - g_orc[k]) / np.linalg.norm(g_orc[k])
         assert e < 1e-3, (k, e)
-    # the search path's probes (learned routing, 256 rows) against route_learned
+    # the search path's probes (learned routing, 1,024 rows) against route_learned
     Qd = to_dev(Q)
     o = hntl.hntl_search_stages(z["ix"], Qd, W.P, W.C, W.k, route="learned")
     gp = o["probes"].cpu().numpy()
@@ -268,7 +268,23 @@ def test_router_parity_full_width(z):
     _check_top_scores(gp, s_orc, W.P, "learned probes")
     announce(f"learned probes equal to route_learned in {(gp == lp).all(1).mean():.4f} of rows")
     # and the plan's results equal the staged learned search on those rows
-    plan = hntl.hntl_plan_create(z["ix"], W.P, W.C, W.k, 256, route="learned")
+    plan = hntl.hntl_plan_create(z["ix"], W.P, W.C, W.k, 1024, route="learned")
     ids, dist = hntl.hntl_plan_search(plan, Qd)
     torch.cuda.synchronize()
     assert torch.equal(ids, o["ids"]) and torch.equal(dist, o["dist"])
+
+
+def test_bf16_routing_forms_full_size(z):
+    """At G = 8,192 and 2,048 rows (the large-tile GEMM with its direct LDS
+    loads), the plain and split BF16 shortlists give the same probes and
+    distances as FP32 MFMA routing: the P = 16 winners are FP32 direct
+    differences in every form."""
+    W, hntl, torch = z["W"], z["hntl"], z["torch"]
+    announce("10M: BF16 / split-BF16 / FP32 routing forms agree at 2,048 rows")
+    Q = z["Qd"][:2048].contiguous()
+    ref = hntl.hntl_search_stages(z["ix"], Q, W.P, W.C, W.k)
+    for fl in (hntl.HNTL_FLAG_ROUTE_BF16, hntl.HNTL_FLAG_ROUTE_BF16X3):
+        o = hntl.hntl_search_stages(z["ix"], Q, W.P, W.C, W.k, flags=hntl.HNTL_FLAG_SYNC | fl)
+        assert torch.equal(o["probes"], ref["probes"]), fl
+        assert torch.equal(o["pdist"], ref["pdist"]), fl
+        assert torch.equal(o["ids"], ref["ids"]) and torch.equal(o["dist"], ref["dist"]), fl
