@@ -241,6 +241,10 @@ def parse():
                     help="learned: train the router first (router-train queries, brute-force kNN targets)")
     ap.add_argument("--P", type=int, default=0, help="probes per query (0 = the workload's)")
     ap.add_argument("--tau", type=float, default=0.0, help="learned routing: centroid fallback below this max prob")
+    ap.add_argument("--mass", type=float, default=0.0,
+                    help="learned routing: probe budget, stop at this cumulative softmax probability (0 = all P)")
+    ap.add_argument("--compare-mass", type=float, default=0.99,
+                    help="probe budget of the learned comparison's second line (0 = skip that line)")
     ap.add_argument("--mode", choices=("A", "B"), default="B",
                     help="B: exact rerank against the raw vectors; A: the answer from the index alone")
     ap.add_argument("--route-form", choices=("auto", "fp32", "bf16", "bf16x3"), default="auto",
@@ -382,7 +386,7 @@ def main():
         flags |= {"fp32": 0, "bf16": hntl.HNTL_FLAG_ROUTE_BF16, "bf16x3": hntl.HNTL_FLAG_ROUTE_BF16X3}[route_form]
     if args.mode == "A":
         flags |= hntl.HNTL_FLAG_MODE_A
-    rkw = dict(route=args.route, tau=args.tau)
+    rkw = dict(route=args.route, tau=args.tau, mass=args.mass)
     plan_mask = (hntl.HNTL_FLAG_PROJECT_BF16 | hntl.HNTL_FLAG_NO_PRUNE | hntl.HNTL_FLAG_ROUTE_BF16X3 |
                  hntl.HNTL_FLAG_ROUTE_BF16 | hntl.HNTL_FLAG_MODE_A)
     pflags = flags & plan_mask
@@ -556,6 +560,21 @@ def main():
                    "vectors_scored_per_step": int(rl["scored"])}
         log(f"[bench] learned + BF16: {learned}")
         del rl
+        if args.compare_mass > 0:
+            # the same with the router's probability-mass probe budget
+            mkw = dict(route="learned", tau=args.tau, mass=args.compare_mass)
+            rm = time_plan(hntl, torch, ix, Q, P, W.C, W.k, W.nq, "bf16", fl_l, mkw, args.steps, args.warmup)
+            rec_m = recall_at_k(rm["ids"].cpu().numpy()[rs], gt, W.k)
+            pm = hntl.hntl_search_stages(ix, Q, P, W.C, W.k, codes="bf16", flags=hntl.HNTL_FLAG_SYNC | fl_l,
+                                         **mkw)["probes"]
+            learned["probe_budget"] = {
+                "mass": args.compare_mass, "value": round(W.nq / (rm["ms"] / 1e3), 1),
+                "ms_per_step": round(rm["ms"], 4), "recall_at_10": round(rec_m, 4),
+                "mean_probes_per_query": round(float((pm >= 0).sum().item()) / W.nq, 3),
+                "stage_ms": {kk: round(v, 4) for kk, v in rm["stage"].items()}, "schedule": rm["sched"],
+                "speedup_vs_plain_fp32": round(ms_per_step / rm["ms"], 4)}
+            log(f"[bench] learned + BF16 + probe budget: {learned['probe_budget']}")
+            del rm, pm
 
     # CPU oracle over the process pool, on the same index (timing only)
     cpu = None

@@ -279,6 +279,10 @@ typedef struct hntl_search_params {
   uint32_t route;   /* hntl_route; LEARNED needs a trained or imported router (else ESTATE) */
   float tau;        /* learned routing only: a query whose largest softmax probability over the grains
                        is below tau is routed by centroids instead (0 = never) */
+  float mass;       /* learned routing only, a probe budget: the top-P grains are kept up to and
+                       including the first slot at which the cumulative softmax probability (over all
+                       G router scores) reaches mass; later slots are probe -1 (not searched).
+                       0 or 1 = all P slots; must lie in [0, 1].  Ignored by centroid routing */
 } hntl_search_params;
 
 /*

@@ -137,6 +137,34 @@ def route_learned(params, x, mean, std, P, bf16=True):
     return order, np.take_along_axis(s, order, 1)
 
 
+def mass_cut(scores, probes, mass):
+    """Probability-mass probe budget: probes (rows x P, descending score) are
+    kept up to and including the first slot at which the cumulative softmax
+    probability (over all G scores of the row) reaches `mass`; later slots
+    become -1.  mass <= 0 or >= 1 keeps every slot."""
+    probes = np.array(probes, copy=True)
+    if mass <= 0.0 or mass >= 1.0:
+        return probes
+    s = np.asarray(scores, dtype=np.float64)
+    for i in range(len(s)):
+        m = s[i].max()
+        z = np.exp(s[i] - m).sum()
+        c = 0.0
+        for j in range(probes.shape[1]):
+            c += np.exp(s[i, probes[i, j]] - m) / z
+            if c >= mass:
+                probes[i, j + 1:] = -1
+                break
+    return probes
+
+
+def route_learned_mass(params, x, mean, std, P, mass, bf16=True):
+    """Learned routing under a probability-mass budget (mass_cut of the top-P)."""
+    s, _ = forward(params, x, mean, std, bf16)
+    probes, _ = route_learned(params, x, mean, std, P, bf16)
+    return mass_cut(s, probes, mass), s
+
+
 def route_with_fallback(params, x, mean, std, centroids, P, tau, bf16=True):
     """Learned routing with the centroid fallback: a query whose largest softmax
     probability over the grains is below tau takes the P nearest centroids

@@ -191,6 +191,7 @@ hntl_status check_search(const hntl_index* index, const float* Q, uint32_t nq, c
   if (sp->route > HNTL_ROUTE_LEARNED) return fail(HNTL_EINVAL, "unknown route");
   if ((sp->flags & HNTL_FLAG_ROUTE_BF16X3) && (sp->flags & HNTL_FLAG_ROUTE_BF16))
     return fail(HNTL_EINVAL, "choose one centroid routing form");
+  if (!(sp->mass >= 0.f && sp->mass <= 1.f)) return fail(HNTL_EINVAL, "mass must lie in [0, 1]");
   const bool learned = sp->route == HNTL_ROUTE_LEARNED && !io.probes_in && !io.pool_in;
   if (learned && !(ix.router && ix.router->trained)) return fail(HNTL_ESTATE, "learned routing needs a trained router");
   const bool mode_a = (sp->flags & HNTL_FLAG_MODE_A) != 0;
@@ -301,7 +302,7 @@ void run_staged(const Index& ix, const float* Q, uint32_t nq, const hntl_search_
       clk.at(HNTL_STAGE_ROUTE);
       int32_t* pr = io.probes_out ? io.probes_out : w.probes;
       if (sp.route == HNTL_ROUTE_LEARNED)
-        launch_route_learned(ix, Q, nq, (int)P, sp.tau, pr, io.pdist_out, w.rw, s);
+        launch_route_learned(ix, Q, nq, (int)P, sp.tau, pr, io.pdist_out, w.rw, s, nullptr, sp.mass);
       else
         launch_route_centroid(ix, Q, nq, (int)P, w.cw, pr, io.pdist_out, s);
       probes = pr;

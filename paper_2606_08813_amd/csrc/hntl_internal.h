@@ -326,8 +326,11 @@ struct FusedArgs {
 // products with fused bias / GELU epilogues, then a top-P over the scores);
 // rows whose largest softmax probability is below tau fall back to centroid
 // routing.  Rows from *nlim on are skipped.
+// mass in (0, 1): each learned row keeps its probes up to the first slot at
+// which the cumulative softmax probability reaches mass (later slots: -1).
 void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, float tau, int32_t* probes,
-                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr);
+                          float* pdist, const RouterScratch& w, hipStream_t s, const int32_t* nlim = nullptr,
+                          float mass = 0.f);
 
 // build helpers
 void launch_pack_codes(const Index& ix, const float* codes_go, const float* eps_go, hipStream_t s);

@@ -126,7 +126,7 @@ std::string tune_key(const Index& ix, const hntl_search_params& sp, uint32_t nq)
   std::ostringstream k;
   k << device_key(ix.device) << " N=" << ix.N << " d=" << ix.d << " G=" << ix.G << " r=" << ix.r
     << " maxgrain=" << ix.max_grain << " P=" << sp.P << " C=" << sp.C << " k=" << sp.k << " codes=" << sp.codes
-    << " flags=" << (sp.flags & PLAN_FLAGS) << " route=" << sp.route
+    << " flags=" << (sp.flags & PLAN_FLAGS) << " route=" << sp.route << " mass=" << sp.mass
     << " nq=" << nq;
   return k.str();
 }
@@ -322,7 +322,7 @@ struct Plan {
     launch_fill_multi(f, s);
     // routing reads the batch size from nq_dev: rows past it get probes -1
     if (sp.route == HNTL_ROUTE_LEARNED)
-      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev);
+      launch_route_learned(x, Q, max_nq, P, sp.tau, probes, nullptr, rs, s, nq_dev, sp.mass);
     else
       launch_route_centroid(x, Q, max_nq, P, route, probes, nullptr, s, nq_dev);
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
@@ -369,6 +369,7 @@ void check_plan_shape(const Index& ix, const hntl_search_params& sp) {
   if ((sp.flags & HNTL_FLAG_PROJECT_BF16) && !ix.basis_bf16)
     throw ArgError{HNTL_ESTATE, "BF16 projection needs the BF16 basis (build a reduced-precision code form)"};
   if (sp.route > HNTL_ROUTE_LEARNED) throw ArgError{HNTL_EINVAL, "unknown route"};
+  if (!(sp.mass >= 0.f && sp.mass <= 1.f)) throw ArgError{HNTL_EINVAL, "mass must lie in [0, 1]"};
   if (sp.route == HNTL_ROUTE_LEARNED && !(ix.router && ix.router->trained))
     throw ArgError{HNTL_ESTATE, "learned routing needs a trained router"};
   if (ix.d % 8 != 0) throw ArgError{HNTL_EUNSUPPORTED, "the fused kernel needs d % 8 == 0"};

@@ -43,7 +43,8 @@ class hntl_append_params(C.Structure):
 
 class hntl_search_params(C.Structure):
     _fields_ = [("P", C.c_uint32), ("C", C.c_uint32), ("k", C.c_uint32), ("codes", C.c_uint32),
-                ("flags", C.c_uint32), ("route", C.c_uint32), ("tau", C.c_float)]
+                ("flags", C.c_uint32), ("route", C.c_uint32), ("tau", C.c_float),
+                ("mass", C.c_float)]
 
 
 class hntl_router_params(C.Structure):
@@ -332,13 +333,13 @@ def hntl_index_free(index: Index):
         index.handle = None
 
 
-def _params(P, C_, k, codes, flags, route="centroid", tau=0.0):
+def _params(P, C_, k, codes, flags, route="centroid", tau=0.0, mass=0.0):
     return hntl_search_params(P, C_, k, CODES[codes] if isinstance(codes, str) else codes, flags,
-                              ROUTES[route] if isinstance(route, str) else route, tau)
+                              ROUTES[route] if isinstance(route, str) else route, tau, mass)
 
 
 def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None,
-                route="centroid", tau=0.0):
+                route="centroid", tau=0.0, mass=0.0):
     """Top-k ids (int32) and squared distances (float32) per query, as CUDA tensors."""
     import torch
     _cuda_f32(Q, "Q")
@@ -348,14 +349,14 @@ def hntl_search(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0,
         dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
     else:
         ids, dist = out
-    sp = _params(P, C_, k, codes, flags, route, tau)
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     _check(lib().hntl_search(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
                              _stream(stream)))
     return ids, dist
 
 
 def hntl_search_noalloc(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, out=None, stream=None,
-                        route="centroid", tau=0.0):
+                        route="centroid", tau=0.0, mass=0.0):
     """hntl_search with its scratch in the library's static per-GPU array (no device
     allocation by the library); out = (ids, dist) CUDA tensors, else new ones."""
     import torch
@@ -366,7 +367,7 @@ def hntl_search_noalloc(index: Index, Q, P: int, C_: int, k: int, codes="fp32", 
         dist = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
     else:
         ids, dist = out
-    sp = _params(P, C_, k, codes, flags, route, tau)
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     _check(lib().hntl_search_noalloc(index.handle, Q.data_ptr(), nq, C.byref(sp), ids.data_ptr(), dist.data_ptr(),
                                      _stream(stream)))
     return ids, dist
@@ -387,7 +388,7 @@ def hntl_profile_read():
 
 def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=HNTL_FLAG_SYNC,
                        probes_in=None, tangent_in=None, epsq_in=None, pool_in=None, stream=None,
-                       route="centroid", tau=0.0):
+                       route="centroid", tau=0.0, mass=0.0):
     """Run the lifecycle with stage outputs returned and optional stage inputs (CUDA tensors)."""
     import torch
     _cuda_f32(Q, "Q")
@@ -406,7 +407,7 @@ def hntl_search_stages(index: Index, Q, P: int, C_: int, k: int, codes="fp32", f
         o["pool_D"] = torch.full((nq, C_), float("nan"), dtype=torch.float32, device=dev)
     o["ids"] = torch.full((nq, k), -7, dtype=torch.int32, device=dev)
     o["dist"] = torch.full((nq, k), float("nan"), dtype=torch.float32, device=dev)
-    sp = _params(P, C_, k, codes, flags, route, tau)
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     _check(lib().hntl_search_stages(
         index.handle, Q.data_ptr(), nq, C.byref(sp), _ptr(probes_in), _ptr(o.get("probes")), _ptr(o.get("pdist")),
         _ptr(tangent_in), _ptr(epsq_in), _ptr(o.get("zq")), _ptr(o.get("epsq")), _ptr(pool_in),
@@ -447,8 +448,8 @@ def sched_dict(s: hntl_schedule) -> dict:
 
 
 def hntl_plan_create(index: Index, P: int, C_: int, k: int, max_nq: int, codes="fp32", flags=0, sched=None,
-                     graph=True, stream=None, route="centroid", tau=0.0) -> Plan:
-    sp = _params(P, C_, k, codes, flags, route, tau)
+                     graph=True, stream=None, route="centroid", tau=0.0, mass=0.0) -> Plan:
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     sc = _sched(sched)
     h = C.c_void_p()
     _check(lib().hntl_plan_create(index.handle, C.byref(sp), max_nq, C.byref(sc) if sc is not None else None,
@@ -507,10 +508,10 @@ def hntl_plan_free(plan: Plan):
 
 
 def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, db_path=None, stream=None,
-              route="centroid", tau=0.0):
+              route="centroid", tau=0.0, mass=0.0):
     """Autotune the fused kernel's schedule on the batch Q; returns (schedule dict, median ms)."""
     _cuda_f32(Q, "Q")
-    sp = _params(P, C_, k, codes, flags, route, tau)
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     best = hntl_schedule()
     ms = C.c_float(0.0)
     _check(lib().hntl_tune(index.handle, C.byref(sp), Q.data_ptr(), Q.shape[0],
@@ -519,8 +520,8 @@ def hntl_tune(index: Index, Q, P: int, C_: int, k: int, codes="fp32", flags=0, d
 
 
 def hntl_schedule_lookup(index: Index, P: int, C_: int, k: int, max_nq: int, db_path, codes="fp32", flags=0,
-                         route="centroid", tau=0.0):
-    sp = _params(P, C_, k, codes, flags, route, tau)
+                         route="centroid", tau=0.0, mass=0.0):
+    sp = _params(P, C_, k, codes, flags, route, tau, mass)
     out = hntl_schedule()
     _check(lib().hntl_schedule_lookup(index.handle, C.byref(sp), max_nq, str(db_path).encode(), C.byref(out)))
     return sched_dict(out)

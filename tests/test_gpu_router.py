@@ -154,9 +154,11 @@ def test_training_reduces_loss(rt, trained):
     assert trained[-1] < 0.8 * trained[0]
 
 
-def test_learned_routing_gain(rt, trained):
+def test_learned_probe_recall_at_equal_p(rt, trained):
     """Probe recall (true neighbours inside the probed grains) on held-out
-    queries: learned routing against centroid routing at equal P."""
+    queries, learned against centroid routing at equal P: the trained router
+    loses at most 0.01 (on this mixture the nearest centroids are already
+    near-perfect probes; the router's gain is the probe budget below)."""
     hntl, W = rt["hntl"], rt["W"]
     Qh = W.queries(nq=1000, query_seed=3006).X
     gt, _ = brute.knn(rt["X"], Qh, 10)
@@ -169,6 +171,99 @@ def test_learned_routing_gain(rt, trained):
     announce("probe recall " + ", ".join(f"{r} P={p}: {v:.4f}" for (r, p), v in sorted(rec.items())))
     for P in (1, 2, 4):
         assert rec[("learned", P)] >= rec[("centroid", P)] - 0.01, (P, rec)
+
+
+def test_mass_budget_parity(rt, trained):
+    """The probability-mass probe budget on the GPU against the oracle's
+    mass_cut, on the oracle's weights with the output layer scaled by 12 (so
+    the softmax is peaked and cuts happen): the kept probes are a prefix of the
+    uncut learned probes, and the number kept equals the oracle's except where
+    the oracle's cumulative probability at the cut lies within 1e-3 of the
+    mass (the GPU's scores differ from the BF16 emulation by about 1e-4)."""
+    hntl, W = rt["hntl"], rt["W"]
+    announce("mass budget: GPU cut vs oracle mass_cut")
+    saved = hntl.hntl_router_export(rt["ix"])  # the trained router, put back afterwards
+    params = {k: v.copy() for k, v in rt["params"].items()}
+    params["W3"] *= 12.0
+    hntl.hntl_router_set(rt["ix"], {k: v.astype(np.float32) for k, v in params.items()},
+                         rt["mean"].astype(np.float32), rt["std"].astype(np.float32))
+    try:
+        p = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
+        m, sd = rt["mean"].astype(np.float32).astype(np.float64), rt["std"].astype(np.float32).astype(np.float64)
+        Q = rt["Q"][:512]
+        Qd = to_dev(Q)
+        P = 6
+        full = hntl.hntl_search_stages(rt["ix"], Qd, P, W.C, W.k, route="learned")["probes"].cpu().numpy()
+        s_orc, _ = orr.forward(p, Q, m, sd, bf16=True)
+        cuts = 0
+        for mass in (0.5, 0.9, 0.99):
+            cut = hntl.hntl_search_stages(rt["ix"], Qd, P, W.C, W.k, route="learned",
+                                          mass=mass)["probes"].cpu().numpy()
+            kept = (cut >= 0).sum(1)
+            assert (kept >= 1).all()
+            for i in range(len(Q)):
+                assert (cut[i, :kept[i]] == full[i, :kept[i]]).all() and (cut[i, kept[i]:] == -1).all()
+            ref = orr.mass_cut(s_orc, full, mass)
+            kref = (ref >= 0).sum(1)
+            for i in np.nonzero(kept != kref)[0]:
+                e = np.exp(s_orc[i] - s_orc[i].max())
+                c = np.cumsum(e[full[i]] / e.sum())
+                j = min(kept[i], kref[i]) - 1
+                assert abs(c[j] - mass) < 1e-3, (mass, i, kept[i], kref[i], c)
+            cuts += int((kept < P).sum())
+            announce(f"mass {mass}: mean probes {kept.mean():.3f}, rows differing from the oracle "
+                     f"{int((kept != kref).sum())}")
+        assert cuts > 0
+    finally:
+        hntl.hntl_router_set(rt["ix"], {k: saved[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")},
+                             saved["mean"], saved["std"])
+
+
+def test_learned_probe_budget_gain():
+    """What the trained router gains over centroid routing: its softmax
+    probabilities are a calibrated confidence, so a probability-mass budget
+    spends probes only on uncertain queries.  Index: the 10k patch mixture
+    split into 256 grains (4 per patch, so neighbours straddle grains), router
+    trained on 20,000 generated queries with brute-force kNN targets.  On
+    1,000 held-out queries (C = 20, k = 10), the budget reaches the Recall@10
+    of centroid routing at some fixed P with fewer probed (query, grain)
+    pairs: the measured gain is asserted > 0 and stated."""
+    torch = require_gpu()
+    from paper_2606_08813_amd import hntl
+    from workloads import SMALL_10K as W
+    announce("router gain: 10k corpus in 256 grains, router trained on 20,000 queries")
+    X = W.corpus().X
+    ix = hntl.hntl_build(to_dev(X), 256, 32, seed=W.kmeans_seed)
+    Qtr = W.queries(nq=20000, query_seed=3005).X
+    hntl.hntl_router_train(ix, to_dev(Qtr), hidden=DIMS_H, epochs=8, batch=512, knn=10, lr=1e-3, seed=7)
+    Qh = W.queries(nq=1000, query_seed=3006).X
+    gt, _ = brute.knn(X, Qh, 10)
+    Qd = to_dev(Qh)
+    C, k = 20, 10
+
+    def recall(o):
+        ids = o["ids"].cpu().numpy()
+        return float(np.mean([len(set(a.tolist()) & set(b.tolist())) / k for a, b in zip(ids, gt)]))
+
+    cen = {}
+    for P in (1, 2, 3, 4, 6, 8):
+        o = hntl.hntl_search_stages(ix, Qd, P, C, k)
+        cen[P] = (recall(o), P * len(Qh))
+    lrn = {}
+    for mass in (0.9, 0.99, 0.999):
+        o = hntl.hntl_search_stages(ix, Qd, 8, C, k, route="learned", mass=mass)
+        lrn[mass] = (recall(o), int((o["probes"] >= 0).sum()))
+    announce("centroid (Recall@10, pairs): " + ", ".join(f"P={P}: {v[0]:.4f} {v[1]}" for P, v in cen.items()))
+    announce("learned budget (Recall@10, pairs): " + ", ".join(f"mass={m}: {v[0]:.4f} {v[1]}" for m, v in lrn.items()))
+    gains = []
+    for mass, (rl, pl) in lrn.items():
+        matched = [pairs for rc, pairs in cen.values() if rc >= rl]
+        if matched:
+            gains.append((min(matched) / pl, mass, rl))
+    assert gains, "no centroid P reaches the learned budget's recall"
+    best = max(gains)
+    announce(f"gain: {best[0]:.2f}x fewer probed pairs at Recall@10 {best[2]:.4f} (mass {best[1]})")
+    assert best[0] > 1.0, gains
 
 
 def test_learned_plan_equals_staged(rt, trained):

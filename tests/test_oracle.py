@@ -689,3 +689,22 @@ def test_bf16_projection_rounds_the_centred_query():
     # eps_q by Pythagoras from the unrounded q': ||q'||^2 - ||z_bf16||^2
     qn = float((np.float32(Q[0]).astype(np.float64) ** 2).sum())
     assert eb[0, 0] == max(0.0, qn - float(zb[0, 0] @ zb[0, 0]))
+
+
+def test_mass_cut_hand_computed():
+    """Scores log(0.5), log(0.3), log(0.15), log(0.05) (softmax = those
+    probabilities): cumulative 0.5, 0.8, 0.95, 1.0.  mass 0.79 keeps 2 slots,
+    0.81 keeps 3, 0.49 keeps 1, 0.96 keeps 4, 0 and 1 keep every slot."""
+    s = np.log(np.array([[0.5, 0.3, 0.15, 0.05]]))
+    pr = np.array([[0, 1, 2, 3]])
+    assert router.mass_cut(s, pr, 0.79).tolist() == [[0, 1, -1, -1]]
+    assert router.mass_cut(s, pr, 0.81).tolist() == [[0, 1, 2, -1]]
+    assert router.mass_cut(s, pr, 0.49).tolist() == [[0, -1, -1, -1]]
+    assert router.mass_cut(s, pr, 0.96).tolist() == [[0, 1, 2, 3]]
+    assert router.mass_cut(s, pr, 0.0).tolist() == [[0, 1, 2, 3]]
+    assert router.mass_cut(s, pr, 1.0).tolist() == [[0, 1, 2, 3]]
+    # only the probed slots count: a grain outside the top-P still weighs in z
+    s2 = np.log(np.array([[0.4, 0.35, 0.25]]))
+    assert router.mass_cut(s2, np.array([[0, 1]]), 0.76).tolist() == [[0, 1]]
+    assert router.mass_cut(s2, np.array([[0, 1]]), 0.7).tolist() == [[0, 1]]
+    assert router.mass_cut(s2, np.array([[0, 1]]), 0.39).tolist() == [[0, -1]]
