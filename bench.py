@@ -256,6 +256,8 @@ def parse():
     ap.add_argument("--compare", choices=("auto", "on", "off"), default="auto",
                     help="also time the learned router + BF16 codes + BF16 projection plan at the same P and C "
                          "(auto: on for the batching workload's default plain FP32 plan)")
+    ap.add_argument("--hbm-sched", default="",
+                    help="schedule of the HBM-regime plan instead of autotuning it (format of --sched)")
     ap.add_argument("--hbm-batch", type=int, default=-1,
                     help="queries of the scan's HBM-regime measurement (-1: 256 on the batching workload, 0: off)")
     ap.add_argument("--uneven", choices=("auto", "on", "off"), default="auto",
@@ -267,6 +269,9 @@ def parse():
     ap.add_argument("--append-rows", type=int, default=0,
                     help="after the search timing, time hntl_index_append of this many new rows of the workload")
     ap.add_argument("--split-max", type=int, default=0, help="split_max of the timed append (0 = no splits)")
+    ap.add_argument("--index-cache", default="",
+                    help="directory: on a miss the built index's stored-format arrays are written there, on a "
+                         "hit the index is made from them (hntl_index_create) instead of being built")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="run one plain device copy of this many GiB first (calibrates HBM counters)")
     return ap.parse_args()
@@ -337,7 +342,7 @@ def main():
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)  # one elementwise kernel: n bytes read, n bytes written
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {n * 4} bytes")
         del src, dst
@@ -350,12 +355,28 @@ def main():
     t0 = time.time()
     codes_list = ["fp32"] + ([args.codes] if args.codes != "fp32" else []) + (["bf16"] if compare else [])
     codes_list = list(dict.fromkeys(codes_list))
-    ix = hntl.hntl_build(X, W.G, W.r, seed=W.kmeans_seed, codes=tuple(codes_list))
-    torch.cuda.synchronize()
-    build_s = time.time() - t0
-    info = hntl.hntl_index_info_get(ix)
-    log(f"[bench] build {build_s:.1f}s, captured variance {info['captured_variance']:.4f}, "
-        f"k-means iters {info['kmeans_iters_run']}, max grain {info['max_grain']}")
+    cache = Path(args.index_cache) / W.name if args.index_cache else None
+    stored_names = ("centroids", "basis", "offsets", "perm", "codes", "eps")
+    if cache is not None and all((cache / f"{nm}.npy").exists() for nm in stored_names):
+        stored = {nm: np.load(cache / f"{nm}.npy") for nm in stored_names}
+        ix = hntl.hntl_index_create(stored, X, codes=tuple(codes_list))
+        del stored
+        torch.cuda.synchronize()
+        build_s = None
+        info = hntl.hntl_index_info_get(ix)
+        log(f"[bench] index made from the stored arrays in {cache} in {time.time() - t0:.1f}s")
+    else:
+        ix = hntl.hntl_build(X, W.G, W.r, seed=W.kmeans_seed, codes=tuple(codes_list))
+        torch.cuda.synchronize()
+        build_s = time.time() - t0
+        info = hntl.hntl_index_info_get(ix)
+        log(f"[bench] build {build_s:.1f}s, captured variance {info['captured_variance']:.4f}, "
+            f"k-means iters {info['kmeans_iters_run']}, max grain {info['max_grain']}")
+        if cache is not None:
+            cache.mkdir(parents=True, exist_ok=True)
+            for nm, a in hntl.hntl_index_export(ix).items():
+                np.save(cache / f"{nm}.npy", a)
+            log(f"[bench] stored arrays written to {cache}")
     del X
     torch.cuda.empty_cache()
 
@@ -500,7 +521,7 @@ def main():
     if hbm_batch > 0 and args.form == "plan":
         nb = min(hbm_batch, W.nq)
         Qh = Q[:nb].contiguous()
-        rh = time_plan(hntl, torch, ix, Qh, P, W.C, W.k, nb, args.codes, pflags, rkw, args.steps, 2)
+        rh = time_plan(hntl, torch, ix, Qh, P, W.C, W.k, nb, args.codes, pflags, rkw, args.steps, 2, args.hbm_sched)
         ph = hntl.hntl_search_stages(ix, Qh, P, W.C, W.k, codes=args.codes,
                                      flags=hntl.HNTL_FLAG_SYNC | (pflags & ~hntl.HNTL_FLAG_NO_PRUNE), **rkw)["probes"]
         pg = np.unique(ph.cpu().numpy())
@@ -650,7 +671,7 @@ def main():
         "vectors_in_probed_grains_per_step": scanned,
         "prune": not args.no_prune,
         "stage_ms": {kk: round(v, 4) for kk, v in stage_avg.items()},
-        "build_s": round(build_s, 2),
+        "build_s": None if build_s is None else round(build_s, 2),
         "captured_variance": round(info["captured_variance"], 5),
         "roofline": dict(roof.get(dominant, {}), kernel=dominant,
                          traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode, W.nq))

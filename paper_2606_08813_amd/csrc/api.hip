@@ -231,7 +231,8 @@ struct StagedScratch {
   float* eq = nullptr;
   uint64_t* part = nullptr;
 
-  size_t layout(char* base, const Index& ix, uint32_t nq, const hntl_search_params& sp, const StagedIO& io) {
+  size_t layout(char* base, const Index& ix, const float* Q, uint32_t nq, const hntl_search_params& sp,
+                const StagedIO& io) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
       off = (off + 255) / 256 * 256;
@@ -260,7 +261,8 @@ struct StagedScratch {
     b.cur0 = (int32_t*)take(4 * (size_t)ix.G);
     b.cur1 = (int32_t*)take(4 * (size_t)ix.G);
     b.order = (int32_t*)take(4 * (size_t)npairs);
-    const int tiles[3] = {16, 16, PROJECT_TILE};
+    // the projection item size depends only on d, the code form and Q's alignment
+    const int tiles[3] = {16, 16, project_tile(ix, Q, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0)};
     const int64_t np[3] = {(int64_t)nq, (int64_t)nq * (P - 1), npairs};
     for (int L = 0; L < 3; ++L) {
       b.lists.tile[L] = tiles[L];
@@ -636,8 +638,8 @@ hntl_status hntl_search_stages(const hntl_index* index, const float* Q, uint32_t
     derive_search_data(const_cast<Index&>(ix), *sp, io, s);  // derived index data, made once under a lock
     Scratch sc(s);
     StagedScratch w;
-    char* base = sc.get<char>(w.layout(nullptr, ix, nq, *sp, io));
-    w.layout(base, ix, nq, *sp, io);
+    char* base = sc.get<char>(w.layout(nullptr, ix, Q, nq, *sp, io));
+    w.layout(base, ix, Q, nq, *sp, io);
     run_staged(ix, Q, nq, *sp, io, w, s);
   });
 }
@@ -656,7 +658,7 @@ hntl_status hntl_search_noalloc(const hntl_index* index, const float* Q, uint32_
     return fail(HNTL_ESTATE, "derived index data missing (split centroids of a BF16 routing form, or eps by id of "
                              "Mode A): run one hntl_search with the same flags first");
   StagedScratch w;
-  const size_t need = w.layout(nullptr, ix, nq, *sp, io);
+  const size_t need = w.layout(nullptr, ix, Q, nq, *sp, io);
   if (need > (size_t)HNTL_NOALLOC_SCRATCH_BYTES)
     return fail(HNTL_EINVAL, "hntl_search_noalloc needs " + std::to_string(need) + " bytes of scratch for this call, "
                              "more than HNTL_NOALLOC_SCRATCH_BYTES (" + std::to_string(HNTL_NOALLOC_SCRATCH_BYTES) +
@@ -665,7 +667,7 @@ hntl_status hntl_search_noalloc(const hntl_index* index, const float* Q, uint32_
   return guarded([&] {
     HIP_TRY(hipSetDevice(ix.device));
     char* base = noalloc_scratch(ix.device);
-    w.layout(base, ix, nq, *sp, io);
+    w.layout(base, ix, Q, nq, *sp, io);
     run_staged(ix, Q, nq, *sp, io, w, s);
   });
 }

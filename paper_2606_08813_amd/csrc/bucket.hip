@@ -408,10 +408,11 @@ __global__ __launch_bounds__(256) void item_table_kernel(ItemLists lists, const 
   if (it < nP) {
     const int rank = item_rank(lists.ioff[LIST_ALL], G, it);
     const int g = gorder ? gorder[rank] : rank;
-    const int first = (it - lists.ioff[LIST_ALL][rank]) * 16;
+    const int tp = lists.tile[LIST_ALL];
+    const int first = (it - lists.ioff[LIST_ALL][rank]) * tp;
     d.g = g;
     d.off = lists.lstart[LIST_ALL][g] + first;
-    d.cnt = min(16, lists.lcount[LIST_ALL][g] - first);
+    d.cnt = min(tp, lists.lcount[LIST_ALL][g] - first);
     d.c0 = d.c1 = it;
   } else {
     const int L = it < nP + n0 ? LIST_SLOT0 : LIST_REST;
@@ -428,7 +429,8 @@ __global__ __launch_bounds__(256) void item_table_kernel(ItemLists lists, const 
     d.off = lists.lstart[L][g] + first;
     d.cnt = min(qt, lc - first);
     // a grain's projection list is its slot-0 pairs followed by the others, in
-    // 16-pair items: this tile's pairs lie in items c0 .. c1 (at most two)
+    // 16-pair items when the fused kernel projects (the only reader of c0 / c1):
+    // this tile's pairs lie in items c0 .. c1 (at most two)
     const int base = (L == LIST_SLOT0 ? 0 : lists.lcount[LIST_SLOT0][g]) + first;
     const int pi0 = lists.ioff[LIST_ALL][rank];
     d.c0 = pi0 + base / 16;

@@ -245,7 +245,11 @@ void launch_pair_lists(const int32_t* probes, int64_t nq, int P, int G, const in
                        int32_t* qoff, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
-constexpr int PROJECT_TILE = 128;  // pairs per workgroup of the grain-major projection kernel
+constexpr int PROJECT_TILE = 64;  // pairs per workgroup of the shared-basis projection kernel
+// Projection item size (LIST_ALL tile) for queries Q: PROJECT_TILE where the
+// shared-basis kernel applies (vector loads: d % 4 == 0 FP32, d % 8 == 0 BF16,
+// 16-byte aligned Q), else 16.
+int project_tile(const Index& ix, const float* Q, bool bf16);
 // gorder: the rank -> grain map when the buckets were built in that order (ioff by rank), else null
 void launch_project(const Index& ix, const float* Q, int P, const Buckets& b, float* T, float* epsq, bool bf16,
                     const int32_t* gorder, hipStream_t s);  // over LIST_ALL

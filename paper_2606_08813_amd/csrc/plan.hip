@@ -220,9 +220,9 @@ struct Plan {
       b.lists.lcount[l] = L.take<int32_t>(x.G);
     }
     b.lists.tile[LIST_SLOT0] = b.lists.tile[LIST_REST] = (int)sch.qt;  // scan item: qt pairs (one wave)
-    // projection item: 16 pairs, one wave (of the fused kernel, or a
-    // single-wave workgroup of the separate projection launch)
-    b.lists.tile[LIST_ALL] = 16;
+    // projection item: 16 pairs, one wave, inside the fused kernel; with a
+    // separate projection launch, the shared-basis kernel's item where it applies
+    b.lists.tile[LIST_ALL] = sch.proj ? project_tile(x, Q, (sp.flags & HNTL_FLAG_PROJECT_BF16) != 0) : 16;
     b.max_items[LIST_ALL] = (int)(np / b.lists.tile[LIST_ALL] + std::min<int64_t>(x.G, np) + 1);
     nsplit = L.take<int32_t>(x.G);
     lbase = L.take<int32_t>(np);

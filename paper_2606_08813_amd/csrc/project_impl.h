@@ -41,6 +41,45 @@ __device__ __forceinline__ void load_ks(float (&v)[KS], const float* __restrict_
   }
 }
 
+// Epilogue of every projection form.  In: the wave's NCT accumulator tiles
+// (MFMA layout: lane l holds rows 4 (l / 16) + t, t < 4, of column c 16 + l % 16)
+// and each lane's partial ||q'||^2 of row l % 16 (one of its four K slots).
+// Writes z_q (T[pair][0..r)) and eps_q = max(0, ||q'||^2 - ||z_q||^2) of the
+// first cnt rows.
+template <int NCT>
+__device__ __forceinline__ void project_store(const floatx4 (&acc)[NCT], float sq, int r,
+                                              const int32_t* __restrict__ pairs, int cnt, float* __restrict__ T,
+                                              float* __restrict__ epsq) {
+  const int lane = lane_id();
+  // ||q'||^2 of row i: the four K slots of the row
+  sq += __uint_as_float(lane_xor<16>(__float_as_uint(sq)));
+  sq += __uint_as_float(lane_xor<32>(__float_as_uint(sq)));
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int row = 4 * (lane >> 4) + t;
+    float zz = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c * 16 + (lane & 15);
+      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
+    }
+    zz += __uint_as_float(lane_xor<1>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<2>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<4>(__float_as_uint(zz)));
+    zz += __uint_as_float(lane_xor<8>(__float_as_uint(zz)));
+    const float q2 = __shfl(sq, row, 64);  // lane `row` holds row `row`'s ||q'||^2
+    if (row < cnt) {
+      const int p = ldg(pairs + row);
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const int col = c * 16 + (lane & 15);
+        if (col < r) stg(T + (size_t)p * r + col, acc[c][t]);
+      }
+      if ((lane & 15) == 0) stg(epsq + p, fmaxf(q2 - zz, 0.f));
+    }
+  }
+}
+
 // The MFMA sums over the four K slots of each
 // instruction; lane (i = lane % 16, kq = lane / 16) feeds slot kq with depth
 // k0 + KS kq + e in step e, for the A operand (centred query row i) and the B
@@ -100,34 +139,7 @@ __device__ __forceinline__ void project_wave(const float* __restrict__ Q, int d,
     }
   }
 
-  // ||q'||^2 of row i: the four K slots of the row
-  sq += __uint_as_float(lane_xor<16>(__float_as_uint(sq)));
-  sq += __uint_as_float(lane_xor<32>(__float_as_uint(sq)));
-  // ||z||^2 per output row (MFMA layout: row 4 * (lane >> 4) + t, column lane & 15)
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int row = 4 * (lane >> 4) + t;
-    float zz = 0.f;
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) {
-      const int col = c * 16 + (lane & 15);
-      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
-    }
-    zz += __uint_as_float(lane_xor<1>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<2>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<4>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<8>(__float_as_uint(zz)));
-    const float q2 = __shfl(sq, row, 64);  // lane `row` holds row `row`'s ||q'||^2
-    if (row < cnt) {
-      const int p = ldg(pairs + row);
-#pragma unroll
-      for (int c = 0; c < NCT; ++c) {
-        const int col = c * 16 + (lane & 15);
-        if (col < r) stg(T + (size_t)p * r + col, acc[c][t]);
-      }
-      if ((lane & 15) == 0) stg(epsq + p, fmaxf(q2 - zz, 0.f));
-    }
-  }
+  project_store<NCT>(acc, sq, r, pairs, cnt, T, epsq);
 }
 
 // BF16 projection (the precision form): q' = q - mu_g is formed in FP32 and
@@ -185,32 +197,7 @@ __device__ __forceinline__ void project_wave_bf16(const float* __restrict__ Q, i
                                                         acc[c], 0, 0, 0);
     }
   }
-  sq += __uint_as_float(lane_xor<16>(__float_as_uint(sq)));
-  sq += __uint_as_float(lane_xor<32>(__float_as_uint(sq)));
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int row = 4 * (lane >> 4) + t;
-    float zz = 0.f;
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) {
-      const int col = c * 16 + (lane & 15);
-      if (col < r) zz = fmaf(acc[c][t], acc[c][t], zz);
-    }
-    zz += __uint_as_float(lane_xor<1>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<2>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<4>(__float_as_uint(zz)));
-    zz += __uint_as_float(lane_xor<8>(__float_as_uint(zz)));
-    const float q2 = __shfl(sq, row, 64);
-    if (row < cnt) {
-      const int p = ldg(pairs + row);
-#pragma unroll
-      for (int c = 0; c < NCT; ++c) {
-        const int col = c * 16 + (lane & 15);
-        if (col < r) stg(T + (size_t)p * r + col, acc[c][t]);
-      }
-      if ((lane & 15) == 0) stg(epsq + p, fmaxf(q2 - zz, 0.f));
-    }
-  }
+  project_store<NCT>(acc, sq, r, pairs, cnt, T, epsq);
 }
 
 }  // namespace proj_detail
