@@ -78,9 +78,17 @@ __device__ __forceinline__ uint64_t bound_key(uint32_t ord) {
   return ord == NO_BOUND ? KEY_NONE : (((uint64_t)ord << 32) | 0xFFFFFFFFull);
 }
 
+// A wave's LDS: the tile's query tangents zq[QT][RP] first (16-byte rows, so
+// the scoring loop reads them as 16-byte vectors at small constant offsets
+// from one base), then eps_q[QT] (padded to 16 bytes), then the QT lists'
+// staging areas.
+template <int RP, int QT>
+constexpr size_t zq_lds_bytes() {
+  return (size_t)QT * RP * 4 + ((size_t)QT * 4 + 15) / 16 * 16;
+}
 template <int RP, int QT, int LK>
 constexpr size_t wave_lds_bytes() {
-  return (size_t)QT * LK * 8 + (((size_t)QT * RP + QT) * 4 + 7) / 8 * 8;
+  return zq_lds_bytes<RP, QT>() + (size_t)QT * LK * 8;
 }
 
 // One wave's part of a scan item: its cnt (<= QT) pairs of grain g against
@@ -92,9 +100,9 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   constexpr int LK = ListOf<CAP>::lds;
   const int lane = lane_id();
   const int P = a.P, C = a.C, r = a.r;
-  uint64_t* lists_lds = my;
-  float(*zq)[RP] = reinterpret_cast<float(*)[RP]>(my + QT * LK);
-  float* eq = reinterpret_cast<float*>(my + QT * LK) + QT * RP;
+  float(*zq)[RP] = reinterpret_cast<float(*)[RP]>(my);
+  float* eq = reinterpret_cast<float*>(my) + QT * RP;
+  uint64_t* lists_lds = my + zq_lds_bytes<RP, QT>() / 8;
   const int pos0 = ldg(a.goff + g);
   const int ng = ldg(a.goff + g + 1) - pos0;
   const int b0 = ldg(a.boff + g);
@@ -246,15 +254,20 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
       if (live[t]) {
         if constexpr (CT == 3) {
           const uint64_t S = int_sq_dist<RP>(zq[t], c);
-          Ls[t].offer(make_key(fmaf((float)S, d2, e + eq[t]), pos), valid);
+          Ls[t].offer_f(fmaf((float)S, d2, e + eq[t]), pos, valid);
         } else {
+          const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
           float acc = 0.f;
 #pragma unroll
-          for (int j = 0; j < RP; ++j) {
-            const float df = zq[t][j] - c[j];
-            acc = fmaf(df, df, acc);
+          for (int j4 = 0; j4 < RP / 4; ++j4) {
+            const floatx4 z = z4[j4];
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+              const float df = z[e4] - c[4 * j4 + e4];
+              acc = fmaf(df, df, acc);
+            }
           }
-          Ls[t].offer(make_key(acc + eq[t] + e, pos), valid);
+          Ls[t].offer_f(acc + eq[t] + e, pos, valid);
         }
       }
     }

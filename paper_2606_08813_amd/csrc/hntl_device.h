@@ -199,11 +199,18 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
   return key;
 }
 
+// The value part of a threshold key as a float ceiling: a key whose value
+// exceeds it cannot enter (no threshold: +inf).  Comparing values against it
+// admits a superset of the keys below the threshold key (equal values with
+// larger ids too); a flush orders them by the whole key.
+__device__ __forceinline__ float key_ceil(uint64_t k) { return k == KEY_NONE ? __builtin_inff() : key_dist(k); }
+
 struct WaveTop64 {
   uint64_t* stage;  // 64 keys of LDS
   uint64_t best;    // this lane's entry of the sorted list
   uint64_t thr;     // uniform
   uint64_t bound;   // uniform
+  float thr_f;      // uniform: key_ceil(thr)
   int nstage;       // uniform
   int C;
 
@@ -213,6 +220,7 @@ struct WaveTop64 {
     nstage = 0;
     bound = bound_;
     thr = bound_;
+    thr_f = key_ceil(thr);
     best = KEY_NONE;
   }
 
@@ -230,6 +238,7 @@ struct WaveTop64 {
     best = m;
     const uint64_t t = lane_u64(best, C - 1);
     thr = t < bound ? t : bound;
+    thr_f = key_ceil(thr);
     nstage = 0;
   }
 
@@ -249,12 +258,31 @@ struct WaveTop64 {
     nstage += cnt;
   }
 
+  // offer(make_key(v, id), valid) for v >= 0 or any non-NaN v: the threshold
+  // test on the float value, the key formed only for staged candidates
+  __device__ __forceinline__ void offer_f(float v, uint32_t id, bool valid) {
+    bool pass = valid && v <= thr_f;
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    if (nstage + cnt > 64) {
+      flush();
+      pass = valid && v <= thr_f;
+      m = __ballot(pass);
+      if (m == 0) return;
+      cnt = __popcll(m);
+    }
+    if (pass) stage[nstage + mbcnt64(m)] = make_key(v, id);
+    nstage += cnt;
+  }
+
   // After finish(), lane i holds the i-th smallest key (KEY_NONE padded).
   __device__ __forceinline__ void finish() { flush(); }
 
   __device__ __forceinline__ void tighten(uint64_t b) {
     if (b < bound) bound = b;
     if (b < thr) thr = b;
+    thr_f = key_ceil(thr);
   }
   __device__ __forceinline__ uint64_t cth() const { return lane_u64(best, C - 1); }
 };
@@ -273,6 +301,7 @@ struct WaveTopR {
   uint64_t best[NR];
   uint64_t thr;      // uniform
   uint64_t bound;    // uniform
+  float thr_f;       // uniform: key_ceil(thr)
   int nstage;        // uniform
   int C;
 
@@ -282,6 +311,7 @@ struct WaveTopR {
     nstage = 0;
     bound = bound_;
     thr = bound_;
+    thr_f = key_ceil(thr);
 #pragma unroll
     for (int r = 0; r < NR; ++r) best[r] = KEY_NONE;
   }
@@ -311,6 +341,7 @@ struct WaveTopR {
     }
     const uint64_t t = cth();
     thr = t < bound ? t : bound;
+    thr_f = key_ceil(thr);
     nstage = 0;
   }
 
@@ -330,12 +361,30 @@ struct WaveTopR {
     nstage += cnt;
   }
 
+  // as WaveTop64::offer_f
+  __device__ __forceinline__ void offer_f(float v, uint32_t id, bool valid) {
+    bool pass = valid && v <= thr_f;
+    uint64_t m = __ballot(pass);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    if (nstage + cnt > 64) {
+      flush();
+      pass = valid && v <= thr_f;
+      m = __ballot(pass);
+      if (m == 0) return;
+      cnt = __popcll(m);
+    }
+    if (pass) stage[nstage + mbcnt64(m)] = make_key(v, id);
+    nstage += cnt;
+  }
+
   // After finish(), list element r * 64 + lane is best[r] (KEY_NONE padded).
   __device__ __forceinline__ void finish() { flush(); }
 
   __device__ __forceinline__ void tighten(uint64_t b) {
     if (b < bound) bound = b;
     if (b < thr) thr = b;
+    thr_f = key_ceil(thr);
   }
   // The C-th smallest key merged so far (KEY_NONE while fewer than C).
   __device__ __forceinline__ uint64_t cth() const {

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
     unsigned long long* __restrict__ scored) {
   using List = typename ListOf<CAP>::type;
   constexpr int NW = ITEM / QT;
-  __shared__ float zq_all[NW][QT][RP];
+  __shared__ __align__(16) float zq_all[NW][QT][RP];
   __shared__ float eq_all[NW][QT];
   __shared__ uint64_t lists_all[NW][QT][ListOf<CAP>::lds];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -247,15 +247,20 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
           if constexpr (CT == 3) {
             // the integer distance, exact; then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
             const uint64_t S = int_sq_dist<RP>(zq[t], c);
-            L[t].offer(make_key(fmaf((float)S, d2, ei + eq[t]), pos), valid);
+            L[t].offer_f(fmaf((float)S, d2, ei + eq[t]), pos, valid);
           } else {
+            const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
             float acc = 0.f;
 #pragma unroll
-            for (int j = 0; j < RP; ++j) {
-              const float df = zq[t][j] - c[j];
-              acc = fmaf(df, df, acc);
+            for (int j4 = 0; j4 < RP / 4; ++j4) {
+              const floatx4 z = z4[j4];
+#pragma unroll
+              for (int e4 = 0; e4 < 4; ++e4) {
+                const float df = z[e4] - c[4 * j4 + e4];
+                acc = fmaf(df, df, acc);
+              }
             }
-            L[t].offer(make_key(acc + eq[t] + ei, pos), valid);
+            L[t].offer_f(acc + eq[t] + ei, pos, valid);
           }
         }
       }
