@@ -253,7 +253,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     for (int t = 0; t < QT; ++t) {
       if (live[t]) {
         if constexpr (CT == 3) {
-          const uint64_t S = int_sq_dist<RP>(zq[t], c);
+          const double S = int_sq_dist<RP>(zq[t], c);
           Ls[t].offer_f(fmaf((float)S, d2, e + eq[t]), pos, valid);
         } else {
           const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
@@ -273,27 +273,36 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     }
   };
   if constexpr (QT == 1) {
-    // one pair per wave (small batches, latency-bound): two register buffers,
-    // the next block loads while this one scores
-    float ca[RP], cb[RP];
-    float ea = 0.f, eb = 0.f;
-    if (rb0 < rb1) {
-      load_block<RP, CT>(ca, codes, (size_t)(b0 + rb0), lane, sg);
-      ea = ldg(a.eps + (size_t)(b0 + rb0) * B + lane);
-    }
-    for (int b = rb0; b < rb1; b += 2) {
-      if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
-      const bool has_b = b + 1 < rb1;
-      if (has_b) {
-        load_block<RP, CT>(cb, codes, (size_t)(b0 + b + 1), lane, sg);
-        eb = ldg(a.eps + (size_t)(b0 + b + 1) * B + lane);
+    // one pair per wave (small batches, few waves, latency-bound): a ring of
+    // NBUF register buffers of raw code words, NBUF - 1 blocks requested ahead
+    // of the one being scored (decoded only when scored, so no wait is forced
+    // at the request)
+    constexpr int RW = scan_detail::RawWords<RP, CT>::n;
+    constexpr int NBUF = RW * 4 <= 160 ? 4 : (RW * 3 <= 160 ? 3 : 2);
+    uint32_t wr[NBUF][RW];
+    float er[NBUF];
+#pragma unroll
+    for (int u = 0; u < NBUF - 1; ++u)
+      if (rb0 + u < rb1) {
+        scan_detail::load_raw<RP, CT>(wr[u], codes, (size_t)(b0 + rb0 + u), lane);
+        er[u] = ldg(a.eps + (size_t)(b0 + rb0 + u) * B + lane);
       }
-      score(ca, ea, b);
-      if (b + 2 < rb1) {
-        load_block<RP, CT>(ca, codes, (size_t)(b0 + b + 2), lane, sg);
-        ea = ldg(a.eps + (size_t)(b0 + b + 2) * B + lane);
+    for (int b = rb0; b < rb1; b += NBUF) {
+#pragma unroll
+      for (int u = 0; u < NBUF; ++u) {
+        const int bb = b + u;
+        if (bb < rb1) {
+          if (bb > rb0 && ((bb - rb0) % REFRESH) == 0) exchange();
+          const int nx = bb + NBUF - 1;
+          if (nx < rb1) {
+            scan_detail::load_raw<RP, CT>(wr[(u + NBUF - 1) % NBUF], codes, (size_t)(b0 + nx), lane);
+            er[(u + NBUF - 1) % NBUF] = ldg(a.eps + (size_t)(b0 + nx) * B + lane);
+          }
+          float c[RP];
+          scan_detail::decode_raw<RP, CT>(c, wr[u], sg);
+          score(c, er[u], bb);
+        }
       }
-      if (has_b) score(cb, eb, b + 1);
     }
   } else {
     // one block of codes in registers per wave; the loads of the other waves

@@ -36,37 +36,45 @@ struct ListOf {
 // stream the same grain (the repeated code reads hit in L1/L2).
 // CT: code form (0 FP32, 1 BF16 packed in pairs, 2 FP8 E4M3 packed in fours
 // with a per-grain scale; the decoded value of an FP8 code is fl32(code * s_g)).
+// 32-bit words per lane and block of a code form: one FP32 code, two BF16 or
+// int16 codes, four FP8 codes per word.
 template <int RP, int CT>
-__device__ __forceinline__ void load_block(float (&c)[RP], const void* __restrict__ codes, size_t blk, int lane,
-                                           float s) {
-  if constexpr (CT == 0) {
-    const float* cb = reinterpret_cast<const float*>(codes) + blk * RP * B;
+struct RawWords {
+  static constexpr int n = CT == 0 ? RP : (CT == 2 ? RP / 4 : RP / 2);
+};
+
+// The lane's words of block `blk` (word j of the block is row j of B words).
+template <int RP, int CT, int RW = RawWords<RP, CT>::n>
+__device__ __forceinline__ void load_raw(uint32_t (&w)[RW], const void* __restrict__ codes, size_t blk, int lane) {
+  const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * RW * B;
 #pragma unroll
-    for (int j = 0; j < RP; ++j) c[j] = ldg(cb + j * B + lane);
+  for (int j = 0; j < RW; ++j) w[j] = ldg(wb + j * B + lane);
+}
+
+// The decoded code values of a lane's words.
+template <int RP, int CT, int RW = RawWords<RP, CT>::n>
+__device__ __forceinline__ void decode_raw(float (&c)[RP], const uint32_t (&w)[RW], float s) {
+  if constexpr (CT == 0) {
+#pragma unroll
+    for (int j = 0; j < RP; ++j) c[j] = __uint_as_float(w[j]);
   } else if constexpr (CT == 1) {
-    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
 #pragma unroll
     for (int j = 0; j < RP / 2; ++j) {
-      const uint32_t w = ldg(wb + j * B + lane);
-      c[2 * j] = __uint_as_float(w << 16);
-      c[2 * j + 1] = __uint_as_float(w & 0xFFFF0000u);
+      c[2 * j] = __uint_as_float(w[j] << 16);
+      c[2 * j + 1] = __uint_as_float(w[j] & 0xFFFF0000u);
     }
   } else if constexpr (CT == 3) {
     // int16 codes as exact float integers
-    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 2) * B;
 #pragma unroll
     for (int j = 0; j < RP / 2; ++j) {
-      const uint32_t w = ldg(wb + j * B + lane);
-      c[2 * j] = (float)(int16_t)(w & 0xFFFFu);
-      c[2 * j + 1] = (float)(int16_t)(w >> 16);
+      c[2 * j] = (float)(int16_t)(w[j] & 0xFFFFu);
+      c[2 * j + 1] = (float)(int16_t)(w[j] >> 16);
     }
   } else {
-    const uint32_t* wb = reinterpret_cast<const uint32_t*>(codes) + blk * (RP / 4) * B;
 #pragma unroll
     for (int j = 0; j < RP / 4; ++j) {
-      const int w = (int)ldg(wb + j * B + lane);
-      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);  // bytes 0, 1
-      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);   // bytes 2, 3
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], false);  // bytes 0, 1
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], true);   // bytes 2, 3
       c[4 * j] = lo[0] * s;
       c[4 * j + 1] = lo[1] * s;
       c[4 * j + 2] = hi[0] * s;
@@ -75,18 +83,27 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
   }
 }
 
+template <int RP, int CT>
+__device__ __forceinline__ void load_block(float (&c)[RP], const void* __restrict__ codes, size_t blk, int lane,
+                                           float s) {
+  uint32_t w[RawWords<RP, CT>::n];
+  load_raw<RP, CT>(w, codes, blk, lane);
+  decode_raw<RP, CT>(c, w, s);
+}
+
 // int16 form: sum_j (zq_j - c_j)^2 over integers.  Query coordinates and codes
 // are integers in [-32767, 32767] held as floats, so the float difference is
-// exact, |d| <= 65534 < 2^16, and the unsigned 24-bit product |d| |d|
-// (v_mul_u32_u24) is d^2 exactly in 32 bits (< 2^32); the sum runs in 64-bit
-// integers.  No step is signed: a square above 2^31 stays an unsigned value.
+// exact (|d| <= 65534 < 2^17), d^2 < 2^34, and every partial sum of at most
+// HNTL_MAX_R squares is an integer below 2^40: a float64 FMA chain (53-bit
+// significand) computes the sum exactly, in three VALU operations per term
+// (difference, widening, FMA; float64 FMA issues at the float32 rate here).
 template <int RP>
-__device__ __forceinline__ uint64_t int_sq_dist(const float* __restrict__ zq, const float (&c)[RP]) {
-  uint64_t acc = 0;
+__device__ __forceinline__ double int_sq_dist(const float* __restrict__ zq, const float (&c)[RP]) {
+  double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < RP; ++j) {
-    const uint32_t ad = (uint32_t)fabsf(zq[j] - c[j]);
-    acc += (uint64_t)(uint32_t)__umul24(ad, ad);
+    const double d = (double)(zq[j] - c[j]);
+    acc = fma(d, d, acc);
   }
   return acc;
 }
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
         if (live[t]) {
           if constexpr (CT == 3) {
             // the integer distance, exact; then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
-            const uint64_t S = int_sq_dist<RP>(zq[t], c);
+            const double S = int_sq_dist<RP>(zq[t], c);
             L[t].offer_f(fmaf((float)S, d2, ei + eq[t]), pos, valid);
           } else {
             const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
