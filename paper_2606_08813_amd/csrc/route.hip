@@ -324,7 +324,7 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * HNTL_WAVE + lane;
-      L.offer(make_key(v[u], (uint32_t)c), c < cols);
+      L.offer_f(v[u], (uint32_t)c, c < cols);
     }
   }
   L.finish();

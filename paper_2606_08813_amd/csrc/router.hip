@@ -93,6 +93,37 @@ __device__ __forceinline__ void epi_store(const Epi& e, int row, int col, float 
   }
 }
 
+// The same epilogue with its per-row term rt (EPI_DIST: an[row]) and per-column
+// term ct (EPI_DIST: bn[col]; the bias forms: bias[col]) loaded once per row
+// and column by the caller instead of once per element; same arithmetic.
+template <int EPI>
+__device__ __forceinline__ float epi_row_term(const Epi& e, int row) {
+  if constexpr (EPI == EPI_DIST) return e.an[row];
+  return 0.f;
+}
+template <int EPI>
+__device__ __forceinline__ float epi_col_term(const Epi& e, int col) {
+  if constexpr (EPI == EPI_DIST) return e.bn[col];
+  if constexpr (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU) return e.bias[col];
+  return 0.f;
+}
+template <int EPI>
+__device__ __forceinline__ void epi_store_t(const Epi& e, int row, int col, float v, float rt, float ct) {
+  if constexpr (EPI == EPI_F32) {
+    e.C[(size_t)row * e.ldc + col] = v;
+  } else if constexpr (EPI == EPI_BIAS_F32) {
+    e.C[(size_t)row * e.ldc + col] = e.scale * (v + ct);
+  } else if constexpr (EPI == EPI_BIAS_GELU) {
+    const float z = v + ct;
+    if (e.C) e.C[(size_t)row * e.ldc + col] = z;
+    e.H[(size_t)row * e.ldh + col] = to_bf16(gelu(z));
+  } else if constexpr (EPI == EPI_DIST) {
+    e.C[(size_t)row * e.ldc + col] = fmaxf(rt + ct - 2.f * v, 0.f);
+  } else {
+    epi_store<EPI>(e, row, col, v);
+  }
+}
+
 // One thread's share of a 128 x 64 tile of X(r, k) (rows r0.., depths k0..):
 // 32 bf16 in four 16-byte words.  XT = false: X(r, k) = X[r * ld + k], the
 // thread holds row t / 2, depths 32 (t % 2) .. + 31; XT = true:
@@ -353,6 +384,7 @@ constexpr size_t NN_LDS = (size_t)2 * (NM + NN) * NLD * sizeof(uint16_t);
 // output element is accumulated in the same order as in gemm_nn_kernel (depth
 // tiles of 64, MFMA steps of 32), so the kernels give identical results.
 constexpr int BM = 256, BN = 256;
+constexpr int BIG_GROUP = 4;  // row blocks per tile group
 constexpr size_t DL_STAGE = (size_t)(BM + BN) * NK * sizeof(uint16_t);  // 64 KiB
 constexpr size_t BIG_LDS = 2 * DL_STAGE;
 
@@ -386,12 +418,17 @@ __global__ __launch_bounds__(512) void gemm_big_kernel(const uint16_t* __restric
                                                        Epi e, const int32_t* __restrict__ mlim, int tiles_n,
                                                        int ntiles) {
   extern __shared__ __attribute__((aligned(16))) uint16_t dsm[];
-  // XCD-contiguous tile order: workgroup b runs on XCD b % 8
+  // XCD-contiguous tile order: workgroup b runs on XCD b % 8; inside an XCD's
+  // range, tiles go in groups of BIG_GROUP row blocks (down a group's rows
+  // first, then across its columns), so the tiles that run together on one
+  // XCD read few distinct operand panels through its L2
   const int nb = (int)gridDim.x, per = nb / 8;
   const int bid = (int)blockIdx.x;
   const int tile = (nb % 8 == 0) ? (bid % 8) * per + bid / 8 : bid;
   if (tile >= ntiles) return;
-  const int m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+  const int tiles_m = ntiles / tiles_n, in_group = BIG_GROUP * tiles_n;
+  const int first = tile / in_group * BIG_GROUP, gsz = min(tiles_m - first, BIG_GROUP), r = tile % in_group;
+  const int m0 = (first + r % gsz) * BM, n0 = (r / gsz) * BN;
   if (mlim) {
     const int lim = (int)(*mlim - e.row_base);
     if (m0 >= lim) return;
@@ -434,16 +471,24 @@ __global__ __launch_bounds__(512) void gemm_big_kernel(const uint16_t* __restric
       }
     }
   }
+  float ct[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int col = n0 + wn + 16 * b + i;
+    ct[b] = col < N ? epi_col_term<EPI>(e, col) : 0.f;
+  }
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int j = 0; j < 4; ++j) {
+      const int row = m0 + wm + 16 * a + 4 * kq + j;
+      const float rt = row < M ? epi_row_term<EPI>(e, row) : 0.f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm + 16 * a + 4 * kq + j;
+      for (int b = 0; b < 4; ++b) {
         const int col = n0 + wn + 16 * b + i;
-        if (row < M && col < N) epi_store<EPI>(e, row, col, acc[a][b][j]);
+        if (row < M && col < N) epi_store_t<EPI>(e, row, col, acc[a][b][j], rt, ct[b]);
       }
+    }
 }
 constexpr int BIG_MIN_ROWS = 512;  // fewer rows: the 256 x 128 tiles keep more workgroups busy
 
