@@ -60,7 +60,52 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # kernels on given workloads; valid while the kernel's sources are unchanged
 # (sha1 of the listed files).  Each entry names the profile summary it comes
 # from.
-TRAFFIC = []
+_SCAN_SRC = ("paper_2606_08813_amd/csrc/fused_impl.h", "paper_2606_08813_amd/csrc/scan_impl.h",
+             "paper_2606_08813_amd/csrc/hntl_device.h", "paper_2606_08813_amd/csrc/plan.hip",
+             "paper_2606_08813_amd/csrc/bucket.hip")
+_SHA = {
+    "paper_2606_08813_amd/csrc/fused_impl.h": "709714f59d8c77635c6b7619e0de344a4acf6d94",
+    "paper_2606_08813_amd/csrc/scan_impl.h": "f5cf70255c13644ef7f583e8c5fb911a995647fa",
+    "paper_2606_08813_amd/csrc/hntl_device.h": "7d53f2cb1ea12e28ecec99de76357ff1137165f9",
+    "paper_2606_08813_amd/csrc/plan.hip": "8dfe7b76b35f078782f21abfc23e610dd88075dc",
+    "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
+    "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
+    "paper_2606_08813_amd/csrc/fused_ct1.hip": "a15377c01ab0b4b06e0a90b3788ed3259d5aad97",
+    "paper_2606_08813_amd/csrc/rerank.hip": "4616a1568044311e49c3d3680623e71d312b47f8",
+    "paper_2606_08813_amd/csrc/project.hip": "ac70a7ba410f94fcf3a0388a38a0e5c439942fd7",
+    "paper_2606_08813_amd/csrc/project_impl.h": "b7f2c4adb2e898712edc62fc094072e5ff0dab9b",
+}
+
+
+def _traffic(kernel, codes, batch, fetch_kib, write_kib, sources, profile):
+    return {"kernel": kernel, "workload": "zipf10M_d768_G8192_r48", "form": "plan", "codes": codes, "P": 16,
+            "mode": "B", "batch": batch, "fetch_kib": fetch_kib, "write_kib": write_kib, "fetch_scale": 2.0,
+            "write_scale": 1.0, "sources": {f: _SHA[f] for f in sources}, "profile": profile}
+
+
+# per plan run: the fused scan launch(es), the separate projection launch, the
+# merge + rerank launch (KiB per dispatch; the two-pass 256-query plan's two
+# scan launches summed)
+TRAFFIC = [
+    _traffic("scan", "fp32", 16384, 2.202e6, 8.653e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+    _traffic("scan", "fp32", 256, 7.962e4 + 1.121e5, 710.0 + 891.8,
+             _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+    _traffic("scan", "bf16", 16384, 1.122e6, 8.749e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+    _traffic("scan", "bf16", 256, 4.122e4 + 5.823e4, 709.9 + 891.6,
+             _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+    _traffic("rerank", "fp32", 16384, 2.666e6, 3712.0, ("paper_2606_08813_amd/csrc/rerank.hip",),
+             "profiles/merge_rerank_zipf10M_d768_G8192_r48_dram_counters.md"),
+    _traffic("project", "fp32", 16384, 7.475e5, 5.759e4,
+             ("paper_2606_08813_amd/csrc/project.hip", "paper_2606_08813_amd/csrc/project_impl.h"),
+             "profiles/projection_zipf10M_d768_G8192_r48_counters.md"),
+    _traffic("project", "bf16", 16384, 5.59e5, 5.745e4,
+             ("paper_2606_08813_amd/csrc/project.hip", "paper_2606_08813_amd/csrc/project_impl.h"),
+             "profiles/projection_zipf10M_d768_G8192_r48_counters.md"),
+]
 
 
 def measured_traffic(kernel, workload, form, codes, P, mode, batch):
@@ -512,6 +557,11 @@ def main():
         achieved = s["work"] / t / (1e12 if s["unit"] == "TFLOP/s" else 1e9)
         roof[name] = {"bound": s["bound"], "achieved": round(achieved, 3), "peak": s["peak"], "unit": s["unit"],
                       "frac": round(achieved / s["peak"], 4), "ms": round(stage_avg[name], 4)}
+        tr = measured_traffic(name, W.name, args.form, args.codes if name != "project" else
+                              ("bf16" if bf16_project else "fp32"), P, args.mode, W.nq)
+        if tr:  # the stage's DRAM bytes from counters on this kernel source
+            roof[name]["traffic"] = tr
+            roof[name]["dram_GBps"] = round(tr / t / 1e9, 1)
     dominant = max(roof, key=lambda n: roof[n]["ms"]) if roof else None
     scan_ms = stage_avg.get("scan", 0.0)
 
@@ -529,7 +579,7 @@ def main():
         nblk = (sizes[pg] + 63) // 64
         unique_bytes = int(nblk.sum()) * 64 * (rp * code_bytes + 4)
         t_scan = rh["stage"]["scan"]
-        traffic = measured_traffic("fused_scan", W.name, "plan", args.codes, P, args.mode, nb)
+        traffic = measured_traffic("scan", W.name, "plan", args.codes, P, args.mode, nb)
         scan_hbm = {"batch": nb, "schedule": rh["sched"], "scan_ms": round(t_scan, 4),
                     "probed_grains": int(len(pg)), "unique_code_bytes": unique_bytes,
                     "scored": int(rh["scored"]),
