@@ -48,6 +48,7 @@ struct RouterScratch {
   float* negS = nullptr;
   int32_t *fb_rows = nullptr, *fb_count = nullptr, *fb_probes = nullptr;
   float *fb_Q = nullptr, *fb_qn = nullptr, *fb_pdist = nullptr;
+  float2* znorm = nullptr;  // per row: the smallest negated score and the softmax normaliser
   size_t layout(char* base, const Index& ix, int64_t nq, int P);
 };
 
@@ -170,7 +171,7 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A = nullptr, const float* an = nullptr, const float* Bm = nullptr,
                       const float* bn = nullptr, int d = 0, float err = 0.f, const int32_t* nlim = nullptr,
-                      int64_t row_base = 0, unsigned int* overflow = nullptr);
+                      int64_t row_base = 0, unsigned int* overflow = nullptr, float2* znorm = nullptr);
 
 // Centroid routing (Section 2.1 step 1): the P nearest centroids of every row
 // of Q by FP32 direct differences, from a shortlist of expansion distances
@@ -277,7 +278,8 @@ void ensure_eps_by_id(Index& ix, hipStream_t s);
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k,
                          const int32_t* probes, const uint64_t* part, const int32_t* pool_in, int32_t* pool_out,
                          float* pool_D_out, int32_t* ids, float* dist, hipStream_t s,
-                         const int32_t* qoff = nullptr, const float* eps_id = nullptr);
+                         const int32_t* qoff = nullptr, const float* eps_id = nullptr,
+                         const int32_t* nlim = nullptr);  // rows from *nlim on: -1 / +inf only
 
 // Persistent fused project-scan-select kernel (the batching form).  Its
 // waves take work items from one device ticket counter, in three runs:

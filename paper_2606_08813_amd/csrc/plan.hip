@@ -340,7 +340,7 @@ struct Plan {
     }
     if (ev) HIP_TRY(hipEventRecord(ev[4], s));
     launch_merge_rerank(x, Q, max_nq, P, (int)sp.C, (int)sp.k, probes, part, nullptr, nullptr, nullptr, ids, dist, s,
-                        sch.range ? qoff : nullptr, (sp.flags & HNTL_FLAG_MODE_A) ? x.eps_id : nullptr);
+                        sch.range ? qoff : nullptr, (sp.flags & HNTL_FLAG_MODE_A) ? x.eps_id : nullptr, nq_dev);
     if (ev) HIP_TRY(hipEventRecord(ev[5], s));
   }
 

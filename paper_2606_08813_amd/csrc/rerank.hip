@@ -27,12 +27,23 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
                                                            float* __restrict__ pool_D_out, int32_t* __restrict__ ids,
                                                            float* __restrict__ dist, bool vec4,
                                                            const int32_t* __restrict__ qoff,
-                                                           const float* __restrict__ eps_id) {
+                                                           const float* __restrict__ eps_id, int64_t nrows,
+                                                           const int32_t* __restrict__ nlim) {
   __shared__ uint64_t lst[2 * CAP];
   __shared__ int32_t pool[CAP];
   __shared__ float delta[CAP];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
+  // one workgroup per row; rows from the batch size *nlim on (a plan's device
+  // batch size) only get -1 / +inf results
   const int64_t q = blockIdx.x;
+  if (q >= nrows) return;
+  if (nlim && q >= (int64_t)*nlim) {
+    if ((int)threadIdx.x < k) {
+      ids[q * k + threadIdx.x] = -1;
+      dist[q * k + threadIdx.x] = __builtin_inff();
+    }
+    return;  // uniform over the workgroup, before any barrier
+  }
 
   if (pool_in == nullptr) {
     if constexpr (CAP == 64) {
@@ -204,9 +215,7 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
         dist[q * k + lane] = key == KEY_NONE ? __builtin_inff() : key_dist(key);
       }
     }
-    return;
-  }
-  if (wave == 0) {
+  } else if (wave == 0) {
     WaveTopR<CAP / 64> L;
     L.init(lst, k);
     for (int c0 = 0; c0 < C; c0 += HNTL_WAVE) {
@@ -251,7 +260,7 @@ void ensure_eps_by_id(Index& ix, hipStream_t s) {
 void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int C, int k, const int32_t* probes,
                          const uint64_t* part,
                          const int32_t* pool_in, int32_t* pool_out, float* pool_D_out, int32_t* ids, float* dist,
-                         hipStream_t s, const int32_t* qoff, const float* eps_id) {
+                         hipStream_t s, const int32_t* qoff, const float* eps_id, const int32_t* nlim) {
   if (nq <= 0) return;
   if (eps_id && pool_in) throw ArgError{HNTL_EUNSUPPORTED, "Mode A answers need the merged pool, not an injected one"};
   if (!eps_id && !ix.X) throw ArgError{HNTL_ESTATE, "this index holds no raw vectors: only Mode A searches"};
@@ -263,7 +272,7 @@ void launch_merge_rerank(const Index& ix, const float* Q, int64_t nq, int P, int
 #define HNTL_MR(CAPV, RRV, JUV)                                                                                  \
   hipLaunchKernelGGL((merge_rerank_kernel<CAPV, RRV, JUV, true>), grid, dim3(256), 0, s, Q, (int)ix.d, P, C, k,      \
                      (int)ix.G, (int64_t)ix.N, probes, part, pool_in, ix.X, pool_out, pool_D_out, ids, dist, vec4,   \
-                     qoff, eps_id)
+                     qoff, eps_id, nq, nlim)
   const bool narrow = ix.d <= 4 * HNTL_WAVE;
   if (cap == 64) {
     if (narrow)

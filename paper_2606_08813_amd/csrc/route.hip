@@ -284,11 +284,29 @@ constexpr int TOPK_ROWS = 8;
 
 // Direct FP32 squared distance of row a and column row b (both d long), one
 // wave, every lane ends with the total.
-__device__ __forceinline__ float wave_dist(const float* __restrict__ a, const float* __restrict__ b, int d) {
+// With vec4 (d % 4 == 0, 16-byte aligned rows) lane l covers depths
+// 4 l .. 4 l + 3 of every 256-wide chunk, in that order; otherwise depths l,
+// l + 64, ...
+__device__ __forceinline__ float wave_dist(const float* __restrict__ a, const float* __restrict__ b, int d,
+                                           bool vec4) {
   float acc = 0.f;
-  for (int t = lane_id(); t < d; t += HNTL_WAVE) {
-    const float df = a[t] - b[t];
-    acc = fmaf(df, df, acc);
+  if (vec4) {
+    for (int t = lane_id() * 4; t < d; t += 4 * HNTL_WAVE) {
+      const float4 x = *reinterpret_cast<const float4*>(a + t), y = *reinterpret_cast<const float4*>(b + t);
+      float df = x.x - y.x;
+      acc = fmaf(df, df, acc);
+      df = x.y - y.y;
+      acc = fmaf(df, df, acc);
+      df = x.z - y.z;
+      acc = fmaf(df, df, acc);
+      df = x.w - y.w;
+      acc = fmaf(df, df, acc);
+    }
+  } else {
+    for (int t = lane_id(); t < d; t += HNTL_WAVE) {
+      const float df = a[t] - b[t];
+      acc = fmaf(df, df, acc);
+    }
   }
   return wave_sum(acc);
 }
@@ -297,7 +315,7 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
     const float* __restrict__ D, int64_t rows, int cols, int P, int M, const float* __restrict__ A,
     const float* __restrict__ an, const float* __restrict__ Bm, const float* __restrict__ bn, int d, float err,
     int32_t* __restrict__ idx, float* __restrict__ val, const int32_t* __restrict__ nlim, int64_t row_base,
-    unsigned int* __restrict__ overflow) {
+    unsigned int* __restrict__ overflow, float2* __restrict__ znorm, bool vec4) {
   __shared__ uint64_t stage[TOPK_ROWS][64];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * TOPK_ROWS + wave;
@@ -314,6 +332,10 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
   L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
   constexpr int U = 8;  // chunks of 64 loaded together (memory-level parallelism for one row)
+  // znorm (negated scores): the row's smallest value mn and z = sum exp(mn - D_c),
+  // the softmax normaliser of the scores, accumulated per lane against the
+  // lane's running minimum and rescaled when it drops
+  float lmn = __builtin_inff(), lz = 0.f;
   for (int c0 = 0; c0 < cols; c0 += U * HNTL_WAVE) {
     float v[U];
 #pragma unroll
@@ -326,8 +348,29 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
       const int c = c0 + u * HNTL_WAVE + lane;
       L.offer_f(v[u], (uint32_t)c, c < cols);
     }
+    if (znorm) {
+      float cm = __builtin_inff();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (c0 + u * HNTL_WAVE + lane < cols) cm = fminf(cm, v[u]);
+      if (cm < __builtin_inff()) {
+        const float nm = fminf(lmn, cm);
+        lz = lmn < __builtin_inff() ? lz * expf(nm - lmn) : 0.f;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c0 + u * HNTL_WAVE + lane < cols) lz += expf(nm - v[u]);
+        lmn = nm;
+      }
+    }
   }
   L.finish();
+  if (znorm) {
+    float mn = lmn;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
+    const float z = wave_sum(lmn < __builtin_inff() ? lz * expf(mn - lmn) : 0.f);
+    if (lane == 0) znorm[row] = make_float2(mn, z);
+  }
   if (!exact) {
     if (lane < P) {
       idx[row * P + lane] = L.best == KEY_NONE ? -1 : (int32_t)key_id(L.best);
@@ -361,7 +404,7 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
       while (m) {  // wave-uniform loop over the window columns of this chunk
         const int j = __builtin_ctzll(m);
         m &= m - 1;
-        const float dd = wave_dist(a, Bm + (size_t)(c0 + j) * d, d);
+        const float dd = wave_dist(a, Bm + (size_t)(c0 + j) * d, d, vec4);
         if (lane == j) keyc = make_key(dd, (uint32_t)(c0 + j));
       }
       X.offer(keyc, w);
@@ -381,12 +424,44 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
         bp[u] = Bm + (size_t)cs[u] * d;
         acc[u] = 0.f;
       }
-      for (int t = lane; t < d; t += HNTL_WAVE) {
-        const float av = a[t];
+      if (vec4) {
+        // 16-byte loads: a round of RB entries covers 256 depths per load
+        // instruction (3 rounds for d = 768 instead of 12 with 4-byte loads)
+        constexpr int CH = 1;
+        for (int t0 = lane * 4; t0 < d; t0 += CH * 4 * HNTL_WAVE) {
+          float4 av[CH], bv[CH][RB];
 #pragma unroll
-        for (int u = 0; u < RB; ++u) {
-          const float df = av - bp[u][t];
-          acc[u] = fmaf(df, df, acc[u]);
+          for (int i = 0; i < CH; ++i) {
+            const int t = t0 + i * 4 * HNTL_WAVE;
+            av[i] = t < d ? *reinterpret_cast<const float4*>(a + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+              bv[i][u] = t < d ? *reinterpret_cast<const float4*>(bp[u] + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int i = 0; i < CH; ++i) {
+            if (t0 + i * 4 * HNTL_WAVE >= d) break;  // uniform
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+              float df = av[i].x - bv[i][u].x;
+              acc[u] = fmaf(df, df, acc[u]);
+              df = av[i].y - bv[i][u].y;
+              acc[u] = fmaf(df, df, acc[u]);
+              df = av[i].z - bv[i][u].z;
+              acc[u] = fmaf(df, df, acc[u]);
+              df = av[i].w - bv[i][u].w;
+              acc[u] = fmaf(df, df, acc[u]);
+            }
+          }
+        }
+      } else {
+        for (int t = lane; t < d; t += HNTL_WAVE) {
+          const float av = a[t];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const float df = av - bp[u][t];
+            acc[u] = fmaf(df, df, acc[u]);
+          }
         }
       }
 #pragma unroll
@@ -538,15 +613,18 @@ void launch_argmin_rows(const float* A, const float* an, int64_t rows, const flo
 
 void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* idx, float* val, hipStream_t s,
                       const float* A, const float* an, const float* Bm, const float* bn, int d, float err,
-                      const int32_t* nlim, int64_t row_base, unsigned int* overflow) {
+                      const int32_t* nlim, int64_t row_base, unsigned int* overflow, float2* znorm) {
   if (A && (!an || !bn || !Bm)) throw ArgError{HNTL_EINVAL, "routing re-score needs both norm vectors and the centroids"};
+  if (A && znorm) throw ArgError{HNTL_EINVAL, "the softmax normaliser is for score rows (no re-score)"};
   if (rows <= 0) return;
   if (P > HNTL_MAX_P) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
   dim3 grid((unsigned)((rows + TOPK_ROWS - 1) / TOPK_ROWS)), block(TOPK_ROWS * 64);
   // shortlist: the window of the P-th entry plus 48 more (one key per lane)
   const int M = A ? std::min(cols, std::min(64, P + 48)) : P;
+  // float4 re-score loads where rows allow them
+  const bool vec4 = A && (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
   hipLaunchKernelGGL(topk_rows_kernel, grid, block, 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, err, idx, val, nlim,
-                     row_base, overflow);
+                     row_base, overflow, znorm, vec4);
   HIP_TRY(hipGetLastError());
 }
 

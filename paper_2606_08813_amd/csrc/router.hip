@@ -658,45 +658,33 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
   if (wb) wb[i] = to_bf16(wi);
 }
 
-// Max softmax probability of each row of negated scores (1 / sum exp(s - max));
-// rows below tau are appended to the fallback list.
-// (negS + colbias when the bias is not in negS yet)
-__global__ __launch_bounds__(256) void fallback_select_kernel(const float* __restrict__ negS, int64_t rows, int G,
+// Max softmax probability of each row of negated scores (1 / z, z from the
+// top-P pass that read the row); rows below tau are appended to the fallback
+// list.  One thread per row.
+__global__ __launch_bounds__(256) void fallback_select_kernel(const float2* __restrict__ znorm, int64_t rows,
                                                               float tau, int32_t* __restrict__ fb_rows,
                                                               int32_t* __restrict__ fb_count,
                                                               const int32_t* __restrict__ nlim) {
-  const int lane = lane_id();
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows || (nlim && r >= *nlim)) return;
-  const float* s = negS + r * G;
-  float mn = __builtin_inff();
-  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
-  float z = 0.f;
-  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
-  z = wave_sum(z);
-  if (lane == 0 && 1.f / z < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
+  if (1.f / znorm[r].y < tau) fb_rows[atomicAdd(fb_count, 1)] = (int32_t)r;
 }
 
 // Probability-mass probe budget of one learned row (one wave): with
 // m = max score and z = sum_g exp(s_g - m) over all G scores, slots are kept
 // up to and including the first j at which sum_{i <= j} exp(s_{p_i} - m) / z
 // reaches mass; later slots become probe -1 (pdist +inf).
-__global__ __launch_bounds__(256) void mass_cut_kernel(const float* __restrict__ negS, int64_t rows, int G, int P,
-                                                       float mass, int32_t* __restrict__ probes,
-                                                       float* __restrict__ pdist, const int32_t* __restrict__ nlim) {
+__global__ __launch_bounds__(256) void mass_cut_kernel(const float* __restrict__ negS, const float2* __restrict__ znorm,
+                                                       int64_t rows, int G, int P, float mass,
+                                                       int32_t* __restrict__ probes, float* __restrict__ pdist,
+                                                       const int32_t* __restrict__ nlim) {
   const int lane = lane_id();
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows || (nlim && r >= *nlim)) return;
   const float* s = negS + r * G;  // negated scores
-  float mn = __builtin_inff();
-  for (int g = lane; g < G; g += HNTL_WAVE) mn = fminf(mn, s[g]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
-  float z = 0.f;
-  for (int g = lane; g < G; g += HNTL_WAVE) z += expf(mn - s[g]);
-  z = wave_sum(z);
+  // m and z of the row, from the top-P pass that read the row
+  const float2 mz = znorm[r];
+  const float mn = mz.x, z = mz.y;
   // lane j < P: probability of slot j; an inclusive prefix sum over the lanes
   const int32_t pj = lane < P ? probes[r * P + lane] : -1;
   float p = pj >= 0 ? expf(mn - s[pj]) / z : 0.f;
@@ -952,17 +940,18 @@ void launch_route_learned(const Index& ix, const float* Q, int64_t nq, int P, fl
   o.bias = rt.b[2];
   o.scale = -1.f;
   gemm<false, false, EPI_BIAS_F32>(w.h2, rt.h2, rt.Wb[2], rt.h2, (int)nq, rt.G, rt.h2, o, s, nlim);
+  const bool budget = mass > 0.f && mass < 1.f && P > 1;
   launch_topk_rows(w.negS, nq, rt.G, P, probes, pdist, s, nullptr, nullptr, nullptr, nullptr, 0, 0.f, nlim, 0,
-                   nullptr);
-  if (mass > 0.f && mass < 1.f && P > 1) {
-    hipLaunchKernelGGL(mass_cut_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, P, mass, probes, pdist,
-                       nlim);
+                   nullptr, (budget || tau > 0.f) ? w.znorm : nullptr);
+  if (budget) {
+    hipLaunchKernelGGL(mass_cut_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, w.znorm, nq, rt.G, P, mass,
+                       probes, pdist, nlim);
     HIP_TRY(hipGetLastError());
   }
   if (tau > 0.f) {
     launch_fill_i32(w.fb_count, 1, 0, s);
-    hipLaunchKernelGGL(fallback_select_kernel, dim3(blocks(nq, 4)), dim3(256), 0, s, w.negS, nq, rt.G, tau, w.fb_rows,
-                       w.fb_count, nlim);
+    hipLaunchKernelGGL(fallback_select_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, w.znorm, nq, tau,
+                       w.fb_rows, w.fb_count, nlim);
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)nq), dim3(256), 0, s, Q, (int)ix.d, w.fb_rows, w.fb_count,
                        w.fb_Q);
     launch_row_norms(w.fb_Q, nq, (int)ix.d, w.fb_qn, s);
@@ -1003,6 +992,7 @@ size_t RouterScratch::layout(char* base, const Index& ix, int64_t nq, int P) {
   fb_qn = (float*)take(4 * (size_t)nq);
   fb_probes = (int32_t*)take(4 * (size_t)nq * P);
   fb_pdist = (float*)take(4 * (size_t)nq * P);
+  znorm = (float2*)take(sizeof(float2) * (size_t)nq);
   return off;
 }
 
