@@ -77,8 +77,10 @@ typedef enum hntl_codes {
 } hntl_codes;
 
 /* Search flags. */
-#define HNTL_FLAG_SYNC 1u       /* synchronise the stream before returning and report device errors */
-#define HNTL_FLAG_CHECK_Q 2u    /* reject non-finite query values with HNTL_EINVAL (implies a sync) */
+#define HNTL_FLAG_SYNC 1u       /* synchronise the stream before returning, report device errors, and
+                                   reject non-finite query values with HNTL_EINVAL */
+#define HNTL_FLAG_CHECK_Q 2u    /* reject non-finite query values with HNTL_EINVAL (implies a sync);
+                                   asynchronous calls without it do not check */
 #define HNTL_FLAG_PROFILE 4u    /* record HIP events around each stage on the call's stream (see hntl_profile_read) */
 #define HNTL_FLAG_NO_PRUNE 8u   /* scan every member of every probed grain (see below) */
 #define HNTL_FLAG_PROJECT_BF16 16u /* projection on BF16 MFMA: q - mu_g (FP32) and W_g rounded to BF16 (nearest

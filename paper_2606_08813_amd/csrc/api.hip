@@ -158,6 +158,13 @@ __global__ void nonfinite_kernel(const float* __restrict__ A, int64_t n, int* __
 
 // Caller buffers of one staged search (any stage input may be injected, any
 // stage output observed; see hntl_search_stages).
+// Non-finite query values are rejected (EINVAL) by every call that returns
+// after its work has finished: HNTL_FLAG_SYNC, or HNTL_FLAG_CHECK_Q (which
+// implies the wait).  An asynchronous call cannot report them.
+inline bool checks_queries(const hntl_search_params& sp) {
+  return (sp.flags & (HNTL_FLAG_CHECK_Q | HNTL_FLAG_SYNC)) != 0;
+}
+
 struct StagedIO {
   const int32_t* probes_in;
   int32_t* probes_out;
@@ -241,7 +248,7 @@ struct StagedScratch {
       return p;
     };
     const int64_t P = sp.P, npairs = (int64_t)nq * P;
-    if (sp.flags & HNTL_FLAG_CHECK_Q) qflag = (int*)take(sizeof(int));
+    if (checks_queries(sp)) qflag = (int*)take(sizeof(int));
     if (io.pool_in) return off;
     if (!io.probes_in) {
       if (!io.probes_out) probes = (int32_t*)take(sizeof(int32_t) * npairs);
@@ -284,7 +291,7 @@ struct StagedScratch {
 void run_staged(const Index& ix, const float* Q, uint32_t nq, const hntl_search_params& sp, const StagedIO& io,
                 StagedScratch& w, hipStream_t s) {
   const uint32_t P = sp.P, C = sp.C, k = sp.k;
-  if (sp.flags & HNTL_FLAG_CHECK_Q) {
+  if (checks_queries(sp)) {
     launch_fill_i32(w.qflag, 1, 0, s);
     const int64_t n = (int64_t)nq * ix.d;
     hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Q, n, w.qflag);

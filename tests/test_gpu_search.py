@@ -169,6 +169,11 @@ def test_empty_batch_and_errors():
     with pytest.raises(hntl.HNTLError) as e:
         hntl.hntl_search(ix, bad, 2, 20, 10, flags=hntl.HNTL_FLAG_CHECK_Q)
     assert e.value.status == hntl.HNTL_EINVAL
+    # every synchronous call checks (an infinite value this time)
+    bad[1, 3] = float("inf")
+    with pytest.raises(hntl.HNTLError) as e:
+        hntl.hntl_search(ix, bad, 2, 20, 10, flags=hntl.HNTL_FLAG_SYNC)
+    assert e.value.status == hntl.HNTL_EINVAL
     with pytest.raises(hntl.HNTLError) as e:
         hntl.hntl_search(ix, Qd, 2, 20, 10, codes="bf16")
     assert e.value.status == hntl.HNTL_ESTATE
