@@ -491,6 +491,7 @@ __global__ __launch_bounds__(512) void gemm_big_kernel(const uint16_t* __restric
     }
 }
 constexpr int BIG_MIN_ROWS = 512;  // fewer rows: the 256 x 128 tiles keep more workgroups busy
+constexpr int64_t BIG_MIN_TILES = 256;  // fewer 256 x 256 tiles than CUs: the 256 x 128 tiles
 
 template <bool AT, bool BT, int EPI>
 void gemm(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K, const Epi& e, hipStream_t s,
@@ -498,7 +499,8 @@ void gemm(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, 
   if (M <= 0 || N <= 0) return;
   if constexpr (!AT && !BT) {
     if ((K % 8) == 0 && (lda % 8) == 0 && (ldb % 8) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 &&
-        M >= BIG_MIN_ROWS && N >= BN && (K % NK) == 0) {
+        M >= BIG_MIN_ROWS && N >= BN && (K % NK) == 0 &&
+        (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN) >= BIG_MIN_TILES) {
       const int tn = (N + BN - 1) / BN, tm = (M + BM - 1) / BM;
       const int nt = tn * tm;
       const int grid = (nt + 7) / 8 * 8;  // a multiple of 8 for the XCD-contiguous order
