@@ -67,11 +67,11 @@ _SHA = {
     "paper_2606_08813_amd/csrc/fused_impl.h": "709714f59d8c77635c6b7619e0de344a4acf6d94",
     "paper_2606_08813_amd/csrc/scan_impl.h": "f5cf70255c13644ef7f583e8c5fb911a995647fa",
     "paper_2606_08813_amd/csrc/hntl_device.h": "7d53f2cb1ea12e28ecec99de76357ff1137165f9",
-    "paper_2606_08813_amd/csrc/plan.hip": "8dfe7b76b35f078782f21abfc23e610dd88075dc",
+    "paper_2606_08813_amd/csrc/plan.hip": "e0cf1732648e8b136282930dff421ce558bdf943",
     "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
     "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
     "paper_2606_08813_amd/csrc/fused_ct1.hip": "a15377c01ab0b4b06e0a90b3788ed3259d5aad97",
-    "paper_2606_08813_amd/csrc/rerank.hip": "4616a1568044311e49c3d3680623e71d312b47f8",
+    "paper_2606_08813_amd/csrc/rerank.hip": "eadb0a7606d798bc31bc66008d2b796749fe6e32",
     "paper_2606_08813_amd/csrc/project.hip": "ac70a7ba410f94fcf3a0388a38a0e5c439942fd7",
     "paper_2606_08813_amd/csrc/project_impl.h": "b7f2c4adb2e898712edc62fc094072e5ff0dab9b",
 }
