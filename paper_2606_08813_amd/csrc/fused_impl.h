@@ -57,7 +57,9 @@ namespace fused_detail {
 
 using proj_detail::project_wave;
 using proj_detail::project_wave_bf16;
-using scan_detail::int_sq_dist;
+using scan_detail::i16_cross;
+using scan_detail::i16_sq_norm;
+using scan_detail::i16_split_query;
 using scan_detail::ListOf;
 using scan_detail::load_block;
 using scan_detail::PRUNE_SLACK;
@@ -223,6 +225,13 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
   }
   wave_sync();
   if (nlive == 0) return;
+  // int16 form: each pair's query as split words, and |q|^2
+  double qn[QT];
+  if constexpr (CT == 3) {
+#pragma unroll
+    for (int t = 0; t < QT; ++t) qn[t] = i16_split_query<RP>(zq[t], lane);
+    wave_sync();
+  }
   if (a.scored && lane == 0) {
     const int nvec = min(ng, rb1 * B) - rb0 * B;
     if (nvec > 0)
@@ -252,23 +261,33 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       if (live[t]) {
-        if constexpr (CT == 3) {
-          const double S = int_sq_dist<RP>(zq[t], c);
-          Ls[t].offer_f(fmaf((float)S, d2, e + eq[t]), pos, valid);
-        } else {
-          const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
-          float acc = 0.f;
+        const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
+        float acc = 0.f;
 #pragma unroll
-          for (int j4 = 0; j4 < RP / 4; ++j4) {
-            const floatx4 z = z4[j4];
+        for (int j4 = 0; j4 < RP / 4; ++j4) {
+          const floatx4 z = z4[j4];
 #pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-              const float df = z[e4] - c[4 * j4 + e4];
-              acc = fmaf(df, df, acc);
-            }
+          for (int e4 = 0; e4 < 4; ++e4) {
+            const float df = z[e4] - c[4 * j4 + e4];
+            acc = fmaf(df, df, acc);
           }
-          Ls[t].offer_f(acc + eq[t] + e, pos, valid);
         }
+        Ls[t].offer_f(acc + eq[t] + e, pos, valid);
+      }
+    }
+  };
+  // int16 form: scored from the raw code words; the integer distance is exact,
+  // then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
+  constexpr int RW = scan_detail::RawWords<RP, CT>::n;
+  auto score16 = [&](const uint32_t(&w)[RW], float e, int b) {
+    const bool valid = b * B + lane < ng;
+    const uint32_t pos = (uint32_t)(pos0 + b * B + lane);
+    const double cn = i16_sq_norm<RW>(w);
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      if (live[t]) {
+        const double S = fma(-2.0, i16_cross<RW>(reinterpret_cast<const uint32_t*>(zq[t]), w), qn[t] + cn);
+        Ls[t].offer_f(fmaf((float)S, d2, e + eq[t]), pos, valid);
       }
     }
   };
@@ -277,7 +296,6 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     // NBUF register buffers of raw code words, NBUF - 1 blocks requested ahead
     // of the one being scored (decoded only when scored, so no wait is forced
     // at the request)
-    constexpr int RW = scan_detail::RawWords<RP, CT>::n;
     constexpr int NBUF = RW * 4 <= 160 ? 4 : (RW * 3 <= 160 ? 3 : 2);
     uint32_t wr[NBUF][RW];
     float er[NBUF];
@@ -298,9 +316,13 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
             scan_detail::load_raw<RP, CT>(wr[(u + NBUF - 1) % NBUF], codes, (size_t)(b0 + nx), lane);
             er[(u + NBUF - 1) % NBUF] = ldg(a.eps + (size_t)(b0 + nx) * B + lane);
           }
-          float c[RP];
-          scan_detail::decode_raw<RP, CT>(c, wr[u], sg);
-          score(c, er[u], bb);
+          if constexpr (CT == 3) {
+            score16(wr[u], er[u], bb);
+          } else {
+            float c[RP];
+            scan_detail::decode_raw<RP, CT>(c, wr[u], sg);
+            score(c, er[u], bb);
+          }
         }
       }
     }
@@ -309,9 +331,15 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     // on the CU cover the HBM latency
     for (int b = rb0; b < rb1; ++b) {
       if (b > rb0 && ((b - rb0) % REFRESH) == 0) exchange();
-      float c[RP];
-      load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
-      score(c, ldg(a.eps + (size_t)(b0 + b) * B + lane), b);
+      if constexpr (CT == 3) {
+        uint32_t w[RW];
+        scan_detail::load_raw<RP, CT>(w, codes, (size_t)(b0 + b), lane);
+        score16(w, ldg(a.eps + (size_t)(b0 + b) * B + lane), b);
+      } else {
+        float c[RP];
+        load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
+        score(c, ldg(a.eps + (size_t)(b0 + b) * B + lane), b);
+      }
     }
   }
 

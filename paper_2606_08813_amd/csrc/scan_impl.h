@@ -91,21 +91,79 @@ __device__ __forceinline__ void load_block(float (&c)[RP], const void* __restric
   decode_raw<RP, CT>(c, w, s);
 }
 
-// int16 form: sum_j (zq_j - c_j)^2 over integers.  Query coordinates and codes
-// are integers in [-32767, 32767] held as floats, so the float difference is
-// exact (|d| <= 65534 < 2^17), d^2 < 2^34, and every partial sum of at most
-// HNTL_MAX_R squares is an integer below 2^40: a float64 FMA chain (53-bit
-// significand) computes the sum exactly, in three VALU operations per term
-// (difference, widening, FMA; float64 FMA issues at the float32 rate here).
-template <int RP>
-__device__ __forceinline__ double int_sq_dist(const float* __restrict__ zq, const float (&c)[RP]) {
-  double acc = 0.0;
+// int16 form: S = sum_j (q_j - c_j)^2 over integers, evaluated exactly as
+// |q|^2 + |c|^2 - 2 q.c with packed 16-bit dot products (two products and a
+// 32-bit accumulation per instruction, no decoding of the code words).  Query
+// coordinates and codes lie in [-32767, 32767] and there are at most 64 of
+// them.  |c|^2: the dot of one word with itself is at most 2 * 32767^2 < 2^31;
+// widened to float64 and summed (integers below 2^37) it is exact.  q.c: each pair's
+// query is split once as q = 256 qh + ql (qh = q >> 8 in [-128, 127],
+// ql = q & 255), so the partial dots qh.c (|.| < 64 * 128 * 32767 < 2^29) and
+// ql.c (< 64 * 255 * 32767 < 2^30) accumulate exactly in 32 bits, and
+// q.c = 256 qh.c + ql.c.  Every float64 step holds integers below 2^53, so S
+// is the same integer as the sum of squared differences.
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef uint32_t uint32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int sdot2w(uint32_t a, uint32_t b, int acc) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), acc, false);
+}
+
+// |c|^2 of a lane's code words (RW even).  Two words' self-dots start from
+// -2^31: -2^31 + s0 + s1 stays inside int32 for s0, s1 <= 2 * 32767^2, so one
+// float64 widening and add serve two words; the offsets are added back at the
+// end (all exact).
+template <int RW>
+__device__ __forceinline__ double i16_sq_norm(const uint32_t (&w)[RW]) {
+  double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < RP; ++j) {
-    const double d = (double)(zq[j] - c[j]);
-    acc = fma(d, d, acc);
+  for (int j = 0; j < RW; j += 2) s += (double)sdot2w(w[j + 1], w[j + 1], sdot2w(w[j], w[j], INT32_MIN));
+  return s + (double)(RW / 2) * 2147483648.0;
+}
+
+// q.c from a pair's split query words (qh in words [0, RW), ql in [RW, 2 RW),
+// 16-byte aligned, RW a multiple of 4) and a lane's code words
+template <int RW>
+__device__ __forceinline__ double i16_cross(const uint32_t* __restrict__ qw, const uint32_t (&w)[RW]) {
+  const uint32x4* h4 = reinterpret_cast<const uint32x4*>(qw);
+  const uint32x4* l4 = reinterpret_cast<const uint32x4*>(qw + RW);
+  int a = 0, b = 0;
+#pragma unroll
+  for (int k = 0; k < RW / 4; ++k) {
+    const uint32x4 h = h4[k], l = l4[k];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a = sdot2w(h[e], w[4 * k + e], a);
+      b = sdot2w(l[e], w[4 * k + e], b);
+    }
   }
-  return acc;
+  return fma((double)a, 256.0, (double)b);
+}
+
+// Rewrites a pair's quantised query (RP exact float integers, zero beyond r)
+// in place as its split words and returns |q|^2 (one wave, all lanes).
+template <int RP>
+__device__ __forceinline__ double i16_split_query(float* __restrict__ zrow, int lane) {
+  constexpr int RW = RP / 2;
+  const float v = lane < RP ? zrow[lane] : 0.f;
+  const double qn = wave_sum_d((double)v * (double)v);
+  uint32_t hw = 0, lw = 0;
+  if (lane < RW) {
+    const int i0 = (int)zrow[2 * lane], i1 = (int)zrow[2 * lane + 1];
+    hw = ((uint32_t)(i0 >> 8) & 0xFFFFu) | ((uint32_t)(i1 >> 8) << 16);
+    lw = (uint32_t)(i0 & 255) | ((uint32_t)(i1 & 255) << 16);
+  }
+  wave_sync();  // every lane's reads of the row precede the writes
+  uint32_t* qw = reinterpret_cast<uint32_t*>(zrow);
+  if (lane < RW) {
+    qw[lane] = hw;
+    qw[RW + lane] = lw;
+  }
+  // the sum is the same in every lane: keep it in scalar registers
+  const uint64_t u = (uint64_t)__double_as_longlong(qn);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // int16 code of a float code value (float32 product, ties to even, clamped),
@@ -250,22 +308,39 @@ __global__ __launch_bounds__(64 * (ITEM / QT)) void scan_f32_kernel(
   }
   wave_sync();
   if (scored && lane == 0 && nlive > 0) atomicAdd(scored, (unsigned long long)nlive * (unsigned long long)ng);
+  // int16 form: each pair's query as split words, and |q|^2
+  double qn[QT];
+  if constexpr (CT == 3) {
+#pragma unroll
+    for (int t = 0; t < QT; ++t) qn[t] = i16_split_query<RP>(zq[t], lane);
+    wave_sync();
+  }
 
   if (nlive > 0) {
     for (int b = 0; b < nb; ++b) {
-      float c[RP];
-      load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
       const float ei = eps[(size_t)(b0 + b) * B + lane];
       const bool valid = b * B + lane < ng;
       const uint32_t pos = (uint32_t)(pos0 + b * B + lane);
+      if constexpr (CT == 3) {
+        uint32_t w[RP / 2];
+        load_raw<RP, CT>(w, codes, (size_t)(b0 + b), lane);
+        const double cn = i16_sq_norm<RP / 2>(w);
+#pragma unroll
+        for (int t = 0; t < QT; ++t) {
+          if (live[t]) {
+            // the integer distance, exact; then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
+            const double S = fma(-2.0, i16_cross<RP / 2>(reinterpret_cast<const uint32_t*>(zq[t]), w), qn[t] + cn);
+            L[t].offer_f(fmaf((float)S, d2, ei + eq[t]), pos, valid);
+          }
+        }
+        continue;
+      }
+      float c[RP];
+      load_block<RP, CT>(c, codes, (size_t)(b0 + b), lane, sg);
 #pragma unroll
       for (int t = 0; t < QT; ++t) {
         if (live[t]) {
-          if constexpr (CT == 3) {
-            // the integer distance, exact; then (1 / inv_g)^2 S + r_hat_i / rinv_g + eps_q
-            const double S = int_sq_dist<RP>(zq[t], c);
-            L[t].offer_f(fmaf((float)S, d2, ei + eq[t]), pos, valid);
-          } else {
+          {
             const floatx4* z4 = reinterpret_cast<const floatx4*>(zq[t]);
             float acc = 0.f;
 #pragma unroll
