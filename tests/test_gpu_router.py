@@ -129,6 +129,47 @@ def test_router_adam_step_parity(rt):
         assert bad.mean() < 0.02, (k, float(bad.mean()))
 
 
+def test_router_adam_two_steps_parity(rt):
+    """Two Adam steps (two batches of 128 rows in input order: t = 1, then
+    t = 2, where the moments mix both gradients and the bias corrections no
+    longer cancel) move the weights as the oracle's `adam_step` does when fed
+    the GPU's own gradients at the GPU's own weights: `hntl_router_grad` (whose
+    parity with the oracle's backward is tested above) at the starting weights
+    on the first batch, and at the weights after a one-step run on the second.
+    This isolates the optimiser's arithmetic from the BF16 gradient noise that
+    a second step amplifies where two gradients nearly cancel."""
+    announce("two Adam steps on two batches vs the oracle's Adam on the GPU's gradients")
+    hntl = rt["hntl"]
+    X = rt["Qtr"][:256]
+    tg = knn_targets(rt, X)
+    lr = 1e-3
+    flags = hntl.HNTL_ROUTER_KEEP_WEIGHTS | hntl.HNTL_ROUTER_NO_SHUFFLE
+    keys = ("W1", "b1", "W2", "b2", "W3", "b3")
+    set_weights(rt)
+    _, g1 = hntl.hntl_router_grad(rt["ix"], to_dev(X[:128]), to_dev(tg[:128]))
+    hntl.hntl_router_train(rt["ix"], to_dev(X[:128]), targets=to_dev(tg[:128]), hidden=DIMS_H, epochs=1, batch=128,
+                           knn=10, lr=lr, flags=flags)
+    p1 = hntl.hntl_router_export(rt["ix"])
+    hntl.hntl_router_set(rt["ix"], {k: p1[k] for k in keys}, p1["mean"], p1["std"])
+    _, g2 = hntl.hntl_router_grad(rt["ix"], to_dev(X[128:]), to_dev(tg[128:]))
+    set_weights(rt)
+    hntl.hntl_router_train(rt["ix"], to_dev(X), targets=to_dev(tg), hidden=DIMS_H, epochs=1, batch=128, knn=10,
+                           lr=lr, flags=flags)
+    after = hntl.hntl_router_export(rt["ix"])
+    p, _, _ = oracle_params32(rt)
+    state = {}
+    cur = orr.adam_step(dict(p), {k: g1[k].astype(np.float64) for k in keys}, state, 1, lr=lr)
+    d1 = {k: cur[k] - p[k] for k in keys}
+    cur = orr.adam_step(dict(cur), {k: g2[k].astype(np.float64) for k in keys}, state, 2, lr=lr)
+    for k in keys:
+        # the first step alone, then both: FP32 masters and moments against
+        # FP64, far inside 1e-3 lr
+        np.testing.assert_allclose(p1[k].astype(np.float64) - p[k], d1[k], rtol=0, atol=1e-3 * lr, err_msg=k)
+        np.testing.assert_allclose(after[k].astype(np.float64) - p[k], cur[k] - p[k], rtol=0, atol=1e-3 * lr,
+                                   err_msg=k)
+        assert np.abs(cur[k] - p[k]).max() > 0.5 * lr  # the steps moved the weights
+
+
 def probe_recall(probes, gt_ids, lab):
     """Fraction of the true top-10 neighbours whose grain is probed."""
     hit = 0
