@@ -71,7 +71,7 @@ _SHA = {
     "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
     "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
     "paper_2606_08813_amd/csrc/fused_ct1.hip": "a15377c01ab0b4b06e0a90b3788ed3259d5aad97",
-    "paper_2606_08813_amd/csrc/rerank.hip": "eadb0a7606d798bc31bc66008d2b796749fe6e32",
+    "paper_2606_08813_amd/csrc/rerank.hip": "10c86c447d3bd19bc14c2dbd764d3fc5305ff15d",
     "paper_2606_08813_amd/csrc/project.hip": "ac70a7ba410f94fcf3a0388a38a0e5c439942fd7",
     "paper_2606_08813_amd/csrc/project_impl.h": "b7f2c4adb2e898712edc62fc094072e5ff0dab9b",
 }

@@ -343,10 +343,18 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
     }
   }
 
+  // The merge takes each list's keys in any order, so a list whose staged
+  // arrivals fit after its sorted keys is written without the final flush
+  // (about half of the lists on the 10M Zipf workload: those that start
+  // from a tight query bound see few arrivals).  Its C-th key is published
+  // only when it is full and sorted.
+  wave_sync();
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
     if (live[t]) {
-      Ls[t].finish();
+      const int nm = Ls[t].merged();
+      const bool as_is = nm + Ls[t].nstage <= C;
+      if (!as_is) Ls[t].finish();
       const int p = __builtin_amdgcn_readlane(pv, t);
       const uint64_t own = Ls[t].cth();
       if (own != KEY_NONE && lane == 0)
@@ -356,7 +364,7 @@ __device__ __forceinline__ void scan_tile(const FusedArgs& a, uint64_t* my, int 
 #pragma unroll
       for (int rr = 0; rr < CAP / 64; ++rr) {
         const int i = rr * 64 + lane;
-        const uint64_t kk = Ls[t].best[rr];
+        const uint64_t kk = as_is ? Ls[t].unsorted_at(i, rr, nm) : Ls[t].best[rr];
         if (i < C) stg(out + i, (kk == KEY_NONE) ? KEY_NONE : make_key(key_dist(kk), (uint32_t)ldg(a.perm + key_id(kk))));
       }
     }

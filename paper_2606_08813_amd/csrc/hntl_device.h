@@ -381,6 +381,22 @@ struct WaveTopR {
   // After finish(), list element r * 64 + lane is best[r] (KEY_NONE padded).
   __device__ __forceinline__ void finish() { flush(); }
 
+  // Keys merged into the sorted list so far (its valid prefix; uniform).
+  __device__ __forceinline__ int merged() const {
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) n += __popcll(__ballot(best[r] != KEY_NONE));
+    return n;
+  }
+
+  // Element i < merged() + nstage of the list's keys without a flush: the
+  // sorted ones first, then the staged arrivals in arrival order (KEY_NONE
+  // past the end).  Call wave_sync() first (stage entries of other lanes).
+  __device__ __forceinline__ uint64_t unsorted_at(int i, int r, int nm) const {
+    if (i < nm) return best[r];
+    return i < nm + nstage ? stage[i - nm] : KEY_NONE;
+  }
+
   __device__ __forceinline__ void tighten(uint64_t b) {
     if (b < bound) bound = b;
     if (b < thr) thr = b;

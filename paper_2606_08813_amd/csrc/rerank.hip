@@ -68,7 +68,9 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
             }
             key[u] = (ok && lane < C) ? src[(size_t)s * C + lane] : KEY_NONE;
           }
-          // a pruned list holds one KEY_NONE and nothing else written: skip it whole
+          // lists hold their keys in any order (a non-empty one with a key
+          // first); a pruned list holds one KEY_NONE and nothing else written:
+          // skip it whole
 #pragma unroll
           for (int u = 0; u < U; ++u)
             if (lane_u64(key[u], 0) != KEY_NONE) L.offer(key[u], key[u] != KEY_NONE);
@@ -106,8 +108,9 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(const float* __restri
             key[u][r] = (ok && c < C) ? src[(size_t)s * C + c] : KEY_NONE;
           }
         }
-        // lists are ascending and KEY_NONE-padded; a pruned list holds one
-        // KEY_NONE and nothing else written: skip it whole
+        // lists hold their keys in any order, KEY_NONE-padded, a non-empty
+        // one with a key first; a pruned list holds one KEY_NONE and nothing
+        // else written: skip it whole
 #pragma unroll
         for (int u = 0; u < U; ++u)
           if (lane_u64(key[u][0], 0) != KEY_NONE)
