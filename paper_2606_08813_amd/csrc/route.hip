@@ -331,7 +331,15 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
   WaveTop64 L;
   L.init(stage[wave], exact ? M : P);
   const float* drow = D + row * cols;
-  constexpr int U = 8;  // chunks of 64 loaded together (memory-level parallelism for one row)
+  // Segments of U chunks of 64 columns, loaded together.  The 64 lanes'
+  // minima over a segment are 64 entries of the row, so their maximum bounds
+  // the row's 64th smallest value (>= its M-th and P-th) from above: entries
+  // above the smallest such bound so far cannot be selected and are not
+  // offered (fewer list flushes; the selection is unchanged).  Segments of
+  // 16 chunks measured best (0.573 against 0.588 ms of routing without the
+  // bound at 16,384 x 8,192; longer segments cost more in occupancy).
+  constexpr int U = 16;
+  float T = __builtin_inff();  // uniform
   // znorm (negated scores): the row's smallest value mn and z = sum exp(mn - D_c),
   // the softmax normaliser of the scores, accumulated per lane against the
   // lane's running minimum and rescaled when it drops
@@ -341,12 +349,18 @@ __global__ __launch_bounds__(TOPK_ROWS * 64) void topk_rows_kernel(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * HNTL_WAVE + lane;
-      v[u] = c < cols ? drow[c] : 0.f;
+      v[u] = c < cols ? drow[c] : __builtin_inff();
     }
+    float seg = v[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) seg = fminf(seg, v[u]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) seg = fmaxf(seg, __shfl_xor(seg, o, 64));
+    T = fminf(T, seg);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * HNTL_WAVE + lane;
-      L.offer_f(v[u], (uint32_t)c, c < cols);
+      L.offer_f(v[u], (uint32_t)c, c < cols && v[u] <= T);
     }
     if (znorm) {
       float cm = __builtin_inff();
@@ -618,11 +632,11 @@ void launch_topk_rows(const float* D, int64_t rows, int cols, int P, int32_t* id
   if (A && znorm) throw ArgError{HNTL_EINVAL, "the softmax normaliser is for score rows (no re-score)"};
   if (rows <= 0) return;
   if (P > HNTL_MAX_P) throw ArgError{HNTL_EUNSUPPORTED, "routing supports P <= 48"};
-  dim3 grid((unsigned)((rows + TOPK_ROWS - 1) / TOPK_ROWS)), block(TOPK_ROWS * 64);
   // shortlist: the window of the P-th entry plus 48 more (one key per lane)
   const int M = A ? std::min(cols, std::min(64, P + 48)) : P;
   // float4 re-score loads where rows allow them
   const bool vec4 = A && (d % 4) == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
+  dim3 grid((unsigned)((rows + TOPK_ROWS - 1) / TOPK_ROWS)), block(TOPK_ROWS * 64);
   hipLaunchKernelGGL(topk_rows_kernel, grid, block, 0, s, D, rows, cols, P, M, A, an, Bm, bn, d, err, idx, val, nlim,
                      row_base, overflow, znorm, vec4);
   HIP_TRY(hipGetLastError());
