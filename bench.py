@@ -64,9 +64,9 @@ _SCAN_SRC = ("paper_2606_08813_amd/csrc/fused_impl.h", "paper_2606_08813_amd/csr
              "paper_2606_08813_amd/csrc/hntl_device.h", "paper_2606_08813_amd/csrc/plan.hip",
              "paper_2606_08813_amd/csrc/bucket.hip")
 _SHA = {
-    "paper_2606_08813_amd/csrc/fused_impl.h": "709714f59d8c77635c6b7619e0de344a4acf6d94",
-    "paper_2606_08813_amd/csrc/scan_impl.h": "f5cf70255c13644ef7f583e8c5fb911a995647fa",
-    "paper_2606_08813_amd/csrc/hntl_device.h": "7d53f2cb1ea12e28ecec99de76357ff1137165f9",
+    "paper_2606_08813_amd/csrc/fused_impl.h": "077cb0221488c77b89f0cfbb719688a9350e9d16",
+    "paper_2606_08813_amd/csrc/scan_impl.h": "08b1aa9c637b5afc8f01025d863320b4b9fa4998",
+    "paper_2606_08813_amd/csrc/hntl_device.h": "0f507370ccb3791fb9a34385536f3c326c60f0bf",
     "paper_2606_08813_amd/csrc/plan.hip": "e0cf1732648e8b136282930dff421ce558bdf943",
     "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
     "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
@@ -87,12 +87,12 @@ def _traffic(kernel, codes, batch, fetch_kib, write_kib, sources, profile):
 # merge + rerank launch (KiB per dispatch; the two-pass 256-query plan's two
 # scan launches summed)
 TRAFFIC = [
-    _traffic("scan", "fp32", 16384, 2.202e6, 8.653e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
+    _traffic("scan", "fp32", 16384, 2.202e6, 8.668e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
     _traffic("scan", "fp32", 256, 7.962e4 + 1.121e5, 710.0 + 891.8,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
-    _traffic("scan", "bf16", 16384, 1.122e6, 8.749e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
+    _traffic("scan", "bf16", 16384, 1.120e6, 8.757e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
     _traffic("scan", "bf16", 256, 4.122e4 + 5.823e4, 709.9 + 891.6,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
