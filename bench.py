@@ -77,10 +77,16 @@ _SHA = {
 }
 
 
-def _traffic(kernel, codes, batch, fetch_kib, write_kib, sources, profile):
+def _traffic(kernel, codes, batch, fetch_kib, write_kib, sources, profile, sched=None):
     return {"kernel": kernel, "workload": "zipf10M_d768_G8192_r48", "form": "plan", "codes": codes, "P": 16,
             "mode": "B", "batch": batch, "fetch_kib": fetch_kib, "write_kib": write_kib, "fetch_scale": 2.0,
-            "write_scale": 1.0, "sources": {f: _SHA[f] for f in sources}, "profile": profile}
+            "write_scale": 1.0, "sources": {f: _SHA[f] for f in sources}, "profile": profile, "sched": sched}
+
+
+# the fused scan's traffic depends on its tiles, ranges and passes (not on the
+# waves per workgroup)
+_WIDE = {"qt": 8, "range": 32, "passes": 1}
+_NARROW = {"qt": 1, "range": 32, "passes": 2}
 
 
 # per plan run: the fused scan launch(es), the separate projection launch, the
@@ -88,15 +94,15 @@ def _traffic(kernel, codes, batch, fetch_kib, write_kib, sources, profile):
 # scan launches summed)
 TRAFFIC = [
     _traffic("scan", "fp32", 16384, 2.202e6, 8.668e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
-             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _WIDE),
     _traffic("scan", "fp32", 256, 7.962e4 + 1.121e5, 710.0 + 891.8,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
-             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _NARROW),
     _traffic("scan", "bf16", 16384, 1.120e6, 8.757e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
-             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _WIDE),
     _traffic("scan", "bf16", 256, 4.122e4 + 5.823e4, 709.9 + 891.6,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
-             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md"),
+             "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _NARROW),
     _traffic("rerank", "fp32", 16384, 2.666e6, 3712.0, ("paper_2606_08813_amd/csrc/rerank.hip",),
              "profiles/merge_rerank_zipf10M_d768_G8192_r48_dram_counters.md"),
     _traffic("project", "fp32", 16384, 7.475e5, 5.759e4,
@@ -108,12 +114,14 @@ TRAFFIC = [
 ]
 
 
-def measured_traffic(kernel, workload, form, codes, P, mode, batch):
+def measured_traffic(kernel, workload, form, codes, P, mode, batch, sched=None):
     import hashlib
     for t in TRAFFIC:
         if (kernel, workload, form, codes, P, mode, batch) != (t["kernel"], t["workload"], t["form"], t["codes"],
                                                                t["P"], t["mode"], t["batch"]):
             continue
+        if t["sched"] and (sched is None or any(sched.get(k) != v for k, v in t["sched"].items())):
+            return None  # counted under another schedule
         for src, sha in t["sources"].items():
             p = ROOT / src
             if not p.exists() or hashlib.sha1(p.read_bytes()).hexdigest() != sha:
@@ -558,7 +566,7 @@ def main():
         roof[name] = {"bound": s["bound"], "achieved": round(achieved, 3), "peak": s["peak"], "unit": s["unit"],
                       "frac": round(achieved / s["peak"], 4), "ms": round(stage_avg[name], 4)}
         tr = measured_traffic(name, W.name, args.form, args.codes if name != "project" else
-                              ("bf16" if bf16_project else "fp32"), P, args.mode, W.nq)
+                              ("bf16" if bf16_project else "fp32"), P, args.mode, W.nq, sched)
         if tr:  # the stage's DRAM bytes from counters on this kernel source
             roof[name]["traffic"] = tr
             roof[name]["dram_GBps"] = round(tr / t / 1e9, 1)
@@ -579,7 +587,7 @@ def main():
         nblk = (sizes[pg] + 63) // 64
         unique_bytes = int(nblk.sum()) * 64 * (rp * code_bytes + 4)
         t_scan = rh["stage"]["scan"]
-        traffic = measured_traffic("scan", W.name, "plan", args.codes, P, args.mode, nb)
+        traffic = measured_traffic("scan", W.name, "plan", args.codes, P, args.mode, nb, rh["sched"])
         scan_hbm = {"batch": nb, "schedule": rh["sched"], "scan_ms": round(t_scan, 4),
                     "probed_grains": int(len(pg)), "unique_code_bytes": unique_bytes,
                     "scored": int(rh["scored"]),
@@ -724,7 +732,8 @@ def main():
         "build_s": None if build_s is None else round(build_s, 2),
         "captured_variance": round(info["captured_variance"], 5),
         "roofline": dict(roof.get(dominant, {}), kernel=dominant,
-                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode, W.nq))
+                         traffic=measured_traffic(dominant, W.name, args.form, args.codes, P, args.mode, W.nq,
+                                                  sched))
         if dominant else None,
         "stage_rooflines": roof,
         "scan_hbm": scan_hbm,
