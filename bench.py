@@ -11,6 +11,8 @@ runs with HIP events on the plan's stream).
 
 Beside the headline (plain FP32 plan) the same JSON line carries, by default on
 the batching workload:
+  centroid_bf16  centroid routing with BF16 codes and BF16 projection, same P
+                 and C (the precision form without the router)
   learned_bf16   the learned router (768-1024-1024-8192, trained first on
                  200,000 generated queries with brute-force kNN targets) with
                  BF16 codes and BF16 projection, same P and C, its Recall@10 on
@@ -625,10 +627,23 @@ def main():
         log(f"[bench] uneven batches: {uneven_out}")
         del ru, plan_u, Qu, views
 
-    # the learned router + BF16 codes + BF16 projection at the same P and C
+    # the learned router + BF16 codes + BF16 projection at the same P and C,
+    # and centroid routing with the same BF16 codes and projection (what the
+    # precision form gives without the router)
     learned = None
+    centroid_bf16 = None
     if compare:
         fl_l = hntl.HNTL_FLAG_PROJECT_BF16
+        fl_c = fl_l | (pflags & (hntl.HNTL_FLAG_ROUTE_BF16 | hntl.HNTL_FLAG_ROUTE_BF16X3))  # the headline's shortlist
+        rc = time_plan(hntl, torch, ix, Q, P, W.C, W.k, W.nq, "bf16", fl_c, {}, args.steps, args.warmup)
+        rec_c = recall_at_k(rc["ids"].cpu().numpy()[rs], gt, W.k)
+        centroid_bf16 = {"form": "plan", "route": "centroid", "codes": "bf16", "projection": "bf16", "P": P,
+                         "C": W.C, "value": round(W.nq / (rc["ms"] / 1e3), 1), "ms_per_step": round(rc["ms"], 4),
+                         "recall_at_10": round(rec_c, 4),
+                         "stage_ms": {kk: round(v, 4) for kk, v in rc["stage"].items()}, "schedule": rc["sched"],
+                         "speedup_vs_plain_fp32": round(ms_per_step / rc["ms"], 4)}
+        log(f"[bench] centroid + BF16: {centroid_bf16}")
+        del rc
         rl = time_plan(hntl, torch, ix, Q, P, W.C, W.k, W.nq, "bf16", fl_l, dict(route="learned", tau=args.tau),
                        args.steps, args.warmup)
         rec_l = recall_at_k(rl["ids"].cpu().numpy()[rs], gt, W.k)
@@ -737,6 +752,7 @@ def main():
         if dominant else None,
         "stage_rooflines": roof,
         "scan_hbm": scan_hbm,
+        "centroid_bf16": centroid_bf16,
         "learned_bf16": learned,
         "uneven_batches": uneven_out,
         "cpu_baseline": cpu,
