@@ -44,3 +44,33 @@ def test_fp64_grain_scores_match_the_oracle():
             hi, hd = b.fp64_grain_scores(Q[i], int(probes[i, s]), st)
             np.testing.assert_array_equal(hi, gi)
             np.testing.assert_allclose(hd, gd, rtol=1e-12, atol=1e-12)
+
+
+def test_traffic_entries_apply_only_to_their_sources_and_schedule():
+    """A counter-derived traffic figure is reported only while the kernel's
+    sources hash as when the counters were taken, and for the scan only under
+    the tiles, ranges and passes they were taken with; the bytes are
+    FETCH_SIZE x 2 + WRITE_SIZE x 1 KiB."""
+    b = _bench()
+    wide = {"qt": 8, "nw": 4, "range": 32, "grid": 0, "passes": 1, "proj": 1}
+    for t in b.TRAFFIC:
+        sched = dict(wide, **t["sched"]) if t["sched"] else wide
+        got = b.measured_traffic(t["kernel"], t["workload"], t["form"], t["codes"], t["P"], t["mode"], t["batch"],
+                                 sched)
+        assert got == round((t["fetch_kib"] * 2.0 + t["write_kib"]) * 1024.0), t["kernel"]
+        if t["sched"]:
+            assert b.measured_traffic(t["kernel"], t["workload"], t["form"], t["codes"], t["P"], t["mode"],
+                                      t["batch"], dict(sched, qt=sched["qt"] * 2)) is None
+            assert b.measured_traffic(t["kernel"], t["workload"], t["form"], t["codes"], t["P"], t["mode"],
+                                      t["batch"], None) is None
+    assert b.measured_traffic("scan", "zipf10M_d768_G8192_r48", "plan", "fp8", 16, "B", 16384, wide) is None
+    # a changed source voids the entry
+    t0 = b.TRAFFIC[0]
+    src = next(iter(t0["sources"]))
+    saved = t0["sources"][src]
+    try:
+        t0["sources"][src] = "0" * 40
+        assert b.measured_traffic(t0["kernel"], t0["workload"], t0["form"], t0["codes"], t0["P"], t0["mode"],
+                                  t0["batch"], dict(wide, **(t0["sched"] or {}))) is None
+    finally:
+        t0["sources"][src] = saved
