@@ -111,9 +111,13 @@ constexpr int DPP_FROM_UP4 = 0x104;  // row_shl:4, lane i reads lane i + 4 of it
 constexpr int DPP_FROM_DN4 = 0x114;  // row_shr:4, lane i reads lane i - 4 of its row
 constexpr int DPP_ROR8 = 0x128;      // row_ror:8, lane i reads lane i ^ 8 of its row
 
+// A DPP move with no old value to keep: every lane a caller uses reads a
+// valid source lane (the two shifts by 4 leave four lanes of each row without
+// one, and lane_xor<4> takes each lane's value from the shift that has it), so
+// the result needs no copy of the source into the destination first.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
 
 template <int J>
