@@ -68,7 +68,7 @@ _SCAN_SRC = ("paper_2606_08813_amd/csrc/fused_impl.h", "paper_2606_08813_amd/csr
 _SHA = {
     "paper_2606_08813_amd/csrc/fused_impl.h": "077cb0221488c77b89f0cfbb719688a9350e9d16",
     "paper_2606_08813_amd/csrc/scan_impl.h": "08b1aa9c637b5afc8f01025d863320b4b9fa4998",
-    "paper_2606_08813_amd/csrc/hntl_device.h": "0f507370ccb3791fb9a34385536f3c326c60f0bf",
+    "paper_2606_08813_amd/csrc/hntl_device.h": "8042d049177634c7c50bf9f741925e63359e7b21",
     "paper_2606_08813_amd/csrc/plan.hip": "e0cf1732648e8b136282930dff421ce558bdf943",
     "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
     "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
@@ -95,12 +95,12 @@ _NARROW = {"qt": 1, "range": 32, "passes": 2}
 # merge + rerank launch (KiB per dispatch; the two-pass 256-query plan's two
 # scan launches summed)
 TRAFFIC = [
-    _traffic("scan", "fp32", 16384, 2.202e6, 8.668e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
+    _traffic("scan", "fp32", 16384, 2.196e6, 8.634e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _WIDE),
     _traffic("scan", "fp32", 256, 7.962e4 + 1.121e5, 710.0 + 891.8,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct0.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _NARROW),
-    _traffic("scan", "bf16", 16384, 1.120e6, 8.757e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
+    _traffic("scan", "bf16", 16384, 1.120e6, 8.752e4, _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
              "profiles/fused_scan_zipf10M_d768_G8192_r48_dram_counters.md", _WIDE),
     _traffic("scan", "bf16", 256, 4.122e4 + 5.823e4, 709.9 + 891.6,
              _SCAN_SRC + ("paper_2606_08813_amd/csrc/fused_ct1.hip",),
