@@ -232,3 +232,46 @@ def test_int16_unsupported_forms(i16):
         hntl.hntl_search(i16["ix"], i16["Qd"][:4].contiguous(), W.P, W.C, W.k, codes="int16",
                          flags=hntl.HNTL_FLAG_MODE_A)
     assert e.value.status == hntl.HNTL_EUNSUPPORTED
+
+
+def test_int16_extreme_range_scores():
+    """The integer distance at the ends of the int16 range, at the largest rank
+    (r = 64): three quarters of every member's codes and of every query's
+    quantised coordinates sit at +-32767 (signs at random), the rest spread
+    over the range, so the partial dot products the scan accumulates in 32
+    bits reach their largest magnitudes.  Scores, pools and their order match
+    the oracle's exact integer evaluation of eq. 5 on the same injected
+    tangents."""
+    torch = require_gpu()
+    from paper_2606_08813_amd import hntl
+    from oracle import index as oi
+    from workloads import patch_mixture as pm
+    announce("int16 at the range extremes, r = 64")
+    m = pm.uniform_mixture(2400, 96, 4, seed=51, threads=2)
+    q = pm.uniform_queries(48, 96, 4, 51, 1051, threads=2)
+    st = oi.build(m.X, 4, 64, seed=53).stored()
+    st = {k: st[k] for k in KEYS}
+    rng = np.random.default_rng(57)
+    A = 3.0
+
+    def extreme(shape):
+        v = A * rng.choice([-1.0, 1.0], size=shape)
+        spread = rng.random(shape) < 0.25
+        return np.where(spread, rng.uniform(-A, A, size=shape), v)
+
+    st["codes"] = extreme(st["codes"].shape).astype(st["codes"].dtype)
+    ix = hntl.hntl_index_create(st, m.X, codes=("fp32", "int16"))
+    P, C, k = 2, 40, 10
+    probes = np.stack([np.arange(48) % 4, (np.arange(48) + 1 + np.arange(48) // 4) % 4], axis=1)
+    probes[probes[:, 0] == probes[:, 1], 1] = (probes[probes[:, 0] == probes[:, 1], 0] + 1) % 4
+    zq = extreme((48, P, 64)).astype(np.float32)
+    epsq = rng.uniform(0.0, 1.0, size=(48, P)).astype(np.float32)
+    zh, _, inv, _ = quant.int16_grain_codes(st["codes"], st["eps"], st["offsets"], 64)
+    assert (np.abs(zh) == 32767).mean() > 0.7  # the codes do sit at the range ends
+    o = hntl.hntl_search_stages(ix, to_dev(q.X), P, C, k, codes="int16", probes_in=to_dev(probes.astype(np.int32)),
+                                tangent_in=to_dev(zq), epsq_in=to_dev(epsq))
+    z64 = zq.astype(np.float64)
+    pool_ids, pool_D = osr.scan_pool(z64, epsq.astype(np.float64), probes, st, C, "int16")
+    assert (pool_ids >= 0).all()
+    parity.check_lists(o["pool_ids"].cpu().numpy(), o["pool_D"].cpu().numpy(), pool_ids, pool_D,
+                       int16_score_fn(st, z64, epsq.astype(np.float64), probes), what="int16 extremes")
