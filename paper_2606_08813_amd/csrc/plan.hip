@@ -7,18 +7,16 @@
 //
 //   reset (fill kernels: ticket, per-grain projection counters, per-query
 //          bounds; graphs hold kernel nodes only)
-//   routing          row norms, centroid dot products (library GEMM) or distances
-//                    (MFMA kernels), top-P + exact re-score
+//   routing          row norms, centroid distances (own MFMA GEMMs with a
+//                    distance epilogue), top-P + exact re-score
 //   bucketing        pairs grouped by grain, items numbered largest grain first
 //   pair lists       per-pair list slots when grains are split into ranges
 //   fused kernel     projection + scan + per-list top-C (persistent)
 //   merge + rerank   pool = exact top C over the query's lists, FP32 rerank
 //
 // The batch size lives in device memory (written by a one-thread kernel
-// before each run) and the kernels skip rows past it.  The library GEMM of
-// centroid routing cannot, so a plan captures one graph per routing row
-// bucket (64, 128, ... up to max_nq rows); a run replays the smallest bucket
-// that holds its batch.
+// before each run) and every kernel, the routing GEMMs included, skips rows
+// past it, so one captured graph serves every batch size up to max_nq.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
