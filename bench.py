@@ -69,7 +69,7 @@ _SHA = {
     "paper_2606_08813_amd/csrc/fused_impl.h": "077cb0221488c77b89f0cfbb719688a9350e9d16",
     "paper_2606_08813_amd/csrc/scan_impl.h": "08b1aa9c637b5afc8f01025d863320b4b9fa4998",
     "paper_2606_08813_amd/csrc/hntl_device.h": "8042d049177634c7c50bf9f741925e63359e7b21",
-    "paper_2606_08813_amd/csrc/plan.hip": "e0cf1732648e8b136282930dff421ce558bdf943",
+    "paper_2606_08813_amd/csrc/plan.hip": "7a6f9b44aa5f8ef18a7c9574b2ad2af57c79e889",
     "paper_2606_08813_amd/csrc/bucket.hip": "dc32fc07f95bbf8d60d3997767278e18c59cc518",
     "paper_2606_08813_amd/csrc/fused_ct0.hip": "dce4677b8d7025d96f78ce59f33911b619912e08",
     "paper_2606_08813_amd/csrc/fused_ct1.hip": "a15377c01ab0b4b06e0a90b3788ed3259d5aad97",
